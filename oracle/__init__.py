@@ -1,0 +1,676 @@
+"""FP64 CPU oracle for the TTI and elastic propagators.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the CPU-baseline leg of ``bench.py``; never by the product library, which
+must not depend on it.  It shares no code with the HIP path: only the seeded
+input generators (``paper_2004_10519_amd.inputs``) feed both.
+
+Spatial operators are plain C loops in ``oracle.c`` (FP64, OpenMP over
+output points).  Time loops, sparse source/receiver operators, damping, FD
+weights and the checkpoint codec are written here in numpy, following the
+paper's problem statement (Eq. "acou" and the Grid / Function /
+SparseTimeFunction listings), the TTI section (Eq. "rot", the rotated
+derivative listing) and the elastic section (Eq. "elas1", the elastic
+listing).  Every reading of a passage that the paper leaves open is listed in
+DESIGN.md's "Readings" table; the functions below say which one they take.
+
+Parity status: every function here is pinned by ``tests/test_oracle_*.py``
+against closed forms, textbook results, invariants or brute force, except the
+readings that no external fact fixes (damping profile, half-node averaging,
+recorded quantity, Ricker delay), which are "parity unpinned" by nature.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass, field
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, FP64, OpenMP)."""
+    if force or not os.path.exists(_SO):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               os.path.join(_HERE, "oracle.c"), "-o", _SO + ".tmp", "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_SO + ".tmp", _SO)
+    return _SO
+
+
+class _CGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int), ("n", ctypes.c_long * 3), ("h", ctypes.c_double * 3)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_SO):
+            build(force=False)
+        L = ctypes.CDLL(_SO)
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp = ctypes.POINTER(_CGrid)
+        L.orc_dcen.argtypes = [gp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_dcen_T.argtypes = [gp, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_dstag.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_dstag_T.argtypes = [gp, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
+        L.orc_tti_H.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, ctypes.c_int, dp]
+        L.orc_tti_step.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, dp, dp, dp, ctypes.c_double,
+                                   ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        pp = ctypes.POINTER(dp)
+        L.orc_el_step.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, pp, pp]
+        L.orc_el_step_T.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, pp, pp]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _pp(arrs):
+    arr_t = ctypes.POINTER(ctypes.c_double) * len(arrs)
+    return arr_t(*[_p(a) for a in arrs])
+
+
+# ---------------------------------------------------------------------------
+# Grid
+# ---------------------------------------------------------------------------
+@dataclass
+class Grid:
+    """A discretised model domain (the paper's Grid listing: shape, extent, origin).
+
+    shape = (nx, ny, nz) with ny = 1 in 2D; arrays are (nz, ny, nx).  z is depth.
+    nbl = width (points) of the absorbing layer, counted inside ``shape``.
+    """
+    shape: tuple
+    spacing: tuple
+    origin: tuple = (0.0, 0.0, 0.0)
+    space_order: int = 8
+    nbl: int = 0
+    dt: float = 1e-3
+    nt: int = 1
+    vref: float = 1500.0
+
+    @property
+    def ndim(self) -> int:
+        return 2 if self.shape[1] == 1 else 3
+
+    @property
+    def r(self) -> int:
+        return self.space_order // 2
+
+    @property
+    def arr_shape(self):
+        nx, ny, nz = self.shape
+        return (nz, ny, nx)
+
+    def axes(self):
+        return (0, 2) if self.ndim == 2 else (0, 1, 2)
+
+    def c(self) -> _CGrid:
+        g = _CGrid()
+        g.ndim = self.ndim
+        for i in range(3):
+            g.n[i] = int(self.shape[i])
+            g.h[i] = float(self.spacing[i])
+        return g
+
+
+# ---------------------------------------------------------------------------
+# Finite-difference weights (exact rationals)
+# ---------------------------------------------------------------------------
+def fd_centered(so: int) -> list:
+    """Centred first-derivative weights a_1..a_r of accuracy order so = 2r (closed form).
+
+    a_j = (-1)^(j+1) (r!)^2 / (j (r-j)! (r+j)!).   (Reading: "space order so" means the
+    accuracy order of every first derivative that the rotated operators compose.)
+    """
+    r = so // 2
+    f = math.factorial
+    return [Fraction((-1) ** (j + 1) * f(r) ** 2, j * f(r - j) * f(r + j)) for j in range(1, r + 1)]
+
+
+def fornberg(order: int, z, xs) -> list:
+    """Finite-difference weights for the ``order``-th derivative at z on nodes xs.
+
+    Fornberg's recursive algorithm (B. Fornberg, Math. Comp. 51, 1988; SIAM Rev. 40, 1998),
+    in exact rational arithmetic.  Returns one weight per node.
+    """
+    z = Fraction(z)
+    xs = [Fraction(x) for x in xs]
+    n = len(xs)
+    C = [[Fraction(0)] * (order + 1) for _ in range(n)]
+    c1 = Fraction(1)
+    c4 = xs[0] - z
+    C[0][0] = Fraction(1)
+    for i in range(1, n):
+        mn = min(i, order)
+        c2 = Fraction(1)
+        c5 = c4
+        c4 = xs[i] - z
+        for j in range(i):
+            c3 = xs[i] - xs[j]
+            c2 *= c3
+            if j == i - 1:
+                for k in range(mn, 0, -1):
+                    C[i][k] = c1 * (k * C[i - 1][k - 1] - c5 * C[i - 1][k]) / c2
+                C[i][0] = -c1 * c5 * C[i - 1][0] / c2
+            for k in range(mn, 0, -1):
+                C[j][k] = (c4 * C[j][k] - k * C[j][k - 1]) / c3
+            C[j][0] = c4 * C[j][0] / c3
+        c1 = c2
+    return [C[i][order] for i in range(n)]
+
+
+def fd_staggered(so: int) -> list:
+    """Staggered first-derivative weights c_1..c_r (nodes at +-(j - 1/2)), by Fornberg's algorithm."""
+    r = so // 2
+    nodes = [Fraction(2 * j - 1, 2) for j in range(1, r + 1)]
+    xs = [-x for x in reversed(nodes)] + nodes
+    w = fornberg(1, 0, xs)
+    return w[r:]  # weights of +(j - 1/2), j = 1..r
+
+
+def _wf(ws) -> np.ndarray:
+    return np.array([float(x) for x in ws], dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Derivative primitives (thin wrappers of the C loops)
+# ---------------------------------------------------------------------------
+def dcen(g: Grid, axis: int, f: np.ndarray, transpose: bool = False) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.arr_shape)
+    out = np.empty_like(f)
+    a = _wf(fd_centered(g.space_order))
+    fn = lib().orc_dcen_T if transpose else lib().orc_dcen
+    cg = g.c()
+    fn(ctypes.byref(cg), axis, g.r, _p(a), _p(f), _p(out))
+    return out
+
+
+def dstag(g: Grid, axis: int, plus: bool, f: np.ndarray, transpose: bool = False) -> np.ndarray:
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.arr_shape)
+    out = np.empty_like(f)
+    c = _wf(fd_staggered(g.space_order))
+    fn = lib().orc_dstag_T if transpose else lib().orc_dstag
+    cg = g.c()
+    fn(ctypes.byref(cg), axis, int(plus), g.r, _p(c), _p(f), _p(out))
+    return out
+
+
+def tti_H(g: Grid, theta, phi, f, group: int) -> np.ndarray:
+    """H0 f (group 0) or Hz f (group 1): the paper's rotated operators, literally -D_i^T D_i."""
+    th = np.ascontiguousarray(theta, dtype=np.float64).reshape(g.arr_shape)
+    ph = np.ascontiguousarray(phi, dtype=np.float64).reshape(g.arr_shape)
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(g.arr_shape)
+    out = np.empty_like(f)
+    a = _wf(fd_centered(g.space_order))
+    cg = g.c()
+    lib().orc_tti_H(ctypes.byref(cg), g.r, _p(a), _p(th), _p(ph), _p(f), group, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Absorbing layer (reading: quadratic Cerjan-type profile, frozen reference velocity)
+# ---------------------------------------------------------------------------
+def damping_kappa(g: Grid) -> np.ndarray:
+    """kappa(x) = sum_a kmax_a (d_a / nbl)^2 (1/s), d_a = depth in points into the layer along axis a,
+    kmax_a = 3 vref ln(1000) / (2 nbl h_a).  Zero when nbl = 0."""
+    k = np.zeros(g.arr_shape, dtype=np.float64)
+    if g.nbl <= 0:
+        return k
+    for ax in g.axes():
+        n = g.shape[ax]
+        i = np.arange(n, dtype=np.float64)
+        d = np.maximum(np.maximum(g.nbl - i, i - (n - 1 - g.nbl)), 0.0)
+        kmax = 3.0 * g.vref * math.log(1000.0) / (2.0 * g.nbl * g.spacing[ax])
+        prof = kmax * (d / g.nbl) ** 2
+        shp = [1, 1, 1]
+        shp[2 - ax] = n
+        k = k + prof.reshape(shp)
+    return k
+
+
+def tti_eta(g: Grid) -> np.ndarray:
+    """eta = kappa / vref^2 (s/m^2), the damping coefficient of the TTI equations."""
+    return damping_kappa(g) / (g.vref ** 2)
+
+
+def elastic_damp(g: Grid) -> np.ndarray:
+    """Multiplicative damping factor exp(-kappa dt) of the elastic update (the listing's ``damp``)."""
+    return np.exp(-damping_kappa(g) * g.dt)
+
+
+# ---------------------------------------------------------------------------
+# Sparse points: multilinear interpolation / injection (reading: multilinear)
+# ---------------------------------------------------------------------------
+@dataclass
+class Sparse:
+    idx: np.ndarray   # (npoint, 2^d) flat indices
+    w: np.ndarray     # (npoint, 2^d) weights
+
+
+def sparse_setup(g: Grid, xyz, stagger=(0.0, 0.0, 0.0)) -> Sparse:
+    """Corner indices and weights of off-grid points (coordinates in metres, npoint x ndim).
+
+    Per axis: u = (x - o)/h, i0 = floor(u), alpha = u - i0; a point on the last node uses
+    i0 = n-2, alpha = 1.  ``stagger`` shifts the grid by a fraction of h (vz lives at z + h/2).
+    """
+    xyz = np.asarray(xyz, dtype=np.float64).reshape(-1, g.ndim)
+    axes = g.axes()
+    npt = xyz.shape[0]
+    base = np.zeros(npt, dtype=np.int64)
+    corner_idx = [np.zeros(npt, dtype=np.int64)]
+    corner_w = [np.ones(npt, dtype=np.float64)]
+    strides = (1, g.shape[0], g.shape[0] * g.shape[1])
+    for k, ax in enumerate(axes):
+        n, h, o = g.shape[ax], g.spacing[ax], g.origin[ax] + stagger[ax] * g.spacing[ax]
+        u = (xyz[:, k] - o) / h
+        if np.any(u < 0) or np.any(u > n - 1):
+            raise ValueError("sparse point outside the grid")
+        i0 = np.floor(u).astype(np.int64)
+        al = u - i0
+        last = i0 >= n - 1
+        i0[last] = n - 2
+        al[last] = 1.0
+        new_idx, new_w = [], []
+        for ci, cw in zip(corner_idx, corner_w):
+            new_idx += [ci + i0 * strides[ax], ci + (i0 + 1) * strides[ax]]
+            new_w += [cw * (1.0 - al), cw * al]
+        corner_idx, corner_w = new_idx, new_w
+    del base
+    return Sparse(np.stack(corner_idx, axis=1), np.stack(corner_w, axis=1))
+
+
+def interp(sp: Sparse, f: np.ndarray) -> np.ndarray:
+    return (f.reshape(-1)[sp.idx] * sp.w).sum(axis=1)
+
+
+def inject(sp: Sparse, f: np.ndarray, vals: np.ndarray, scale=None) -> None:
+    """f[corners] += w * vals (optionally divided pointwise by ``scale`` at the corners)."""
+    flat = f.reshape(-1)
+    contrib = sp.w * np.asarray(vals, dtype=np.float64)[:, None]
+    if scale is not None:
+        contrib = contrib / scale.reshape(-1)[sp.idx]
+    np.add.at(flat, sp.idx.ravel(), contrib.ravel())
+
+
+# ---------------------------------------------------------------------------
+# TTI: forward, adjoint, gradient
+# ---------------------------------------------------------------------------
+@dataclass
+class TTIModel:
+    m: np.ndarray
+    eps: np.ndarray
+    delta: np.ndarray
+    theta: np.ndarray
+    phi: np.ndarray
+
+    @staticmethod
+    def from_arrays(g: Grid, m, eps, delta, theta, phi) -> "TTIModel":
+        c = lambda a: np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(g.arr_shape))
+        ph = c(phi) if g.ndim == 3 else np.zeros(g.arr_shape)
+        return TTIModel(c(m), c(eps), c(delta), c(theta), ph)
+
+
+def _tti_a(g: Grid, mod: TTIModel, eta):
+    return mod.m / g.dt ** 2 + eta / (2.0 * g.dt)
+
+
+def _tti_step(g, mod, eta, adjoint, p, q, pm, qm):
+    pn = np.empty_like(p)
+    qn = np.empty_like(q)
+    a = _wf(fd_centered(g.space_order))
+    cg = g.c()
+    lib().orc_tti_step(ctypes.byref(cg), g.r, _p(a), _p(mod.m), _p(mod.eps), _p(mod.delta),
+                       _p(mod.theta), _p(mod.phi), _p(eta), g.dt, int(adjoint),
+                       _p(p), _p(q), _p(pm), _p(qm), _p(pn), _p(qn))
+    return pn, qn
+
+
+def tti_forward(g: Grid, mod: TTIModel, src_xyz, wavelet, rec_xyz, nt=None, force=None,
+                keep=False, callback=None):
+    """Forward TTI modelling.
+
+    State recurrence a f^{n+1} = b f^n - c f^{n-1} + L(p^n, q^n) + P_s^T s^n for f in {p, q},
+    zero initial state, n = 0..nt-1; trace sample d^n = P_r p^{n+1} (reading: record p).
+    ``force(n)`` may return dense (fp, fq) forcing added like the source term (dot tests).
+    Returns (traces (nt, nrec), final (p, q, p_prev, q_prev), list of states if keep).
+    """
+    nt = g.nt if nt is None else nt
+    shp = g.arr_shape
+    p, q, pm, qm = (np.zeros(shp) for _ in range(4))
+    eta = tti_eta(g)
+    a = _tti_a(g, mod, eta)
+    src = sparse_setup(g, src_xyz) if src_xyz is not None and len(src_xyz) else None
+    rec = sparse_setup(g, rec_xyz) if rec_xyz is not None and len(rec_xyz) else None
+    wav = None if wavelet is None else np.asarray(wavelet, dtype=np.float64).reshape(nt, -1)
+    traces = np.zeros((nt, 0 if rec is None else rec.idx.shape[0]))
+    states = [(p.copy(), q.copy())] if keep else None
+    for n in range(nt):
+        pn, qn = _tti_step(g, mod, eta, False, p, q, pm, qm)
+        if src is not None:
+            inject(src, pn, wav[n], scale=a)
+            inject(src, qn, wav[n], scale=a)
+        if force is not None:
+            fr = force(n)
+            if fr is not None:
+                pn += fr[0] / a
+                qn += fr[1] / a
+        if rec is not None:
+            traces[n] = interp(rec, pn)
+        pm, qm, p, q = p, q, pn, qn
+        if keep:
+            states.append((p.copy(), q.copy()))
+        if callback is not None:
+            callback(n, p, q)
+    return traces, (p, q, pm, qm), states
+
+
+def tti_adjoint(g: Grid, mod: TTIModel, src_xyz, rec_xyz, rec_data, nt=None, force=None,
+                callback=None):
+    """Exact transpose of ``tti_forward`` (wavelet -> traces).
+
+    With y^{N+1} = y^{N+2} = 0, for k = N..1:
+        a y^k = b y^{k+1} - c y^{k+2} + L^T y^{k+1} + P_r^T d^{k-1}  (into the p component)
+        s^{k-1} = P_s (y_p^k + y_q^k)
+    ``force(k-1)`` may return dense (gp, gq) adjoint forcing; ``callback(k, yp, yq)`` sees y^k.
+    Returns (source traces (nt, nsrc), final (y_p^1, y_q^1)).
+    """
+    nt = g.nt if nt is None else nt
+    shp = g.arr_shape
+    y1p, y1q, y2p, y2q = (np.zeros(shp) for _ in range(4))
+    eta = tti_eta(g)
+    a = _tti_a(g, mod, eta)
+    src = sparse_setup(g, src_xyz) if src_xyz is not None and len(src_xyz) else None
+    rec = sparse_setup(g, rec_xyz) if rec_xyz is not None and len(rec_xyz) else None
+    dat = None if rec_data is None else np.asarray(rec_data, dtype=np.float64).reshape(nt, -1)
+    out = np.zeros((nt, 0 if src is None else src.idx.shape[0]))
+    for k in range(nt, 0, -1):
+        ykp, ykq = _tti_step(g, mod, eta, True, y1p, y1q, y2p, y2q)
+        if rec is not None:
+            inject(rec, ykp, dat[k - 1], scale=a)
+        if force is not None:
+            fr = force(k - 1)
+            if fr is not None:
+                ykp += fr[0] / a
+                ykq += fr[1] / a
+        if src is not None:
+            out[k - 1] = interp(src, ykp) + interp(src, ykq)
+        if callback is not None:
+            callback(k, ykp, ykq)
+        y2p, y2q, y1p, y1q = y1p, y1q, ykp, ykq
+    return out, (y1p, y1q)
+
+
+def tti_gradient(g: Grid, mod: TTIModel, src_xyz, wavelet, rec_xyz, d_obs, nt=None):
+    """Gradient of J(m) = 1/2 sum_n ||d^n - d_obs^n||^2 with respect to m (exact for the discrete system).
+
+    Residual form of step n: R^n = a f^{n+1} - b f^n + c f^{n-1} - L f^n - P_s^T s^n, with
+    dR^n/dm = (f^{n+1} - 2 f^n + f^{n-1}) / dt^2 (L, eta and the source do not depend on m).
+    g = -(1/dt^2) sum_{n=0}^{N-1} sum_{f in p,q} y_f^{n+1} (f^{n+1} - 2 f^n + f^{n-1}),
+    with y the adjoint state driven by the residual d - d_obs.  Returns (J, g, traces).
+    """
+    nt = g.nt if nt is None else nt
+    d, _, states = tti_forward(g, mod, src_xyz, wavelet, rec_xyz, nt=nt, keep=True)
+    res = d - np.asarray(d_obs, dtype=np.float64).reshape(d.shape)
+    J = 0.5 * float(np.sum(res * res))
+    grad = np.zeros(g.arr_shape)
+    zero = np.zeros(g.arr_shape)
+
+    def cb(k, yp, yq):
+        fk, fk1 = states[k], states[k - 1]
+        fk2 = states[k - 2] if k >= 2 else (zero, zero)
+        grad[...] -= (yp * (fk[0] - 2 * fk1[0] + fk2[0]) + yq * (fk[1] - 2 * fk1[1] + fk2[1])) / g.dt ** 2
+
+    tti_adjoint(g, mod, src_xyz, rec_xyz, res, nt=nt, callback=cb)
+    return J, grad, d
+
+
+# ---------------------------------------------------------------------------
+# Independent acoustic steppers (for reduction checks)
+# ---------------------------------------------------------------------------
+def acoustic_wide_forward(g: Grid, m, src_xyz, wavelet, rec_xyz, nt=None):
+    """u^{n+1} = 2u^n - u^{n-1} + dt^2/m (-sum_a D_a^T D_a u^n + P_s^T s^n), the listing "WE" scheme
+    with the composed (wide) Laplacian; no damping.  Returns (traces, final u)."""
+    nt = g.nt if nt is None else nt
+    m = np.asarray(m, dtype=np.float64).reshape(g.arr_shape)
+    u, um = np.zeros(g.arr_shape), np.zeros(g.arr_shape)
+    src = sparse_setup(g, src_xyz)
+    rec = sparse_setup(g, rec_xyz)
+    wav = np.asarray(wavelet, dtype=np.float64).reshape(nt, -1)
+    tr = np.zeros((nt, rec.idx.shape[0]))
+    for n in range(nt):
+        lap = np.zeros(g.arr_shape)
+        for ax in g.axes():
+            lap -= dcen(g, ax, dcen(g, ax, u), transpose=True)
+        rhs = lap
+        inject(src, rhs, wav[n])
+        un = 2 * u - um + g.dt ** 2 / m * rhs
+        tr[n] = interp(rec, un)
+        um, u = u, un
+    return tr, u
+
+
+# ---------------------------------------------------------------------------
+# Elastic: forward and adjoint
+# ---------------------------------------------------------------------------
+@dataclass
+class ElasticModel:
+    lam: np.ndarray
+    mu: np.ndarray
+    b: np.ndarray
+
+    @staticmethod
+    def from_velocities(g: Grid, vp, vs, rho) -> "ElasticModel":
+        c = lambda a: np.asarray(a, dtype=np.float64).reshape(g.arr_shape)
+        vp, vs, rho = c(vp), c(vs), c(rho)
+        return ElasticModel(np.ascontiguousarray(rho * (vp * vp - 2 * vs * vs)),
+                            np.ascontiguousarray(rho * vs * vs), np.ascontiguousarray(1.0 / rho))
+
+
+VZ_STAGGER = (0.0, 0.0, 0.5)
+
+
+def _el_call(fn, g, mod, damp, v, t):
+    c = _wf(fd_staggered(g.space_order))
+    cg = g.c()
+    fn(ctypes.byref(cg), g.r, _p(c), _p(mod.lam), _p(mod.mu), _p(mod.b), _p(damp), g.dt, _pp(v), _pp(t))
+
+
+def _el_receivers(g, rec_xyz, rec_kind):
+    if rec_xyz is None:
+        return np.zeros(0, int), np.zeros(0, int), None, None
+    rec_xyz = np.asarray(rec_xyz, dtype=np.float64).reshape(-1, g.ndim)
+    kind = np.zeros(rec_xyz.shape[0], dtype=np.int32) if rec_kind is None else np.asarray(rec_kind)
+    iP, iV = np.nonzero(kind == 0)[0], np.nonzero(kind == 1)[0]
+    spP = sparse_setup(g, rec_xyz[iP]) if iP.size else None
+    spV = sparse_setup(g, rec_xyz[iV], stagger=VZ_STAGGER) if iV.size else None
+    return iP, iV, spP, spV
+
+
+def elastic_forward(g: Grid, mod: ElasticModel, src_xyz, wavelet, rec_xyz, rec_kind=None, nt=None,
+                    force=None, callback=None):
+    """Velocity-stress forward modelling (velocities, then stresses from the new velocities).
+
+    After the stress update of step n the explosive source adds dt * P_s^T s^n to txx, tyy, tzz
+    (reading), then receivers record pressure = P_r (txx + tyy + tzz) (kind 0; the trace of the
+    stress tensor, no -1/3 factor) or vz on its staggered grid (kind 1).
+    ``force(n)`` may return 9 dense arrays added to the fields after step n (dot tests) and
+    ``callback(n, fields)`` sees the fields after step n.
+    Returns (traces (nt, nrec), final fields [vx, vy, vz, txx, tyy, tzz, txy, txz, tyz]).
+    """
+    nt = g.nt if nt is None else nt
+    v = [np.zeros(g.arr_shape) for _ in range(3)]
+    t = [np.zeros(g.arr_shape) for _ in range(6)]
+    damp = np.ascontiguousarray(elastic_damp(g))
+    src = sparse_setup(g, src_xyz) if src_xyz is not None and len(src_xyz) else None
+    wav = None if wavelet is None else np.asarray(wavelet, dtype=np.float64).reshape(nt, -1)
+    iP, iV, spP, spV = _el_receivers(g, rec_xyz, rec_kind)
+    traces = np.zeros((nt, iP.size + iV.size))
+    for n in range(nt):
+        _el_call(lib().orc_el_step, g, mod, damp, v, t)
+        if src is not None:
+            for c in range(3):
+                inject(src, t[c], g.dt * wav[n])
+        if force is not None:
+            fr = force(n)
+            if fr is not None:
+                for arr, add in zip(v + t, fr):
+                    arr += add
+        if callback is not None:
+            callback(n, v + t)
+        if spP is not None:
+            traces[n, iP] = interp(spP, t[0] + t[1] + t[2])
+        if spV is not None:
+            traces[n, iV] = interp(spV, v[2])
+    return traces, v + t
+
+
+def elastic_adjoint(g: Grid, mod: ElasticModel, src_xyz, rec_xyz, rec_data, rec_kind=None, nt=None,
+                    force=None, callback=None):
+    """Exact transpose of ``elastic_forward`` (wavelet -> traces), steps n = N-1..0:
+    add receiver adjoints, read the source adjoint dt * P_s (txx + tyy + tzz), then apply the
+    transposed stress update followed by the transposed velocity update.
+    ``force(n)`` may return 9 dense arrays added to the adjoint fields at the start of step n and
+    ``callback(n, fields)`` then sees them (dense dot tests).
+    Returns (source traces (nt, nsrc), final adjoint fields)."""
+    nt = g.nt if nt is None else nt
+    v = [np.zeros(g.arr_shape) for _ in range(3)]
+    t = [np.zeros(g.arr_shape) for _ in range(6)]
+    damp = np.ascontiguousarray(elastic_damp(g))
+    src = sparse_setup(g, src_xyz) if src_xyz is not None and len(src_xyz) else None
+    iP, iV, spP, spV = _el_receivers(g, rec_xyz, rec_kind)
+    dat = None if rec_data is None else np.asarray(rec_data, dtype=np.float64).reshape(nt, -1)
+    out = np.zeros((nt, 0 if src is None else src.idx.shape[0]))
+    for n in range(nt - 1, -1, -1):
+        if spP is not None:
+            for c in range(3):
+                inject(spP, t[c], dat[n, iP])
+        if spV is not None:
+            inject(spV, v[2], dat[n, iV])
+        if force is not None:
+            fr = force(n)
+            if fr is not None:
+                for arr, add in zip(v + t, fr):
+                    arr += add
+        if callback is not None:
+            callback(n, v + t)
+        if src is not None:
+            out[n] = g.dt * interp(src, t[0] + t[1] + t[2])
+        _el_call(lib().orc_el_step_T, g, mod, damp, v, t)
+    return out, v + t
+
+
+def acoustic_staggered_forward(g: Grid, lam, b, src_xyz, wavelet, nt=None):
+    """Independent second-order stepper that the elastic scheme must reduce to when mu = 0:
+    tau^{n+1} = 2 tau^n - tau^{n-1} + dt^2 lam sum_a D-_a(b_a D+_a tau^n) + dt P_s^T (s^n - s^{n-1}),
+    with b_a the half-node mean of b along axis a.  Returns the list of tau^{n+1}."""
+    nt = g.nt if nt is None else nt
+    lam = np.asarray(lam, dtype=np.float64).reshape(g.arr_shape)
+    b = np.asarray(b, dtype=np.float64).reshape(g.arr_shape)
+    wav = np.asarray(wavelet, dtype=np.float64).reshape(nt, -1)
+    src = sparse_setup(g, src_xyz)
+    bbar = {}
+    for ax in g.axes():
+        npax = 2 - ax
+        nxt = np.concatenate([np.take(b, np.arange(1, b.shape[npax]), axis=npax),
+                              np.take(b, [b.shape[npax] - 1], axis=npax)], axis=npax)
+        bbar[ax] = 0.5 * (b + nxt)
+    tau, taum = np.zeros(g.arr_shape), np.zeros(g.arr_shape)
+    prev = np.zeros(wav.shape[1])
+    out = []
+    for n in range(nt):
+        acc = np.zeros(g.arr_shape)
+        for ax in g.axes():
+            acc += dstag(g, ax, False, bbar[ax] * dstag(g, ax, True, tau))
+        tn = 2 * tau - taum + g.dt ** 2 * lam * acc
+        inject(src, tn, g.dt * (wav[n] - prev))
+        prev = wav[n]
+        taum, tau = tau, tn
+        out.append(tau.copy())
+    return out
+
+
+# ---------------------------------------------------------------------------
+# Checkpoint codec: power-of-two scale + round-to-nearest-even to FP16 / BF16
+# ---------------------------------------------------------------------------
+def ckpt_scale(f: np.ndarray) -> float:
+    """s = 2^ceil(log2(max|f|)) (1 for an all-zero field), so that |f|/s <= 1."""
+    mx = float(np.max(np.abs(np.asarray(f, dtype=np.float32)))) if np.size(f) else 0.0
+    if mx == 0.0:
+        return 1.0
+    mant, e = math.frexp(mx)          # mx = mant * 2^e, mant in [0.5, 1)
+    s = 2.0 ** (e - 1) if mant == 0.5 else 2.0 ** e
+    return min(s, 2.0 ** 127)
+
+
+def bf16_bits_rne(x32: np.ndarray) -> np.ndarray:
+    """Bits of the BF16 value nearest to each FP32 value, ties to the even BF16 mantissa.
+
+    BF16 keeps the top 16 bits of the FP32 pattern.  Candidates: the truncation ``lo`` (toward
+    zero) and the next BF16 away from zero ``lo + 1``; the discarded low 16 bits decide.
+    """
+    b = np.asarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lo = b >> 16
+    rem = b & 0xFFFF
+    up = (rem > 0x8000) | ((rem == 0x8000) & ((lo & 1) == 1))
+    return (lo + up.astype(np.uint64)).astype(np.uint16)
+
+
+def ckpt_encode(f: np.ndarray, dtype: str):
+    """Returns (scale, codes) with codes uint16 bit patterns (f16 / bf16) or float32 copy (f32)."""
+    f = np.asarray(f, dtype=np.float32)
+    if dtype == "f32":
+        return 1.0, f.copy()
+    s = ckpt_scale(f)
+    x = (f.astype(np.float64) / s).astype(np.float32)  # exact: power-of-two scale
+    if dtype == "f16":
+        return s, x.astype(np.float16).view(np.uint16)
+    if dtype == "bf16":
+        return s, bf16_bits_rne(x)
+    raise ValueError(dtype)
+
+
+def ckpt_decode(s: float, codes: np.ndarray, dtype: str) -> np.ndarray:
+    if dtype == "f32":
+        return np.asarray(codes, dtype=np.float32)
+    if dtype == "f16":
+        x = np.asarray(codes, dtype=np.uint16).view(np.float16).astype(np.float64)
+    else:
+        x = (np.asarray(codes, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return (x * s).astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Time-step bound
+# ---------------------------------------------------------------------------
+def symbol_max_sq(so: int, nsamp: int = 200001) -> float:
+    """S_D = max over wavenumbers of (sum_j 2 a_j sin(j k h))^2: the largest eigenvalue of D^T D times h^2."""
+    a = _wf(fd_centered(so))
+    th = np.linspace(0.0, math.pi, nsamp)
+    s = sum(2 * a[j] * np.sin((j + 1) * th) for j in range(len(a)))
+    return float(np.max(s * s))
+
+
+def tti_dt_max(g: Grid, vmax: float, eps_max: float) -> float:
+    """Leapfrog bound dt <= 2 / sqrt(lambda_max(m^-1 L)) with lambda_max <= (1+2 eps_max) vmax^2 sum_a S_D/h_a^2."""
+    S = symbol_max_sq(g.space_order)
+    lam = (1 + 2 * eps_max) * vmax ** 2 * sum(S / g.spacing[ax] ** 2 for ax in g.axes())
+    return 2.0 / math.sqrt(lam)
+
+
+def elastic_dt_max(g: Grid, vpmax: float) -> float:
+    """Staggered velocity-stress bound dt <= h_min / (vp_max sqrt(d) sum_j |c_j|)."""
+    c = _wf(fd_staggered(g.space_order))
+    hmin = min(g.spacing[ax] for ax in g.axes())
+    return hmin / (vpmax * math.sqrt(len(g.axes())) * float(np.sum(np.abs(c))))

@@ -1,0 +1,156 @@
+"""Seeded synthetic inputs shared by the propagator library's tests and benchmarks.
+
+This module only *makes inputs*: earth models, source wavelets and acquisition
+geometry.  It holds none of the propagators' arithmetic (no finite
+differences, no damping, no time stepping), so both the HIP library and the
+FP64 checker can consume exactly the same FP32 arrays.
+
+Recipe (the paper's workloads use an SEG/EAGE-derived TTI model, Marmousi-ii
+and a SEAM-like model, none of which is available; these seeded stand-ins have
+the same kind of structure and value ranges):
+
+* layered P velocity, 10 flat layers, 1.5 km/s at the top to 4.5 km/s at the
+  bottom, interface depths drawn uniformly in the physical part of the model,
+  times (1 + 5 % x smooth noise);
+* Thomsen epsilon in [0, 0.3] (smooth noise), delta = epsilon / 2 so that
+  epsilon >= delta everywhere (the pseudo-acoustic system is only stable
+  when epsilon >= delta);
+* tilt and azimuth in [-45, 45] degrees (smooth noise), in radians;
+* elastic: vs = vp / 1.8 except vs = 0 in the water (top) layer, density from
+  Gardner's relation rho = 310 vp^0.25 (kg/m^3, vp in m/s);
+* Ricker wavelet with peak at t0 = 1/f0.
+
+Arrays follow the library's layout: shape (nz, ny, nx), x fastest, FP32.
+Generation happens in FP64 and is rounded to FP32 once at the end.
+"""
+from __future__ import annotations
+
+import math
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import scipy.ndimage as ndi
+
+__all__ = [
+    "ricker", "tti_model", "elastic_model", "smooth", "slowness_squared",
+    "surface_receivers", "random_unit_field",
+]
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def ricker(f0: float, dt: float, nt: int, t0: float | None = None) -> np.ndarray:
+    """Ricker wavelet sampled at t = n*dt, n = 0..nt-1, peak 1 at t0 (default 1/f0)."""
+    if t0 is None:
+        t0 = 1.0 / f0
+    t = np.arange(nt, dtype=np.float64) * dt - t0
+    a = (math.pi * f0 * t) ** 2
+    return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
+
+
+def smooth(field: np.ndarray, sigma: float) -> np.ndarray:
+    """Gaussian smoothing (sigma in grid points, reflecting edges), FP64 in, FP64 out."""
+    if sigma <= 0:
+        return np.asarray(field, dtype=np.float64)
+    return ndi.gaussian_filter(np.asarray(field, dtype=np.float64), sigma, truncate=3.0, mode="reflect")
+
+
+def _minmax(a: np.ndarray, lo: float, hi: float) -> np.ndarray:
+    amin, amax = float(a.min()), float(a.max())
+    if amax <= amin:
+        return np.full_like(a, 0.5 * (lo + hi))
+    return lo + (hi - lo) * (a - amin) / (amax - amin)
+
+
+def _smooth_noise(shape, sigma, rng) -> np.ndarray:
+    """N(0,1) noise drawn in a fixed order, returned unsmoothed (smoothing is done in parallel later)."""
+    return rng.standard_normal(shape)
+
+
+def _layer_index(nz: int, nbl: int, seed_rng: np.random.Generator, nlayers: int) -> np.ndarray:
+    """Layer number (0..nlayers-1) of every depth index 0..nz-1."""
+    nz_phys = max(nz - 2 * nbl, 1)
+    depths = np.sort(seed_rng.uniform(0.1, 0.95, nlayers - 1)) * nz_phys + nbl
+    k = np.arange(nz, dtype=np.float64)
+    return np.searchsorted(depths, k, side="right")
+
+
+def tti_model(shape_xyz, nbl: int, seed: int, nlayers: int = 10, vmin: float = 1500.0,
+              vmax: float = 4500.0, pert: float = 0.05, eps_max: float = 0.3,
+              angle_max_deg: float = 45.0) -> dict:
+    """Seeded TTI model: dict of FP32 arrays vp (m/s), eps, delta, theta, phi (rad), shape (nz, ny, nx).
+
+    For 2D grids pass ny = 1; phi is then zero.
+    """
+    nx, ny, nz = (int(s) for s in shape_xyz)
+    shp = (nz, ny, nx)
+    rng = _rng(seed)
+    layer = _layer_index(nz, nbl, rng, nlayers)
+    v_layer = vmin + (vmax - vmin) * layer / (nlayers - 1)
+    noises = [_smooth_noise(shp, s, rng) for s in (4.0, 8.0, 8.0, 8.0)]
+    sig = (4.0, 8.0, 8.0, 8.0)
+    with ThreadPoolExecutor(4) as ex:
+        sm = list(ex.map(lambda i: smooth(noises[i], sig[i]), range(4)))
+    del noises
+    xi_v = _minmax(sm[0], -1.0, 1.0)
+    vp = v_layer[:, None, None] * (1.0 + pert * xi_v)
+    eps = eps_max * _minmax(sm[1], 0.0, 1.0)
+    delta = 0.5 * eps
+    amax = math.radians(angle_max_deg)
+    theta = amax * _minmax(sm[2], -1.0, 1.0)
+    phi = amax * _minmax(sm[3], -1.0, 1.0)
+    if ny == 1:
+        phi[:] = 0.0
+    return {k: np.ascontiguousarray(v, dtype=np.float32)
+            for k, v in (("vp", vp), ("eps", eps), ("delta", delta), ("theta", theta), ("phi", phi))}
+
+
+def elastic_model(shape_xyz, nbl: int, seed: int, nlayers: int = 10, vmin: float = 1500.0,
+                  vmax: float = 4500.0, pert: float = 0.05, vp_vs: float = 1.8) -> dict:
+    """Seeded isotropic elastic model: FP32 vp, vs (m/s), rho (kg/m^3); layer 0 is water (vs = 0)."""
+    nx, ny, nz = (int(s) for s in shape_xyz)
+    shp = (nz, ny, nx)
+    rng = _rng(seed)
+    layer = _layer_index(nz, nbl, rng, nlayers)
+    v_layer = vmin + (vmax - vmin) * layer / (nlayers - 1)
+    xi = _minmax(smooth(rng.standard_normal(shp), 4.0), -1.0, 1.0)
+    water = (layer == 0)[:, None, None]
+    vp = v_layer[:, None, None] * np.where(water, 1.0, 1.0 + pert * xi)
+    vs = np.where(water, 0.0, vp / vp_vs)
+    rho = 310.0 * vp ** 0.25
+    return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in (("vp", vp), ("vs", vs), ("rho", rho))}
+
+
+def slowness_squared(vp: np.ndarray) -> np.ndarray:
+    """The model parameter m = 1/vp^2 (s^2/m^2) as FP32, computed in FP64 from the FP32 velocities."""
+    v = np.asarray(vp, dtype=np.float64)
+    return (1.0 / (v * v)).astype(np.float32)
+
+
+def random_unit_field(shape, seed: int, sigma: float = 0.0) -> np.ndarray:
+    """Seeded N(0,1) field (optionally smoothed), FP32; used for perturbations and dot tests."""
+    a = _rng(seed).standard_normal(shape)
+    if sigma > 0:
+        a = smooth(a, sigma)
+    return a.astype(np.float32)
+
+
+def surface_receivers(shape_xyz, spacing, origin, nbl: int, depth_index: float, nrx: int, nry: int,
+                      inset: float = 0.25) -> np.ndarray:
+    """Receiver coordinates (metres, FP32, nrec x ndim) on an even lattice over the physical x-y interior.
+
+    The lattice spans [nbl + inset, n - 1 - nbl - inset] in index units so that it is generally off-grid.
+    For 2D grids (ny = 1) pass nry = 1; the result is then nrec x 2 (x, z).
+    """
+    nx, ny, nz = shape_xyz
+    hx, hy, hz = spacing
+    ox, oy, oz = origin
+    xs = ox + hx * np.linspace(nbl + inset, nx - 1 - nbl - inset, nrx)
+    z = oz + hz * depth_index
+    if ny == 1:
+        return np.stack([xs, np.full_like(xs, z)], axis=1).astype(np.float32)
+    ys = oy + hy * np.linspace(nbl + inset, ny - 1 - nbl - inset, nry)
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    return np.stack([X.ravel(), Y.ravel(), np.full(X.size, z)], axis=1).astype(np.float32)

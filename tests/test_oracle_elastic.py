@@ -1,0 +1,104 @@
+"""Pins of the oracle's elastic velocity-stress propagator (no GPU).
+
+* mu = 0, no damping: the three normal stresses stay equal and follow an independent
+  second-order acoustic stepper built from the staggered pair D-(b D+);
+* water layer (mu = 0): shear stresses stay exactly zero away from the sea bed, as the paper
+  reports for its 2D Marmousi-ii run;
+* dot tests of the exact transpose (user map with pressure and vz receivers, and a dense
+  space-time map), with absorbing layers.
+"""
+import numpy as np
+import pytest
+
+from paper_2004_10519_amd import inputs
+
+
+def _grid(orc, shape, nbl, nt, so=8, dt=5e-4):
+    return orc.Grid(shape, (10.0, 9.0, 8.0), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=2000.0)
+
+
+@pytest.mark.parametrize("shape", [(14, 13, 12), (24, 1, 22)])
+def test_mu_zero_reduces_to_acoustic(orc, shape):
+    g = _grid(orc, shape, 0, 40)
+    rng = np.random.default_rng(3)
+    lam = 2000.0 * 2000.0 * (1 + 0.2 * rng.uniform(size=g.arr_shape))
+    b = 1.0 / (1000.0 * (1 + 0.3 * rng.uniform(size=g.arr_shape)))
+    mod = orc.ElasticModel(np.ascontiguousarray(lam), np.zeros(g.arr_shape), np.ascontiguousarray(b))
+    nx, ny, nz = shape
+    src = np.array([[10.0 * (nx / 2 + 0.3), 9.0 * (ny / 2 - 0.1), 8.0 * (nz / 2 + 0.4)]]) if g.ndim == 3 else \
+        np.array([[10.0 * (nx / 2 + 0.3), 8.0 * (nz / 2 + 0.4)]])
+    wav = inputs.ricker(40.0, g.dt, g.nt).astype(np.float64)[:, None]
+    states = []
+    orc.elastic_forward(g, mod, src, wav, None, callback=lambda n, f: states.append([x.copy() for x in f]))
+    ref = orc.acoustic_staggered_forward(g, lam, b, src, wav)
+    s = max(np.abs(r).max() for r in ref)
+    for n in range(g.nt):
+        txx, tyy, tzz = states[n][3], states[n][4], states[n][5]
+        assert np.abs(txx - tzz).max() <= 1e-12 * s
+        if g.ndim == 3:
+            assert np.abs(txx - tyy).max() <= 1e-12 * s
+        assert np.abs(txx - ref[n]).max() <= 1e-11 * s
+        assert np.abs(states[n][6]).max() == 0 and np.abs(states[n][7]).max() == 0
+
+
+def test_water_layer_has_no_shear_stress(orc):
+    shape = (20, 18, 40)
+    g = _grid(orc, shape, 4, 120)
+    mdl = inputs.elastic_model(shape, 4, 12)
+    mod = orc.ElasticModel.from_velocities(g, mdl["vp"], mdl["vs"], mdl["rho"])
+    water = np.nonzero(mdl["vs"][:, 0, 0] == 0)[0]
+    assert water.size > 6
+    src = np.array([[10.0 * 10.2, 9.0 * 9.1, 8.0 * (water[-1] - 3)]])
+    wav = inputs.ricker(30.0, g.dt, g.nt).astype(np.float64)[:, None]
+    _, f = orc.elastic_forward(g, mod, src, wav, None)
+    wz = slice(0, water[-1])  # the sea bed averages mu across the interface
+    assert np.abs(f[4]).max() > 0
+    for c in (6, 7, 8):
+        assert np.abs(f[c][wz]).max() == 0.0
+    assert np.abs(f[6][water[-1] + 2:]).max() > 0
+
+
+def _el_case(orc, shape, nt, seed):
+    g = _grid(orc, shape, 3, nt)
+    mdl = inputs.elastic_model(shape, 3, seed)
+    mod = orc.ElasticModel.from_velocities(g, mdl["vp"], mdl["vs"], mdl["rho"])
+    nx, ny, nz = shape
+    rng = np.random.default_rng(seed)
+    h = g.spacing
+    if g.ndim == 3:
+        src = np.array([[h[0] * (nx / 2 + 0.3), h[1] * (ny / 2 - 0.2), h[2] * (nz / 2 + 0.1)],
+                        [h[0] * 2.2, h[1] * 4.7, h[2] * 3.3]])
+        rec = np.stack([rng.uniform(0, (nx - 1) * h[0], 8), rng.uniform(0, (ny - 1) * h[1], 8),
+                        rng.uniform(0, (nz - 1.5) * h[2], 8) + 0.5 * h[2]], axis=1)
+    else:
+        src = np.array([[h[0] * (nx / 2 + 0.3), h[2] * (nz / 2 + 0.1)]])
+        rec = np.stack([rng.uniform(0, (nx - 1) * h[0], 6), rng.uniform(0.5, nz - 1, 6) * h[2]], axis=1)
+    kind = (np.arange(len(rec)) % 2).astype(np.int32)
+    return g, mod, src, rec, kind
+
+
+@pytest.mark.parametrize("shape", [(11, 10, 12), (20, 1, 18)])
+def test_elastic_dot_user_map(orc, shape):
+    g, mod, src, rec, kind = _el_case(orc, shape, 30, 5)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((g.nt, len(src)))
+    y = rng.standard_normal((g.nt, len(rec)))
+    Fx, _ = orc.elastic_forward(g, mod, src, x, rec, kind)
+    FTy, _ = orc.elastic_adjoint(g, mod, src, rec, y, kind)
+    lhs, rhs = np.vdot(Fx, y), np.vdot(x, FTy)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+def test_elastic_dot_dense_map(orc):
+    g, mod, _, _, _ = _el_case(orc, (9, 8, 10), 8, 6)
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((g.nt, 9) + g.arr_shape)
+    Y = rng.standard_normal((g.nt, 9) + g.arr_shape)
+    out = np.zeros_like(X)
+    orc.elastic_forward(g, mod, None, None, None, force=lambda n: list(X[n]),
+                        callback=lambda n, f: out.__setitem__(n, np.stack(f)))
+    adj = np.zeros_like(Y)
+    orc.elastic_adjoint(g, mod, None, None, None, force=lambda n: list(Y[n]),
+                        callback=lambda n, f: adj.__setitem__(n, np.stack(f)))
+    lhs, rhs = np.vdot(out, Y), np.vdot(X, adj)
+    assert abs(lhs - rhs) / abs(lhs) < 1e-12
