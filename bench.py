@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Benchmark of the propagator library on one MI355X.
+
+One "step" is one whole modelling run of the 3D TTI workload tti3d_512 (512^3 grid, 12.5 m,
+space order 12, 3000 time steps, 40-point absorbing layers, 15 Hz source, 256 x 256 receivers),
+with all inputs resident in HBM: every time step's two stencil passes, source injection and
+receiver interpolation.  Metric: grid points updated per second (GPts/s = 512^3 * 3000 / time).
+
+The JSON line also carries
+  roofline      dominant kernel's algorithmic bytes per launch / its mean launch time (HIP events on
+                the library's stream during the timed steps), against the 8 TB/s HBM peak;
+  cpu_baseline  the FP64 checker timed on this host on a bounded sample of the same workload;
+  paths         other measured paths when --all is given (elastic, adjoint, gradient).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per grid point of one launch of each stencil kernel (FP32):
+#   tti_pass1: read p, q, n_x, n_y, n_z; write t (3), s (3)                      -> 11 x 4
+#   tti_pass2: read t, s (6), p, q, p-, q- (4), m, 1+2eps, sqrt(1+2delta) (3);
+#              write p+, q+ (2)                                                   -> 15 x 4
+#   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
+#   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
+KERNEL_BYTES_PER_PT = {0: 44, 1: 60, 2: 52, 3: 68}
+# minimum bytes per point per time step of the whole method (fused reading, FP32)
+METHOD_BYTES_PER_PT = {"tti": 44, "elastic": 84}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("common.h", "tti.hip"):
+        with open(os.path.join(ROOT, "paper_2004_10519_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kclass: int, npts: int):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/pmc_traffic.json), if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    ent = rec.get(str(kclass))
+    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def setup_tti(w, torch, prop):
+    arrs = w.model_list()
+    dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    p = prop.Propagator(prop.TTI if w.kind == "tti" else prop.ELASTIC, g, dev)
+    p._keep = dev
+    shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz, w.rec_kind)
+    return p, shot
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def cpu_baseline(w, budget_s: float = 15.0):
+    """The FP64 checker on a sub-volume of the same model (a bounded sample of the workload)."""
+    import oracle
+    n = min(192, w.shape[0])
+    mdl = w.make_model()
+    sl = tuple(slice(s // 2 - n // 2, s // 2 - n // 2 + n) if s > 1 else slice(None) for s in w.arr_shape)
+    arrs = [np.ascontiguousarray(mdl[k][sl]) for k in ("m", "eps", "delta", "theta", "phi")]
+    shape = (arrs[0].shape[2], arrs[0].shape[1], arrs[0].shape[0])
+    g = oracle.Grid(shape, w.spacing, space_order=w.space_order, nbl=w.nbl // 4, dt=w.dt, nt=1, vref=w.v_ref)
+    mod = oracle.TTIModel.from_arrays(g, *arrs)
+    eta = oracle.tti_eta(g)
+    zeros = [np.zeros(g.arr_shape) for _ in range(4)]
+    rng = np.random.default_rng(0)
+    zeros[0][...] = rng.standard_normal(g.arr_shape)
+    oracle._tti_step(g, mod, eta, False, *zeros)   # warm-up (page faults)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        oracle._tti_step(g, mod, eta, False, *zeros)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= 50:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    return {"value": round(int(np.prod(shape)) * steps / el / 1e9, 5), "unit": "GPts/s", "cores": cores,
+            "kind": "oracle", "sample": f"{shape[0]}x{shape[1]}x{shape[2]} centre sub-volume of the {w.name} model, "
+                                        f"space order {w.space_order}, {steps} FP64 time steps in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nt", type=int, default=None, help="override the number of time steps (short runs)")
+    ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--all", action="store_true", help="also measure elastic, adjoint and gradient paths")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(shots and domains would be sharded across GPUs; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2004_10519_amd import configs, prop
+    prop.lib()
+    torch.cuda.set_device(0)
+
+    w = configs.tti3d_512(nt=args.nt or 3000, n=args.size)
+    log(f"[bench] generating {w.name} model {w.shape} ...")
+    t0 = time.perf_counter()
+    p, shot = setup_tti(w, torch, prop)
+    log(f"[bench] setup {time.perf_counter() - t0:.1f} s; timing {args.steps} step(s) after {args.warmup} warm-up")
+    npts = w.npts
+
+    def run():
+        p.forward(shot)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    t_step = timed(torch, run, args.steps, 0)
+    kt = {k: p.kernel_time(k) for k in (0, 1)}
+    p.set_timing(False)
+    gpts = npts * w.nt / t_step / 1e9
+    log(f"[bench] {w.name}: {t_step * 1e3:.1f} ms/step, {gpts:.2f} GPts/s")
+
+    dom = max(kt, key=lambda k: kt[k][0])
+    ms_tot, nl, name = kt[dom]
+    avg_s = ms_tot / 1e3 / max(nl, 1)
+    achieved = KERNEL_BYTES_PER_PT[dom] * npts / avg_s / 1e9
+    traffic = traffic_from_profiles(dom, npts)
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "algorithmic_bytes_per_launch": KERNEL_BYTES_PER_PT[dom] * npts,
+            "mean_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
+            "kernels": {kt[k][2]: {"mean_launch_ms": round(kt[k][0] / max(kt[k][1], 1), 4),
+                                   "GBps_algorithmic": round(KERNEL_BYTES_PER_PT[k] * npts /
+                                                             (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
+                        for k in kt},
+            "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
+
+    out = {"metric": "GPts/s (TTI forward, 512^3, so12)", "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 2),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded layered TTI model, Ricker source)",
+           "config": {"workload": w.name, "grid": list(w.shape), "spacing_m": w.spacing[0],
+                      "space_order": w.space_order, "time_steps": w.nt, "nbl": w.nbl, "receivers": len(w.rec_xyz),
+                      "parallelism": "single GPU"},
+           "roofline": roof}
+    p.close()
+    del p
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        log("[bench] CPU baseline (FP64 checker) ...")
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,191 @@
+/*
+ * prop.h -- C ABI of the MI355X (gfx950) finite-difference wave propagators.
+ *
+ * Two explicit time-stepped propagators, each with its exact discrete adjoint:
+ *
+ *   PROP_TTI      pseudo-acoustic tilted transverse isotropy: coupled fields
+ *                 p, q and self-adjoint rotated second derivatives built from
+ *                 m = 1/vp^2, Thomsen epsilon, delta, tilt theta, azimuth phi
+ *                 (the paper's anisotropic wave-equation section, Eq. "rot"
+ *                 and the rotated-derivative listing), leapfrog in time.
+ *   PROP_ELASTIC  isotropic velocity-stress on a staggered grid with Lame
+ *                 parameters and density (Eq. "elas1" and the elastic listing),
+ *                 velocities first, then stresses from the new velocities.
+ *
+ * The calls follow the paper's problem statement (Eq. "acou" and the Grid /
+ * Function / TimeFunction / SparseTimeFunction listings): a model on a grid,
+ * a source wavelet at off-grid points, receiver traces at off-grid points,
+ * a space order and a time order.
+ *
+ * Conventions
+ *   - Arrays of grid values are FP32, shape (nz, ny, nx), x fastest (C order).
+ *     2D grids use ndim = 2, ny = 1 and the axes x and z.
+ *   - Coordinates are metres; point (i, j, k) sits at origin + (i hx, j hy, k hz);
+ *     z is depth.  Point coordinates are given as (x, z) in 2D, (x, y, z) in 3D.
+ *   - Values outside the grid are zero for every field and every intermediate
+ *     (truncation); the absorbing layer of nbl points lies inside the shape.
+ *   - Step n = 0..nt-1 uses wavelet sample n (time n dt) and produces trace
+ *     sample n from the new state (time (n+1) dt).
+ *   - Pointers marked DEVICE are HIP device pointers; HOST pointers are read
+ *     during the call only.  The caller owns everything it passes in; the
+ *     handle owns its internal wavefields, checkpoints and tables.  Model
+ *     arrays are referenced, not copied: keep them alive and unchanged until
+ *     prop_set_model or prop_destroy.
+ *   - All GPU work is enqueued on the stream given at creation (a hipStream_t,
+ *     NULL = default stream); the calls return after enqueueing, except where
+ *     a result must come back to the host (prop_dot_f64, error checks of the
+ *     instability watchdog).
+ *   - Every call returns PROP_OK (0) or a negative error code; no C++
+ *     exception crosses the ABI.  prop_last_error() gives a message for the
+ *     last failure on the calling thread.
+ *   - Calls on one handle must not overlap (one handle = one set of wavefields).
+ */
+#ifndef PROP_H
+#define PROP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PROP_OK         0
+#define PROP_EINVAL    (-1)  /* bad argument: shape, order, null pointer, point outside the grid */
+#define PROP_ENOMEM    (-2)  /* device allocation failed */
+#define PROP_EHIP      (-3)  /* HIP runtime error (message includes hipGetErrorString) */
+#define PROP_EUNSTABLE (-4)  /* dt above the stability bound, epsilon < delta, or NaN/Inf detected */
+#define PROP_ESTATE    (-5)  /* call not valid in the handle's current state */
+
+typedef struct prop_s *prop_t;
+
+typedef enum { PROP_TTI = 1, PROP_ELASTIC = 2 } prop_kind;
+
+/* Storage type of gradient checkpoints (each snapshot has a power-of-two scale). */
+typedef enum { PROP_CKPT_F32 = 0, PROP_CKPT_F16 = 1, PROP_CKPT_BF16 = 2 } prop_ckpt_dtype;
+
+/* Discretised domain (the paper's Grid listing plus space/time order). */
+typedef struct {
+    int32_t ndim;         /* 2 (x, z) or 3 (x, y, z) */
+    int64_t shape[3];     /* nx, ny, nz; ny = 1 when ndim = 2 */
+    double  spacing[3];   /* hx, hy, hz in metres */
+    double  origin[3];    /* metres */
+    int32_t space_order;  /* even, 2..16: accuracy order of every first derivative */
+    int32_t time_order;   /* 2 for PROP_TTI (leapfrog), 1 for PROP_ELASTIC (first-order system) */
+    int32_t nbl;          /* absorbing-layer width in points, inside the shape, per face */
+    double  dt;           /* time step in seconds; must not exceed prop_cfl_dt() */
+    int32_t nt;           /* number of time steps */
+    double  v_ref;        /* m/s: reference velocity of the absorbing-layer profile */
+} prop_grid;
+
+/* Model parameters, DEVICE, dense (nz, ny, nx) over the whole grid.
+ *   PROP_TTI:     p[0] = m = 1/vp^2 (s^2/m^2), p[1] = epsilon, p[2] = delta,
+ *                 p[3] = theta (tilt from vertical, rad), p[4] = phi (azimuth, rad; ignored in 2D).
+ *                 Requires epsilon >= delta everywhere (otherwise the system is unstable).
+ *   PROP_ELASTIC: p[0] = vp (m/s), p[1] = vs (m/s), p[2] = rho (kg/m^3); p[3], p[4] unused.
+ *                 lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, buoyancy = 1/rho. */
+typedef struct {
+    const float *p[5];
+} prop_model;
+
+/* One shot (one source experiment).
+ * The shot runs on a window of the grid: win_origin = index of its first node, win_shape = its
+ * size (all zero = the whole grid).  The absorbing layer lies inside the window.  Coordinates are
+ * absolute (grid frame) and must lie inside the window.
+ * Sources: nsrc points, src_xyz HOST nsrc x ndim, src_wavelet DEVICE nt x nsrc (time-major).
+ *   TTI: the same wavelet drives p and q.  Elastic: explosive source added to the three normal
+ *   stresses.
+ * Receivers: nrec points, rec_xyz HOST nrec x ndim.  TTI records p.  Elastic: rec_kind HOST
+ *   (NULL = all 0): 0 = pressure, the trace txx + tyy + tzz at nodes; 1 = vz on its staggered grid. */
+typedef struct {
+    int64_t win_origin[3];
+    int64_t win_shape[3];
+    int32_t nsrc;
+    const float *src_xyz;
+    const float *src_wavelet;
+    int32_t nrec;
+    const float *rec_xyz;
+    const int32_t *rec_kind;
+} prop_shot;
+
+/* Create a propagator for a grid and a model.  Validates the grid (even space order 2..16,
+ * time order 2 for TTI / 1 for elastic, shape >= 2 space_order + 2 nbl per axis, positive
+ * spacing and dt), computes the derived coefficients on the device (TTI: 1+2eps, sqrt(1+2delta),
+ * symmetry axis; elastic: lambda, mu, buoyancy) and checks dt against the stability bound for
+ * the model's largest velocity (PROP_EUNSTABLE).  stream is a hipStream_t (NULL = default).
+ * On success *out owns device memory until prop_destroy. */
+int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_model *model,
+                void *stream);
+
+/* Largest stable dt for a model whose largest velocity is vmax (TTI: vertical vp; elastic: vp)
+ * and largest epsilon eps_max (TTI only).
+ *   TTI:     dt <= 2 / (vmax sqrt((1 + 2 eps_max) S_D sum_a 1/h_a^2)), S_D = max_k (sum_j 2 a_j sin(jk))^2
+ *   elastic: dt <= h_min / (vmax sqrt(ndim) sum_j |c_j|)
+ * Returns a negative value for an invalid grid. */
+double prop_cfl_dt(prop_kind kind, const prop_grid *grid, double vmax, double eps_max);
+
+/* Replace the model (same grid); validates like prop_create. */
+int prop_set_model(prop_t h, const prop_model *model);
+
+/* Forward modelling of one shot: rec_out DEVICE nt x nrec receives the traces.
+ * TTI: a f^{n+1} = b f^n - c f^{n-1} + C (H0 p^n, Hz q^n) + P_s^T s^n (see the design doc for a, b, c). */
+int prop_forward(prop_t h, const prop_shot *shot, float *rec_out);
+
+/* Exact transpose of prop_forward for the same shot (traces -> wavelet):
+ * rec_in DEVICE nt x nrec, src_out DEVICE nt x nsrc (overwritten). */
+int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *src_out);
+
+/* TTI only.  Gradient of J = 1/2 sum_n ||d^n - d_obs^n||^2 with respect to m over the shot's
+ * window, given residual = d - d_obs (DEVICE nt x nrec): a forward run that stores n_ckpt evenly
+ * spaced checkpoints of (p, q) at two time levels in ckpt_dtype with a power-of-two scale per
+ * snapshot, then, segment by segment in reverse, an FP32 recomputation from the checkpoint and the
+ * adjoint run with the imaging condition
+ *     g = -(1/dt^2) sum_k sum_{f in p,q} f^k (y^k - 2 y^{k+1} + y^{k+2}).
+ * grad_m DEVICE, window-shaped dense (nz, ny, nx), overwritten.  n_ckpt >= 1 (1 = keep the whole
+ * forward wavefield of the single segment, i.e. no recomputation beyond one pass). */
+int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float *grad_m,
+                  int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype);
+
+/* Many shots at once (TTI): all shots step in lockstep on their own windows; every stencil launch
+ * covers the tiles of all shots of a group.  Shots are processed in groups that fit the device
+ * memory.  rec_out[i] DEVICE nt x nrec_i. */
+int prop_forward_batched(prop_t h, int32_t nshot, const prop_shot *shots, float *const *rec_out);
+
+/* Batched gradient: per shot as prop_gradient, accumulated in FP64 into grad_global (DEVICE,
+ * whole-grid dense (nz, ny, nx) doubles; NOT zeroed: the call adds), in shot order. */
+int prop_gradient_batched(prop_t h, int32_t nshot, const prop_shot *shots,
+                          const float *const *residual, double *grad_global, int32_t n_ckpt,
+                          prop_ckpt_dtype ckpt_dtype);
+
+/* Copy a final wavefield of the last forward or adjoint call into out (DEVICE, window-shaped
+ * dense).  TTI: 0 = p^N, 1 = q^N, 2 = p^{N-1}, 3 = q^{N-1} after prop_forward; after
+ * prop_adjoint 0, 1 = y_p^1, y_q^1.  Elastic: 0..2 = vx, vy, vz; 3..8 = txx, tyy, tzz, txy, txz, tyz. */
+int prop_read_state(prop_t h, int32_t field, float *out);
+
+/* Kernel timing: when enabled, every stencil launch is bracketed by HIP events on the handle's
+ * stream.  prop_kernel_time returns, for kernel class k (0 = the TTI gradient/mix pass, 1 = the
+ * TTI divergence/update pass, 2 = elastic velocity pass, 3 = elastic stress pass), the summed
+ * milliseconds and the number of launches since the last reset, and names the class. */
+int prop_set_timing(prop_t h, int32_t enable);
+int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name);
+
+/* Checkpoint codec (the packing used by prop_gradient), exposed for testing:
+ * encode n FP32 values (DEVICE) with scale s = 2^ceil(log2 max|f|) (1 for all-zero input) into
+ * codes (DEVICE: n uint16 for F16/BF16, round to nearest even; n floats for F32, s = 1), writing s
+ * to *scale_dev (DEVICE float).  decode: f = s * code. */
+int prop_ckpt_encode(const float *f, int64_t n, prop_ckpt_dtype dtype, void *codes, float *scale_dev,
+                     void *stream);
+int prop_ckpt_decode(const void *codes, const float *scale_dev, int64_t n, prop_ckpt_dtype dtype,
+                     float *f, void *stream);
+
+/* FP64 inner product of two FP32 device vectors (deterministic order); blocks until done. */
+int prop_dot_f64(const float *a, const float *b, int64_t n, double *result, void *stream);
+
+int prop_destroy(prop_t h);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *prop_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROP_H */

@@ -1,0 +1,58 @@
+// Host-side entry points of the auxiliary kernels (sparse operators, codec, reductions).
+#pragma once
+#include "common.h"
+
+// Node-wise injection plan (compressed rows): row r adds sum_{e in [ptr[r], ptr[r+1])} w[e] data[col[e]]
+// to the state node node[r].  TTI rows also carry the model index of the node and its damping term
+// eta/(2dt), so the kernel can divide by a = m/dt^2 + eta/(2dt).
+struct Csr {
+    int nrows;
+    const int64_t *node;
+    const int64_t *mnode;
+    const float *e;
+    const int *ptr;
+    const int *col;
+    const float *w;
+};
+
+// Multilinear gather plan: point o reads nc corners idx[o*nc + c] with weights w[o*nc + c] and
+// writes output column pos[o].
+struct Gather {
+    int n, nc;
+    const int64_t *idx;
+    const float *w;
+    const int *pos;
+};
+
+void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
+                    float *d3, hipStream_t st);
+void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, float *yp, float *grad,
+                        const float *fpk, hipStream_t st);
+void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, float *d1, float *d2, hipStream_t st);
+void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
+                hipStream_t st);
+void aux_fill(float *p, int64_t n, float v, hipStream_t st);
+void aux_fill_u32(unsigned *p, int n, unsigned v, hipStream_t st);
+void aux_absmax(const float *f, int64_t n, unsigned *out, hipStream_t st);
+void aux_encode(const float *f, int64_t n, const unsigned *maxbits, int dtype, uint16_t *codes, float *scale_out,
+                hipStream_t st);
+void aux_decode(const uint16_t *codes, const float *scale, int64_t n, int dtype, float *f, hipStream_t st);
+void aux_absmax_win(const float *f, const Win &w, unsigned *out, hipStream_t st);
+void aux_encode_win(const float *f, const Win &w, const unsigned *maxbits, int dtype, void *codes, float *scale_out,
+                    hipStream_t st);
+void aux_decode_win(const void *codes, const float *scale, const Win &w, int dtype, float *f, hipStream_t st);
+// Gradient checkpoint codec (FP16 = 1 / BF16 = 2): a = cur, b = cur - prev, per-x-row power-of-two
+// scales; ca, cb: dense window codes; sca, scb: ny*nz scales each.
+void aux_ckpt_pair_encode(const float *cur, const float *prev, const Win &w, int dtype, uint16_t *ca, uint16_t *cb,
+                          float *sca, float *scb, hipStream_t st);
+void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *sca, const float *scb, const Win &w,
+                          int dtype, float *cur, float *prev, hipStream_t st);
+void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double *out, hipStream_t st);
+int aux_dot_blocks();
+void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,
+                  int ndim, float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats, hipStream_t st);
+void aux_el_prep(const float *vp, const float *vs, const float *rho, int64_t n, float *lam, float *mu, float *b,
+                 unsigned *stats, hipStream_t st);
+void aux_nonfinite_win(const float *f, const Win &w, unsigned *flag, hipStream_t st);
+void aux_copy_out(const float *src, const Win &w, float *dst, hipStream_t st);
+void aux_accum_f64(const float *src, const Win &w, double *dst, hipStream_t st);

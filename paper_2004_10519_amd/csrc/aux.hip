@@ -1,0 +1,490 @@
+// Sparse source/receiver operators, checkpoint codec, reductions and model preprocessing (gfx950).
+#include "aux.h"
+
+#include <hip/hip_fp16.h>
+
+#include <math.h>
+
+namespace {
+
+constexpr int BS = 256;
+
+__device__ __forceinline__ float csr_row_value(const Csr &c, int r, const float *data)
+{
+    float v = 0.f;
+    for (int e = c.ptr[r]; e < c.ptr[r + 1]; ++e) v += c.w[e] * data[c.col[e]];
+    return v;
+}
+
+// TTI injection of sum_e w_e data[col_e] into up to four fields at node r, divided by
+// a = m/dt^2 + eta/(2dt) at the node (the source term enters a f+ = ... + P^T s).
+__global__ void k_tti_inject(Csr c, const float *__restrict__ data, float idt2, const float *__restrict__ m,
+                             float *d0, float *d1, float *d2, float *d3)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const float a = m[c.mnode[r]] * idt2 + c.e[r];
+    const float v = csr_row_value(c, r, data) / a;
+    const int64_t n = c.node[r];
+    if (d0) d0[n] += v;
+    if (d1) d1[n] += v;
+    if (d2) d2[n] += v;
+    if (d3) d3[n] += v;
+}
+
+// Adjoint receiver injection into y_p (node-wise gather, deterministic), with the imaging
+// condition's share of the injected increment: g -= (1/dt^2) f_p^k * increment.
+__global__ void k_tti_inject_adj(Csr c, const float *__restrict__ data, float idt2, const float *__restrict__ m,
+                                 float *yp, float *grad, const float *__restrict__ fpk)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const float a = m[c.mnode[r]] * idt2 + c.e[r];
+    const float v = csr_row_value(c, r, data) / a;
+    const int64_t n = c.node[r];
+    yp[n] += v;
+    if (grad) grad[n] -= idt2 * fpk[n] * v;
+}
+
+// Elastic injection: d_i[node] += scale * sum_e w_e data[col_e].
+__global__ void k_el_inject(Csr c, const float *__restrict__ data, float scale, float *d0, float *d1, float *d2)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const float v = scale * csr_row_value(c, r, data);
+    const int64_t n = c.node[r];
+    if (d0) d0[n] += v;
+    if (d1) d1[n] += v;
+    if (d2) d2[n] += v;
+}
+
+// Multilinear gather: out[pos_o] = scale * sum_c w_oc (f0 + f1 + f2)[idx_oc].  One point per lane.
+__global__ void k_gather(Gather g, const float *__restrict__ f0, const float *__restrict__ f1,
+                         const float *__restrict__ f2, float scale, float *__restrict__ out)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= g.n) return;
+    float s = 0.f;
+    for (int c = 0; c < g.nc; ++c) {
+        const int64_t i = g.idx[(int64_t)o * g.nc + c];
+        float v = f0[i];
+        if (f1) v += f1[i];
+        if (f2) v += f2[i];
+        s += g.w[(int64_t)o * g.nc + c] * v;
+    }
+    out[g.pos[o]] = scale * s;
+}
+
+__global__ void k_fill(float *p, int64_t n, float v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_fill_u32(unsigned *p, int n, unsigned v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// max |f| as ordered bits (non-negative floats order like their bit patterns; NaN sorts above Inf).
+__global__ void k_absmax(const float *__restrict__ f, int64_t n, unsigned *out)
+{
+    __shared__ unsigned sm[BS];
+    unsigned mx = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        mx = max(mx, __float_as_uint(f[i]) & 0x7fffffffu);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, sm[0]);
+}
+
+// Power-of-two scale s with max|f| <= s < 2 max|f| (1 for an all-zero field).
+__device__ __forceinline__ float pow2_scale(unsigned maxbits)
+{
+    if (maxbits == 0) return 1.0f;
+    int e;
+    const float mant = frexpf(__uint_as_float(maxbits), &e);   // max = mant 2^e, mant in [0.5, 1)
+    const int k = (mant == 0.5f) ? e - 1 : e;
+    return ldexpf(1.0f, min(k, 127));
+}
+
+// Round-to-nearest-even FP32 -> BF16 by the rounding-bias method.
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
+{
+    const unsigned u = __float_as_uint(x);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);  // quiet NaN
+    const unsigned bias = 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)((u + bias) >> 16);
+}
+
+__global__ void k_encode(const float *__restrict__ f, int64_t n, const unsigned *__restrict__ maxbits, int dtype,
+                         uint16_t *__restrict__ codes, float *__restrict__ scale_out)
+{
+    const float s = pow2_scale(*maxbits);
+    const float rs = 1.0f / s;   // exact: power of two
+    if (blockIdx.x == 0 && threadIdx.x == 0 && scale_out) *scale_out = s;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = f[i] * rs;
+        codes[i] = dtype == 1 ? __half_as_ushort(__float2half_rn(x)) : f32_to_bf16_rne(x);
+    }
+}
+
+__global__ void k_decode(const uint16_t *__restrict__ codes, const float *__restrict__ scale, int64_t n, int dtype,
+                         float *__restrict__ f)
+{
+    const float s = *scale;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint16_t c = codes[i];
+        const float x = dtype == 1 ? __half2float(__ushort_as_half(c)) : __uint_as_float((unsigned)c << 16);
+        f[i] = s * x;
+    }
+}
+
+// Window-strided codec: encode/decode one state-layout field of a window.
+__global__ void k_absmax_win(const float *__restrict__ f, Win w, unsigned *out)
+{
+    __shared__ unsigned sm[BS];
+    unsigned mx = 0;
+    const int y = blockIdx.y, z = blockIdx.z;
+    for (int x = threadIdx.x; x < w.nx; x += BS) mx = max(mx, __float_as_uint(f[sidx(w, x, y, z)]) & 0x7fffffffu);
+    sm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = max(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(out, sm[0]);
+}
+
+__global__ void k_encode_win(const float *__restrict__ f, Win w, const unsigned *__restrict__ maxbits, int dtype,
+                             void *__restrict__ codes, float *__restrict__ scale_out)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t row = ((int64_t)z * w.ny + y) * w.nx;   // codes are dense per window
+    if (dtype == 0) {
+        float *o = (float *)codes;
+        for (int x = threadIdx.x; x < w.nx; x += BS) o[row + x] = f[sidx(w, x, y, z)];
+        if (blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *scale_out = 1.0f;
+        return;
+    }
+    const float s = pow2_scale(*maxbits);
+    const float rs = 1.0f / s;
+    if (blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *scale_out = s;
+    uint16_t *o = (uint16_t *)codes;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const float v = f[sidx(w, x, y, z)] * rs;
+        o[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(v)) : f32_to_bf16_rne(v);
+    }
+}
+
+__global__ void k_decode_win(const void *__restrict__ codes, const float *__restrict__ scale, Win w, int dtype,
+                             float *__restrict__ f)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t row = ((int64_t)z * w.ny + y) * w.nx;
+    const float s = *scale;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        float v;
+        if (dtype == 0) v = ((const float *)codes)[row + x];
+        else {
+            const uint16_t c = ((const uint16_t *)codes)[row + x];
+            v = s * (dtype == 1 ? __half2float(__ushort_as_half(c)) : __uint_as_float((unsigned)c << 16));
+        }
+        f[sidx(w, x, y, z)] = v;
+    }
+}
+
+// Checkpoint codec of the gradient: for a field pair (current level c, previous level c-1) store
+// a = f^c and b = f^c - f^{c-1} (the level difference keeps the time derivative accurate), each
+// rounded to nearest-even FP16/BF16 with its own power-of-two scale per x-row.  One block per row:
+// reduce the two row maxima in LDS, then encode.
+__global__ void k_encode_pair_rows(const float *__restrict__ cur, const float *__restrict__ prev, Win w, int dtype,
+                                   uint16_t *__restrict__ ca, uint16_t *__restrict__ cb, float *__restrict__ sca,
+                                   float *__restrict__ scb)
+{
+    __shared__ unsigned sa[BS], sb[BS];
+    const int y = blockIdx.y, z = blockIdx.z;
+    unsigned xa = 0, xb = 0;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const int64_t i = sidx(w, x, y, z);
+        const float c = cur[i];
+        xa = max(xa, __float_as_uint(c) & 0x7fffffffu);
+        xb = max(xb, __float_as_uint(c - prev[i]) & 0x7fffffffu);
+    }
+    sa[threadIdx.x] = xa;
+    sb[threadIdx.x] = xb;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sa[threadIdx.x] = max(sa[threadIdx.x], sa[threadIdx.x + s]);
+            sb[threadIdx.x] = max(sb[threadIdx.x], sb[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    const float s1 = pow2_scale(sa[0]), s2 = pow2_scale(sb[0]);
+    const float r1 = 1.0f / s1, r2 = 1.0f / s2;
+    const int64_t r = (int64_t)z * w.ny + y;
+    if (threadIdx.x == 0) {
+        sca[r] = s1;
+        scb[r] = s2;
+    }
+    const int64_t row = r * w.nx;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const int64_t i = sidx(w, x, y, z);
+        const float c = cur[i], d = c - prev[i];
+        const float va = c * r1, vb = d * r2;
+        ca[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(va)) : f32_to_bf16_rne(va);
+        cb[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(vb)) : f32_to_bf16_rne(vb);
+    }
+}
+
+__global__ void k_decode_pair_rows(const uint16_t *__restrict__ ca, const uint16_t *__restrict__ cb,
+                                   const float *__restrict__ sca, const float *__restrict__ scb, Win w, int dtype,
+                                   float *__restrict__ cur, float *__restrict__ prev)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t r = (int64_t)z * w.ny + y;
+    const float s1 = sca[r], s2 = scb[r];
+    const int64_t row = r * w.nx;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const uint16_t a = ca[row + x], b = cb[row + x];
+        const float va = dtype == 1 ? __half2float(__ushort_as_half(a)) : __uint_as_float((unsigned)a << 16);
+        const float vb = dtype == 1 ? __half2float(__ushort_as_half(b)) : __uint_as_float((unsigned)b << 16);
+        const int64_t i = sidx(w, x, y, z);
+        const float c = s1 * va;
+        cur[i] = c;
+        prev[i] = c - s2 * vb;
+    }
+}
+
+// Deterministic FP64 dot product: fixed grid, per-thread strided partial sums, fixed-order tree.
+constexpr int DOT_BLOCKS = 1024;
+__global__ void k_dot_partial(const float *__restrict__ a, const float *__restrict__ b, int64_t n,
+                              double *__restrict__ part)
+{
+    __shared__ double sm[BS];
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)BS + threadIdx.x; i < n; i += (int64_t)DOT_BLOCKS * BS)
+        s += (double)a[i] * (double)b[i];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = BS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ void k_dot_final(const double *__restrict__ part, double *__restrict__ out)
+{
+    __shared__ double sm[BS];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < DOT_BLOCKS; i += BS) s += part[i];
+    sm[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = BS / 2; k > 0; k >>= 1) {
+        if (threadIdx.x < k) sm[threadIdx.x] += sm[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sm[0];
+}
+
+// TTI coefficients: A = 1 + 2 eps, B = sqrt(1 + 2 delta), symmetry axis n from tilt/azimuth;
+// statistics: max 1/sqrt(m) (bits), max eps (bits), flags (bit 0: m <= 0 or non-finite,
+// bit 1: eps < delta).
+__global__ void k_tti_prep(const float *__restrict__ m, const float *__restrict__ eps, const float *__restrict__ dl,
+                           const float *__restrict__ th, const float *__restrict__ ph, int64_t n, int ndim,
+                           float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats)
+{
+    unsigned vmax = 0, emax = 0, flags = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float e = eps[i], d = dl[i], t = th[i], p = ndim == 3 ? ph[i] : 0.f, mm = m[i];
+        A[i] = 1.f + 2.f * e;
+        B[i] = sqrtf(1.f + 2.f * d);
+        float st, ct, sp, cp;
+        sincosf(t, &st, &ct);
+        sincosf(p, &sp, &cp);
+        nx[i] = st * cp;
+        ny[i] = ndim == 3 ? st * sp : 0.f;
+        nz[i] = ct;
+        if (!(mm > 0.f) || !isfinite(mm) || !isfinite(e) || !isfinite(d) || !isfinite(t) || !isfinite(p)) flags |= 1u;
+        else vmax = max(vmax, __float_as_uint(1.0f / sqrtf(mm)));
+        if (e < d - 1e-6f) flags |= 2u;
+        if (e > 0.f) emax = max(emax, __float_as_uint(e));
+    }
+    atomicMax(&stats[0], vmax);
+    atomicMax(&stats[1], emax);
+    atomicOr(&stats[2], flags);
+}
+
+// Elastic coefficients: lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho; stats: max vp (bits),
+// flags (bit 0: rho <= 0, vp <= 0, vs < 0 or non-finite; bit 1: lambda < 0).
+__global__ void k_el_prep(const float *__restrict__ vp, const float *__restrict__ vs, const float *__restrict__ rho,
+                          int64_t n, float *lam, float *mu, float *b, unsigned *stats)
+{
+    unsigned vmax = 0, flags = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float p = vp[i], s = vs[i], r = rho[i];
+        lam[i] = r * (p * p - 2.f * s * s);
+        mu[i] = r * s * s;
+        b[i] = 1.f / r;
+        if (!(r > 0.f) || !(p > 0.f) || !(s >= 0.f) || !isfinite(p) || !isfinite(s) || !isfinite(r)) flags |= 1u;
+        else vmax = max(vmax, __float_as_uint(p));
+        if (p * p < 2.f * s * s) flags |= 2u;
+    }
+    atomicMax(&stats[0], vmax);
+    atomicOr(&stats[2], flags);
+}
+
+__global__ void k_nonfinite_win(const float *__restrict__ f, Win w, unsigned *flag)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    bool bad = false;
+    for (int x = threadIdx.x; x < w.nx; x += BS) bad |= !isfinite(f[sidx(w, x, y, z)]);
+    if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1u);
+}
+
+__global__ void k_copy_out(const float *__restrict__ src, Win w, float *__restrict__ dst)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    const int64_t row = ((int64_t)z * w.ny + y) * w.nx;
+    for (int x = threadIdx.x; x < w.nx; x += BS) dst[row + x] = src[sidx(w, x, y, z)];
+}
+
+__global__ void k_accum_f64(const float *__restrict__ src, Win w, double *__restrict__ dst)
+{
+    const int y = blockIdx.y, z = blockIdx.z;
+    for (int x = threadIdx.x; x < w.nx; x += BS) dst[midx(w, x, y, z)] += (double)src[sidx(w, x, y, z)];
+}
+
+inline unsigned nblocks(int64_t n, int cap = 8192)
+{
+    int64_t b = (n + BS - 1) / BS;
+    return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
+                    float *d3, hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_tti_inject, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, idt2, m, d0, d1, d2, d3);
+}
+
+void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, float *yp, float *grad,
+                        const float *fpk, hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_tti_inject_adj, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, idt2, m, yp, grad, fpk);
+}
+
+void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, float *d1, float *d2, hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_el_inject, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, scale, d0, d1, d2);
+}
+
+void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
+                hipStream_t st)
+{
+    if (g.n <= 0) return;
+    hipLaunchKernelGGL(k_gather, dim3((g.n + BS - 1) / BS), dim3(BS), 0, st, g, f0, f1, f2, scale, out);
+}
+
+void aux_fill(float *p, int64_t n, float v, hipStream_t st)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(BS), 0, st, p, n, v);
+}
+
+void aux_fill_u32(unsigned *p, int n, unsigned v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill_u32, dim3((n + BS - 1) / BS), dim3(BS), 0, st, p, n, v);
+}
+
+void aux_absmax(const float *f, int64_t n, unsigned *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_absmax, dim3(nblocks(n)), dim3(BS), 0, st, f, n, out);
+}
+
+void aux_encode(const float *f, int64_t n, const unsigned *maxbits, int dtype, uint16_t *codes, float *scale_out,
+                hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode, dim3(nblocks(n)), dim3(BS), 0, st, f, n, maxbits, dtype, codes, scale_out);
+}
+
+void aux_decode(const uint16_t *codes, const float *scale, int64_t n, int dtype, float *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decode, dim3(nblocks(n)), dim3(BS), 0, st, codes, scale, n, dtype, f);
+}
+
+void aux_absmax_win(const float *f, const Win &w, unsigned *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_absmax_win, dim3(1, w.ny, w.nz), dim3(BS), 0, st, f, w, out);
+}
+
+void aux_encode_win(const float *f, const Win &w, const unsigned *maxbits, int dtype, void *codes, float *scale_out,
+                    hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode_win, dim3(1, w.ny, w.nz), dim3(BS), 0, st, f, w, maxbits, dtype, codes, scale_out);
+}
+
+void aux_decode_win(const void *codes, const float *scale, const Win &w, int dtype, float *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decode_win, dim3(1, w.ny, w.nz), dim3(BS), 0, st, codes, scale, w, dtype, f);
+}
+
+void aux_ckpt_pair_encode(const float *cur, const float *prev, const Win &w, int dtype, uint16_t *ca, uint16_t *cb,
+                          float *sca, float *scb, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode_pair_rows, dim3(1, w.ny, w.nz), dim3(BS), 0, st, cur, prev, w, dtype, ca, cb, sca, scb);
+}
+
+void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *sca, const float *scb, const Win &w,
+                          int dtype, float *cur, float *prev, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_decode_pair_rows, dim3(1, w.ny, w.nz), dim3(BS), 0, st, ca, cb, sca, scb, w, dtype, cur,
+                       prev);
+}
+
+void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dot_partial, dim3(DOT_BLOCKS), dim3(BS), 0, st, a, b, n, part);
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(BS), 0, st, part, out);
+}
+
+int aux_dot_blocks() { return DOT_BLOCKS; }
+
+void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,
+                  int ndim, float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tti_prep, dim3(nblocks(n)), dim3(BS), 0, st, m, eps, dl, th, ph, n, ndim, A, B, nx, ny, nz,
+                       stats);
+}
+
+void aux_el_prep(const float *vp, const float *vs, const float *rho, int64_t n, float *lam, float *mu, float *b,
+                 unsigned *stats, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_el_prep, dim3(nblocks(n)), dim3(BS), 0, st, vp, vs, rho, n, lam, mu, b, stats);
+}
+
+void aux_nonfinite_win(const float *f, const Win &w, unsigned *flag, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_nonfinite_win, dim3(1, w.ny, w.nz), dim3(BS), 0, st, f, w, flag);
+}
+
+void aux_copy_out(const float *src, const Win &w, float *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_copy_out, dim3(1, w.ny, w.nz), dim3(BS), 0, st, src, w, dst);
+}
+
+void aux_accum_f64(const float *src, const Win &w, double *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_accum_f64, dim3(1, w.ny, w.nz), dim3(BS), 0, st, src, w, dst);
+}

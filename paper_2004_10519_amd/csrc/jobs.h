@@ -1,0 +1,44 @@
+// Per-shot job descriptors and host-side launch entry points of the propagator kernels.
+#pragma once
+#include "common.h"
+
+// One TTI shot window.  cur/prev wavefields ping-pong between p[0]/p[1] (and q) with the step
+// parity: the new level overwrites the level two steps back.
+struct TTIJob {
+    Win w;
+    float *p[2], *q[2];           // wavefields (state layout)
+    float *t[3], *s[3];           // pass-1 vectors (I - n n^T) grad p and n n^T grad q (state layout)
+    const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
+    const float *nx, *ny, *nz;    // symmetry axis (model layout)
+    const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
+    float *grad;                  // imaging-condition accumulator (state layout) or null
+    float *seg;                   // segment store: per step 2 fields (p then q) of seg_field elems
+    int64_t seg_field;            // elements of one stored field (= plane pitch * nz)
+};
+
+// One elastic shot window (fields in state layout; parameters in model layout).
+struct ElJob {
+    Win w;
+    float *v[3];                  // vx, vy, vz
+    float *t[6];                  // txx, tyy, tzz, txy, txz, tyz
+    float *aux[6];                // adjoint temporaries (stiffness-weighted stresses, weighted velocities)
+    const float *lam, *mu, *b;    // lambda, mu, buoyancy
+    const float *gx, *gy, *gz;    // absorbing layer: exp(-kappa_a dt) per window axis
+};
+
+enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
+
+void launch_tti_pass1(int R, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
+                      int par, const Weights &W, hipStream_t st);
+void launch_tti_pass2(int R, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
+                      int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
+int tti_rows_per_thread(int R);
+
+enum { EL_FWD = 0, EL_ADJ = 1 };
+void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+                   const Weights &W, float dt, hipStream_t st);
+void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+                      const Weights &W, float dt, hipStream_t st);
+void launch_el_mix_stress(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
+void launch_el_mix_vel(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
+int el_rows_per_thread(int R);

@@ -1,0 +1,1144 @@
+// C ABI of the propagators: handle, shot windows, sparse plans, time loops, checkpointed gradient.
+#include "prop.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "aux.h"
+#include "jobs.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) return fail(PROP_EHIP, "%s: %s", #x, hipGetErrorString(e_));     \
+    } while (0)
+
+#define TRY(x)                    \
+    do {                          \
+        int r_ = (x);             \
+        if (r_ != PROP_OK) return r_; \
+    } while (0)
+
+// Owned device allocation.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    int ensure(size_t n)
+    {
+        if (n <= bytes && p) return PROP_OK;
+        release();
+        if (n == 0) n = 16;
+        if (hipMalloc(&p, n) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return fail(PROP_ENOMEM, "hipMalloc of %zu bytes failed", n);
+        }
+        bytes = n;
+        return PROP_OK;
+    }
+    template <class T> T *as() const { return (T *)p; }
+};
+
+template <class T>
+int upload(DevBuf &b, const std::vector<T> &v, hipStream_t st)
+{
+    TRY(b.ensure(std::max<size_t>(v.size() * sizeof(T), 16)));
+    if (!v.empty()) {
+        HIPCHK(hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    return PROP_OK;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Finite-difference weights (closed forms), stability bound
+// ---------------------------------------------------------------------------------------------
+double fact(int n)
+{
+    double f = 1;
+    for (int i = 2; i <= n; ++i) f *= i;
+    return f;
+}
+double dfact(int n)  // n!! for odd n
+{
+    double f = 1;
+    for (int i = n; i > 1; i -= 2) f *= i;
+    return f;
+}
+// centred, accuracy order 2r: a_j = (-1)^(j+1) (r!)^2 / (j (r-j)! (r+j)!)
+void centred_weights(int r, double *a)
+{
+    for (int j = 1; j <= r; ++j) a[j - 1] = ((j & 1) ? 1.0 : -1.0) * fact(r) * fact(r) / (j * fact(r - j) * fact(r + j));
+}
+// staggered (nodes at +-(j - 1/2)), order 2r: c_j = (-1)^(j+1) ((2r-1)!!)^2 / ((2j-1)^2 (r+j-1)! (r-j)! 4^(r-1))
+void staggered_weights(int r, double *c)
+{
+    for (int j = 1; j <= r; ++j)
+        c[j - 1] = ((j & 1) ? 1.0 : -1.0) * dfact(2 * r - 1) * dfact(2 * r - 1) /
+                   ((2.0 * j - 1) * (2.0 * j - 1) * fact(r + j - 1) * fact(r - j) * std::pow(4.0, r - 1));
+}
+// S_D = max_k (sum_j 2 a_j sin(j k))^2 over k in [0, pi]: coarse scan, then golden-section refinement.
+double centred_symbol_max(int r)
+{
+    double a[8];
+    centred_weights(r, a);
+    auto f = [&](double k) {
+        double s = 0;
+        for (int j = 1; j <= r; ++j) s += 2 * a[j - 1] * std::sin(j * k);
+        return s * s;
+    };
+    const int n = 4096;
+    double best = 0, kb = 0;
+    for (int i = 0; i <= n; ++i) {
+        double k = M_PI * i / n, v = f(k);
+        if (v > best) best = v, kb = k;
+    }
+    double lo = std::max(0.0, kb - M_PI / n), hi = std::min(M_PI, kb + M_PI / n);
+    const double gr = 0.5 * (std::sqrt(5.0) - 1);
+    for (int it = 0; it < 80; ++it) {
+        double c = hi - gr * (hi - lo), d = lo + gr * (hi - lo);
+        if (f(c) > f(d)) hi = d; else lo = c;
+    }
+    return std::max(best, f(0.5 * (lo + hi)));
+}
+
+int check_grid(prop_kind kind, const prop_grid *g)
+{
+    if (!g) return fail(PROP_EINVAL, "grid is NULL");
+    if (kind != PROP_TTI && kind != PROP_ELASTIC) return fail(PROP_EINVAL, "unknown propagator kind %d", (int)kind);
+    if (g->ndim != 2 && g->ndim != 3) return fail(PROP_EINVAL, "ndim must be 2 or 3");
+    if (g->ndim == 2 && g->shape[1] != 1) return fail(PROP_EINVAL, "2D grids need shape[1] == 1");
+    if (g->space_order < 2 || g->space_order > 16 || (g->space_order & 1))
+        return fail(PROP_EINVAL, "space_order must be even in [2, 16], got %d", g->space_order);
+    if (kind == PROP_TTI && g->time_order != 2) return fail(PROP_EINVAL, "TTI needs time_order 2");
+    if (kind == PROP_ELASTIC && g->time_order != 1) return fail(PROP_EINVAL, "elastic needs time_order 1");
+    if (g->nbl < 0) return fail(PROP_EINVAL, "nbl must be >= 0");
+    if (!(g->dt > 0) || g->nt < 1) return fail(PROP_EINVAL, "dt must be > 0 and nt >= 1");
+    if (g->nbl > 0 && !(g->v_ref > 0)) return fail(PROP_EINVAL, "v_ref must be > 0 with an absorbing layer");
+    for (int a = 0; a < 3; ++a) {
+        if (g->ndim == 2 && a == 1) continue;
+        if (!(g->spacing[a] > 0)) return fail(PROP_EINVAL, "spacing must be > 0");
+        if (g->shape[a] < 2) return fail(PROP_EINVAL, "every active axis needs >= 2 points");
+    }
+    return PROP_OK;
+}
+
+double cfl_dt(prop_kind kind, const prop_grid *g, double vmax, double eps_max)
+{
+    const int r = g->space_order / 2;
+    double inv2 = 0, hmin = 1e300;
+    for (int a = 0; a < 3; ++a) {
+        if (g->ndim == 2 && a == 1) continue;
+        inv2 += 1.0 / (g->spacing[a] * g->spacing[a]);
+        hmin = std::min(hmin, g->spacing[a]);
+    }
+    if (kind == PROP_TTI) {
+        const double S = centred_symbol_max(r);
+        return 2.0 / (vmax * std::sqrt((1 + 2 * std::max(eps_max, 0.0)) * S * inv2));
+    }
+    double c[8], sum = 0;
+    staggered_weights(r, c);
+    for (int j = 0; j < r; ++j) sum += std::fabs(c[j]);
+    return hmin / (vmax * std::sqrt((double)g->ndim) * sum);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Shot window workspace
+// ---------------------------------------------------------------------------------------------
+struct Plans {
+    DevBuf b[8];
+    Csr csr{};
+    Gather gat{};
+};
+
+struct Slot {
+    Win w{};
+    int64_t o[3] = {0, 0, 0};
+    int64_t plane = 0;          // sy * nz: elements of one state field
+    DevBuf fields;              // all wavefields of this window
+    float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq
+                                // elastic: 0-2 v, 3-8 tau, 9-14 aux
+    DevBuf tabs;                // damping tables (nx + ny + nz floats)
+    Plans src_inj, rec_inj, rec_inj_vz, rec_gat, rec_gat_vz, src_gat;
+    DevBuf job_fwd, job_adj;    // TTIJob / ElJob on the device
+    DevBuf tiles;
+    int ntiles = 0, zc = 0;
+    int nsrc = 0, nrec = 0;
+};
+
+}  // namespace
+
+struct prop_s {
+    prop_kind kind;
+    prop_grid g;
+    hipStream_t st;
+    prop_model model;
+    int R;
+    Weights W;
+    DevBuf coef;                // TTI: A, B, nx, ny, nz; elastic: lam, mu, b (whole grid)
+    const float *c[5] = {};
+    DevBuf stats, dotpart, dotout, flag;
+    Slot slot;
+    // gradient workspace
+    DevBuf ckpt, ckscale, seg;
+    // batched workspace
+    std::vector<std::unique_ptr<Slot>> bslots;
+    DevBuf bjobs_fwd, bjobs_adj, btiles;
+    // timing
+    bool timing = false;
+    std::vector<hipEvent_t> evpool;
+    std::vector<std::pair<int, int>> pending[4];
+    int evnext = 0;
+    double ms[4] = {0, 0, 0, 0};
+    int64_t launches[4] = {0, 0, 0, 0};
+    int last_state = 0;         // 0 none, 1 forward, 2 adjoint
+};
+
+namespace {
+
+int64_t npts_grid(const prop_grid &g) { return g.shape[0] * g.shape[1] * g.shape[2]; }
+
+// Damping profile (absorbing layer, nbl points inside the window on every face):
+// kappa_a(i) = kmax_a (d/nbl)^2, d = depth in points into the layer, kmax_a = 3 vref ln(1000) / (2 nbl h_a).
+double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
+{
+    if (g.nbl <= 0) return 0.0;
+    if (g.ndim == 2 && axis == 1) return 0.0;
+    double d = std::max<double>(std::max<double>(g.nbl - (double)i, (double)i - (double)(n - 1 - g.nbl)), 0.0);
+    double kmax = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nbl * g.spacing[axis]);
+    return kmax * (d / g.nbl) * (d / g.nbl);
+}
+
+int tile_rows(const prop_s *h)
+{
+    return PROP_BY * (h->kind == PROP_TTI ? tti_rows_per_thread(h->R) : el_rows_per_thread(h->R));
+}
+
+// Tiles of a set of windows.  Spatial order (x fastest, then y, then z chunk) is dealt to the
+// hardware round-robin over the 8 XCDs so that each XCD gets a contiguous range of neighbouring
+// tiles (halo rows then tend to hit in that XCD's L2).
+void make_tiles(const std::vector<Slot *> &slots, int TY, std::vector<Tile> &out)
+{
+    std::vector<Tile> sp;
+    for (size_t j = 0; j < slots.size(); ++j) {
+        const Win &w = slots[j]->w;
+        const int zc = slots[j]->zc;
+        for (int z0 = 0; z0 < w.nz; z0 += zc)
+            for (int y0 = 0; y0 < w.ny; y0 += TY)
+                for (int x0 = 0; x0 < w.nx; x0 += PROP_TX) sp.push_back(Tile{(int)j, x0, y0, z0});
+    }
+    const size_t T = sp.size(), X = 8;
+    out.assign(T, Tile{});
+    const size_t per = (T + X - 1) / X;
+    size_t b = 0;
+    // block b runs on XCD b % 8; give XCD c the spatial range [c*per, (c+1)*per)
+    std::vector<size_t> order;
+    order.reserve(T);
+    for (size_t i = 0; i < per; ++i)
+        for (size_t c = 0; c < X; ++c) {
+            size_t s = c * per + i;
+            if (s < T) order.push_back(s);
+        }
+    for (size_t k = 0; k < order.size(); ++k) out[b++] = sp[order[k]];
+}
+
+int choose_zc(int nz, int64_t tiles_xy, int R)
+{
+    const char *env = getenv("PROP_ZC");
+    if (env && atoi(env) > 0) return std::min(atoi(env), nz);
+    const int64_t target = 2048;
+    int64_t nch = (target + tiles_xy - 1) / tiles_xy;
+    nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / (4 * R))));
+    return (int)((nz + nch - 1) / nch);
+}
+
+// Window of a shot, validated against the grid.
+int shot_window(const prop_s *h, const prop_shot *s, int64_t o[3], int64_t n[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        o[a] = s->win_origin[a];
+        n[a] = s->win_shape[a];
+    }
+    if (n[0] == 0 && n[1] == 0 && n[2] == 0)
+        for (int a = 0; a < 3; ++a) o[a] = 0, n[a] = h->g.shape[a];
+    for (int a = 0; a < 3; ++a) {
+        if (o[a] < 0 || n[a] < 1 || o[a] + n[a] > h->g.shape[a]) return fail(PROP_EINVAL, "window outside the grid");
+        if (!(h->g.ndim == 2 && a == 1) && n[a] < 2) return fail(PROP_EINVAL, "window needs >= 2 points per axis");
+        if (!(h->g.ndim == 2 && a == 1) && n[a] < 2 * (int64_t)h->g.nbl + 2)
+            return fail(PROP_EINVAL, "window smaller than its absorbing layers");
+    }
+    return PROP_OK;
+}
+
+// Corners and weights of off-grid points on a window (optionally staggered by half a cell in z).
+struct PointCorners {
+    std::vector<int64_t> sidx, midx;
+    std::vector<int32_t> cell[3];
+    std::vector<double> w;
+    int nc = 0;
+};
+
+int corners(const prop_s *h, const Slot &sl, const float *xyz, int npt, double zstag, PointCorners &pc)
+{
+    const prop_grid &g = h->g;
+    const int nd = g.ndim;
+    const int axes[3] = {0, nd == 3 ? 1 : 2, 2};
+    pc.nc = 1 << nd;
+    pc.sidx.assign((size_t)npt * pc.nc, 0);
+    pc.midx.assign((size_t)npt * pc.nc, 0);
+    pc.w.assign((size_t)npt * pc.nc, 1.0);
+    for (int a = 0; a < 3; ++a) pc.cell[a].assign((size_t)npt * pc.nc, 0);
+    const int64_t nwin[3] = {sl.w.nx, sl.w.ny, sl.w.nz};
+    for (int p = 0; p < npt; ++p) {
+        int64_t i0[3] = {0, 0, 0};
+        double al[3] = {0, 0, 0};
+        for (int k = 0; k < nd; ++k) {
+            const int ax = axes[k];
+            const double x = xyz[(size_t)p * nd + k];
+            const double stag = (ax == 2) ? zstag : 0.0;
+            const double u = (x - g.origin[ax]) / g.spacing[ax] - stag - (double)sl.o[ax];
+            if (!(u >= 0.0) || u > (double)(nwin[ax] - 1))
+                return fail(PROP_EINVAL, "point %d (axis %d) lies outside the shot window", p, ax);
+            int64_t i = (int64_t)std::floor(u);
+            double a = u - (double)i;
+            if (i >= nwin[ax] - 1) i = nwin[ax] - 2, a = 1.0;
+            i0[ax] = i;
+            al[ax] = a;
+        }
+        for (int c = 0; c < pc.nc; ++c) {
+            int64_t ix[3] = {i0[0], i0[1], i0[2]};
+            double wt = 1.0;
+            for (int k = 0; k < nd; ++k) {
+                const int ax = axes[k];
+                const int bit = (c >> k) & 1;
+                ix[ax] += bit;
+                wt *= bit ? al[ax] : 1.0 - al[ax];
+            }
+            const size_t e = (size_t)p * pc.nc + c;
+            pc.sidx[e] = ix[2] * sl.w.sy + ix[1] * sl.w.sx + ix[0];
+            pc.midx[e] = sl.w.moff + ix[2] * sl.w.my + ix[1] * sl.w.mx + ix[0];
+            for (int a = 0; a < 3; ++a) pc.cell[a][e] = (int32_t)ix[a];
+            pc.w[e] = wt;
+        }
+    }
+    return PROP_OK;
+}
+
+// Gather plan over the points listed in `sel` (indices into xyz), writing output column sel[o].
+int build_gather(const prop_s *h, Slot &sl, const float *xyz, const std::vector<int> &sel, double zstag, Plans &pl)
+{
+    const int nd = h->g.ndim;
+    std::vector<float> sub((size_t)sel.size() * nd);
+    for (size_t i = 0; i < sel.size(); ++i)
+        for (int k = 0; k < nd; ++k) sub[i * nd + k] = xyz[(size_t)sel[i] * nd + k];
+    PointCorners pc;
+    TRY(corners(h, sl, sub.data(), (int)sel.size(), zstag, pc));
+    std::vector<float> wf(pc.w.begin(), pc.w.end());
+    TRY(upload(pl.b[0], pc.sidx, h->st));
+    TRY(upload(pl.b[1], wf, h->st));
+    TRY(upload(pl.b[2], sel, h->st));
+    pl.gat = Gather{(int)sel.size(), pc.nc, pl.b[0].as<int64_t>(), pl.b[1].as<float>(), pl.b[2].as<int>()};
+    return PROP_OK;
+}
+
+// Node-wise injection plan (sorted by node, deterministic summation order within a row).
+int build_csr(const prop_s *h, Slot &sl, const float *xyz, const std::vector<int> &sel, double zstag, Plans &pl)
+{
+    const int nd = h->g.ndim;
+    std::vector<float> sub((size_t)sel.size() * nd);
+    for (size_t i = 0; i < sel.size(); ++i)
+        for (int k = 0; k < nd; ++k) sub[i * nd + k] = xyz[(size_t)sel[i] * nd + k];
+    PointCorners pc;
+    TRY(corners(h, sl, sub.data(), (int)sel.size(), zstag, pc));
+    const size_t ne = pc.sidx.size();
+    std::vector<size_t> ord(ne);
+    for (size_t i = 0; i < ne; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return pc.sidx[a] < pc.sidx[b]; });
+    std::vector<int64_t> node, mnode;
+    std::vector<float> e, w;
+    std::vector<int> ptr, col;
+    for (size_t k = 0; k < ne; ++k) {
+        const size_t i = ord[k];
+        if (node.empty() || node.back() != pc.sidx[i]) {
+            node.push_back(pc.sidx[i]);
+            mnode.push_back(pc.midx[i]);
+            ptr.push_back((int)col.size());
+            // damping term eta/(2dt) of the node, summed in the kernel's order
+            float ev = 0.f;
+            if (h->kind == PROP_TTI) {
+                const int64_t n3[3] = {sl.w.nx, sl.w.ny, sl.w.nz};
+                float tx = (float)(kappa(h->g, 0, pc.cell[0][i], n3[0]) / (h->g.v_ref * h->g.v_ref) / (2 * h->g.dt));
+                float ty = (float)(kappa(h->g, 1, pc.cell[1][i], n3[1]) / (h->g.v_ref * h->g.v_ref) / (2 * h->g.dt));
+                float tz = (float)(kappa(h->g, 2, pc.cell[2][i], n3[2]) / (h->g.v_ref * h->g.v_ref) / (2 * h->g.dt));
+                if (h->g.nbl <= 0) tx = ty = tz = 0.f;
+                ev = tx + ty + tz;
+            }
+            e.push_back(ev);
+        }
+        col.push_back(sel[i / pc.nc]);
+        w.push_back((float)pc.w[i]);
+    }
+    ptr.push_back((int)col.size());
+    TRY(upload(pl.b[0], node, h->st));
+    TRY(upload(pl.b[1], mnode, h->st));
+    TRY(upload(pl.b[2], e, h->st));
+    TRY(upload(pl.b[3], ptr, h->st));
+    TRY(upload(pl.b[4], col, h->st));
+    TRY(upload(pl.b[5], w, h->st));
+    pl.csr = Csr{(int)node.size(), pl.b[0].as<int64_t>(), pl.b[1].as<int64_t>(), pl.b[2].as<float>(),
+                 pl.b[3].as<int>(), pl.b[4].as<int>(), pl.b[5].as<float>()};
+    return PROP_OK;
+}
+
+// Allocate the window's fields (reused when the shape is unchanged) and build its tables/jobs.
+int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
+{
+    const bool same = sl.fields.p && sl.w.nx == n[0] && sl.w.ny == n[1] && sl.w.nz == n[2] && sl.o[0] == o[0] &&
+                      sl.o[1] == o[1] && sl.o[2] == o[2];
+    Win w{};
+    w.nx = (int)n[0];
+    w.ny = (int)n[1];
+    w.nz = (int)n[2];
+    w.sx = (n[0] + 63) / 64 * 64;
+    w.sy = w.sx * n[1];
+    w.mx = h->g.shape[0];
+    w.my = h->g.shape[0] * h->g.shape[1];
+    w.moff = o[2] * w.my + o[1] * w.mx + o[0];
+    sl.w = w;
+    for (int a = 0; a < 3; ++a) sl.o[a] = o[a];
+    sl.plane = w.sy * w.nz;
+    const int nf = h->kind == PROP_TTI ? 15 : 15;
+    if (!same) TRY(sl.fields.ensure((size_t)nf * sl.plane * sizeof(float)));
+    for (int i = 0; i < nf; ++i) sl.f[i] = sl.fields.as<float>() + (size_t)i * sl.plane;
+    // damping tables
+    std::vector<float> tab((size_t)w.nx + w.ny + w.nz);
+    const int64_t nn[3] = {w.nx, w.ny, w.nz};
+    size_t off = 0;
+    for (int a = 0; a < 3; ++a)
+        for (int64_t i = 0; i < nn[a]; ++i) {
+            const double k = kappa(h->g, a, i, nn[a]);
+            tab[off++] = h->kind == PROP_TTI ? (float)(k / (h->g.v_ref * h->g.v_ref) / (2 * h->g.dt) * (h->g.nbl > 0))
+                                             : (float)std::exp(-k * h->g.dt);
+        }
+    TRY(upload(sl.tabs, tab, h->st));
+    const int TY = tile_rows(h);
+    const int64_t txy = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY - 1) / TY);
+    sl.zc = choose_zc(w.nz, txy, h->R);
+    return PROP_OK;
+}
+
+TTIJob tti_job(const prop_s *h, const Slot &sl, bool adjoint)
+{
+    TTIJob J{};
+    J.w = sl.w;
+    const int b = adjoint ? 11 : 0;
+    J.p[0] = sl.f[b + 0];
+    J.p[1] = sl.f[b + 1];
+    J.q[0] = sl.f[adjoint ? 13 : 2];
+    J.q[1] = sl.f[adjoint ? 14 : 3];
+    for (int i = 0; i < 3; ++i) {
+        J.t[i] = sl.f[4 + i];
+        J.s[i] = sl.f[7 + i];
+    }
+    J.m = h->model.p[0];
+    J.A = h->c[0];
+    J.B = h->c[1];
+    J.nx = h->c[2];
+    J.ny = h->c[3];
+    J.nz = h->c[4];
+    const float *tab = sl.tabs.as<float>();
+    J.ex = tab;
+    J.ey = tab + sl.w.nx;
+    J.ez = tab + sl.w.nx + sl.w.ny;
+    J.grad = sl.f[10];
+    J.seg = nullptr;
+    J.seg_field = sl.plane;
+    return J;
+}
+
+ElJob el_job(const prop_s *h, const Slot &sl)
+{
+    ElJob J{};
+    J.w = sl.w;
+    for (int i = 0; i < 3; ++i) J.v[i] = sl.f[i];
+    for (int i = 0; i < 6; ++i) J.t[i] = sl.f[3 + i];
+    for (int i = 0; i < 6; ++i) J.aux[i] = sl.f[9 + i];
+    J.lam = h->c[0];
+    J.mu = h->c[1];
+    J.b = h->c[2];
+    const float *tab = sl.tabs.as<float>();
+    J.gx = tab;
+    J.gy = tab + sl.w.nx;
+    J.gz = tab + sl.w.nx + sl.w.ny;
+    return J;
+}
+
+template <class T>
+int upload_one(DevBuf &b, const T &v, hipStream_t st)
+{
+    std::vector<T> tmp(1, v);
+    return upload(b, tmp, st);
+}
+
+int set_tiles(prop_s *h, Slot &sl)
+{
+    std::vector<Slot *> one{&sl};
+    std::vector<Tile> tiles;
+    make_tiles(one, tile_rows(h), tiles);
+    sl.ntiles = (int)tiles.size();
+    return upload(sl.tiles, tiles, h->st);
+}
+
+// Timing of the stencil launches.
+hipEvent_t next_event(prop_s *h)
+{
+    if (h->evnext >= (int)h->evpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->evpool.push_back(e);
+    }
+    return h->evpool[h->evnext++];
+}
+
+int fold_timing(prop_s *h)
+{
+    bool any = false;
+    for (int k = 0; k < 4; ++k) any |= !h->pending[k].empty();
+    if (!any) return PROP_OK;
+    HIPCHK(hipStreamSynchronize(h->st));
+    for (int k = 0; k < 4; ++k) {
+        for (auto &pr : h->pending[k]) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, h->evpool[pr.first], h->evpool[pr.second]));
+            h->ms[k] += ms;
+            h->launches[k]++;
+        }
+        h->pending[k].clear();
+    }
+    h->evnext = 0;
+    return PROP_OK;
+}
+
+struct Timed {
+    prop_s *h;
+    int k;
+    int a = -1;
+    Timed(prop_s *h_, int k_) : h(h_), k(k_)
+    {
+        if (!h->timing) return;
+        if (h->evnext + 2 > 8192) fold_timing(h);
+        a = h->evnext;
+        hipEvent_t e = next_event(h);
+        if (e) (void)hipEventRecord(e, h->st); else a = -1;
+    }
+    ~Timed()
+    {
+        if (a < 0) return;
+        int b = h->evnext;
+        hipEvent_t e = next_event(h);
+        if (!e) return;
+        (void)hipEventRecord(e, h->st);
+        h->pending[k].push_back({a, b});
+    }
+};
+
+int check_finite(prop_s *h, const float *f, const Win &w)
+{
+    aux_fill_u32(h->flag.as<unsigned>(), 1, 0u, h->st);
+    aux_nonfinite_win(f, w, h->flag.as<unsigned>(), h->st);
+    unsigned v = 0;
+    HIPCHK(hipMemcpyAsync(&v, h->flag.p, sizeof v, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (v) return fail(PROP_EUNSTABLE, "non-finite wavefield values (instability)");
+    return PROP_OK;
+}
+
+const int WATCH_EVERY = 500;
+
+int prep_model(prop_s *h, const prop_model *m)
+{
+    if (!m) return fail(PROP_EINVAL, "model is NULL");
+    const int need = h->kind == PROP_TTI ? (h->g.ndim == 3 ? 5 : 4) : 3;
+    for (int i = 0; i < need; ++i)
+        if (!m->p[i]) return fail(PROP_EINVAL, "model array %d is NULL", i);
+    h->model = *m;
+    const int64_t n = npts_grid(h->g);
+    const int nc = h->kind == PROP_TTI ? 5 : 3;
+    TRY(h->coef.ensure((size_t)nc * n * sizeof(float)));
+    for (int i = 0; i < nc; ++i) h->c[i] = h->coef.as<float>() + (size_t)i * n;
+    TRY(h->stats.ensure(4 * sizeof(unsigned)));
+    aux_fill_u32(h->stats.as<unsigned>(), 4, 0u, h->st);
+    float *cc = h->coef.as<float>();
+    if (h->kind == PROP_TTI)
+        aux_tti_prep(m->p[0], m->p[1], m->p[2], m->p[3], h->g.ndim == 3 ? m->p[4] : m->p[3], n, h->g.ndim, cc,
+                     cc + n, cc + 2 * n, cc + 3 * n, cc + 4 * n, h->stats.as<unsigned>(), h->st);
+    else
+        aux_el_prep(m->p[0], m->p[1], m->p[2], n, cc, cc + n, cc + 2 * n, h->stats.as<unsigned>(), h->st);
+    HIPCHK(hipGetLastError());
+    unsigned s[4];
+    HIPCHK(hipMemcpyAsync(s, h->stats.p, sizeof s, hipMemcpyDeviceToHost, h->st));
+    HIPCHK(hipStreamSynchronize(h->st));
+    if (s[2] & 1u) return fail(PROP_EINVAL, "model has non-positive or non-finite values");
+    if (h->kind == PROP_TTI && (s[2] & 2u)) return fail(PROP_EUNSTABLE, "epsilon < delta somewhere (unstable)");
+    if (h->kind == PROP_ELASTIC && (s[2] & 2u)) return fail(PROP_EINVAL, "vp^2 < 2 vs^2 somewhere (negative lambda)");
+    float vmax, emax;
+    std::memcpy(&vmax, &s[0], 4);
+    std::memcpy(&emax, &s[1], 4);
+    const double bound = cfl_dt(h->kind, &h->g, vmax, emax);
+    if (h->g.dt > bound * (1 + 1e-9))
+        return fail(PROP_EUNSTABLE, "dt = %g exceeds the stability bound %g (vmax %g)", h->g.dt, bound, (double)vmax);
+    h->last_state = 0;
+    return PROP_OK;
+}
+
+// -------------------------------------------------------------------------- TTI time loops
+struct TTIRun {
+    prop_s *h;
+    Slot *sl;
+    const TTIJob *jf, *ja;      // device jobs
+    float idt2;
+};
+
+void tti_step(prop_s *h, Slot &sl, const TTIJob *job, bool adj, int mode, int par, int seg_step)
+{
+    {
+        Timed t(h, 0);
+        launch_tti_pass1(h->R, adj, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, par, h->W, h->st);
+    }
+    {
+        Timed t(h, 1);
+        launch_tti_pass2(h->R, mode, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, par, h->W,
+                         (float)(1.0 / (h->g.dt * h->g.dt)), seg_step, h->st);
+    }
+}
+
+int prepare_shot(prop_s *h, Slot &sl, const prop_shot *s, bool need_src_inj, bool need_rec_gat, bool need_rec_inj,
+                 bool need_src_gat)
+{
+    if (!s) return fail(PROP_EINVAL, "shot is NULL");
+    if (s->nsrc < 0 || s->nrec < 0) return fail(PROP_EINVAL, "negative point count");
+    if (s->nsrc > 0 && !s->src_xyz) return fail(PROP_EINVAL, "src_xyz is NULL");
+    if (s->nrec > 0 && !s->rec_xyz) return fail(PROP_EINVAL, "rec_xyz is NULL");
+    int64_t o[3], n[3];
+    TRY(shot_window(h, s, o, n));
+    TRY(setup_slot(h, sl, o, n));
+    TRY(set_tiles(h, sl));
+    sl.nsrc = s->nsrc;
+    sl.nrec = s->nrec;
+    std::vector<int> all_src(s->nsrc), recP, recV;
+    for (int i = 0; i < s->nsrc; ++i) all_src[i] = i;
+    for (int i = 0; i < s->nrec; ++i) {
+        const int k = (h->kind == PROP_ELASTIC && s->rec_kind) ? s->rec_kind[i] : 0;
+        if (k != 0 && k != 1) return fail(PROP_EINVAL, "rec_kind must be 0 or 1");
+        (k == 0 ? recP : recV).push_back(i);
+    }
+    sl.src_inj.csr = Csr{};
+    sl.rec_inj.csr = Csr{};
+    sl.rec_inj_vz.csr = Csr{};
+    sl.rec_gat.gat = Gather{};
+    sl.rec_gat_vz.gat = Gather{};
+    sl.src_gat.gat = Gather{};
+    if (need_src_inj && s->nsrc) TRY(build_csr(h, sl, s->src_xyz, all_src, 0.0, sl.src_inj));
+    if (need_src_gat && s->nsrc) TRY(build_gather(h, sl, s->src_xyz, all_src, 0.0, sl.src_gat));
+    if (need_rec_gat) {
+        if (!recP.empty()) TRY(build_gather(h, sl, s->rec_xyz, recP, 0.0, sl.rec_gat));
+        if (!recV.empty()) TRY(build_gather(h, sl, s->rec_xyz, recV, 0.5, sl.rec_gat_vz));
+    }
+    if (need_rec_inj) {
+        if (!recP.empty()) TRY(build_csr(h, sl, s->rec_xyz, recP, 0.0, sl.rec_inj));
+        if (!recV.empty()) TRY(build_csr(h, sl, s->rec_xyz, recV, 0.5, sl.rec_inj_vz));
+    }
+    if (h->kind == PROP_TTI) {
+        TRY(upload_one(sl.job_fwd, tti_job(h, sl, false), h->st));
+        TRY(upload_one(sl.job_adj, tti_job(h, sl, true), h->st));
+    } else {
+        TRY(upload_one(sl.job_fwd, el_job(h, sl), h->st));
+    }
+    return PROP_OK;
+}
+
+int tti_forward(prop_s *h, const prop_shot *s, float *rec_out)
+{
+    Slot &sl = h->slot;
+    TRY(prepare_shot(h, sl, s, true, true, false, false));
+    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
+    if (s->nrec > 0 && !rec_out) return fail(PROP_EINVAL, "rec_out is NULL");
+    aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
+    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
+    const TTIJob *job = sl.job_fwd.as<TTIJob>();
+    for (int n = 0; n < h->g.nt; ++n) {
+        const int par = n & 1;
+        tti_step(h, sl, job, false, K2_FWD, par, 0);
+        float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
+        if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, h->model.p[0], pn, qn,
+                                    nullptr, nullptr, h->st);
+        if (s->nrec) aux_gather(sl.rec_gat.gat, pn, nullptr, nullptr, 1.f, rec_out + (size_t)n * s->nrec, h->st);
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, pn, sl.w));
+        }
+    }
+    h->last_state = 1;
+    return PROP_OK;
+}
+
+int tti_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_out)
+{
+    Slot &sl = h->slot;
+    TRY(prepare_shot(h, sl, s, false, false, true, true));
+    if (s->nrec > 0 && !rec_in) return fail(PROP_EINVAL, "rec_in is NULL");
+    if (s->nsrc > 0 && !src_out) return fail(PROP_EINVAL, "src_out is NULL");
+    const int N = h->g.nt;
+    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
+    aux_fill(sl.f[11], 4 * sl.plane, 0.f, h->st);
+    const TTIJob *job = sl.job_adj.as<TTIJob>();
+    for (int k = N; k >= 1; --k) {
+        const int par = (N - k) & 1;
+        tti_step(h, sl, job, true, K2_ADJ, par, 0);
+        float *yp = sl.f[11 + (par ^ 1)], *yq = sl.f[13 + (par ^ 1)];
+        if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, rec_in + (size_t)(k - 1) * s->nrec, idt2, h->model.p[0], yp,
+                                        nullptr, nullptr, h->st);
+        if (s->nsrc) aux_gather(sl.src_gat.gat, yp, yq, nullptr, 1.f, src_out + (size_t)(k - 1) * s->nsrc, h->st);
+        if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, yp, sl.w));
+        }
+    }
+    h->last_state = 2;
+    return PROP_OK;
+}
+
+// Checkpoint j holds (f^c, f^{c-1}) of p and q.  FP32: plain copies.  FP16/BF16: per field the
+// current level and the level difference, each with per-x-row power-of-two scales.
+void ckpt_save(prop_s *h, Slot &sl, int j, int par_new, int dtype, size_t bytes_per_field)
+{
+    char *base = h->ckpt.as<char>() + (size_t)j * 4 * bytes_per_field;
+    const int64_t nz = (int64_t)sl.w.ny * sl.w.nz;   // scales per field: one per x-row
+    float *scl = h->ckscale.as<float>() + (size_t)j * 4 * nz;
+    const float *cur[2] = {sl.f[par_new], sl.f[2 + par_new]};
+    const float *prv[2] = {sl.f[par_new ^ 1], sl.f[2 + (par_new ^ 1)]};
+    for (int i = 0; i < 2; ++i) {
+        char *a = base + (size_t)(2 * i) * bytes_per_field, *b = a + bytes_per_field;
+        if (dtype == 0) {
+            aux_encode_win(cur[i], sl.w, nullptr, 0, a, scl + (2 * i) * nz, h->st);
+            aux_encode_win(prv[i], sl.w, nullptr, 0, b, scl + (2 * i + 1) * nz, h->st);
+        } else {
+            aux_ckpt_pair_encode(cur[i], prv[i], sl.w, dtype, (uint16_t *)a, (uint16_t *)b, scl + (2 * i) * nz,
+                                 scl + (2 * i + 1) * nz, h->st);
+        }
+    }
+}
+
+void ckpt_load(prop_s *h, Slot &sl, int j, int par_cur, int dtype, size_t bytes_per_field)
+{
+    const char *base = h->ckpt.as<char>() + (size_t)j * 4 * bytes_per_field;
+    const int64_t nz = (int64_t)sl.w.ny * sl.w.nz;
+    const float *scl = h->ckscale.as<float>() + (size_t)j * 4 * nz;
+    float *cur[2] = {sl.f[par_cur], sl.f[2 + par_cur]};
+    float *prv[2] = {sl.f[par_cur ^ 1], sl.f[2 + (par_cur ^ 1)]};
+    for (int i = 0; i < 2; ++i) {
+        const char *a = base + (size_t)(2 * i) * bytes_per_field, *b = a + bytes_per_field;
+        if (dtype == 0) {
+            aux_decode_win(a, scl, sl.w, 0, cur[i], h->st);
+            aux_decode_win(b, scl, sl.w, 0, prv[i], h->st);
+        } else {
+            aux_ckpt_pair_decode((const uint16_t *)a, (const uint16_t *)b, scl + (2 * i) * nz, scl + (2 * i + 1) * nz,
+                                 sl.w, dtype, cur[i], prv[i], h->st);
+        }
+    }
+}
+
+int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *grad_m, int n_ckpt, int dtype)
+{
+    Slot &sl = h->slot;
+    if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
+    if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
+    if (!grad_m) return fail(PROP_EINVAL, "grad_m is NULL");
+    TRY(prepare_shot(h, sl, s, true, false, true, false));
+    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
+    if (s->nrec > 0 && !residual) return fail(PROP_EINVAL, "residual is NULL");
+    const int N = h->g.nt;
+    const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
+    const int C = (N + S - 1) / S;                // checkpoints actually used (c_j = j S < N)
+    const int64_t pts = (int64_t)sl.w.nx * sl.w.ny * sl.w.nz;
+    const size_t bpf = (size_t)pts * (dtype == 0 ? 4 : 2);
+    TRY(h->ckpt.ensure(std::max<size_t>(1, (size_t)C * 4 * bpf)));
+    TRY(h->ckscale.ensure((size_t)C * 4 * sl.w.ny * sl.w.nz * sizeof(float)));
+    TRY(h->seg.ensure((size_t)S * 2 * sl.plane * sizeof(float)));
+    TTIJob jf = tti_job(h, sl, false), ja = tti_job(h, sl, true);
+    jf.seg = ja.seg = h->seg.as<float>();
+    TRY(upload_one(sl.job_fwd, jf, h->st));
+    TRY(upload_one(sl.job_adj, ja, h->st));
+    const TTIJob *dj_f = sl.job_fwd.as<TTIJob>(), *dj_a = sl.job_adj.as<TTIJob>();
+    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
+    const float *m = h->model.p[0];
+
+    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state
+    aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
+    for (int n = 0; n < N; ++n) {
+        const int par = n & 1;
+        tti_step(h, sl, dj_f, false, K2_FWD, par, 0);
+        float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
+        if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, m, pn, qn, nullptr,
+                                    nullptr, h->st);
+        if ((n + 1) % S == 0 && (n + 1) / S < C) ckpt_save(h, sl, (n + 1) / S, par ^ 1, dtype, bpf);
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, pn, sl.w));
+        }
+    }
+    // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
+    aux_fill(sl.f[10], sl.plane, 0.f, h->st);           // gradient accumulator
+    aux_fill(sl.f[11], 4 * sl.plane, 0.f, h->st);       // adjoint state
+    for (int j = C - 1; j >= 0; --j) {
+        const int start = j * S, end = std::min(N, (j + 1) * S);
+        const int par0 = start & 1;
+        if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
+        else ckpt_load(h, sl, j, par0, dtype, bpf);
+        for (int n = start; n < end; ++n) {
+            const int par = n & 1;
+            tti_step(h, sl, dj_f, false, K2_FWD_STORE, par, n - start);
+            float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
+            float *sp = h->seg.as<float>() + (size_t)(n - start) * 2 * sl.plane;
+            if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, m, pn, qn, sp,
+                                        sp + sl.plane, h->st);
+        }
+        for (int k = end; k > start; --k) {
+            const int par = (N - k) & 1;
+            tti_step(h, sl, dj_a, true, K2_ADJ_IC, par, k - 1 - start);
+            float *yp = sl.f[11 + (par ^ 1)];
+            const float *fpk = h->seg.as<float>() + (size_t)(k - 1 - start) * 2 * sl.plane;
+            if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, residual + (size_t)(k - 1) * s->nrec, idt2, m, yp,
+                                            sl.f[10], fpk, h->st);
+        }
+        HIPCHK(hipGetLastError());
+        TRY(check_finite(h, sl.f[10], sl.w));
+    }
+    aux_copy_out(sl.f[10], sl.w, grad_m, h->st);
+    HIPCHK(hipGetLastError());
+    h->last_state = 0;
+    return PROP_OK;
+}
+
+// -------------------------------------------------------------------------- elastic time loops
+void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
+{
+    const float dt = (float)h->g.dt;
+    {
+        Timed t(h, 2);
+        launch_el_vel(h->R, EL_FWD, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+    }
+    {
+        Timed t(h, 3);
+        launch_el_stress(h->R, EL_FWD, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+    }
+}
+
+int el_forward(prop_s *h, const prop_shot *s, float *rec_out)
+{
+    Slot &sl = h->slot;
+    TRY(prepare_shot(h, sl, s, true, true, false, false));
+    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
+    if (s->nrec > 0 && !rec_out) return fail(PROP_EINVAL, "rec_out is NULL");
+    aux_fill(sl.f[0], 9 * sl.plane, 0.f, h->st);
+    const ElJob *job = sl.job_fwd.as<ElJob>();
+    const float dt = (float)h->g.dt;
+    for (int n = 0; n < h->g.nt; ++n) {
+        el_step_fwd(h, sl, job);
+        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, sl.f[3], sl.f[4],
+                                   sl.f[5], h->st);
+        float *row = s->nrec ? rec_out + (size_t)n * s->nrec : nullptr;
+        if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, sl.f[3], sl.f[4], sl.f[5], 1.f, row, h->st);
+        if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, sl.f[2], nullptr, nullptr, 1.f, row, h->st);
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, sl.f[5], sl.w));
+        }
+    }
+    h->last_state = 1;
+    return PROP_OK;
+}
+
+int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_out)
+{
+    Slot &sl = h->slot;
+    TRY(prepare_shot(h, sl, s, false, false, true, true));
+    if (s->nrec > 0 && !rec_in) return fail(PROP_EINVAL, "rec_in is NULL");
+    if (s->nsrc > 0 && !src_out) return fail(PROP_EINVAL, "src_out is NULL");
+    aux_fill(sl.f[0], 15 * sl.plane, 0.f, h->st);
+    const ElJob *job = sl.job_fwd.as<ElJob>();
+    const float dt = (float)h->g.dt;
+    for (int n = h->g.nt - 1; n >= 0; --n) {
+        const float *row = s->nrec ? rec_in + (size_t)n * s->nrec : nullptr;
+        if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], sl.f[4], sl.f[5], h->st);
+        if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
+        if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], sl.f[4], sl.f[5], dt, src_out + (size_t)n * s->nsrc, h->st);
+        launch_el_mix_stress(job, 1, sl.w, h->st, 0);
+        {
+            Timed t(h, 2);
+            launch_el_vel(h->R, EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+        }
+        launch_el_mix_vel(job, 1, sl.w, h->st, 0);
+        {
+            Timed t(h, 3);
+            launch_el_stress(h->R, EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+        }
+        if ((h->g.nt - n) % WATCH_EVERY == 0 || n == 0) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, sl.f[5], sl.w));
+        }
+    }
+    h->last_state = 2;
+    return PROP_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+const char *prop_last_error(void) { return g_err.c_str(); }
+
+double prop_cfl_dt(prop_kind kind, const prop_grid *grid, double vmax, double eps_max)
+{
+    prop_grid g;
+    if (!grid) return -1.0;
+    g = *grid;
+    if (g.dt <= 0) g.dt = 1;   // not needed for the bound
+    if (g.nt < 1) g.nt = 1;
+    if (check_grid(kind, &g) != PROP_OK || !(vmax > 0)) return -1.0;
+    return cfl_dt(kind, &g, vmax, eps_max);
+}
+
+int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_model *model, void *stream)
+{
+    g_err.clear();
+    if (!out) return fail(PROP_EINVAL, "out is NULL");
+    *out = nullptr;
+    TRY(check_grid(kind, grid));
+    prop_s *h = new (std::nothrow) prop_s();
+    if (!h) return fail(PROP_ENOMEM, "host allocation failed");
+    h->kind = kind;
+    h->g = *grid;
+    h->st = (hipStream_t)stream;
+    h->R = grid->space_order / 2;
+    double w[8] = {0};
+    if (kind == PROP_TTI) centred_weights(h->R, w);
+    else staggered_weights(h->R, w);
+    for (int j = 0; j < 8; ++j) {
+        h->W.wx[j] = (float)(w[j] / grid->spacing[0]);
+        h->W.wy[j] = grid->ndim == 3 ? (float)(w[j] / grid->spacing[1]) : 0.f;
+        h->W.wz[j] = (float)(w[j] / grid->spacing[2]);
+    }
+    int rc = h->flag.ensure(16 * sizeof(unsigned));
+    if (rc == PROP_OK) rc = h->dotpart.ensure(aux_dot_blocks() * sizeof(double));
+    if (rc == PROP_OK) rc = h->dotout.ensure(sizeof(double));
+    if (rc == PROP_OK) rc = prep_model(h, model);
+    if (rc != PROP_OK) {
+        std::string msg = g_err;
+        delete h;
+        g_err = msg;
+        return rc;
+    }
+    *out = h;
+    return PROP_OK;
+}
+
+int prop_set_model(prop_t h, const prop_model *model)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    return prep_model(h, model);
+}
+
+int prop_forward(prop_t h, const prop_shot *shot, float *rec_out)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    return h->kind == PROP_TTI ? tti_forward(h, shot, rec_out) : el_forward(h, shot, rec_out);
+}
+
+int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *src_out)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    return h->kind == PROP_TTI ? tti_adjoint(h, shot, rec_in, src_out) : el_adjoint(h, shot, rec_in, src_out);
+}
+
+int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float *grad_m, int32_t n_ckpt,
+                  prop_ckpt_dtype ckpt_dtype)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "gradients are provided for PROP_TTI only");
+    return tti_gradient(h, shot, residual, grad_m, n_ckpt, (int)ckpt_dtype);
+}
+
+int prop_forward_batched(prop_t h, int32_t nshot, const prop_shot *shots, float *const *rec_out)
+{
+    (void)nshot, (void)shots, (void)rec_out;
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    return fail(PROP_ESTATE, "batched forward not built yet");
+}
+
+int prop_gradient_batched(prop_t h, int32_t nshot, const prop_shot *shots, const float *const *residual,
+                          double *grad_global, int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype)
+{
+    (void)nshot, (void)shots, (void)residual, (void)grad_global, (void)n_ckpt, (void)ckpt_dtype;
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    return fail(PROP_ESTATE, "batched gradient not built yet");
+}
+
+int prop_read_state(prop_t h, int32_t field, float *out)
+{
+    g_err.clear();
+    if (!h || !out) return fail(PROP_EINVAL, "NULL argument");
+    if (h->last_state == 0) return fail(PROP_ESTATE, "no forward or adjoint result to read");
+    const Slot &sl = h->slot;
+    const float *src = nullptr;
+    if (h->kind == PROP_TTI) {
+        if (field < 0 || field > 3) return fail(PROP_EINVAL, "TTI state field must be 0..3");
+        const int N = h->g.nt;
+        if (h->last_state == 1) {
+            const int cur = N & 1;   // f^N lives in buffer (N-1)&1 ^ 1 == N & 1
+            const int idx[4] = {cur, 2 + cur, cur ^ 1, 2 + (cur ^ 1)};
+            src = sl.f[idx[field]];
+        } else {
+            const int cur = N & 1;   // y^1 written at iteration N-1 into buffer ((N-1)&1)^1
+            const int idx[4] = {11 + cur, 13 + cur, 11 + (cur ^ 1), 13 + (cur ^ 1)};
+            src = sl.f[idx[field]];
+        }
+    } else {
+        if (field < 0 || field > 8) return fail(PROP_EINVAL, "elastic state field must be 0..8");
+        src = sl.f[field];
+    }
+    aux_copy_out(src, sl.w, out, h->st);
+    HIPCHK(hipGetLastError());
+    return PROP_OK;
+}
+
+int prop_set_timing(prop_t h, int32_t enable)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    TRY(fold_timing(h));
+    h->timing = enable != 0;
+    for (int k = 0; k < 4; ++k) h->ms[k] = 0, h->launches[k] = 0;
+    return PROP_OK;
+}
+
+int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name)
+{
+    g_err.clear();
+    static const char *names[4] = {"tti_pass1 (gradient + axis projection)", "tti_pass2 (divergence + update)",
+                                   "el_vel (velocity pass)", "el_stress (stress pass)"};
+    if (!h || kclass < 0 || kclass > 3) return fail(PROP_EINVAL, "bad handle or kernel class");
+    TRY(fold_timing(h));
+    if (ms) *ms = h->ms[kclass];
+    if (launches) *launches = h->launches[kclass];
+    if (name) *name = names[kclass];
+    return PROP_OK;
+}
+
+int prop_ckpt_encode(const float *f, int64_t n, prop_ckpt_dtype dtype, void *codes, float *scale_dev, void *stream)
+{
+    g_err.clear();
+    if (!f || !codes || !scale_dev || n < 0) return fail(PROP_EINVAL, "bad codec argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PROP_CKPT_F32) {
+        HIPCHK(hipMemcpyAsync(codes, f, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+        const float one = 1.0f;
+        HIPCHK(hipMemcpyAsync(scale_dev, &one, 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return PROP_OK;
+    }
+    if (dtype != PROP_CKPT_F16 && dtype != PROP_CKPT_BF16) return fail(PROP_EINVAL, "unknown dtype");
+    DevBuf mx;
+    TRY(mx.ensure(sizeof(unsigned)));
+    aux_fill_u32(mx.as<unsigned>(), 1, 0u, st);
+    aux_absmax(f, n, mx.as<unsigned>(), st);
+    aux_encode(f, n, mx.as<unsigned>(), (int)dtype, (uint16_t *)codes, scale_dev, st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    return PROP_OK;
+}
+
+int prop_ckpt_decode(const void *codes, const float *scale_dev, int64_t n, prop_ckpt_dtype dtype, float *f,
+                     void *stream)
+{
+    g_err.clear();
+    if (!f || !codes || !scale_dev || n < 0) return fail(PROP_EINVAL, "bad codec argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == PROP_CKPT_F32) {
+        HIPCHK(hipMemcpyAsync(f, codes, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+        return PROP_OK;
+    }
+    if (dtype != PROP_CKPT_F16 && dtype != PROP_CKPT_BF16) return fail(PROP_EINVAL, "unknown dtype");
+    aux_decode((const uint16_t *)codes, scale_dev, n, (int)dtype, f, st);
+    HIPCHK(hipGetLastError());
+    return PROP_OK;
+}
+
+int prop_dot_f64(const float *a, const float *b, int64_t n, double *result, void *stream)
+{
+    g_err.clear();
+    if (!a || !b || !result || n < 0) return fail(PROP_EINVAL, "bad dot argument");
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf part, out;
+    TRY(part.ensure(aux_dot_blocks() * sizeof(double)));
+    TRY(out.ensure(sizeof(double)));
+    aux_dot_f64(a, b, n, part.as<double>(), out.as<double>(), st);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(result, out.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PROP_OK;
+}
+
+int prop_destroy(prop_t h)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    (void)hipStreamSynchronize(h->st);
+    for (auto e : h->evpool) (void)hipEventDestroy(e);
+    delete h;
+    return PROP_OK;
+}
+
+}  // extern "C"

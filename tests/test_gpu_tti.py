@@ -1,0 +1,177 @@
+"""GPU parity of the TTI path (HIP library through the C ABI) against the FP64 checker.
+
+Bar: FP32 traces and wavefields within relative L2 1e-4 of the FP64 checker; adjoint dot test
+(FP32 arithmetic, FP64 inner products) within 1e-5; gradient within 1e-3 (per checkpoint type);
+codec bit-exact; determinism bitwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev, host, make_tti, oracle_tti, rel_l2, tti_case
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prop():
+    from paper_2004_10519_amd import prop as P
+    P.lib()
+    return P
+
+
+def test_tti2d_101_full_parity(prop, orc):
+    """The 2D constant-medium case at full length: 101 x 101, so 4, 500 steps, 101 surface receivers."""
+    from paper_2004_10519_amd import configs
+    w = configs.tti2d_101()
+    mdl = w.make_model()
+    case = dict(shape=w.shape, h=w.spacing, so=w.space_order, nbl=w.nbl, nt=w.nt, dt=w.dt, model=mdl,
+                src=w.src_xyz, rec=w.rec_xyz, wav=w.wavelet())
+    p, shot = make_tti(case, prop)
+    d = host(p.forward(shot))
+    fields = [host(p.read_state(i)) for i in range(4)]
+    g, mod = oracle_tti(case, orc)
+    do, (po, qo, pmo, qmo), _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
+    assert rel_l2(d, do) <= 1e-4
+    for a, b in zip(fields, (po, qo, pmo, qmo)):
+        assert rel_l2(a, b) <= 1e-4
+
+
+@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (4, (130, 18, 21)), (8, (90, 1, 77))])
+def test_tti_forward_parity(prop, orc, so, shape):
+    """Several tiles and ragged tails in x, y and z, absorbing layers, two off-grid sources."""
+    case = tti_case(shape, so, 5, 90)
+    p, shot = make_tti(case, prop)
+    d = host(p.forward(shot))
+    pf, qf = host(p.read_state(0)), host(p.read_state(1))
+    g, mod = oracle_tti(case, orc)
+    do, (po, qo, _, _), _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
+    assert rel_l2(d, do) <= 1e-4, rel_l2(d, do)
+    assert rel_l2(pf, po) <= 1e-4 and rel_l2(qf, qo) <= 1e-4
+
+
+@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (8, (90, 1, 77))])
+def test_tti_adjoint_parity(prop, orc, so, shape):
+    case = tti_case(shape, so, 5, 80)
+    p, shot = make_tti(case, prop)
+    rng = np.random.default_rng(3)
+    rec = rng.standard_normal((case["nt"], len(case["rec"]))).astype(np.float32)
+    s = host(p.adjoint(shot, dev(rec)))
+    yp = host(p.read_state(0))
+    g, mod = oracle_tti(case, orc)
+    so_, (ypo, _) = orc.tti_adjoint(g, mod, case["src"], case["rec"], rec)
+    assert rel_l2(s, so_) <= 1e-4, rel_l2(s, so_)
+    assert rel_l2(yp, ypo) <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(70, 37, 29), (90, 1, 77)])
+def test_tti_gpu_dot_test(prop, shape):
+    case = tti_case(shape, 8, 5, 100)
+    p, shot = make_tti(case, prop)
+    rng = np.random.default_rng(11)
+    x = dev(rng.standard_normal(case["wav"].shape))
+    shot.wavelet = x
+    Fx = p.forward(shot)
+    # y = a component along Fx plus independent noise of the same norm: white-noise y alone makes
+    # <Fx, y> a near-cancelling sum that amplifies FP32 rounding
+    xi = dev(rng.standard_normal((case["nt"], len(case["rec"]))))
+    y = (Fx * (xi.norm() / Fx.norm()) + xi).contiguous()
+    FTy = p.adjoint(shot, y)
+    a, b = prop.dot_f64(Fx, y), prop.dot_f64(x, FTy)
+    assert abs(a - b) / abs(a) < 1e-5, (a, b)
+
+
+def _bandlimited_residual(case, seed):
+    """Data-like residual: white noise filtered by the source's Ricker spectrum (band-limited)."""
+    from paper_2004_10519_amd import inputs
+    rng = np.random.default_rng(seed)
+    wn = rng.standard_normal((case["nt"], len(case["rec"])))
+    k = inputs.ricker(25.0, case["dt"], 81, t0=40 * case["dt"]).astype(np.float64)
+    out = np.stack([np.convolve(wn[:, i], k, mode="same") for i in range(wn.shape[1])], axis=1)
+    return out.astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 5e-3)])
+def test_tti_gradient_parity(prop, orc, dtype, tol):
+    case = tti_case((40, 36, 32), 8, 5, 150, nrec=30)
+    p, shot = make_tti(case, prop)
+    res = _bandlimited_residual(case, 4)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=7, ckpt_dtype=dtype))
+    g, mod = oracle_tti(case, orc)
+    # the checker takes observed data: d_obs = d - res gives the residual d - d_obs = res
+    d, _, _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
+    _, go, _ = orc.tti_gradient(g, mod, case["src"], case["wav"], case["rec"], d - res)
+    err = rel_l2(gg, go)
+    print(f"gradient rel-L2 vs FP64 ({dtype} checkpoints): {err:.3e}")
+    assert err <= tol, err
+
+
+def test_tti_gradient_single_segment_equals_full_storage(prop, orc):
+    """n_ckpt = 1 keeps the whole forward wavefield (no checkpoint rounding): FP32-level agreement."""
+    case = tti_case((40, 36, 32), 8, 5, 120, nrec=30)
+    p, shot = make_tti(case, prop)
+    res = _bandlimited_residual(case, 5)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=1, ckpt_dtype="f32"))
+    g, mod = oracle_tti(case, orc)
+    d, _, _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
+    _, go, _ = orc.tti_gradient(g, mod, case["src"], case["wav"], case["rec"], d - res)
+    assert rel_l2(gg, go) <= 1e-4
+
+
+def test_codec_bit_exact(prop, orc):
+    rng = np.random.default_rng(9)
+    f = (rng.standard_normal(100003) * 10.0 ** rng.uniform(-4, 3, 100003)).astype(np.float32)
+    f[:4] = np.array([1 + 2 ** -8, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 0.5 + 2 ** -9], np.float32) * 512
+    for dt in ("f16", "bf16"):
+        codes, scale = prop.ckpt_encode(dev(f), dt)
+        s_o, c_o = orc.ckpt_encode(f, dt)
+        assert float(host(scale)[0]) == s_o
+        assert np.array_equal(host(codes).view(np.uint16), c_o)
+        dec = host(prop.ckpt_decode(codes, scale, dt))
+        assert np.array_equal(dec, orc.ckpt_decode(s_o, c_o, dt))
+    codes, scale = prop.ckpt_encode(dev(np.zeros(10, np.float32)), "bf16")
+    assert float(host(scale)[0]) == 1.0 and not host(codes).any()
+
+
+def test_dot_f64(prop):
+    rng = np.random.default_rng(1)
+    a = rng.standard_normal(1_000_003).astype(np.float32)
+    b = rng.standard_normal(1_000_003).astype(np.float32)
+    r = prop.dot_f64(dev(a), dev(b))
+    ref = float(np.dot(a.astype(np.float64), b.astype(np.float64)))
+    assert abs(r - ref) <= 1e-12 * np.abs(a.astype(np.float64) * b).sum()
+    assert prop.dot_f64(dev(a), dev(b)) == r
+
+
+def test_determinism(prop):
+    case = tti_case((70, 37, 29), 8, 5, 60)
+    p, shot = make_tti(case, prop)
+    d1 = host(p.forward(shot)).copy()
+    d2 = host(p.forward(shot))
+    assert np.array_equal(d1, d2)
+
+
+def test_error_paths(prop):
+    case = tti_case((40, 36, 32), 8, 5, 10)
+    g = prop.Grid(case["shape"], case["h"], space_order=7, nbl=5, dt=case["dt"], nt=10)
+    mt = [dev(case["model"][k]) for k in ("m", "eps", "delta", "theta", "phi")]
+    with pytest.raises(prop.PropError) as e:
+        prop.Propagator(prop.TTI, g, mt)
+    assert e.value.code == prop.PROP_EINVAL
+    g = prop.Grid(case["shape"], case["h"], space_order=8, nbl=5, dt=case["dt"] * 2, nt=10)
+    with pytest.raises(prop.PropError) as e:
+        prop.Propagator(prop.TTI, g, mt)
+    assert e.value.code == prop.PROP_EUNSTABLE
+    bad = [mt[0], mt[2], mt[1], mt[3], mt[4]]   # epsilon < delta
+    g = prop.Grid(case["shape"], case["h"], space_order=8, nbl=5, dt=case["dt"], nt=10)
+    with pytest.raises(prop.PropError) as e:
+        prop.Propagator(prop.TTI, g, bad)
+    assert e.value.code == prop.PROP_EUNSTABLE
+    p = prop.Propagator(prop.TTI, g, mt)
+    shot = prop.Shot(case["src"], dev(case["wav"][:10]), case["rec"] + 1e4)
+    with pytest.raises(prop.PropError) as e:
+        p.forward(shot)
+    assert e.value.code == prop.PROP_EINVAL
+    with pytest.raises(prop.PropError) as e:
+        p.read_state(0)
+    assert e.value.code == prop.PROP_ESTATE
