@@ -26,8 +26,8 @@ struct Gather {
 
 void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
                     float *d3, hipStream_t st);
-void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, float *yp, float *grad,
-                        const float *fpk, hipStream_t st);
+void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, const float *A, const float *B,
+                        float *yp, float *wp, float *wq, float *grad, const float *fpk, hipStream_t st);
 void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, float *d1, float *d2, hipStream_t st);
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
                 hipStream_t st);

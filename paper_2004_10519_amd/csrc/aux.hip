@@ -32,17 +32,22 @@ __global__ void k_tti_inject(Csr c, const float *__restrict__ data, float idt2, 
     if (d3) d3[n] += v;
 }
 
-// Adjoint receiver injection into y_p (node-wise gather, deterministic), with the imaging
-// condition's share of the injected increment: g -= (1/dt^2) f_p^k * increment.
+// Adjoint receiver injection into y_p (node-wise gather, deterministic); keeps w = C y in step
+// (w_p += (1+2eps) v, w_q += sqrt(1+2delta) v) and adds the imaging condition's share of the
+// injected increment: g -= (1/dt^2) f_p^k * increment.
 __global__ void k_tti_inject_adj(Csr c, const float *__restrict__ data, float idt2, const float *__restrict__ m,
-                                 float *yp, float *grad, const float *__restrict__ fpk)
+                                 const float *__restrict__ A, const float *__restrict__ B, float *yp, float *wp,
+                                 float *wq, float *grad, const float *__restrict__ fpk)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= c.nrows) return;
-    const float a = m[c.mnode[r]] * idt2 + c.e[r];
+    const int64_t mn = c.mnode[r];
+    const float a = m[mn] * idt2 + c.e[r];
     const float v = csr_row_value(c, r, data) / a;
     const int64_t n = c.node[r];
     yp[n] += v;
+    wp[n] += A[mn] * v;
+    wq[n] += B[mn] * v;
     if (grad) grad[n] -= idt2 * fpk[n] * v;
 }
 
@@ -377,11 +382,12 @@ void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m,
     hipLaunchKernelGGL(k_tti_inject, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, idt2, m, d0, d1, d2, d3);
 }
 
-void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, float *yp, float *grad,
-                        const float *fpk, hipStream_t st)
+void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, const float *A, const float *B,
+                        float *yp, float *wp, float *wq, float *grad, const float *fpk, hipStream_t st)
 {
     if (c.nrows <= 0) return;
-    hipLaunchKernelGGL(k_tti_inject_adj, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, idt2, m, yp, grad, fpk);
+    hipLaunchKernelGGL(k_tti_inject_adj, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, idt2, m, A, B, yp, wp,
+                       wq, grad, fpk);
 }
 
 void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, float *d1, float *d2, hipStream_t st)

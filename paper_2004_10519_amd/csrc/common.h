@@ -15,7 +15,7 @@
 #include <stdint.h>
 
 #define PROP_TX 64      // tile width in x = wavefront width
-#define PROP_BY 4       // threads per block in y (block = 256 threads = 4 wavefronts)
+#define PROP_BY 8       // threads per block in y (block = 512 threads = 8 wavefronts)
 #define PROP_NT (PROP_TX * PROP_BY)
 
 struct Win {
@@ -127,6 +127,27 @@ __device__ __forceinline__ float ds_q(const float *q, const float *w)
     }
     return s;
 }
+
+// Halo items of a tile plane and their assignment to the threads of a block: x-halo items are
+// the 2R columns beside the tile on each of its TY rows, y-halo items the 2R rows above and below
+// it on its TX columns.  Thread tid handles items tid, tid + NT, ... of each list.
+template <int R, int TY>
+struct Halo {
+    static constexpr int NXI = 2 * R * TY, NYI = 2 * R * PROP_TX;
+    static constexpr int NXH = (NXI + PROP_NT - 1) / PROP_NT, NYH = (NYI + PROP_NT - 1) / PROP_NT;
+    __device__ static __forceinline__ void xitem(int i, int &yy, int &xx)
+    {
+        const int row = i / (2 * R), c = i - row * (2 * R);
+        yy = row;
+        xx = c < R ? c - R : PROP_TX + c - R;
+    }
+    __device__ static __forceinline__ void yitem(int i, int &yy, int &xx)
+    {
+        const int rr = i / PROP_TX;
+        xx = i - rr * PROP_TX;
+        yy = rr < R ? rr - R : TY + rr - R;
+    }
+};
 
 // Tile descriptor of one block: job (shot) index and tile origin.
 struct Tile {

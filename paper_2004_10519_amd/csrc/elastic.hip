@@ -22,7 +22,7 @@ namespace {
 template <int R>
 constexpr int el_ny()
 {
-    return R <= 4 ? 4 : 2;
+    return R <= 4 ? 2 : 1;
 }
 
 // Velocity pass.  Fields read: F[0..5] = (xx, yy, zz, xy, xz, yz) stresses (forward: tau;
@@ -322,7 +322,7 @@ void stress_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles,
 
 int el_rows_per_thread(int R)
 {
-    return R <= 4 ? 4 : 2;
+    return R <= 4 ? 2 : 1;
 }
 
 #define EL_SWITCH(FN, ...)                                  \

@@ -7,6 +7,7 @@
 struct TTIJob {
     Win w;
     float *p[2], *q[2];           // wavefields (state layout)
+    float *wmix[2];               // adjoint only: w = C y of the newest level, the input of pass 1
     float *t[3], *s[3];           // pass-1 vectors (I - n n^T) grad p and n n^T grad q (state layout)
     const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
     const float *nx, *ny, *nz;    // symmetry axis (model layout)
@@ -32,7 +33,7 @@ void launch_tti_pass1(int R, bool adjoint, const TTIJob *jobs, const Tile *tiles
                       int par, const Weights &W, hipStream_t st);
 void launch_tti_pass2(int R, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
                       int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
-int tti_rows_per_thread(int R);
+int tti_rows_per_thread(int R, int pass);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };
 void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,

@@ -191,13 +191,13 @@ struct Slot {
     int64_t o[3] = {0, 0, 0};
     int64_t plane = 0;          // sy * nz: elements of one state field
     DevBuf fields;              // all wavefields of this window
-    float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq
+    float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq, 15-16 w = C y
                                 // elastic: 0-2 v, 3-8 tau, 9-14 aux
     DevBuf tabs;                // damping tables (nx + ny + nz floats)
     Plans src_inj, rec_inj, rec_inj_vz, rec_gat, rec_gat_vz, src_gat;
     DevBuf job_fwd, job_adj;    // TTIJob / ElJob on the device
-    DevBuf tiles;
-    int ntiles = 0, zc = 0;
+    DevBuf tiles, tiles2;        // tile lists (TTI: pass 1 and pass 2 use different tile heights)
+    int ntiles = 0, ntiles2 = 0, zc = 0;
     int nsrc = 0, nrec = 0;
 };
 
@@ -244,9 +244,9 @@ double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
     return kmax * (d / g.nbl) * (d / g.nbl);
 }
 
-int tile_rows(const prop_s *h)
+int tile_rows(const prop_s *h, int pass = 1)
 {
-    return PROP_BY * (h->kind == PROP_TTI ? tti_rows_per_thread(h->R) : el_rows_per_thread(h->R));
+    return PROP_BY * (h->kind == PROP_TTI ? tti_rows_per_thread(h->R, pass) : el_rows_per_thread(h->R));
 }
 
 // Tiles of a set of windows.  Spatial order (x fastest, then y, then z chunk) is dealt to the
@@ -442,7 +442,7 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
     sl.w = w;
     for (int a = 0; a < 3; ++a) sl.o[a] = o[a];
     sl.plane = w.sy * w.nz;
-    const int nf = h->kind == PROP_TTI ? 15 : 15;
+    const int nf = h->kind == PROP_TTI ? 17 : 15;
     if (!same) TRY(sl.fields.ensure((size_t)nf * sl.plane * sizeof(float)));
     for (int i = 0; i < nf; ++i) sl.f[i] = sl.fields.as<float>() + (size_t)i * sl.plane;
     // damping tables
@@ -456,7 +456,7 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
                                              : (float)std::exp(-k * h->g.dt);
         }
     TRY(upload(sl.tabs, tab, h->st));
-    const int TY = tile_rows(h);
+    const int TY = tile_rows(h, 1);
     const int64_t txy = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY - 1) / TY);
     sl.zc = choose_zc(w.nz, txy, h->R);
     return PROP_OK;
@@ -471,6 +471,8 @@ TTIJob tti_job(const prop_s *h, const Slot &sl, bool adjoint)
     J.p[1] = sl.f[b + 1];
     J.q[0] = sl.f[adjoint ? 13 : 2];
     J.q[1] = sl.f[adjoint ? 14 : 3];
+    J.wmix[0] = adjoint ? sl.f[15] : nullptr;
+    J.wmix[1] = adjoint ? sl.f[16] : nullptr;
     for (int i = 0; i < 3; ++i) {
         J.t[i] = sl.f[4 + i];
         J.s[i] = sl.f[7 + i];
@@ -519,9 +521,12 @@ int set_tiles(prop_s *h, Slot &sl)
 {
     std::vector<Slot *> one{&sl};
     std::vector<Tile> tiles;
-    make_tiles(one, tile_rows(h), tiles);
+    make_tiles(one, tile_rows(h, 1), tiles);
     sl.ntiles = (int)tiles.size();
-    return upload(sl.tiles, tiles, h->st);
+    TRY(upload(sl.tiles, tiles, h->st));
+    make_tiles(one, tile_rows(h, 2), tiles);
+    sl.ntiles2 = (int)tiles.size();
+    return upload(sl.tiles2, tiles, h->st);
 }
 
 // Timing of the stencil launches.
@@ -642,7 +647,7 @@ void tti_step(prop_s *h, Slot &sl, const TTIJob *job, bool adj, int mode, int pa
     }
     {
         Timed t(h, 1);
-        launch_tti_pass2(h->R, mode, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, par, h->W,
+        launch_tti_pass2(h->R, mode, job, sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc, par, h->W,
                          (float)(1.0 / (h->g.dt * h->g.dt)), seg_step, h->st);
     }
 }
@@ -725,14 +730,14 @@ int tti_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_o
     if (s->nsrc > 0 && !src_out) return fail(PROP_EINVAL, "src_out is NULL");
     const int N = h->g.nt;
     const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
-    aux_fill(sl.f[11], 4 * sl.plane, 0.f, h->st);
+    aux_fill(sl.f[11], 6 * sl.plane, 0.f, h->st);      // y (both levels) and w
     const TTIJob *job = sl.job_adj.as<TTIJob>();
     for (int k = N; k >= 1; --k) {
         const int par = (N - k) & 1;
         tti_step(h, sl, job, true, K2_ADJ, par, 0);
         float *yp = sl.f[11 + (par ^ 1)], *yq = sl.f[13 + (par ^ 1)];
-        if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, rec_in + (size_t)(k - 1) * s->nrec, idt2, h->model.p[0], yp,
-                                        nullptr, nullptr, h->st);
+        if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, rec_in + (size_t)(k - 1) * s->nrec, idt2, h->model.p[0],
+                                        h->c[0], h->c[1], yp, sl.f[15], sl.f[16], nullptr, nullptr, h->st);
         if (s->nsrc) aux_gather(sl.src_gat.gat, yp, yq, nullptr, 1.f, src_out + (size_t)(k - 1) * s->nsrc, h->st);
         if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) {
             HIPCHK(hipGetLastError());
@@ -824,7 +829,7 @@ int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *gr
     }
     // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
     aux_fill(sl.f[10], sl.plane, 0.f, h->st);           // gradient accumulator
-    aux_fill(sl.f[11], 4 * sl.plane, 0.f, h->st);       // adjoint state
+    aux_fill(sl.f[11], 6 * sl.plane, 0.f, h->st);       // adjoint state and w
     for (int j = C - 1; j >= 0; --j) {
         const int start = j * S, end = std::min(N, (j + 1) * S);
         const int par0 = start & 1;
@@ -843,8 +848,8 @@ int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *gr
             tti_step(h, sl, dj_a, true, K2_ADJ_IC, par, k - 1 - start);
             float *yp = sl.f[11 + (par ^ 1)];
             const float *fpk = h->seg.as<float>() + (size_t)(k - 1 - start) * 2 * sl.plane;
-            if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, residual + (size_t)(k - 1) * s->nrec, idt2, m, yp,
-                                            sl.f[10], fpk, h->st);
+            if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, residual + (size_t)(k - 1) * s->nrec, idt2, m, h->c[0],
+                                            h->c[1], yp, sl.f[15], sl.f[16], sl.f[10], fpk, h->st);
         }
         HIPCHK(hipGetLastError());
         TRY(check_finite(h, sl.f[10], sl.w));

@@ -6,23 +6,40 @@
 //     H0 f = -(G_xbar + G_ybar) f = div_D((I - n n^T) grad_D f),   Hz f = -G_zbar f = div_D(n n^T grad_D f)
 // with n the symmetry axis and grad_D, div_D built from the same truncated centred first
 // derivative D (D^T = -D).  One time step is two passes over the grid:
-//   pass 1: t = (I - n n^T) grad p,  s = n (n . grad q)            (forward)
-//           the same on w = C y (mix first, the transpose order)   (adjoint)
+//   pass 1: t = (I - n n^T) grad u,  s = n (n . grad v)
+//           forward: (u, v) = (p, q); adjoint: (u, v) = w = C y (mix first, the transpose order)
 //   pass 2: H0 = div t, Hz = div s; forward L = C (H0, Hz), adjoint L = (H0, Hz);
 //           a f+ = b f - c f- + L,  a = m/dt^2 + eta/(2dt), b = 2m/dt^2, c = m/dt^2 - eta/(2dt),
-//           with C = [[1+2eps, sqrt(1+2delta)], [sqrt(1+2delta), 1]].
+//           with C = [[1+2eps, sqrt(1+2delta)], [sqrt(1+2delta), 1]]; the adjoint pass also writes
+//           w = C y+ for the next pass 1.
+//
+// Both passes run the pipelined 2.5D z-march: while plane z is computed from LDS (x and y
+// derivatives) and from the register queues (z derivatives), the global loads of plane z+1
+// are already in flight into registers; LDS is double-buffered so one barrier per plane suffices.
 #include "jobs.h"
 
 namespace {
 
+// rows per thread: pass 1 holds two rows of queues; pass 2 (more live values per point) one.
+template <int R>
+constexpr int ny1_of()
+{
+    return R <= 6 ? 2 : 1;
+}
+template <int R>
+constexpr int ny2_of()
+{
+    return 1;
+}
+
 template <int R, int NY, bool ADJ>
-__global__ __launch_bounds__(PROP_NT) void tti_pass1(const TTIJob *__restrict__ jobs,
-                                                    const Tile *__restrict__ tiles, int zc, int par,
-                                                    Weights W)
+__global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict__ jobs,
+                                                       const Tile *__restrict__ tiles, int zc, int par, Weights W)
 {
     constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
     using P = Plane<R, TY>;
-    __shared__ float Lp[P::SIZE], Lq[P::SIZE];
+    using H = Halo<R, TY>;
+    __shared__ float Lp[2][P::SIZE], Lq[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
     const TTIJob &J = jobs[tl.job];
@@ -30,98 +47,128 @@ __global__ __launch_bounds__(PROP_NT) void tti_pass1(const TTIJob *__restrict__ 
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
     const int gx = x0 + tx;
-    const float *__restrict__ fp = J.p[par];
-    const float *__restrict__ fq = J.q[par];
-
-    auto load2 = [&](int x, int y, int z, float &a, float &b) {
-        if (in_win(w, x, y, z)) {
-            const int64_t i = sidx(w, x, y, z);
-            const float yp = fp[i], yq = fq[i];
-            if (ADJ) {
-                const int64_t mi = midx(w, x, y, z);
-                const float A = J.A[mi], B = J.B[mi];
-                a = A * yp + B * yq;
-                b = B * yp + yq;
-            } else {
-                a = yp;
-                b = yq;
-            }
-        } else {
-            a = 0.f;
-            b = 0.f;
-        }
+    const float *__restrict__ U = ADJ ? J.wmix[0] : J.p[par];
+    const float *__restrict__ V = ADJ ? J.wmix[1] : J.q[par];
+    auto ld = [&](const float *f, int x, int y, int z) -> float {
+        return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
     };
 
-    float qp[NY][Q], qq[NY][Q];
+    float qu[NY][Q], qv[NY][Q];                       // z queues of u and v
+    float nu[NY], nv[NY];                             // prefetched plane z+R of the queues
+    float hxu[H::NXH], hxv[H::NXH], hyu[H::NYH], hyv[H::NYH];   // prefetched halos of plane z
+    // before the first shift, slot s holds plane z0 - R + s - 1 (s = 1 .. 2R)
 #pragma unroll
     for (int r = 0; r < NY; ++r)
 #pragma unroll
-        for (int s = 1; s < Q; ++s) load2(gx, y0 + ty * NY + r, z0 - R + s - 1, qp[r][s], qq[r][s]);
-
+        for (int s = 1; s < Q; ++s) {
+            qu[r][s] = ld(U, gx, y0 + ty * NY + r, z0 - R + s - 1);
+            qv[r][s] = ld(V, gx, y0 + ty * NY + r, z0 - R + s - 1);
+        }
+    auto fetch = [&](int z) {
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            nu[r] = ld(U, gx, y0 + ty * NY + r, z + R);
+            nv[r] = ld(V, gx, y0 + ty * NY + r, z + R);
+        }
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * PROP_NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            hxu[k] = i < H::NXI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
+            hxv[k] = i < H::NXI ? ld(V, x0 + xx, y0 + yy, z) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * PROP_NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            hyu[k] = i < H::NYI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
+            hyv[k] = i < H::NYI ? ld(V, x0 + xx, y0 + yy, z) : 0.f;
+        }
+    };
+    fetch(z0);
+    int b = 0;
     for (int z = z0; z < z1; ++z) {
+        float *lu = Lp[b], *lv = Lq[b];
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
 #pragma unroll
             for (int s = 0; s < Q - 1; ++s) {
-                qp[r][s] = qp[r][s + 1];
-                qq[r][s] = qq[r][s + 1];
+                qu[r][s] = qu[r][s + 1];
+                qv[r][s] = qv[r][s + 1];
             }
-            load2(gx, y0 + ty * NY + r, z + R, qp[r][Q - 1], qq[r][Q - 1]);
-            Lp[P::at(ty * NY + r, tx)] = qp[r][R];
-            Lq[P::at(ty * NY + r, tx)] = qq[r][R];
+            qu[r][Q - 1] = nu[r];
+            qv[r][Q - 1] = nv[r];
+            lu[P::at(ty * NY + r, tx)] = qu[r][R];
+            lv[P::at(ty * NY + r, tx)] = qv[r][R];
         }
-        // halo of both fields in one pass over the halo points
-        for (int i = tid; i < 2 * R * TY; i += PROP_NT) {
-            int row = i / (2 * R), c = i - row * (2 * R);
-            int xx = c < R ? c - R : PROP_TX + c - R;
-            float a, b;
-            load2(x0 + xx, y0 + row, z, a, b);
-            Lp[P::at(row, xx)] = a;
-            Lq[P::at(row, xx)] = b;
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * PROP_NT;
+            if (i < H::NXI) {
+                int yy, xx;
+                H::xitem(i, yy, xx);
+                lu[P::at(yy, xx)] = hxu[k];
+                lv[P::at(yy, xx)] = hxv[k];
+            }
         }
-        for (int i = tid; i < 2 * R * PROP_TX; i += PROP_NT) {
-            int rr = i / PROP_TX, xx = i - rr * PROP_TX;
-            int yy = rr < R ? rr - R : TY + rr - R;
-            float a, b;
-            load2(x0 + xx, y0 + yy, z, a, b);
-            Lp[P::at(yy, xx)] = a;
-            Lq[P::at(yy, xx)] = b;
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * PROP_NT;
+            if (i < H::NYI) {
+                int yy, xx;
+                H::yitem(i, yy, xx);
+                lu[P::at(yy, xx)] = hyu[k];
+                lv[P::at(yy, xx)] = hyv[k];
+            }
         }
         __syncthreads();
+        // per-point symmetry axis of plane z first, then the prefetch of plane z+1
+        float n0[NY], n1[NY], n2[NY];
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;
+            const bool in = gx < w.nx && y < w.ny;
+            const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
+            n0[r] = J.nx[mi];
+            n1[r] = J.ny[mi];
+            n2[r] = J.nz[mi];
+        }
+        if (z + 1 < z1) fetch(z + 1);
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            const int y = y0 + ty * NY + r;
+            const int li = P::at(ty * NY + r, tx);
+            const float dpx = dc_lds_x<R>(lu, li, W.wx), dpy = dc_lds_y<R, P::LX>(lu, li, W.wy);
+            const float dqx = dc_lds_x<R>(lv, li, W.wx), dqy = dc_lds_y<R, P::LX>(lv, li, W.wy);
+            const float dpz = dc_q<R>(qu[r], W.wz), dqz = dc_q<R>(qv[r], W.wz);
             if (gx < w.nx && y < w.ny) {
-                const int li = P::at(ty * NY + r, tx);
-                const float dpx = dc_lds_x<R>(Lp, li, W.wx), dpy = dc_lds_y<R, P::LX>(Lp, li, W.wy);
-                const float dqx = dc_lds_x<R>(Lq, li, W.wx), dqy = dc_lds_y<R, P::LX>(Lq, li, W.wy);
-                const float dpz = dc_q<R>(qp[r], W.wz), dqz = dc_q<R>(qq[r], W.wz);
-                const int64_t mi = midx(w, gx, y, z);
-                const float n0 = J.nx[mi], n1 = J.ny[mi], n2 = J.nz[mi];
-                const float wp = n0 * dpx + n1 * dpy + n2 * dpz;
-                const float wq = n0 * dqx + n1 * dqy + n2 * dqz;
+                const float wp = n0[r] * dpx + n1[r] * dpy + n2[r] * dpz;
+                const float wq = n0[r] * dqx + n1[r] * dqy + n2[r] * dqz;
                 const int64_t si = sidx(w, gx, y, z);
-                J.t[0][si] = dpx - n0 * wp;
-                J.t[1][si] = dpy - n1 * wp;
-                J.t[2][si] = dpz - n2 * wp;
-                J.s[0][si] = n0 * wq;
-                J.s[1][si] = n1 * wq;
-                J.s[2][si] = n2 * wq;
+                J.t[0][si] = dpx - n0[r] * wp;
+                J.t[1][si] = dpy - n1[r] * wp;
+                J.t[2][si] = dpz - n2[r] * wp;
+                J.s[0][si] = n0[r] * wq;
+                J.s[1][si] = n1[r] * wq;
+                J.s[2][si] = n2[r] * wq;
             }
         }
-        __syncthreads();
+        b ^= 1;
     }
 }
 
 template <int R, int NY, int MODE>
-__global__ __launch_bounds__(PROP_NT) void tti_pass2(const TTIJob *__restrict__ jobs,
-                                                    const Tile *__restrict__ tiles, int zc, int par,
-                                                    Weights W, float idt2, int seg_step)
+__global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict__ jobs,
+                                                       const Tile *__restrict__ tiles, int zc, int par, Weights W,
+                                                       float idt2, int seg_step)
 {
     constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
     constexpr bool ADJ = (MODE == K2_ADJ || MODE == K2_ADJ_IC);
     using P = Plane<R, TY>;
-    __shared__ float Ltx[P::SIZE], Lty[P::SIZE], Lsx[P::SIZE], Lsy[P::SIZE];
+    using H = Halo<R, TY>;
+    __shared__ float Ltx[2][P::SIZE], Lty[2][P::SIZE], Lsx[2][P::SIZE], Lsy[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
     const TTIJob &J = jobs[tl.job];
@@ -139,12 +186,13 @@ __global__ __launch_bounds__(PROP_NT) void tti_pass2(const TTIJob *__restrict__ 
     const float *__restrict__ qc = J.q[par];
     float *__restrict__ pn = J.p[par ^ 1];   // holds the previous level, receives the new one
     float *__restrict__ qn = J.q[par ^ 1];
-
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
     };
 
     float qt[NY][Q], qs[NY][Q];
+    float nt[NY], ns[NY], itx[NY], ity[NY], isx[NY], isy[NY];
+    float hxt[H::NXH], hxs[H::NXH], hyt[H::NYH], hys[H::NYH];
 #pragma unroll
     for (int r = 0; r < NY; ++r)
 #pragma unroll
@@ -152,94 +200,145 @@ __global__ __launch_bounds__(PROP_NT) void tti_pass2(const TTIJob *__restrict__ 
             qt[r][s] = ld(T2, gx, y0 + ty * NY + r, z0 - R + s - 1);
             qs[r][s] = ld(S2, gx, y0 + ty * NY + r, z0 - R + s - 1);
         }
-
-    for (int z = z0; z < z1; ++z) {
+    auto fetch = [&](int z) {
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;
+            nt[r] = ld(T2, gx, y, z + R);
+            ns[r] = ld(S2, gx, y, z + R);
+            itx[r] = ld(T0, gx, y, z);
+            ity[r] = ld(T1, gx, y, z);
+            isx[r] = ld(S0, gx, y, z);
+            isy[r] = ld(S1, gx, y, z);
+        }
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * PROP_NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            hxt[k] = i < H::NXI ? ld(T0, x0 + xx, y0 + yy, z) : 0.f;
+            hxs[k] = i < H::NXI ? ld(S0, x0 + xx, y0 + yy, z) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * PROP_NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            hyt[k] = i < H::NYI ? ld(T1, x0 + xx, y0 + yy, z) : 0.f;
+            hys[k] = i < H::NYI ? ld(S1, x0 + xx, y0 + yy, z) : 0.f;
+        }
+    };
+    fetch(z0);
+    int b = 0;
+    for (int z = z0; z < z1; ++z) {
+        float *ltx = Ltx[b], *lty = Lty[b], *lsx = Lsx[b], *lsy = Lsy[b];
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
 #pragma unroll
             for (int s = 0; s < Q - 1; ++s) {
                 qt[r][s] = qt[r][s + 1];
                 qs[r][s] = qs[r][s + 1];
             }
-            qt[r][Q - 1] = ld(T2, gx, y, z + R);
-            qs[r][Q - 1] = ld(S2, gx, y, z + R);
+            qt[r][Q - 1] = nt[r];
+            qs[r][Q - 1] = ns[r];
             const int li = P::at(ty * NY + r, tx);
-            Ltx[li] = ld(T0, gx, y, z);
-            Lty[li] = ld(T1, gx, y, z);
-            Lsx[li] = ld(S0, gx, y, z);
-            Lsy[li] = ld(S1, gx, y, z);
+            ltx[li] = itx[r];
+            lty[li] = ity[r];
+            lsx[li] = isx[r];
+            lsy[li] = isy[r];
         }
-        for (int i = tid; i < 2 * R * TY; i += PROP_NT) {
-            int row = i / (2 * R), c = i - row * (2 * R);
-            int xx = c < R ? c - R : PROP_TX + c - R;
-            Ltx[P::at(row, xx)] = ld(T0, x0 + xx, y0 + row, z);
-            Lsx[P::at(row, xx)] = ld(S0, x0 + xx, y0 + row, z);
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * PROP_NT;
+            if (i < H::NXI) {
+                int yy, xx;
+                H::xitem(i, yy, xx);
+                ltx[P::at(yy, xx)] = hxt[k];
+                lsx[P::at(yy, xx)] = hxs[k];
+            }
         }
-        for (int i = tid; i < 2 * R * PROP_TX; i += PROP_NT) {
-            int rr = i / PROP_TX, xx = i - rr * PROP_TX;
-            int yy = rr < R ? rr - R : TY + rr - R;
-            Lty[P::at(yy, xx)] = ld(T1, x0 + xx, y0 + yy, z);
-            Lsy[P::at(yy, xx)] = ld(S1, x0 + xx, y0 + yy, z);
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * PROP_NT;
+            if (i < H::NYI) {
+                int yy, xx;
+                H::yitem(i, yy, xx);
+                lty[P::at(yy, xx)] = hyt[k];
+                lsy[P::at(yy, xx)] = hys[k];
+            }
         }
         __syncthreads();
+        // per-point values of plane z first, then the prefetch of plane z+1
+        float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
         const float ezv = J.ez[z];
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;
+            const bool in = gx < w.nx && y < w.ny;
+            const int64_t si = sidx(w, in ? gx : 0, in ? y : 0, z);
+            const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
+            vp0[r] = pc[si];
+            vq0[r] = qc[si];
+            vp1[r] = pn[si];
+            vq1[r] = qn[si];
+            vm[r] = J.m[mi] * idt2 + 0.f;
+            vA[r] = J.A[mi];
+            vB[r] = J.B[mi];
+            if (MODE == K2_ADJ_IC) {
+                const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
+                fpk[r] = sp[si];
+                fqk[r] = sp[J.seg_field + si];
+                vg[r] = J.grad[si];
+            }
+        }
+        if (z + 1 < z1) fetch(z + 1);
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            const int y = y0 + ty * NY + r;
+            const int li = P::at(ty * NY + r, tx);
+            const float h0 = dc_lds_x<R>(ltx, li, W.wx) + dc_lds_y<R, P::LX>(lty, li, W.wy) + dc_q<R>(qt[r], W.wz);
+            const float hz = dc_lds_x<R>(lsx, li, W.wx) + dc_lds_y<R, P::LX>(lsy, li, W.wy) + dc_q<R>(qs[r], W.wz);
             if (gx < w.nx && y < w.ny) {
-                const int li = P::at(ty * NY + r, tx);
-                const float h0 = dc_lds_x<R>(Ltx, li, W.wx) + dc_lds_y<R, P::LX>(Lty, li, W.wy) +
-                                 dc_q<R>(qt[r], W.wz);
-                const float hz = dc_lds_x<R>(Lsx, li, W.wx) + dc_lds_y<R, P::LX>(Lsy, li, W.wy) +
-                                 dc_q<R>(qs[r], W.wz);
-                const int64_t mi = midx(w, gx, y, z);
                 const int64_t si = sidx(w, gx, y, z);
                 float Lp, Lq;
                 if (ADJ) {
                     Lp = h0;
                     Lq = hz;
                 } else {
-                    const float A = J.A[mi], B = J.B[mi];
-                    Lp = A * h0 + B * hz;
-                    Lq = B * h0 + hz;
+                    Lp = vA[r] * h0 + vB[r] * hz;
+                    Lq = vB[r] * h0 + hz;
                 }
-                const float mm = J.m[mi] * idt2;
+                const float mm = vm[r];
                 const float e = J.ex[gx] + J.ey[y] + ezv;
                 const float ra = 1.0f / (mm + e);
                 const float cc = mm - e;
-                const float p0 = pc[si], q0 = qc[si], p1 = pn[si], q1 = qn[si];
-                const float np_ = (2.f * mm * p0 - cc * p1 + Lp) * ra;
-                const float nq_ = (2.f * mm * q0 - cc * q1 + Lq) * ra;
+                const float np_ = (2.f * mm * vp0[r] - cc * vp1[r] + Lp) * ra;
+                const float nq_ = (2.f * mm * vq0[r] - cc * vq1[r] + Lq) * ra;
                 pn[si] = np_;
                 qn[si] = nq_;
+                if (ADJ) {
+                    J.wmix[0][si] = vA[r] * np_ + vB[r] * nq_;
+                    J.wmix[1][si] = vB[r] * np_ + nq_;
+                }
                 if (MODE == K2_FWD_STORE) {
                     float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
                     sp[si] = np_;
                     sp[J.seg_field + si] = nq_;
                 }
-                if (MODE == K2_ADJ_IC) {
-                    const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                    const float fpk = sp[si], fqk = sp[J.seg_field + si];
-                    J.grad[si] -= idt2 * (fpk * (np_ - 2.f * p0 + p1) + fqk * (nq_ - 2.f * q0 + q1));
-                }
+                if (MODE == K2_ADJ_IC)
+                    J.grad[si] = vg[r] - idt2 * (fpk[r] * (np_ - 2.f * vp0[r] + vp1[r]) +
+                                                 fqk[r] * (nq_ - 2.f * vq0[r] + vq1[r]));
             }
         }
-        __syncthreads();
+        b ^= 1;
     }
-}
-
-template <int R>
-constexpr int ny_of()
-{
-    return R <= 6 ? 4 : 2;
 }
 
 template <int R>
 void p1_dispatch(bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, hipStream_t st)
 {
-    constexpr int NY = ny_of<R>();
+    constexpr int NY = ny1_of<R>();
     dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
     if (adj) hipLaunchKernelGGL((tti_pass1<R, NY, true>), grd, blk, 0, st, jobs, tiles, zc, par, W);
     else     hipLaunchKernelGGL((tti_pass1<R, NY, false>), grd, blk, 0, st, jobs, tiles, zc, par, W);
@@ -249,7 +348,7 @@ template <int R>
 void p2_dispatch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
-    constexpr int NY = ny_of<R>();
+    constexpr int NY = ny2_of<R>();
     dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
     switch (mode) {
     case K2_FWD:
@@ -269,37 +368,31 @@ void p2_dispatch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, in
 
 }  // namespace
 
-int tti_rows_per_thread(int R)
+int tti_rows_per_thread(int R, int pass)
 {
-    return R <= 6 ? 4 : 2;
+    return pass == 1 ? (R <= 6 ? 2 : 1) : 1;
 }
+
+#define R_SWITCH(FN, ...)                   \
+    switch (R) {                            \
+    case 1: FN<1>(__VA_ARGS__); break;      \
+    case 2: FN<2>(__VA_ARGS__); break;      \
+    case 3: FN<3>(__VA_ARGS__); break;      \
+    case 4: FN<4>(__VA_ARGS__); break;      \
+    case 5: FN<5>(__VA_ARGS__); break;      \
+    case 6: FN<6>(__VA_ARGS__); break;      \
+    case 7: FN<7>(__VA_ARGS__); break;      \
+    default: FN<8>(__VA_ARGS__); break;     \
+    }
 
 void launch_tti_pass1(int R, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                       const Weights &W, hipStream_t st)
 {
-    switch (R) {
-    case 1: p1_dispatch<1>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 2: p1_dispatch<2>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 3: p1_dispatch<3>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 4: p1_dispatch<4>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 5: p1_dispatch<5>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 6: p1_dispatch<6>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    case 7: p1_dispatch<7>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    default: p1_dispatch<8>(adj, jobs, tiles, ntiles, zc, par, W, st); break;
-    }
+    R_SWITCH(p1_dispatch, adj, jobs, tiles, ntiles, zc, par, W, st)
 }
 
 void launch_tti_pass2(int R, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                       const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
-    switch (R) {
-    case 1: p2_dispatch<1>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 2: p2_dispatch<2>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 3: p2_dispatch<3>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 4: p2_dispatch<4>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 5: p2_dispatch<5>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 6: p2_dispatch<6>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    case 7: p2_dispatch<7>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    default: p2_dispatch<8>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st); break;
-    }
+    R_SWITCH(p2_dispatch, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st)
 }
