@@ -605,13 +605,14 @@ def acoustic_staggered_forward(g: Grid, lam, b, src_xyz, wavelet, nt=None):
 # Checkpoint codec: power-of-two scale + round-to-nearest-even to FP16 / BF16
 # ---------------------------------------------------------------------------
 def ckpt_scale(f: np.ndarray) -> float:
-    """s = 2^ceil(log2(max|f|)) (1 for an all-zero field), so that |f|/s <= 1."""
+    """s = 2^k with k = ceil(log2(max|f|)) clamped to FP32's normal exponent range [-126, 127]
+    (1 for an all-zero field), so that |f|/s <= 1 and 1/s is a finite FP32 power of two."""
     mx = float(np.max(np.abs(np.asarray(f, dtype=np.float32)))) if np.size(f) else 0.0
     if mx == 0.0:
         return 1.0
     mant, e = math.frexp(mx)          # mx = mant * 2^e, mant in [0.5, 1)
-    s = 2.0 ** (e - 1) if mant == 0.5 else 2.0 ** e
-    return min(s, 2.0 ** 127)
+    k = e - 1 if mant == 0.5 else e
+    return 2.0 ** max(-126, min(k, 127))
 
 
 def bf16_bits_rne(x32: np.ndarray) -> np.ndarray:

@@ -123,3 +123,14 @@ def test_codec_bf16_is_nearest_even(orc):
 def test_codec_zero_field(orc):
     s, codes = orc.ckpt_encode(np.zeros(10, np.float32), "bf16")
     assert s == 1.0 and not codes.any()
+
+
+def test_codec_subnormal_maximum(orc):
+    """A field whose largest magnitude is an FP32 subnormal gets the smallest normal scale 2^-126
+    (a subnormal scale would have no finite FP32 reciprocal)."""
+    f = np.array([3e-41, -1e-40, 0.0], np.float32)
+    for dt in ("f16", "bf16"):
+        s, codes = orc.ckpt_encode(f, dt)
+        assert s == 2.0 ** -126
+        dec = orc.ckpt_decode(s, codes, dt)
+        assert np.all(np.isfinite(dec)) and np.abs(dec - f).max() <= 2.0 ** -126 * 2.0 ** -9
