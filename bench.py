@@ -113,6 +113,91 @@ def cpu_baseline(w, budget_s: float = 15.0):
                                         f"space order {w.space_order}, {steps} FP64 time steps in {el:.1f} s"}
 
 
+def kernel_roof(p, classes, npts):
+    kt = {k: p.kernel_time(k) for k in classes}
+    out = {}
+    for k, (ms, n, name) in kt.items():
+        if n == 0:
+            continue
+        avg = ms / 1e3 / n
+        out[name] = {"mean_launch_ms": round(avg * 1e3, 4), "launches": n,
+                     "GBps_algorithmic": round(KERNEL_BYTES_PER_PT[k] * npts / avg / 1e9, 1),
+                     "frac_of_8TBs": round(KERNEL_BYTES_PER_PT[k] * npts / avg / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def measure_tti_adjoint(torch, prop, w, p, shot):
+    rec = torch.randn((w.nt, len(w.rec_xyz)), device="cuda")
+    p.adjoint(shot, rec)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    t = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
+    roof = kernel_roof(p, (0, 1), w.npts)
+    p.set_timing(False)
+    g = w.npts * w.nt / t / 1e9
+    return {"workload": w.name, "GPts/s": round(g, 3), "ms": round(t * 1e3, 1),
+            "method_hbm_frac": round(g * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4), "kernels": roof}
+
+
+def measure_elastic(torch, prop, nt):
+    from paper_2004_10519_amd import configs
+    w = configs.el3d_400(nt=nt)
+    log(f"[bench] generating {w.name} model ...")
+    p, shot = setup_tti(w, torch, prop)
+    p.forward(shot)
+    torch.cuda.synchronize()
+    p.set_timing(True)
+    t = timed(torch, lambda: p.forward(shot), 1, 0)
+    roof = kernel_roof(p, (2, 3), w.npts)
+    p.set_timing(False)
+    rec = torch.randn((w.nt, len(w.rec_xyz)), device="cuda")
+    p.adjoint(shot, rec)
+    torch.cuda.synchronize()
+    ta = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
+    g, ga = w.npts * w.nt / t / 1e9, w.npts * w.nt / ta / 1e9
+    p.close()
+    return {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
+            "forward_GPts/s": round(g, 3), "adjoint_GPts/s": round(ga, 3),
+            "forward_method_hbm_frac": round(g * METHOD_BYTES_PER_PT["elastic"] / HBM_PEAK_GBS, 4),
+            "forward_kernels": roof}
+
+
+def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
+    from paper_2004_10519_amd import configs
+    w = configs.ttigrad(n=256, nt=nt)
+    log(f"[bench] generating {w.name} models ...")
+    true = [np.ascontiguousarray(a) for a in w.model_list()]
+    m0 = configs.ttigrad_starting_model(w)
+    start = [m0[k] for k in ("m", "eps", "delta", "theta", "phi")]
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    dt_ = [torch.from_numpy(a).cuda() for a in true]
+    p = prop.Propagator(prop.TTI, g, dt_)
+    shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz)
+    dobs = p.forward(shot).clone()
+    ds_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in start]
+    p.set_model(ds_)
+    res = (p.forward(shot) - dobs).contiguous()
+    out = {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
+           "checkpoints": 48}
+    ref = None
+    for dt in ("f32",) + tuple(dtypes):
+        p.gradient(shot, res, 48, dt)
+        torch.cuda.synchronize()
+        t = timed(torch, lambda: p.gradient(shot, res, 48, dt), 1, 0)
+        gr = p.gradient(shot, res, 48, dt)
+        torch.cuda.synchronize()
+        gp = w.npts * w.nt / t / 1e9
+        ent = {"GPts/s": round(gp, 3), "ms": round(t * 1e3, 1),
+               "method_hbm_frac_156B": round(gp * 156 / HBM_PEAK_GBS, 4)}
+        if ref is None:
+            ref = gr.double()
+        else:
+            ent["rel_l2_vs_f32_checkpoints"] = float(((gr.double() - ref).norm() / ref.norm()).item())
+        out[dt] = ent
+    p.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,8 +205,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps (short runs)")
     ap.add_argument("--size", type=int, default=512)
-    ap.add_argument("--all", action="store_true", help="also measure elastic, adjoint and gradient paths")
+    ap.add_argument("--only-main", action="store_true", help="skip the adjoint, elastic and gradient paths")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -132,6 +219,15 @@ def main():
     from paper_2004_10519_amd import configs, prop
     prop.lib()
     torch.cuda.set_device(0)
+
+    if args.copy_probe:
+        a = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("[bench] copy probe: 536870912 bytes read, 536870912 bytes written")
+        del a, b
 
     w = configs.tti3d_512(nt=args.nt or 3000, n=args.size)
     log(f"[bench] generating {w.name} model {w.shape} ...")
@@ -168,6 +264,10 @@ def main():
                         for k in kt},
             "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
 
+    paths = {}
+    if not args.only_main:
+        log("[bench] TTI adjoint ...")
+        paths["tti_adjoint"] = measure_tti_adjoint(torch, prop, w, p, shot)
     out = {"metric": "GPts/s (TTI forward, 512^3, so12)", "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 2),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -179,6 +279,14 @@ def main():
     p.close()
     del p
     torch.cuda.empty_cache()
+    if not args.only_main:
+        nt_el = 2000 if args.nt is None else min(args.nt, 2000)
+        paths["elastic"] = measure_elastic(torch, prop, nt_el)
+        torch.cuda.empty_cache()
+        nt_gr = 2000 if args.nt is None else min(args.nt, 2000)
+        paths["tti_gradient"] = measure_gradient(torch, prop, nt_gr)
+        torch.cuda.empty_cache()
+        out["paths"] = paths
 
     if not args.no_cpu:
         log("[bench] CPU baseline (FP64 checker) ...")

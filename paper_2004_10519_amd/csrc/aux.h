@@ -24,6 +24,36 @@ struct Gather {
     const int *pos;
 };
 
+// Shot-group plans: every row/point carries the index of its shot in the group's job table.
+struct BCsr {
+    int nrows;
+    const int *shot;
+    const int64_t *node;
+    const int64_t *mnode;
+    const float *e;
+    const int *ptr;
+    const int *col;
+    const float *w;
+};
+struct BGather {
+    int n, nc;
+    const int *shot;
+    const int64_t *idx;
+    const float *w;
+    const int *pos;
+};
+struct TTIJob;
+// TTI source injection into p, q of the new level (and its segment copy when seg_step >= 0);
+// data[shot] is that shot's wavelet array (nt x npt[shot]).
+void aux_tti_src(const BCsr &c, const TTIJob *jobs, int par, const float *const *data, const int *npt, int n,
+                 float idt2, int seg_step, hipStream_t st);
+// TTI adjoint receiver injection into y_p (+ w = C y, + imaging condition when ic != 0).
+void aux_tti_rec_adj(const BCsr &c, const TTIJob *jobs, int par, const float *const *data, const int *npt, int n,
+                     float idt2, int ic, int seg_step, hipStream_t st);
+// TTI gather: mode 0 = p of the new level (traces), 1 = y_p + y_q of the new level (source adjoint).
+void aux_tti_gather(const BGather &g, const TTIJob *jobs, int par, int mode, float *const *out, const int *npt, int n,
+                    hipStream_t st);
+
 void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
                     float *d3, hipStream_t st);
 void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, const float *A, const float *B,

@@ -1,5 +1,6 @@
 // Sparse source/receiver operators, checkpoint codec, reductions and model preprocessing (gfx950).
 #include "aux.h"
+#include "jobs.h"
 
 #include <hip/hip_fp16.h>
 
@@ -80,6 +81,70 @@ __global__ void k_gather(Gather g, const float *__restrict__ f0, const float *__
     out[g.pos[o]] = scale * s;
 }
 
+__device__ __forceinline__ float bcsr_row_value(const BCsr &c, int r, const float *data)
+{
+    float v = 0.f;
+    for (int e = c.ptr[r]; e < c.ptr[r + 1]; ++e) v += c.w[e] * data[c.col[e]];
+    return v;
+}
+
+__global__ void k_tti_src(BCsr c, const TTIJob *__restrict__ jobs, int par, const float *const *__restrict__ data,
+                          const int *__restrict__ npt, int n, float idt2, int seg_step)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const int sh = c.shot[r];
+    const TTIJob &J = jobs[sh];
+    const float a = J.m[c.mnode[r]] * idt2 + c.e[r];
+    const float v = bcsr_row_value(c, r, data[sh] + (int64_t)n * npt[sh]) / a;
+    const int64_t nd = c.node[r];
+    J.p[par ^ 1][nd] += v;
+    J.q[par ^ 1][nd] += v;
+    if (seg_step >= 0) {
+        float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
+        sp[nd] += v;
+        sp[J.seg_field + nd] += v;
+    }
+}
+
+__global__ void k_tti_rec_adj(BCsr c, const TTIJob *__restrict__ jobs, int par, const float *const *__restrict__ data,
+                              const int *__restrict__ npt, int n, float idt2, int ic, int seg_step)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const int sh = c.shot[r];
+    const TTIJob &J = jobs[sh];
+    const int64_t mn = c.mnode[r];
+    const float a = J.m[mn] * idt2 + c.e[r];
+    const float v = bcsr_row_value(c, r, data[sh] + (int64_t)n * npt[sh]) / a;
+    const int64_t nd = c.node[r];
+    J.p[par ^ 1][nd] += v;
+    J.wmix[0][nd] += J.A[mn] * v;
+    J.wmix[1][nd] += J.B[mn] * v;
+    if (ic) {
+        const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
+        J.grad[nd] -= idt2 * sp[nd] * v;
+    }
+}
+
+__global__ void k_tti_gather(BGather g, const TTIJob *__restrict__ jobs, int par, int mode, float *const *__restrict__ out,
+                             const int *__restrict__ npt, int n)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= g.n) return;
+    const int sh = g.shot[o];
+    const TTIJob &J = jobs[sh];
+    const float *f0 = J.p[par ^ 1];
+    const float *f1 = J.q[par ^ 1];
+    float s = 0.f;
+    for (int c = 0; c < g.nc; ++c) {
+        const int64_t i = g.idx[(int64_t)o * g.nc + c];
+        const float v = mode == 0 ? f0[i] : f0[i] + f1[i];
+        s += g.w[(int64_t)o * g.nc + c] * v;
+    }
+    out[sh][(int64_t)n * npt[sh] + g.pos[o]] = s;
+}
+
 __global__ void k_fill(float *p, int64_t n, float v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -108,14 +173,17 @@ __global__ void k_absmax(const float *__restrict__ f, int64_t n, unsigned *out)
     if (threadIdx.x == 0) atomicMax(out, sm[0]);
 }
 
-// Power-of-two scale s with max|f| <= s < 2 max|f| (1 for an all-zero field).
+// Power-of-two scale s = 2^k, k = ceil(log2 max|f|) clamped to FP32's normal exponents [-126, 127]
+// (1 for an all-zero field), built from the exponent bits so that 1/s is exact and finite even
+// when the maximum is subnormal.
 __device__ __forceinline__ float pow2_scale(unsigned maxbits)
 {
     if (maxbits == 0) return 1.0f;
-    int e;
-    const float mant = frexpf(__uint_as_float(maxbits), &e);   // max = mant 2^e, mant in [0.5, 1)
-    const int k = (mant == 0.5f) ? e - 1 : e;
-    return ldexpf(1.0f, min(k, 127));
+    const int eb = (int)((maxbits >> 23) & 0xffu);
+    const unsigned mb = maxbits & 0x7fffffu;
+    int k = eb == 0 ? -126 : eb - 127 + (mb != 0u ? 1 : 0);
+    k = max(-126, min(k, 127));
+    return __uint_as_float((unsigned)(k + 127) << 23);
 }
 
 // Round-to-nearest-even FP32 -> BF16 by the rounding-bias method.
@@ -374,6 +442,29 @@ inline unsigned nblocks(int64_t n, int cap = 8192)
 }
 
 }  // namespace
+
+void aux_tti_src(const BCsr &c, const TTIJob *jobs, int par, const float *const *data, const int *npt, int n,
+                 float idt2, int seg_step, hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_tti_src, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, jobs, par, data, npt, n, idt2,
+                       seg_step);
+}
+
+void aux_tti_rec_adj(const BCsr &c, const TTIJob *jobs, int par, const float *const *data, const int *npt, int n,
+                     float idt2, int ic, int seg_step, hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_tti_rec_adj, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, jobs, par, data, npt, n, idt2,
+                       ic, seg_step);
+}
+
+void aux_tti_gather(const BGather &g, const TTIJob *jobs, int par, int mode, float *const *out, const int *npt, int n,
+                    hipStream_t st)
+{
+    if (g.n <= 0) return;
+    hipLaunchKernelGGL(k_tti_gather, dim3((g.n + BS - 1) / BS), dim3(BS), 0, st, g, jobs, par, mode, out, npt, n);
+}
 
 void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
                     float *d3, hipStream_t st)

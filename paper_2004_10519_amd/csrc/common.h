@@ -131,10 +131,10 @@ __device__ __forceinline__ float ds_q(const float *q, const float *w)
 // Halo items of a tile plane and their assignment to the threads of a block: x-halo items are
 // the 2R columns beside the tile on each of its TY rows, y-halo items the 2R rows above and below
 // it on its TX columns.  Thread tid handles items tid, tid + NT, ... of each list.
-template <int R, int TY>
+template <int R, int TY, int NT = PROP_NT>
 struct Halo {
     static constexpr int NXI = 2 * R * TY, NYI = 2 * R * PROP_TX;
-    static constexpr int NXH = (NXI + PROP_NT - 1) / PROP_NT, NYH = (NYI + PROP_NT - 1) / PROP_NT;
+    static constexpr int NXH = (NXI + NT - 1) / NT, NYH = (NYI + NT - 1) / NT;
     __device__ static __forceinline__ void xitem(int i, int &yy, int &xx)
     {
         const int row = i / (2 * R), c = i - row * (2 * R);

@@ -19,30 +19,29 @@
 
 namespace {
 
-template <int R>
-constexpr int el_ny()
-{
-    return R <= 4 ? 2 : 1;
-}
+constexpr int EBY = 16;   // block = 64 x 16 threads, one row each
 
 // Velocity pass.  Fields read: F[0..5] = (xx, yy, zz, xy, xz, yz) stresses (forward: tau;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
-// queues: zz, xz, yz.
-template <int R, int NY, int MODE>
-__global__ __launch_bounds__(PROP_NT) void el_vel(const ElJob *__restrict__ jobs, const Tile *__restrict__ tiles,
-                                                 int zc, Weights W, float dt)
+// register queues: zz, xz, yz.  Pipelined like the TTI passes: the loads of plane z+1 are in
+// flight while plane z is computed; LDS is double-buffered.
+template <int R, int MODE>
+__global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict__ jobs,
+                                                       const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
-    constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
+    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
     using P = Plane<R, TY>;
+    using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
-    __shared__ float Lxx[P::SIZE], Lyy[P::SIZE], Lxy[P::SIZE], Lxz[P::SIZE], Lyz[P::SIZE];
+    __shared__ float Lxx[2][P::SIZE], Lyy[2][P::SIZE], Lxy[2][P::SIZE], Lxz[2][P::SIZE], Lyz[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
     const ElJob &J = jobs[tl.job];
     const Win w = J.w;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
-    const int gx = x0 + tx;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < w.nx && gy < w.ny;
     float *const *F = (MODE == EL_FWD) ? J.t : J.aux;
     const float *__restrict__ Fxx = F[0];
     const float *__restrict__ Fyy = F[1];
@@ -50,203 +49,268 @@ __global__ __launch_bounds__(PROP_NT) void el_vel(const ElJob *__restrict__ jobs
     const float *__restrict__ Fxy = F[3];
     const float *__restrict__ Fxz = F[4];
     const float *__restrict__ Fyz = F[5];
-
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
     };
 
-    float qzz[NY][Q], qxz[NY][Q], qyz[NY][Q];
+    float qzz[Q], qxz[Q], qyz[Q];
+    float nzz, nxz, nyz, ixx, iyy, ixy;
+    float hxx[H::NXH], hxy_x[H::NXH], hxz[H::NXH], hyy[H::NYH], hxy_y[H::NYH], hyz[H::NYH];
 #pragma unroll
-    for (int r = 0; r < NY; ++r)
+    for (int s = 1; s < Q; ++s) {
+        const int z = z0 - R + s - 1;
+        qzz[s] = ld(Fzz, gx, gy, z);
+        qxz[s] = ld(Fxz, gx, gy, z);
+        qyz[s] = ld(Fyz, gx, gy, z);
+    }
+    auto fetch = [&](int z) {
+        nzz = ld(Fzz, gx, gy, z + R);
+        nxz = ld(Fxz, gx, gy, z + R);
+        nyz = ld(Fyz, gx, gy, z + R);
+        ixx = ld(Fxx, gx, gy, z);
+        iyy = ld(Fyy, gx, gy, z);
+        ixy = ld(Fxy, gx, gy, z);
 #pragma unroll
-        for (int s = 1; s < Q; ++s) {
-            const int y = y0 + ty * NY + r, z = z0 - R + s - 1;
-            qzz[r][s] = ld(Fzz, gx, y, z);
-            qxz[r][s] = ld(Fxz, gx, y, z);
-            qyz[r][s] = ld(Fyz, gx, y, z);
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            const bool v = i < H::NXI;
+            hxx[k] = v ? ld(Fxx, x0 + xx, y0 + yy, z) : 0.f;
+            hxy_x[k] = v ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
+            hxz[k] = v ? ld(Fxz, x0 + xx, y0 + yy, z) : 0.f;
         }
-
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            const bool v = i < H::NYI;
+            hyy[k] = v ? ld(Fyy, x0 + xx, y0 + yy, z) : 0.f;
+            hxy_y[k] = v ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
+            hyz[k] = v ? ld(Fyz, x0 + xx, y0 + yy, z) : 0.f;
+        }
+    };
+    fetch(z0);
+    int b = 0;
     for (int z = z0; z < z1; ++z) {
+        float *lxx = Lxx[b], *lyy = Lyy[b], *lxy = Lxy[b], *lxz = Lxz[b], *lyz = Lyz[b];
 #pragma unroll
-        for (int r = 0; r < NY; ++r) {
-            const int y = y0 + ty * NY + r;
+        for (int s = 0; s < Q - 1; ++s) {
+            qzz[s] = qzz[s + 1];
+            qxz[s] = qxz[s + 1];
+            qyz[s] = qyz[s + 1];
+        }
+        qzz[Q - 1] = nzz;
+        qxz[Q - 1] = nxz;
+        qyz[Q - 1] = nyz;
+        const int li = P::at(ty, tx);
+        lxx[li] = ixx;
+        lyy[li] = iyy;
+        lxy[li] = ixy;
+        lxz[li] = qxz[R];
+        lyz[li] = qyz[R];
 #pragma unroll
-            for (int s = 0; s < Q - 1; ++s) {
-                qzz[r][s] = qzz[r][s + 1];
-                qxz[r][s] = qxz[r][s + 1];
-                qyz[r][s] = qyz[r][s + 1];
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NXI) {
+                int yy, xx;
+                H::xitem(i, yy, xx);
+                lxx[P::at(yy, xx)] = hxx[k];
+                lxy[P::at(yy, xx)] = hxy_x[k];
+                lxz[P::at(yy, xx)] = hxz[k];
             }
-            qzz[r][Q - 1] = ld(Fzz, gx, y, z + R);
-            qxz[r][Q - 1] = ld(Fxz, gx, y, z + R);
-            qyz[r][Q - 1] = ld(Fyz, gx, y, z + R);
-            const int li = P::at(ty * NY + r, tx);
-            Lxx[li] = ld(Fxx, gx, y, z);
-            Lyy[li] = ld(Fyy, gx, y, z);
-            Lxy[li] = ld(Fxy, gx, y, z);
-            Lxz[li] = qxz[r][R];
-            Lyz[li] = qyz[r][R];
         }
-        for (int i = tid; i < 2 * R * TY; i += PROP_NT) {
-            int row = i / (2 * R), c = i - row * (2 * R);
-            int xx = c < R ? c - R : PROP_TX + c - R;
-            const int li = P::at(row, xx);
-            Lxx[li] = ld(Fxx, x0 + xx, y0 + row, z);
-            Lxy[li] = ld(Fxy, x0 + xx, y0 + row, z);
-            Lxz[li] = ld(Fxz, x0 + xx, y0 + row, z);
-        }
-        for (int i = tid; i < 2 * R * PROP_TX; i += PROP_NT) {
-            int rr = i / PROP_TX, xx = i - rr * PROP_TX;
-            int yy = rr < R ? rr - R : TY + rr - R;
-            const int li = P::at(yy, xx);
-            Lyy[li] = ld(Fyy, x0 + xx, y0 + yy, z);
-            Lxy[li] = ld(Fxy, x0 + xx, y0 + yy, z);
-            Lyz[li] = ld(Fyz, x0 + xx, y0 + yy, z);
-        }
-        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NY; ++r) {
-            const int y = y0 + ty * NY + r;
-            if (gx < w.nx && y < w.ny) {
-                const int li = P::at(ty * NY + r, tx);
-                const float fx = ds_lds<R, true>(Lxx, li, 1, W.wx) + ds_lds<R, false>(Lxy, li, LX, W.wy) +
-                                 ds_q<R, false>(qxz[r], W.wz);
-                const float fy = ds_lds<R, false>(Lxy, li, 1, W.wx) + ds_lds<R, true>(Lyy, li, LX, W.wy) +
-                                 ds_q<R, false>(qyz[r], W.wz);
-                const float fz = ds_lds<R, false>(Lxz, li, 1, W.wx) + ds_lds<R, false>(Lyz, li, LX, W.wy) +
-                                 ds_q<R, true>(qzz[r], W.wz);
-                const int64_t si = sidx(w, gx, y, z);
-                if (MODE == EL_FWD) {
-                    const float g = J.gx[gx] * J.gy[y] * J.gz[z];
-                    const int64_t mi = midx(w, gx, y, z);
-                    const float b0 = J.b[mi];
-                    const float bx = 0.5f * (b0 + J.b[mi + (gx + 1 < w.nx ? 1 : 0)]);
-                    const float by = 0.5f * (b0 + J.b[mi + (y + 1 < w.ny ? w.mx : 0)]);
-                    const float bz = 0.5f * (b0 + J.b[mi + (z + 1 < w.nz ? w.my : 0)]);
-                    J.v[0][si] = g * (J.v[0][si] + dt * bx * fx);
-                    J.v[1][si] = g * (J.v[1][si] + dt * by * fy);
-                    J.v[2][si] = g * (J.v[2][si] + dt * bz * fz);
-                } else {
-                    J.v[0][si] -= dt * fx;
-                    J.v[1][si] -= dt * fy;
-                    J.v[2][si] -= dt * fz;
-                }
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NYI) {
+                int yy, xx;
+                H::yitem(i, yy, xx);
+                lyy[P::at(yy, xx)] = hyy[k];
+                lxy[P::at(yy, xx)] = hxy_y[k];
+                lyz[P::at(yy, xx)] = hyz[k];
             }
         }
         __syncthreads();
+        // per-point values of plane z, then the prefetch of plane z+1
+        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+        const float v0 = J.v[0][si], v1 = J.v[1][si], v2 = J.v[2][si];
+        float b0 = 0.f, bxn = 0.f, byn = 0.f, bzn = 0.f, g = 1.f;
+        if (MODE == EL_FWD) {
+            b0 = J.b[mi];
+            bxn = J.b[mi + (gx + 1 < w.nx ? 1 : 0)];
+            byn = J.b[mi + (gy + 1 < w.ny ? w.mx : 0)];
+            bzn = J.b[mi + (z + 1 < w.nz ? w.my : 0)];
+            g = J.gx[own ? gx : 0] * J.gy[own ? gy : 0] * J.gz[z];
+        }
+        if (z + 1 < z1) fetch(z + 1);
+        const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
+                         ds_q<R, false>(qxz, W.wz);
+        const float fy = ds_lds<R, false>(lxy, li, 1, W.wx) + ds_lds<R, true>(lyy, li, LX, W.wy) +
+                         ds_q<R, false>(qyz, W.wz);
+        const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + ds_lds<R, false>(lyz, li, LX, W.wy) +
+                         ds_q<R, true>(qzz, W.wz);
+        if (own) {
+            if (MODE == EL_FWD) {
+                J.v[0][si] = g * (v0 + dt * (0.5f * (b0 + bxn)) * fx);
+                J.v[1][si] = g * (v1 + dt * (0.5f * (b0 + byn)) * fy);
+                J.v[2][si] = g * (v2 + dt * (0.5f * (b0 + bzn)) * fz);
+            } else {
+                J.v[0][si] = v0 - dt * fx;
+                J.v[1][si] = v1 - dt * fy;
+                J.v[2][si] = v2 - dt * fz;
+            }
+        }
+        b ^= 1;
     }
 }
 
 // Stress pass.  Fields read: V[0..2] (forward: v; adjoint: u = bbar g v~), each staged in LDS
 // with x and y halos and queued in z.
-template <int R, int NY, int MODE>
-__global__ __launch_bounds__(PROP_NT) void el_stress(const ElJob *__restrict__ jobs, const Tile *__restrict__ tiles,
-                                                    int zc, Weights W, float dt)
+template <int R, int MODE>
+__global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restrict__ jobs,
+                                                          const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
-    constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
+    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
     using P = Plane<R, TY>;
+    using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
-    __shared__ float Lx[P::SIZE], Ly[P::SIZE], Lz[P::SIZE];
+    __shared__ float Lx[2][P::SIZE], Ly[2][P::SIZE], Lz[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
     const ElJob &J = jobs[tl.job];
     const Win w = J.w;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
-    const int gx = x0 + tx;
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < w.nx && gy < w.ny;
     float *const *V = (MODE == EL_FWD) ? J.v : J.aux;
     const float *__restrict__ Vx = V[0];
     const float *__restrict__ Vy = V[1];
     const float *__restrict__ Vz = V[2];
-
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
     };
 
-    float qx[NY][Q], qy[NY][Q], qz[NY][Q];
+    float qx[Q], qy[Q], qz[Q];
+    float nx_, ny_, nz_;
+    float hx[3][H::NXH], hy[3][H::NYH];
 #pragma unroll
-    for (int r = 0; r < NY; ++r)
+    for (int s = 1; s < Q; ++s) {
+        const int z = z0 - R + s - 1;
+        qx[s] = ld(Vx, gx, gy, z);
+        qy[s] = ld(Vy, gx, gy, z);
+        qz[s] = ld(Vz, gx, gy, z);
+    }
+    auto fetch = [&](int z) {
+        nx_ = ld(Vx, gx, gy, z + R);
+        ny_ = ld(Vy, gx, gy, z + R);
+        nz_ = ld(Vz, gx, gy, z + R);
 #pragma unroll
-        for (int s = 1; s < Q; ++s) {
-            const int y = y0 + ty * NY + r, z = z0 - R + s - 1;
-            qx[r][s] = ld(Vx, gx, y, z);
-            qy[r][s] = ld(Vy, gx, y, z);
-            qz[r][s] = ld(Vz, gx, y, z);
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            const bool v = i < H::NXI;
+            hx[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
+            hx[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
+            hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
         }
-
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            const bool v = i < H::NYI;
+            hy[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
+            hy[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
+            hy[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+        }
+    };
+    fetch(z0);
+    int b = 0;
     for (int z = z0; z < z1; ++z) {
+        float *lx = Lx[b], *ly = Ly[b], *lz = Lz[b];
 #pragma unroll
-        for (int r = 0; r < NY; ++r) {
-            const int y = y0 + ty * NY + r;
+        for (int s = 0; s < Q - 1; ++s) {
+            qx[s] = qx[s + 1];
+            qy[s] = qy[s + 1];
+            qz[s] = qz[s + 1];
+        }
+        qx[Q - 1] = nx_;
+        qy[Q - 1] = ny_;
+        qz[Q - 1] = nz_;
+        const int li = P::at(ty, tx);
+        lx[li] = qx[R];
+        ly[li] = qy[R];
+        lz[li] = qz[R];
 #pragma unroll
-            for (int s = 0; s < Q - 1; ++s) {
-                qx[r][s] = qx[r][s + 1];
-                qy[r][s] = qy[r][s + 1];
-                qz[r][s] = qz[r][s + 1];
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NXI) {
+                int yy, xx;
+                H::xitem(i, yy, xx);
+                lx[P::at(yy, xx)] = hx[0][k];
+                ly[P::at(yy, xx)] = hx[1][k];
+                lz[P::at(yy, xx)] = hx[2][k];
             }
-            qx[r][Q - 1] = ld(Vx, gx, y, z + R);
-            qy[r][Q - 1] = ld(Vy, gx, y, z + R);
-            qz[r][Q - 1] = ld(Vz, gx, y, z + R);
-            const int li = P::at(ty * NY + r, tx);
-            Lx[li] = qx[r][R];
-            Ly[li] = qy[r][R];
-            Lz[li] = qz[r][R];
         }
-        for (int i = tid; i < 2 * R * TY; i += PROP_NT) {
-            int row = i / (2 * R), c = i - row * (2 * R);
-            int xx = c < R ? c - R : PROP_TX + c - R;
-            const int li = P::at(row, xx);
-            Lx[li] = ld(Vx, x0 + xx, y0 + row, z);
-            Ly[li] = ld(Vy, x0 + xx, y0 + row, z);
-            Lz[li] = ld(Vz, x0 + xx, y0 + row, z);
-        }
-        for (int i = tid; i < 2 * R * PROP_TX; i += PROP_NT) {
-            int rr = i / PROP_TX, xx = i - rr * PROP_TX;
-            int yy = rr < R ? rr - R : TY + rr - R;
-            const int li = P::at(yy, xx);
-            Lx[li] = ld(Vx, x0 + xx, y0 + yy, z);
-            Ly[li] = ld(Vy, x0 + xx, y0 + yy, z);
-            Lz[li] = ld(Vz, x0 + xx, y0 + yy, z);
-        }
-        __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NY; ++r) {
-            const int y = y0 + ty * NY + r;
-            if (gx < w.nx && y < w.ny) {
-                const int li = P::at(ty * NY + r, tx);
-                const float exx = ds_lds<R, false>(Lx, li, 1, W.wx);
-                const float eyy = ds_lds<R, false>(Ly, li, LX, W.wy);
-                const float ezz = ds_q<R, false>(qz[r], W.wz);
-                const float gxy = ds_lds<R, true>(Lx, li, LX, W.wy) + ds_lds<R, true>(Ly, li, 1, W.wx);
-                const float gxz = ds_q<R, true>(qx[r], W.wz) + ds_lds<R, true>(Lz, li, 1, W.wx);
-                const float gyz = ds_q<R, true>(qy[r], W.wz) + ds_lds<R, true>(Lz, li, LX, W.wy);
-                const int64_t si = sidx(w, gx, y, z);
-                if (MODE == EL_FWD) {
-                    const float g = J.gx[gx] * J.gy[y] * J.gz[z];
-                    const int64_t mi = midx(w, gx, y, z);
-                    const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0,
-                                  oz = z + 1 < w.nz ? w.my : 0;
-                    const float lam = J.lam[mi], mu0 = J.mu[mi];
-                    const float mxy = 0.25f * (mu0 + J.mu[mi + ox] + J.mu[mi + oy] + J.mu[mi + ox + oy]);
-                    const float mxz = 0.25f * (mu0 + J.mu[mi + ox] + J.mu[mi + oz] + J.mu[mi + ox + oz]);
-                    const float myz = 0.25f * (mu0 + J.mu[mi + oy] + J.mu[mi + oz] + J.mu[mi + oy + oz]);
-                    const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
-                    J.t[0][si] = g * (J.t[0][si] + dt * (lt + m2 * exx));
-                    J.t[1][si] = g * (J.t[1][si] + dt * (lt + m2 * eyy));
-                    J.t[2][si] = g * (J.t[2][si] + dt * (lt + m2 * ezz));
-                    J.t[3][si] = g * (J.t[3][si] + dt * mxy * gxy);
-                    J.t[4][si] = g * (J.t[4][si] + dt * mxz * gxz);
-                    J.t[5][si] = g * (J.t[5][si] + dt * myz * gyz);
-                } else {
-                    J.t[0][si] -= dt * exx;
-                    J.t[1][si] -= dt * eyy;
-                    J.t[2][si] -= dt * ezz;
-                    J.t[3][si] -= dt * gxy;
-                    J.t[4][si] -= dt * gxz;
-                    J.t[5][si] -= dt * gyz;
-                }
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NYI) {
+                int yy, xx;
+                H::yitem(i, yy, xx);
+                lx[P::at(yy, xx)] = hy[0][k];
+                ly[P::at(yy, xx)] = hy[1][k];
+                lz[P::at(yy, xx)] = hy[2][k];
             }
         }
         __syncthreads();
+        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+        float t[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = J.t[c][si];
+        float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f, g = 1.f;
+        if (MODE == EL_FWD) {
+            const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
+            lam = J.lam[mi];
+            mu0 = J.mu[mi];
+            const float mx_ = J.mu[mi + ox], my_ = J.mu[mi + oy], mz_ = J.mu[mi + oz];
+            mxy = 0.25f * (mu0 + mx_ + my_ + J.mu[mi + ox + oy]);
+            mxz = 0.25f * (mu0 + mx_ + mz_ + J.mu[mi + ox + oz]);
+            myz = 0.25f * (mu0 + my_ + mz_ + J.mu[mi + oy + oz]);
+            g = J.gx[own ? gx : 0] * J.gy[own ? gy : 0] * J.gz[z];
+        }
+        if (z + 1 < z1) fetch(z + 1);
+        const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
+        const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
+        const float ezz = ds_q<R, false>(qz, W.wz);
+        const float gxy = ds_lds<R, true>(lx, li, LX, W.wy) + ds_lds<R, true>(ly, li, 1, W.wx);
+        const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
+        const float gyz = ds_q<R, true>(qy, W.wz) + ds_lds<R, true>(lz, li, LX, W.wy);
+        if (own) {
+            if (MODE == EL_FWD) {
+                const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
+                J.t[0][si] = g * (t[0] + dt * (lt + m2 * exx));
+                J.t[1][si] = g * (t[1] + dt * (lt + m2 * eyy));
+                J.t[2][si] = g * (t[2] + dt * (lt + m2 * ezz));
+                J.t[3][si] = g * (t[3] + dt * mxy * gxy);
+                J.t[4][si] = g * (t[4] + dt * mxz * gxz);
+                J.t[5][si] = g * (t[5] + dt * myz * gyz);
+            } else {
+                J.t[0][si] = t[0] - dt * exx;
+                J.t[1][si] = t[1] - dt * eyy;
+                J.t[2][si] = t[2] - dt * ezz;
+                J.t[3][si] = t[3] - dt * gxy;
+                J.t[4][si] = t[4] - dt * gxz;
+                J.t[5][si] = t[5] - dt * gyz;
+            }
+        }
+        b ^= 1;
     }
 }
 
@@ -302,27 +366,26 @@ template <int R>
 void vel_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                   float dt, hipStream_t st)
 {
-    constexpr int NY = el_ny<R>();
-    dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
-    if (mode == EL_FWD) hipLaunchKernelGGL((el_vel<R, NY, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
-    else                hipLaunchKernelGGL((el_vel<R, NY, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    dim3 blk(PROP_TX, EBY), grd(ntiles);
+    if (mode == EL_FWD) hipLaunchKernelGGL((el_vel<R, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    else                hipLaunchKernelGGL((el_vel<R, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
 }
 
 template <int R>
 void stress_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                      float dt, hipStream_t st)
 {
-    constexpr int NY = el_ny<R>();
-    dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
-    if (mode == EL_FWD) hipLaunchKernelGGL((el_stress<R, NY, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
-    else                hipLaunchKernelGGL((el_stress<R, NY, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    dim3 blk(PROP_TX, EBY), grd(ntiles);
+    if (mode == EL_FWD) hipLaunchKernelGGL((el_stress<R, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    else                hipLaunchKernelGGL((el_stress<R, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
 }
 
 }  // namespace
 
-int el_rows_per_thread(int R)
+int el_tile_rows(int R)
 {
-    return R <= 4 ? 2 : 1;
+    (void)R;
+    return EBY;
 }
 
 #define EL_SWITCH(FN, ...)                                  \

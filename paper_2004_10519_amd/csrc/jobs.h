@@ -29,11 +29,12 @@ struct ElJob {
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
 
-void launch_tti_pass1(int R, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
+// shape: tile-shape variant of the pass (see tti.hip); tti_tile_rows gives its tile height.
+void launch_tti_pass1(int R, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
                       int par, const Weights &W, hipStream_t st);
-void launch_tti_pass2(int R, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
+void launch_tti_pass2(int R, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
                       int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
-int tti_rows_per_thread(int R, int pass);
+int tti_tile_rows(int R, int pass, int shape);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };
 void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
@@ -42,4 +43,4 @@ void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int
                       const Weights &W, float dt, hipStream_t st);
 void launch_el_mix_stress(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
 void launch_el_mix_vel(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
-int el_rows_per_thread(int R);
+int el_tile_rows(int R);

@@ -227,6 +227,7 @@ struct prop_s {
     double ms[4] = {0, 0, 0, 0};
     int64_t launches[4] = {0, 0, 0, 0};
     int last_state = 0;         // 0 none, 1 forward, 2 adjoint
+    int last_groups = 0;        // shot groups used by the last batched call
 };
 
 namespace {
@@ -244,14 +245,29 @@ double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
     return kmax * (d / g.nbl) * (d / g.nbl);
 }
 
-int tile_rows(const prop_s *h, int pass = 1)
+int env_int(const char *name, int dflt)
 {
-    return PROP_BY * (h->kind == PROP_TTI ? tti_rows_per_thread(h->R, pass) : el_rows_per_thread(h->R));
+    const char *v = getenv(name);
+    return (v && *v) ? atoi(v) : dflt;
 }
 
-// Tiles of a set of windows.  Spatial order (x fastest, then y, then z chunk) is dealt to the
-// hardware round-robin over the 8 XCDs so that each XCD gets a contiguous range of neighbouring
-// tiles (halo rows then tend to hit in that XCD's L2).
+// Tile-shape variants of the two TTI passes (defaults chosen by measurement; PROP_SHAPE1 /
+// PROP_SHAPE2 override them for experiments).
+int shape_of(const prop_s *h, int pass)
+{
+    (void)h;
+    return pass == 1 ? env_int("PROP_SHAPE1", 1) : env_int("PROP_SHAPE2", 1);
+}
+
+int tile_rows(const prop_s *h, int pass = 1)
+{
+    if (h->kind == PROP_TTI) return tti_tile_rows(h->R, pass, shape_of(h, pass));
+    return el_tile_rows(h->R);
+}
+
+// Tiles of a set of windows in spatial order (x fastest, then y, then z chunk).  Optionally
+// (PROP_XCD=1) the order is dealt round-robin over the 8 XCDs so that each XCD gets a contiguous
+// range of neighbouring tiles.
 void make_tiles(const std::vector<Slot *> &slots, int TY, std::vector<Tile> &out)
 {
     std::vector<Tile> sp;
@@ -262,7 +278,8 @@ void make_tiles(const std::vector<Slot *> &slots, int TY, std::vector<Tile> &out
             for (int y0 = 0; y0 < w.ny; y0 += TY)
                 for (int x0 = 0; x0 < w.nx; x0 += PROP_TX) sp.push_back(Tile{(int)j, x0, y0, z0});
     }
-    const size_t T = sp.size(), X = 8;
+    // measured on the 512^3 workload: plain order is ~3% faster than the XCD-grouped order
+    const size_t T = sp.size(), X = env_int("PROP_XCD", 0) ? 8 : 1;
     out.assign(T, Tile{});
     const size_t per = (T + X - 1) / X;
     size_t b = 0;
@@ -582,14 +599,14 @@ struct Timed {
     }
 };
 
-int check_finite(prop_s *h, const float *f, const Win &w)
+int check_finite(prop_s *h, const float *f, const Win &w, const char *what = "wavefield", int step = -1, int shot = 0)
 {
     aux_fill_u32(h->flag.as<unsigned>(), 1, 0u, h->st);
     aux_nonfinite_win(f, w, h->flag.as<unsigned>(), h->st);
     unsigned v = 0;
     HIPCHK(hipMemcpyAsync(&v, h->flag.p, sizeof v, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
-    if (v) return fail(PROP_EUNSTABLE, "non-finite wavefield values (instability)");
+    if (v) return fail(PROP_EUNSTABLE, "non-finite values in %s (shot %d, step %d): instability", what, shot, step);
     return PROP_OK;
 }
 
@@ -631,27 +648,7 @@ int prep_model(prop_s *h, const prop_model *m)
     return PROP_OK;
 }
 
-// -------------------------------------------------------------------------- TTI time loops
-struct TTIRun {
-    prop_s *h;
-    Slot *sl;
-    const TTIJob *jf, *ja;      // device jobs
-    float idt2;
-};
-
-void tti_step(prop_s *h, Slot &sl, const TTIJob *job, bool adj, int mode, int par, int seg_step)
-{
-    {
-        Timed t(h, 0);
-        launch_tti_pass1(h->R, adj, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, par, h->W, h->st);
-    }
-    {
-        Timed t(h, 1);
-        launch_tti_pass2(h->R, mode, job, sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc, par, h->W,
-                         (float)(1.0 / (h->g.dt * h->g.dt)), seg_step, h->st);
-    }
-}
-
+// -------------------------------------------------------------------------- single-shot setup (elastic)
 int prepare_shot(prop_s *h, Slot &sl, const prop_shot *s, bool need_src_inj, bool need_rec_gat, bool need_rec_inj,
                  bool need_src_gat)
 {
@@ -668,7 +665,7 @@ int prepare_shot(prop_s *h, Slot &sl, const prop_shot *s, bool need_src_inj, boo
     std::vector<int> all_src(s->nsrc), recP, recV;
     for (int i = 0; i < s->nsrc; ++i) all_src[i] = i;
     for (int i = 0; i < s->nrec; ++i) {
-        const int k = (h->kind == PROP_ELASTIC && s->rec_kind) ? s->rec_kind[i] : 0;
+        const int k = s->rec_kind ? s->rec_kind[i] : 0;
         if (k != 0 && k != 1) return fail(PROP_EINVAL, "rec_kind must be 0 or 1");
         (k == 0 ? recP : recV).push_back(i);
     }
@@ -688,174 +685,530 @@ int prepare_shot(prop_s *h, Slot &sl, const prop_shot *s, bool need_src_inj, boo
         if (!recP.empty()) TRY(build_csr(h, sl, s->rec_xyz, recP, 0.0, sl.rec_inj));
         if (!recV.empty()) TRY(build_csr(h, sl, s->rec_xyz, recV, 0.5, sl.rec_inj_vz));
     }
-    if (h->kind == PROP_TTI) {
-        TRY(upload_one(sl.job_fwd, tti_job(h, sl, false), h->st));
-        TRY(upload_one(sl.job_adj, tti_job(h, sl, true), h->st));
-    } else {
-        TRY(upload_one(sl.job_fwd, el_job(h, sl), h->st));
+    TRY(upload_one(sl.job_fwd, el_job(h, sl), h->st));
+    return PROP_OK;
+}
+
+// -------------------------------------------------------------------------- TTI shot groups
+// A group is a set of shot windows stepped in lockstep: one job table, one tile list per pass
+// covering the tiles of every shot, and concatenated source/receiver plans whose rows carry the
+// shot's index.  A plain call is a group of one.
+struct HostCsr {
+    std::vector<int> shot, ptr, col;
+    std::vector<int64_t> node, mnode;
+    std::vector<float> e, w;
+};
+struct HostGather {
+    std::vector<int> shot, pos;
+    std::vector<int64_t> idx;
+    std::vector<float> w;
+    int nc = 0;
+};
+
+int append_csr(const prop_s *h, const Slot &sl, int shot, const float *xyz, int npt, HostCsr &hc)
+{
+    std::vector<int> sel(npt);
+    for (int i = 0; i < npt; ++i) sel[i] = i;
+    PointCorners pc;
+    TRY(corners(h, sl, xyz, npt, 0.0, pc));
+    const size_t ne = pc.sidx.size();
+    std::vector<size_t> ord(ne);
+    for (size_t i = 0; i < ne; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return pc.sidx[a] < pc.sidx[b]; });
+    const int64_t n3[3] = {sl.w.nx, sl.w.ny, sl.w.nz};
+    int64_t last = -1;
+    for (size_t k = 0; k < ne; ++k) {
+        const size_t i = ord[k];
+        if (pc.sidx[i] != last) {
+            last = pc.sidx[i];
+            hc.shot.push_back(shot);
+            hc.node.push_back(pc.sidx[i]);
+            hc.mnode.push_back(pc.midx[i]);
+            hc.ptr.push_back((int)hc.col.size());
+            float ev = 0.f;
+            if (h->g.nbl > 0) {
+                const double s2 = h->g.v_ref * h->g.v_ref * 2 * h->g.dt;
+                const float tx = (float)(kappa(h->g, 0, pc.cell[0][i], n3[0]) / s2);
+                const float ty = (float)(kappa(h->g, 1, pc.cell[1][i], n3[1]) / s2);
+                const float tz = (float)(kappa(h->g, 2, pc.cell[2][i], n3[2]) / s2);
+                ev = tx + ty + tz;
+            }
+            hc.e.push_back(ev);
+        }
+        hc.col.push_back((int)(i / pc.nc));
+        hc.w.push_back((float)pc.w[i]);
+    }
+    return PROP_OK;
+}
+
+int append_gather(const prop_s *h, const Slot &sl, int shot, const float *xyz, int npt, HostGather &hg)
+{
+    PointCorners pc;
+    TRY(corners(h, sl, xyz, npt, 0.0, pc));
+    hg.nc = pc.nc;
+    for (int p = 0; p < npt; ++p) {
+        hg.shot.push_back(shot);
+        hg.pos.push_back(p);
+        for (int c = 0; c < pc.nc; ++c) {
+            hg.idx.push_back(pc.sidx[(size_t)p * pc.nc + c]);
+            hg.w.push_back((float)pc.w[(size_t)p * pc.nc + c]);
+        }
+    }
+    return PROP_OK;
+}
+
+struct Group {
+    std::vector<Slot *> slots;
+    std::vector<const prop_shot *> shots;
+    DevBuf jobs_f, jobs_a, t1, t2, io;
+    DevBuf pb[16];
+    int nt1 = 0, nt2 = 0, zc = 1;
+    BCsr src_inj{}, rec_inj{};
+    BGather rec_gat{}, src_gat{};
+    const float *const *src_data = nullptr;
+    const int *nsrc = nullptr;
+    const float *const *rec_data = nullptr;
+    const int *nrec = nullptr;
+    float *const *rec_out = nullptr;
+    float *const *src_out = nullptr;
+    // gradient storage offsets per shot
+    std::vector<size_t> ck_off, sc_off, seg_off;
+};
+
+int upload_csr(prop_s *h, Group &G, int base, const HostCsr &hc, BCsr &c)
+{
+    std::vector<int> ptr = hc.ptr;
+    ptr.push_back((int)hc.col.size());
+    TRY(upload(G.pb[base + 0], hc.shot, h->st));
+    TRY(upload(G.pb[base + 1], hc.node, h->st));
+    TRY(upload(G.pb[base + 2], hc.mnode, h->st));
+    TRY(upload(G.pb[base + 3], hc.e, h->st));
+    TRY(upload(G.pb[base + 4], ptr, h->st));
+    TRY(upload(G.pb[base + 5], hc.col, h->st));
+    TRY(upload(G.pb[base + 6], hc.w, h->st));
+    c = BCsr{(int)hc.node.size(), G.pb[base].as<int>(), G.pb[base + 1].as<int64_t>(), G.pb[base + 2].as<int64_t>(),
+             G.pb[base + 3].as<float>(), G.pb[base + 4].as<int>(), G.pb[base + 5].as<int>(), G.pb[base + 6].as<float>()};
+    return PROP_OK;
+}
+
+// Build a group over `shots` using workspaces `slots` (one per shot).  io pointer tables: wavelets,
+// receiver-side inputs (rec_in / residual), receiver outputs, source outputs (each may be NULL).
+int build_group(prop_s *h, Group &G, const std::vector<const prop_shot *> &shots, const std::vector<Slot *> &slots,
+                bool src_inj, bool rec_gat, bool rec_inj, bool src_gat, const float *const *rec_in,
+                float *const *rec_out, float *const *src_out)
+{
+    G.slots = slots;
+    G.shots = shots;
+    const int ns = (int)shots.size();
+    HostCsr hs, hr;
+    HostGather gr, gs;
+    std::vector<TTIJob> jf, ja;
+    int64_t txy_min = INT64_MAX;
+    for (int j = 0; j < ns; ++j) {
+        const prop_shot *s = shots[j];
+        Slot &sl = *slots[j];
+        if (!s) return fail(PROP_EINVAL, "shot %d is NULL", j);
+        if (s->nsrc < 0 || s->nrec < 0) return fail(PROP_EINVAL, "negative point count");
+        if (s->nsrc > 0 && (!s->src_xyz || (src_inj && !s->src_wavelet))) return fail(PROP_EINVAL, "source arrays NULL");
+        if (s->nrec > 0 && !s->rec_xyz) return fail(PROP_EINVAL, "rec_xyz is NULL");
+        if (s->nrec > 0 && rec_inj && (!rec_in || !rec_in[j])) return fail(PROP_EINVAL, "receiver input NULL");
+        if (s->nrec > 0 && rec_gat && (!rec_out || !rec_out[j])) return fail(PROP_EINVAL, "rec_out is NULL");
+        if (s->nsrc > 0 && src_gat && (!src_out || !src_out[j])) return fail(PROP_EINVAL, "src_out is NULL");
+        int64_t o[3], n[3];
+        TRY(shot_window(h, s, o, n));
+        TRY(setup_slot(h, sl, o, n));
+        sl.nsrc = s->nsrc;
+        sl.nrec = s->nrec;
+        if (src_inj && s->nsrc) TRY(append_csr(h, sl, j, s->src_xyz, s->nsrc, hs));
+        if (rec_inj && s->nrec) TRY(append_csr(h, sl, j, s->rec_xyz, s->nrec, hr));
+        if (rec_gat && s->nrec) TRY(append_gather(h, sl, j, s->rec_xyz, s->nrec, gr));
+        if (src_gat && s->nsrc) TRY(append_gather(h, sl, j, s->src_xyz, s->nsrc, gs));
+        jf.push_back(tti_job(h, sl, false));
+        ja.push_back(tti_job(h, sl, true));
+        const int TY = tile_rows(h, 1);
+        txy_min = std::min<int64_t>(txy_min, (int64_t)((sl.w.nx + PROP_TX - 1) / PROP_TX) * ((sl.w.ny + TY - 1) / TY) * ns);
+    }
+    // one z-chunk size for the group (each job clips it to its own depth)
+    int nzmax = 1;
+    for (auto *sl : slots) nzmax = std::max(nzmax, sl->w.nz);
+    G.zc = choose_zc(nzmax, txy_min, h->R);
+    for (auto *sl : slots) sl->zc = G.zc;
+    std::vector<Tile> tl;
+    make_tiles(slots, tile_rows(h, 1), tl);
+    G.nt1 = (int)tl.size();
+    TRY(upload(G.t1, tl, h->st));
+    make_tiles(slots, tile_rows(h, 2), tl);
+    G.nt2 = (int)tl.size();
+    TRY(upload(G.t2, tl, h->st));
+    TRY(upload(G.jobs_f, jf, h->st));
+    TRY(upload(G.jobs_a, ja, h->st));
+    G.src_inj = BCsr{};
+    G.rec_inj = BCsr{};
+    G.rec_gat = BGather{};
+    G.src_gat = BGather{};
+    if (!hs.node.empty()) TRY(upload_csr(h, G, 0, hs, G.src_inj));
+    if (!hr.node.empty()) TRY(upload_csr(h, G, 7, hr, G.rec_inj));
+    if (!gr.idx.empty()) {
+        TRY(upload(G.pb[14], gr.idx, h->st));
+        std::vector<char> packed;   // shot, pos, w packed in one buffer
+        const size_t n = gr.shot.size();
+        packed.resize(n * 8 + gr.w.size() * 4);
+        std::memcpy(packed.data(), gr.shot.data(), n * 4);
+        std::memcpy(packed.data() + n * 4, gr.pos.data(), n * 4);
+        std::memcpy(packed.data() + n * 8, gr.w.data(), gr.w.size() * 4);
+        TRY(upload(G.pb[15], packed, h->st));
+        const char *b = G.pb[15].as<char>();
+        G.rec_gat = BGather{(int)n, gr.nc, (const int *)b, G.pb[14].as<int64_t>(), (const float *)(b + n * 8),
+                            (const int *)(b + n * 4)};
+    }
+    if (!gs.idx.empty()) {
+        // few source points: keep them in the io buffer's tail
+        G.src_gat.n = (int)gs.shot.size();
+        G.src_gat.nc = gs.nc;
+    }
+    // io tables: pointers then counts
+    std::vector<char> io(ns * 4 * sizeof(void *) + ns * 2 * sizeof(int) + gs.idx.size() * 8 + gs.shot.size() * 8 +
+                         gs.w.size() * 4 + 64);
+    char *p = io.data();
+    std::vector<const void *> ptrs(4 * ns, nullptr);
+    std::vector<int> cnt(2 * ns, 0);
+    for (int j = 0; j < ns; ++j) {
+        ptrs[j] = shots[j]->src_wavelet;
+        ptrs[ns + j] = rec_in ? rec_in[j] : nullptr;
+        ptrs[2 * ns + j] = rec_out ? rec_out[j] : nullptr;
+        ptrs[3 * ns + j] = src_out ? src_out[j] : nullptr;
+        cnt[j] = shots[j]->nsrc;
+        cnt[ns + j] = shots[j]->nrec;
+    }
+    size_t off = 0;
+    std::memcpy(p + off, ptrs.data(), ptrs.size() * sizeof(void *));
+    off += ptrs.size() * sizeof(void *);
+    const size_t cnt_off = off;
+    std::memcpy(p + off, cnt.data(), cnt.size() * sizeof(int));
+    off += cnt.size() * sizeof(int);
+    off = (off + 7) / 8 * 8;
+    const size_t gi_off = off;
+    std::memcpy(p + off, gs.idx.data(), gs.idx.size() * 8);
+    off += gs.idx.size() * 8;
+    const size_t gsh_off = off;
+    std::memcpy(p + off, gs.shot.data(), gs.shot.size() * 4);
+    off += gs.shot.size() * 4;
+    const size_t gp_off = off;
+    std::memcpy(p + off, gs.pos.data(), gs.pos.size() * 4);
+    off += gs.pos.size() * 4;
+    const size_t gw_off = off;
+    std::memcpy(p + off, gs.w.data(), gs.w.size() * 4);
+    off += gs.w.size() * 4;
+    io.resize(std::max<size_t>(off, 16));
+    TRY(upload(G.io, io, h->st));
+    const char *d = G.io.as<char>();
+    G.src_data = (const float *const *)d;
+    G.rec_data = (const float *const *)(d + ns * sizeof(void *));
+    G.rec_out = (float *const *)(d + 2 * ns * sizeof(void *));
+    G.src_out = (float *const *)(d + 3 * ns * sizeof(void *));
+    G.nsrc = (const int *)(d + cnt_off);
+    G.nrec = (const int *)(d + cnt_off + ns * sizeof(int));
+    if (G.src_gat.n)
+        G.src_gat = BGather{G.src_gat.n, gs.nc, (const int *)(d + gsh_off), (const int64_t *)(d + gi_off),
+                            (const float *)(d + gw_off), (const int *)(d + gp_off)};
+    return PROP_OK;
+}
+
+void tti_step(prop_s *h, Group &G, bool adj, int mode, int par, int seg_step)
+{
+    const TTIJob *job = adj ? G.jobs_a.as<TTIJob>() : G.jobs_f.as<TTIJob>();
+    {
+        Timed t(h, 0);
+        launch_tti_pass1(h->R, shape_of(h, 1), adj, job, G.t1.as<Tile>(), G.nt1, G.zc, par, h->W, h->st);
+    }
+    {
+        Timed t(h, 1);
+        launch_tti_pass2(h->R, shape_of(h, 2), mode, job, G.t2.as<Tile>(), G.nt2, G.zc, par, h->W,
+                         (float)(1.0 / (h->g.dt * h->g.dt)), seg_step, h->st);
+    }
+}
+
+int check_group(prop_s *h, Group &G, int field, const char *what, int step)
+{
+    HIPCHK(hipGetLastError());
+    for (size_t j = 0; j < G.slots.size(); ++j) TRY(check_finite(h, G.slots[j]->f[field], G.slots[j]->w, what, step, (int)j));
+    return PROP_OK;
+}
+
+float idt2_of(const prop_s *h) { return (float)(1.0 / (h->g.dt * h->g.dt)); }
+
+int tti_forward_group(prop_s *h, Group &G)
+{
+    for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
+    const TTIJob *jf = G.jobs_f.as<TTIJob>();
+    for (int n = 0; n < h->g.nt; ++n) {
+        const int par = n & 1;
+        tti_step(h, G, false, K2_FWD, par, 0);
+        aux_tti_src(G.src_inj, jf, par, G.src_data, G.nsrc, n, idt2_of(h), -1, h->st);
+        aux_tti_gather(G.rec_gat, jf, par, 0, G.rec_out, G.nrec, n, h->st);
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) TRY(check_group(h, G, par ^ 1, "p (forward)", n));
+    }
+    return PROP_OK;
+}
+
+int tti_adjoint_group(prop_s *h, Group &G)
+{
+    for (auto *sl : G.slots) aux_fill(sl->f[11], 6 * sl->plane, 0.f, h->st);   // y (both levels) and w
+    const TTIJob *ja = G.jobs_a.as<TTIJob>();
+    const int N = h->g.nt;
+    for (int k = N; k >= 1; --k) {
+        const int par = (N - k) & 1;
+        tti_step(h, G, true, K2_ADJ, par, 0);
+        aux_tti_rec_adj(G.rec_inj, ja, par, G.rec_data, G.nrec, k - 1, idt2_of(h), 0, 0, h->st);
+        aux_tti_gather(G.src_gat, ja, par, 1, G.src_out, G.nsrc, k - 1, h->st);
+        if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) TRY(check_group(h, G, 11 + (par ^ 1), "y_p (adjoint)", k));
+    }
+    return PROP_OK;
+}
+
+// Checkpoint j of one shot holds (f^c, f^{c-1}) of p and q.  FP32: plain copies.  FP16/BF16: per
+// field the current level and the level difference, each with per-x-row power-of-two scales.
+void ckpt_save(prop_s *h, Slot &sl, char *ck, float *sc, int j, int par_new, int dtype)
+{
+    const size_t bpf = (size_t)sl.w.nx * sl.w.ny * sl.w.nz * (dtype == 0 ? 4 : 2);
+    const int64_t nr = (int64_t)sl.w.ny * sl.w.nz;   // scales per field: one per x-row
+    char *base = ck + (size_t)j * 4 * bpf;
+    float *scl = sc + (size_t)j * 4 * nr;
+    const float *cur[2] = {sl.f[par_new], sl.f[2 + par_new]};
+    const float *prv[2] = {sl.f[par_new ^ 1], sl.f[2 + (par_new ^ 1)]};
+    for (int i = 0; i < 2; ++i) {
+        char *a = base + (size_t)(2 * i) * bpf, *b = a + bpf;
+        if (dtype == 0) {
+            aux_encode_win(cur[i], sl.w, nullptr, 0, a, scl + (2 * i) * nr, h->st);
+            aux_encode_win(prv[i], sl.w, nullptr, 0, b, scl + (2 * i + 1) * nr, h->st);
+        } else {
+            aux_ckpt_pair_encode(cur[i], prv[i], sl.w, dtype, (uint16_t *)a, (uint16_t *)b, scl + (2 * i) * nr,
+                                 scl + (2 * i + 1) * nr, h->st);
+        }
+    }
+}
+
+void ckpt_load(prop_s *h, Slot &sl, const char *ck, const float *sc, int j, int par_cur, int dtype)
+{
+    const size_t bpf = (size_t)sl.w.nx * sl.w.ny * sl.w.nz * (dtype == 0 ? 4 : 2);
+    const int64_t nr = (int64_t)sl.w.ny * sl.w.nz;
+    const char *base = ck + (size_t)j * 4 * bpf;
+    const float *scl = sc + (size_t)j * 4 * nr;
+    float *cur[2] = {sl.f[par_cur], sl.f[2 + par_cur]};
+    float *prv[2] = {sl.f[par_cur ^ 1], sl.f[2 + (par_cur ^ 1)]};
+    for (int i = 0; i < 2; ++i) {
+        const char *a = base + (size_t)(2 * i) * bpf, *b = a + bpf;
+        if (dtype == 0) {
+            aux_decode_win(a, scl, sl.w, 0, cur[i], h->st);
+            aux_decode_win(b, scl, sl.w, 0, prv[i], h->st);
+        } else {
+            aux_ckpt_pair_decode((const uint16_t *)a, (const uint16_t *)b, scl + (2 * i) * nr, scl + (2 * i + 1) * nr,
+                                 sl.w, dtype, cur[i], prv[i], h->st);
+        }
+    }
+}
+
+// Device bytes of one shot's gradient workspace beyond its wavefields (checkpoints, scales, segment).
+size_t grad_bytes(const Slot &sl, int C, int S, int dtype)
+{
+    const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz;
+    return (size_t)C * 4 * pts * (dtype == 0 ? 4 : 2) + (size_t)C * 4 * sl.w.ny * sl.w.nz * 4 +
+           (size_t)S * 2 * sl.plane * 4 + 1024;
+}
+
+// Checkpointed gradient of a group; each shot's window gradient is left in its slot (field 10).
+int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype)
+{
+    const int N = h->g.nt;
+    const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
+    const int C = (N + S - 1) / S;                // checkpoints used (c_j = j S < N)
+    const int ns = (int)G.slots.size();
+    size_t ck_total = 0, sc_total = 0, seg_total = 0;
+    G.ck_off.assign(ns, 0);
+    G.sc_off.assign(ns, 0);
+    G.seg_off.assign(ns, 0);
+    for (int j = 0; j < ns; ++j) {
+        const Slot &sl = *G.slots[j];
+        const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz;
+        G.ck_off[j] = ck_total;
+        ck_total += ((size_t)C * 4 * pts * (dtype == 0 ? 4 : 2) + 255) / 256 * 256;
+        G.sc_off[j] = sc_total;
+        sc_total += (size_t)C * 4 * sl.w.ny * sl.w.nz;
+        G.seg_off[j] = seg_total;
+        seg_total += (size_t)S * 2 * sl.plane;
+    }
+    TRY(h->ckpt.ensure(std::max<size_t>(ck_total, 16)));
+    TRY(h->ckscale.ensure(std::max<size_t>(sc_total * sizeof(float), 16)));
+    TRY(h->seg.ensure(std::max<size_t>(seg_total * sizeof(float), 16)));
+    std::vector<TTIJob> jf, ja;
+    for (int j = 0; j < ns; ++j) {
+        TTIJob a = tti_job(h, *G.slots[j], false), b = tti_job(h, *G.slots[j], true);
+        a.seg = b.seg = h->seg.as<float>() + G.seg_off[j];
+        jf.push_back(a);
+        ja.push_back(b);
+    }
+    TRY(upload(G.jobs_f, jf, h->st));
+    TRY(upload(G.jobs_a, ja, h->st));
+    const TTIJob *djf = G.jobs_f.as<TTIJob>(), *dja = G.jobs_a.as<TTIJob>();
+    const float idt2 = idt2_of(h);
+    char *ck = h->ckpt.as<char>();
+    float *sc = h->ckscale.as<float>();
+
+    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state
+    for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
+    for (int n = 0; n < N; ++n) {
+        const int par = n & 1;
+        tti_step(h, G, false, K2_FWD, par, 0);
+        aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
+        if ((n + 1) % S == 0 && (n + 1) / S < C)
+            for (int j = 0; j < ns; ++j) ckpt_save(h, *G.slots[j], ck + G.ck_off[j], sc + G.sc_off[j], (n + 1) / S, par ^ 1, dtype);
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) TRY(check_group(h, G, par ^ 1, "p (gradient forward)", n));
+    }
+    // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
+    for (auto *sl : G.slots) {
+        aux_fill(sl->f[10], sl->plane, 0.f, h->st);          // gradient accumulator
+        aux_fill(sl->f[11], 6 * sl->plane, 0.f, h->st);      // adjoint state and w
+    }
+    for (int j = C - 1; j >= 0; --j) {
+        const int start = j * S, end = std::min(N, (j + 1) * S);
+        const int par0 = start & 1;
+        for (int i = 0; i < ns; ++i) {
+            Slot &sl = *G.slots[i];
+            if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
+            else ckpt_load(h, sl, ck + G.ck_off[i], sc + G.sc_off[i], j, par0, dtype);
+        }
+        for (int n = start; n < end; ++n) {
+            const int par = n & 1;
+            tti_step(h, G, false, K2_FWD_STORE, par, n - start);
+            aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, n - start, h->st);
+        }
+        for (int k = end; k > start; --k) {
+            const int par = (N - k) & 1;
+            tti_step(h, G, true, K2_ADJ_IC, par, k - 1 - start);
+            aux_tti_rec_adj(G.rec_inj, dja, par, G.rec_data, G.nrec, k - 1, idt2, 1, k - 1 - start, h->st);
+        }
+        for (int i = 0; i < ns; ++i) {
+            TRY(check_finite(h, G.slots[i]->f[par0], G.slots[i]->w, "restored p", start, i));
+            TRY(check_finite(h, G.slots[i]->f[11 + (((N - start - 1) & 1) ^ 1)], G.slots[i]->w, "y_p", start, i));
+        }
+        TRY(check_group(h, G, 10, "gradient", start));
     }
     return PROP_OK;
 }
 
 int tti_forward(prop_s *h, const prop_shot *s, float *rec_out)
 {
-    Slot &sl = h->slot;
-    TRY(prepare_shot(h, sl, s, true, true, false, false));
-    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
-    if (s->nrec > 0 && !rec_out) return fail(PROP_EINVAL, "rec_out is NULL");
-    aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
-    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
-    const TTIJob *job = sl.job_fwd.as<TTIJob>();
-    for (int n = 0; n < h->g.nt; ++n) {
-        const int par = n & 1;
-        tti_step(h, sl, job, false, K2_FWD, par, 0);
-        float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
-        if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, h->model.p[0], pn, qn,
-                                    nullptr, nullptr, h->st);
-        if (s->nrec) aux_gather(sl.rec_gat.gat, pn, nullptr, nullptr, 1.f, rec_out + (size_t)n * s->nrec, h->st);
-        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) {
-            HIPCHK(hipGetLastError());
-            TRY(check_finite(h, pn, sl.w));
-        }
-    }
+    Group G;
+    float *outs[1] = {rec_out};
+    TRY(build_group(h, G, {s}, {&h->slot}, true, true, false, false, nullptr, outs, nullptr));
+    TRY(tti_forward_group(h, G));
     h->last_state = 1;
     return PROP_OK;
 }
 
 int tti_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_out)
 {
-    Slot &sl = h->slot;
-    TRY(prepare_shot(h, sl, s, false, false, true, true));
-    if (s->nrec > 0 && !rec_in) return fail(PROP_EINVAL, "rec_in is NULL");
-    if (s->nsrc > 0 && !src_out) return fail(PROP_EINVAL, "src_out is NULL");
-    const int N = h->g.nt;
-    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
-    aux_fill(sl.f[11], 6 * sl.plane, 0.f, h->st);      // y (both levels) and w
-    const TTIJob *job = sl.job_adj.as<TTIJob>();
-    for (int k = N; k >= 1; --k) {
-        const int par = (N - k) & 1;
-        tti_step(h, sl, job, true, K2_ADJ, par, 0);
-        float *yp = sl.f[11 + (par ^ 1)], *yq = sl.f[13 + (par ^ 1)];
-        if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, rec_in + (size_t)(k - 1) * s->nrec, idt2, h->model.p[0],
-                                        h->c[0], h->c[1], yp, sl.f[15], sl.f[16], nullptr, nullptr, h->st);
-        if (s->nsrc) aux_gather(sl.src_gat.gat, yp, yq, nullptr, 1.f, src_out + (size_t)(k - 1) * s->nsrc, h->st);
-        if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) {
-            HIPCHK(hipGetLastError());
-            TRY(check_finite(h, yp, sl.w));
-        }
-    }
+    Group G;
+    const float *ins[1] = {rec_in};
+    float *outs[1] = {src_out};
+    TRY(build_group(h, G, {s}, {&h->slot}, false, false, true, true, ins, nullptr, outs));
+    TRY(tti_adjoint_group(h, G));
     h->last_state = 2;
     return PROP_OK;
 }
 
-// Checkpoint j holds (f^c, f^{c-1}) of p and q.  FP32: plain copies.  FP16/BF16: per field the
-// current level and the level difference, each with per-x-row power-of-two scales.
-void ckpt_save(prop_s *h, Slot &sl, int j, int par_new, int dtype, size_t bytes_per_field)
-{
-    char *base = h->ckpt.as<char>() + (size_t)j * 4 * bytes_per_field;
-    const int64_t nz = (int64_t)sl.w.ny * sl.w.nz;   // scales per field: one per x-row
-    float *scl = h->ckscale.as<float>() + (size_t)j * 4 * nz;
-    const float *cur[2] = {sl.f[par_new], sl.f[2 + par_new]};
-    const float *prv[2] = {sl.f[par_new ^ 1], sl.f[2 + (par_new ^ 1)]};
-    for (int i = 0; i < 2; ++i) {
-        char *a = base + (size_t)(2 * i) * bytes_per_field, *b = a + bytes_per_field;
-        if (dtype == 0) {
-            aux_encode_win(cur[i], sl.w, nullptr, 0, a, scl + (2 * i) * nz, h->st);
-            aux_encode_win(prv[i], sl.w, nullptr, 0, b, scl + (2 * i + 1) * nz, h->st);
-        } else {
-            aux_ckpt_pair_encode(cur[i], prv[i], sl.w, dtype, (uint16_t *)a, (uint16_t *)b, scl + (2 * i) * nz,
-                                 scl + (2 * i + 1) * nz, h->st);
-        }
-    }
-}
-
-void ckpt_load(prop_s *h, Slot &sl, int j, int par_cur, int dtype, size_t bytes_per_field)
-{
-    const char *base = h->ckpt.as<char>() + (size_t)j * 4 * bytes_per_field;
-    const int64_t nz = (int64_t)sl.w.ny * sl.w.nz;
-    const float *scl = h->ckscale.as<float>() + (size_t)j * 4 * nz;
-    float *cur[2] = {sl.f[par_cur], sl.f[2 + par_cur]};
-    float *prv[2] = {sl.f[par_cur ^ 1], sl.f[2 + (par_cur ^ 1)]};
-    for (int i = 0; i < 2; ++i) {
-        const char *a = base + (size_t)(2 * i) * bytes_per_field, *b = a + bytes_per_field;
-        if (dtype == 0) {
-            aux_decode_win(a, scl, sl.w, 0, cur[i], h->st);
-            aux_decode_win(b, scl, sl.w, 0, prv[i], h->st);
-        } else {
-            aux_ckpt_pair_decode((const uint16_t *)a, (const uint16_t *)b, scl + (2 * i) * nz, scl + (2 * i + 1) * nz,
-                                 sl.w, dtype, cur[i], prv[i], h->st);
-        }
-    }
-}
-
 int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *grad_m, int n_ckpt, int dtype)
 {
-    Slot &sl = h->slot;
     if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
     if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
     if (!grad_m) return fail(PROP_EINVAL, "grad_m is NULL");
-    TRY(prepare_shot(h, sl, s, true, false, true, false));
-    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
-    if (s->nrec > 0 && !residual) return fail(PROP_EINVAL, "residual is NULL");
-    const int N = h->g.nt;
-    const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
-    const int C = (N + S - 1) / S;                // checkpoints actually used (c_j = j S < N)
-    const int64_t pts = (int64_t)sl.w.nx * sl.w.ny * sl.w.nz;
-    const size_t bpf = (size_t)pts * (dtype == 0 ? 4 : 2);
-    TRY(h->ckpt.ensure(std::max<size_t>(1, (size_t)C * 4 * bpf)));
-    TRY(h->ckscale.ensure((size_t)C * 4 * sl.w.ny * sl.w.nz * sizeof(float)));
-    TRY(h->seg.ensure((size_t)S * 2 * sl.plane * sizeof(float)));
-    TTIJob jf = tti_job(h, sl, false), ja = tti_job(h, sl, true);
-    jf.seg = ja.seg = h->seg.as<float>();
-    TRY(upload_one(sl.job_fwd, jf, h->st));
-    TRY(upload_one(sl.job_adj, ja, h->st));
-    const TTIJob *dj_f = sl.job_fwd.as<TTIJob>(), *dj_a = sl.job_adj.as<TTIJob>();
-    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
-    const float *m = h->model.p[0];
+    Group G;
+    const float *ins[1] = {residual};
+    TRY(build_group(h, G, {s}, {&h->slot}, true, false, true, false, ins, nullptr, nullptr));
+    TRY(tti_gradient_group(h, G, n_ckpt, dtype));
+    aux_copy_out(h->slot.f[10], h->slot.w, grad_m, h->st);
+    HIPCHK(hipGetLastError());
+    h->last_state = 0;
+    return PROP_OK;
+}
 
-    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state
-    aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
-    for (int n = 0; n < N; ++n) {
-        const int par = n & 1;
-        tti_step(h, sl, dj_f, false, K2_FWD, par, 0);
-        float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
-        if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, m, pn, qn, nullptr,
-                                    nullptr, h->st);
-        if ((n + 1) % S == 0 && (n + 1) / S < C) ckpt_save(h, sl, (n + 1) / S, par ^ 1, dtype, bpf);
-        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
-            HIPCHK(hipGetLastError());
-            TRY(check_finite(h, pn, sl.w));
+// Shots per group: greedy in shot order within a budget of the free device memory.
+int plan_groups(prop_s *h, int nshot, const prop_shot *shots, bool grad, int n_ckpt, int dtype,
+                std::vector<std::pair<int, int>> &groups)
+{
+    size_t freeb = 0, totalb = 0;
+    HIPCHK(hipMemGetInfo(&freeb, &totalb));
+    const int64_t budget_env = env_int("PROP_BATCH_MB", 0);
+    // memory already held by the batch workspaces is reusable
+    size_t held = h->ckpt.bytes + h->ckscale.bytes + h->seg.bytes;
+    for (auto &sl : h->bslots) held += sl->fields.bytes;
+    size_t budget = budget_env > 0 ? (size_t)budget_env << 20 : (size_t)((freeb + held) * 0.85);
+    const int N = h->g.nt;
+    const int S = (N + std::max(1, n_ckpt) - 1) / std::max(1, n_ckpt);
+    const int C = (N + S - 1) / S;
+    groups.clear();
+    int start = 0;
+    size_t used = 0;
+    for (int i = 0; i < nshot; ++i) {
+        int64_t o[3], n[3];
+        TRY(shot_window(h, &shots[i], o, n));
+        const size_t sx = (n[0] + 63) / 64 * 64, plane = sx * n[1] * n[2];
+        size_t need = 17 * plane * 4 + 4096;
+        if (grad) {
+            Slot tmp;
+            tmp.w.nx = (int)n[0];
+            tmp.w.ny = (int)n[1];
+            tmp.w.nz = (int)n[2];
+            tmp.plane = plane;
+            need += grad_bytes(tmp, C, S, dtype);
         }
+        if (i > start && used + need > budget) {
+            groups.push_back({start, i});
+            start = i;
+            used = 0;
+        }
+        used += need;
     }
-    // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
-    aux_fill(sl.f[10], sl.plane, 0.f, h->st);           // gradient accumulator
-    aux_fill(sl.f[11], 6 * sl.plane, 0.f, h->st);       // adjoint state and w
-    for (int j = C - 1; j >= 0; --j) {
-        const int start = j * S, end = std::min(N, (j + 1) * S);
-        const int par0 = start & 1;
-        if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
-        else ckpt_load(h, sl, j, par0, dtype, bpf);
-        for (int n = start; n < end; ++n) {
-            const int par = n & 1;
-            tti_step(h, sl, dj_f, false, K2_FWD_STORE, par, n - start);
-            float *pn = sl.f[par ^ 1], *qn = sl.f[2 + (par ^ 1)];
-            float *sp = h->seg.as<float>() + (size_t)(n - start) * 2 * sl.plane;
-            if (s->nsrc) aux_tti_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, idt2, m, pn, qn, sp,
-                                        sp + sl.plane, h->st);
+    if (nshot > start) groups.push_back({start, nshot});
+    return PROP_OK;
+}
+
+int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_out, const float *const *residual,
+                double *grad_global, int n_ckpt, int dtype, bool grad)
+{
+    if (nshot < 1 || !shots) return fail(PROP_EINVAL, "need at least one shot");
+    if (grad) {
+        if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
+        if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
+        if (!grad_global) return fail(PROP_EINVAL, "grad_global is NULL");
+        if (!residual) return fail(PROP_EINVAL, "residual is NULL");
+    } else if (!rec_out) {
+        return fail(PROP_EINVAL, "rec_out is NULL");
+    }
+    std::vector<std::pair<int, int>> groups;
+    TRY(plan_groups(h, nshot, shots, grad, n_ckpt, dtype, groups));
+    h->last_groups = (int)groups.size();
+    for (auto &gr : groups) {
+        const int ns = gr.second - gr.first;
+        while ((int)h->bslots.size() < ns) h->bslots.emplace_back(new Slot());
+        std::vector<const prop_shot *> sh;
+        std::vector<Slot *> sl;
+        for (int i = 0; i < ns; ++i) {
+            sh.push_back(&shots[gr.first + i]);
+            sl.push_back(h->bslots[i].get());
         }
-        for (int k = end; k > start; --k) {
-            const int par = (N - k) & 1;
-            tti_step(h, sl, dj_a, true, K2_ADJ_IC, par, k - 1 - start);
-            float *yp = sl.f[11 + (par ^ 1)];
-            const float *fpk = h->seg.as<float>() + (size_t)(k - 1 - start) * 2 * sl.plane;
-            if (s->nrec) aux_tti_inject_adj(sl.rec_inj.csr, residual + (size_t)(k - 1) * s->nrec, idt2, m, h->c[0],
-                                            h->c[1], yp, sl.f[15], sl.f[16], sl.f[10], fpk, h->st);
+        Group G;
+        if (grad) {
+            TRY(build_group(h, G, sh, sl, true, false, true, false, residual + gr.first, nullptr, nullptr));
+            TRY(tti_gradient_group(h, G, n_ckpt, dtype));
+            for (int i = 0; i < ns; ++i) aux_accum_f64(sl[i]->f[10], sl[i]->w, grad_global, h->st);  // shot order
+        } else {
+            TRY(build_group(h, G, sh, sl, true, true, false, false, nullptr, rec_out + gr.first, nullptr));
+            TRY(tti_forward_group(h, G));
         }
         HIPCHK(hipGetLastError());
-        TRY(check_finite(h, sl.f[10], sl.w));
+        HIPCHK(hipStreamSynchronize(h->st));   // group buffers are reused by the next group
     }
-    aux_copy_out(sl.f[10], sl.w, grad_m, h->st);
-    HIPCHK(hipGetLastError());
     h->last_state = 0;
     return PROP_OK;
 }
@@ -1016,19 +1369,19 @@ int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float 
 
 int prop_forward_batched(prop_t h, int32_t nshot, const prop_shot *shots, float *const *rec_out)
 {
-    (void)nshot, (void)shots, (void)rec_out;
     g_err.clear();
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
-    return fail(PROP_ESTATE, "batched forward not built yet");
+    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "batched calls are provided for PROP_TTI");
+    return tti_batched(h, nshot, shots, rec_out, nullptr, nullptr, 0, 0, false);
 }
 
 int prop_gradient_batched(prop_t h, int32_t nshot, const prop_shot *shots, const float *const *residual,
                           double *grad_global, int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype)
 {
-    (void)nshot, (void)shots, (void)residual, (void)grad_global, (void)n_ckpt, (void)ckpt_dtype;
     g_err.clear();
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
-    return fail(PROP_ESTATE, "batched gradient not built yet");
+    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "batched calls are provided for PROP_TTI");
+    return tti_batched(h, nshot, shots, nullptr, residual, grad_global, n_ckpt, (int)ckpt_dtype, true);
 }
 
 int prop_read_state(prop_t h, int32_t field, float *out)

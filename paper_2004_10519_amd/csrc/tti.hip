@@ -20,25 +20,18 @@
 
 namespace {
 
-// rows per thread: pass 1 holds two rows of queues; pass 2 (more live values per point) one.
-template <int R>
-constexpr int ny1_of()
-{
-    return R <= 6 ? 2 : 1;
-}
-template <int R>
-constexpr int ny2_of()
-{
-    return 1;
-}
+// Tile shapes (threads in y x rows per thread) selectable per pass at run time:
+//   pass 1: 0 -> 8 x 2 (TY 16),  1 -> 16 x 2 (TY 32);   pass 2: 0 -> 8 x 1 (TY 8),  1 -> 16 x 1 (TY 16)
+// Rows per thread drop to 1 for the widest stencils to keep the register queues in budget.
+template <int R> constexpr int ny1_of() { return R <= 6 ? 2 : 1; }
 
-template <int R, int NY, bool ADJ>
-__global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict__ jobs,
+template <int R, int NY, int BY, bool ADJ>
+__global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W)
 {
-    constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
+    constexpr int TY = BY * NY, Q = 2 * R + 1, NT = PROP_TX * BY;
     using P = Plane<R, TY>;
-    using H = Halo<R, TY>;
+    using H = Halo<R, TY, NT>;
     __shared__ float Lp[2][P::SIZE], Lq[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
@@ -72,7 +65,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NXI) H::xitem(i, yy, xx);
             hxu[k] = i < H::NXI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
@@ -80,7 +73,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NYH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
             hyu[k] = i < H::NYI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
@@ -105,7 +98,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             if (i < H::NXI) {
                 int yy, xx;
                 H::xitem(i, yy, xx);
@@ -115,7 +108,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NYH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             if (i < H::NYI) {
                 int yy, xx;
                 H::yitem(i, yy, xx);
@@ -159,15 +152,15 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass1(const TTIJob *__restrict
     }
 }
 
-template <int R, int NY, int MODE>
-__global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict__ jobs,
+template <int R, int NY, int BY, int MODE>
+__global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W,
                                                        float idt2, int seg_step)
 {
-    constexpr int TY = PROP_BY * NY, Q = 2 * R + 1;
+    constexpr int TY = BY * NY, Q = 2 * R + 1, NT = PROP_TX * BY;
     constexpr bool ADJ = (MODE == K2_ADJ || MODE == K2_ADJ_IC);
     using P = Plane<R, TY>;
-    using H = Halo<R, TY>;
+    using H = Halo<R, TY, NT>;
     __shared__ float Ltx[2][P::SIZE], Lty[2][P::SIZE], Lsx[2][P::SIZE], Lsy[2][P::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
@@ -213,7 +206,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NXI) H::xitem(i, yy, xx);
             hxt[k] = i < H::NXI ? ld(T0, x0 + xx, y0 + yy, z) : 0.f;
@@ -221,7 +214,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NYH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
             hyt[k] = i < H::NYI ? ld(T1, x0 + xx, y0 + yy, z) : 0.f;
@@ -249,7 +242,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             if (i < H::NXI) {
                 int yy, xx;
                 H::xitem(i, yy, xx);
@@ -259,7 +252,7 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict
         }
 #pragma unroll
         for (int k = 0; k < H::NYH; ++k) {
-            const int i = tid + k * PROP_NT;
+            const int i = tid + k * NT;
             if (i < H::NYI) {
                 int yy, xx;
                 H::yitem(i, yy, xx);
@@ -334,43 +327,60 @@ __global__ __launch_bounds__(PROP_NT, 4) void tti_pass2(const TTIJob *__restrict
     }
 }
 
-template <int R>
-void p1_dispatch(bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
-                 const Weights &W, hipStream_t st)
+template <int R, int BY>
+void p1_launch(bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
+               hipStream_t st)
 {
     constexpr int NY = ny1_of<R>();
-    dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
-    if (adj) hipLaunchKernelGGL((tti_pass1<R, NY, true>), grd, blk, 0, st, jobs, tiles, zc, par, W);
-    else     hipLaunchKernelGGL((tti_pass1<R, NY, false>), grd, blk, 0, st, jobs, tiles, zc, par, W);
+    dim3 blk(PROP_TX, BY), grd(ntiles);
+    if (adj) hipLaunchKernelGGL((tti_pass1<R, NY, BY, true>), grd, blk, 0, st, jobs, tiles, zc, par, W);
+    else     hipLaunchKernelGGL((tti_pass1<R, NY, BY, false>), grd, blk, 0, st, jobs, tiles, zc, par, W);
 }
 
 template <int R>
-void p2_dispatch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
-                 const Weights &W, float idt2, int seg_step, hipStream_t st)
+void p1_dispatch(int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+                 const Weights &W, hipStream_t st)
 {
-    constexpr int NY = ny2_of<R>();
-    dim3 blk(PROP_TX, PROP_BY), grd(ntiles);
+    if (shape == 1) p1_launch<R, 16>(adj, jobs, tiles, ntiles, zc, par, W, st);
+    else            p1_launch<R, 8>(adj, jobs, tiles, ntiles, zc, par, W, st);
+}
+
+template <int R, int BY>
+void p2_launch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
+               float idt2, int seg_step, hipStream_t st)
+{
+    dim3 blk(PROP_TX, BY), grd(ntiles);
     switch (mode) {
     case K2_FWD:
-        hipLaunchKernelGGL((tti_pass2<R, NY, K2_FWD>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
         break;
     case K2_FWD_STORE:
-        hipLaunchKernelGGL((tti_pass2<R, NY, K2_FWD_STORE>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD_STORE>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
+                           seg_step);
         break;
     case K2_ADJ:
-        hipLaunchKernelGGL((tti_pass2<R, NY, K2_ADJ>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
         break;
     default:
-        hipLaunchKernelGGL((tti_pass2<R, NY, K2_ADJ_IC>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ_IC>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
         break;
     }
 }
 
+template <int R>
+void p2_dispatch(int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+                 const Weights &W, float idt2, int seg_step, hipStream_t st)
+{
+    if (shape == 1) p2_launch<R, 16>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+    else            p2_launch<R, 8>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+}
+
 }  // namespace
 
-int tti_rows_per_thread(int R, int pass)
+int tti_tile_rows(int R, int pass, int shape)
 {
-    return pass == 1 ? (R <= 6 ? 2 : 1) : 1;
+    const int by = shape == 1 ? 16 : 8;
+    return pass == 1 ? by * (R <= 6 ? 2 : 1) : by;
 }
 
 #define R_SWITCH(FN, ...)                   \
@@ -385,14 +395,14 @@ int tti_rows_per_thread(int R, int pass)
     default: FN<8>(__VA_ARGS__); break;     \
     }
 
-void launch_tti_pass1(int R, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+void launch_tti_pass1(int R, int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                       const Weights &W, hipStream_t st)
 {
-    R_SWITCH(p1_dispatch, adj, jobs, tiles, ntiles, zc, par, W, st)
+    R_SWITCH(p1_dispatch, shape, adj, jobs, tiles, ntiles, zc, par, W, st)
 }
 
-void launch_tti_pass2(int R, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+void launch_tti_pass2(int R, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                       const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
-    R_SWITCH(p2_dispatch, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st)
+    R_SWITCH(p2_dispatch, shape, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st)
 }

@@ -1,0 +1,102 @@
+"""Batched shots (shot groups on uneven windows of one model) against plain per-shot calls, and the
+64^3 gradient against the FP64 checker's stored gradient (full 2000 steps)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def prop():
+    from paper_2004_10519_amd import prop as P
+    P.lib()
+    return P
+
+
+def _setup(prop, nt=120):
+    from paper_2004_10519_amd import inputs
+    shape, h, so, nbl = (100, 80, 60), (10.0, 10.0, 10.0), 8, 6
+    mdl = inputs.tti_model(shape, nbl, 31)
+    arrs = [inputs.slowness_squared(mdl["vp"]), mdl["eps"], mdl["delta"], mdl["theta"], mdl["phi"]]
+    dt = 8e-4
+    g = prop.Grid(shape, h, space_order=so, nbl=nbl, dt=dt, nt=nt, v_ref=1500.0)
+    mt = [dev(a) for a in arrs]
+    p = prop.Propagator(prop.TTI, g, mt)
+    p._keep_model = mt
+    wins = [((3, 5, 0), (70, 41, 50)), ((20, 0, 4), (80, 77, 56)), ((0, 30, 0), (37, 50, 60))]
+    shots = []
+    for k, (o, n) in enumerate(wins):
+        cx, cy = h[0] * (o[0] + n[0] / 2 + 0.3), h[1] * (o[1] + n[1] / 2 - 0.2)
+        src = np.array([[cx, cy, h[2] * (o[2] + nbl + 3.3)]], np.float32)
+        xs = h[0] * (o[0] + np.linspace(nbl, n[0] - 1 - nbl, 9))
+        ys = h[1] * (o[1] + np.linspace(nbl, n[1] - 1 - nbl, 7))
+        X, Y = np.meshgrid(xs, ys)
+        rec = np.stack([X.ravel(), Y.ravel(), np.full(X.size, h[2] * (o[2] + nbl + 2.0))], axis=1).astype(np.float32)
+        wav = dev(inputs.ricker(20.0 + 3 * k, dt, nt)[:, None])
+        shots.append(prop.Shot(src, wav, rec, win_origin=o, win_shape=n))
+    return p, shots
+
+
+def test_batched_forward_equals_plain(prop):
+    p, shots = _setup(prop)
+    plain = [host(p.forward(s)).copy() for s in shots]
+    outs = p.forward_batched(shots)
+    for a, b in zip(outs, plain):
+        assert np.array_equal(host(a), b)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_batched_gradient_equals_plain_sum(prop, dtype):
+    p, shots = _setup(prop, nt=100)
+    rng = np.random.default_rng(7)
+    res = [dev(rng.standard_normal((100, s.nrec))) for s in shots]
+    total = np.zeros(p.grid.arr_shape)
+    for s, r in zip(shots, res):
+        g = host(p.gradient(s, r, n_ckpt=5, ckpt_dtype=dtype)).astype(np.float64)
+        (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
+        total[oz:oz + nz, oy:oy + ny, ox:ox + nx] += g
+    gg = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.gradient_batched(shots, res, gg, n_ckpt=5, ckpt_dtype=dtype)
+    assert np.array_equal(host(gg), total)
+
+
+def test_batched_groups_split_by_memory_budget(prop, monkeypatch):
+    """A tiny budget forces one shot per group; results do not change."""
+    p, shots = _setup(prop, nt=60)
+    rng = np.random.default_rng(8)
+    res = [dev(rng.standard_normal((60, s.nrec))) for s in shots]
+    g1 = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.gradient_batched(shots, res, g1, n_ckpt=4, ckpt_dtype="f16")
+    monkeypatch.setenv("PROP_BATCH_MB", "1")
+    g2 = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.gradient_batched(shots, res, g2, n_ckpt=4, ckpt_dtype="f16")
+    assert np.array_equal(host(g1), host(g2))
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 1e-2)])
+def test_gradient_64cubed_vs_checker(prop, dtype, tol):
+    """64^3, so 8, 2000 steps, 48 checkpoints: GPU gradient vs the FP64 checker's stored gradient."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("mk", os.path.join(HERE, "golden", "make_ttigrad64.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    gold = np.load(os.path.join(HERE, "golden", "ttigrad64.npz"))["grad"].astype(np.float64)
+    w, m0, res = mk.case()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    mt = [dev(m0[k]) for k in ("m", "eps", "delta", "theta", "phi")]
+    p = prop.Propagator(prop.TTI, g, mt)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=48, ckpt_dtype=dtype)).astype(np.float64)
+    err = rel_l2(gg, gold)
+    # also without the singular neighbourhoods of the source and the receiver plane
+    mask = np.ones_like(gold, bool)
+    mask[w.nbl + 4 - 5:w.nbl + 4 + 6] = False
+    err_masked = rel_l2(gg[mask], gold[mask])
+    print(f"64^3 gradient rel-L2 vs FP64 ({dtype} checkpoints): {err:.3e} (masked {err_masked:.3e})")
+    assert err <= tol

@@ -131,6 +131,12 @@ def test_codec_bit_exact(prop, orc):
         assert np.array_equal(dec, orc.ckpt_decode(s_o, c_o, dt))
     codes, scale = prop.ckpt_encode(dev(np.zeros(10, np.float32)), "bf16")
     assert float(host(scale)[0]) == 1.0 and not host(codes).any()
+    sub = np.array([3e-41, -1e-40, 0.0, 2e-45], np.float32)       # subnormal maximum
+    for dt in ("f16", "bf16"):
+        codes, scale = prop.ckpt_encode(dev(sub), dt)
+        s_o, c_o = orc.ckpt_encode(sub, dt)
+        assert float(host(scale)[0]) == s_o == 2.0 ** -126
+        assert np.array_equal(host(codes).view(np.uint16), c_o)
 
 
 def test_dot_f64(prop):
