@@ -198,6 +198,50 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
     return out
 
 
+def measure_batched(torch, prop, nt, nshot):
+    """Batched checkpointed gradient of many shots vs the plain per-shot baseline (FP32 checkpoints,
+    one call per shot, per-shot host FP64 sum)."""
+    from paper_2004_10519_amd import configs
+    w, geo = configs.batch_64(nshot=nshot, nt=nt)
+    log(f"[bench] generating {w.name} model {w.shape} ({nshot} shots) ...")
+    arrs = w.model_list()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    dev_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
+    del arrs
+    p = prop.Propagator(prop.TTI, g, dev_)
+    wav = torch.from_numpy(np.ascontiguousarray(w.wavelet()[:, :1])).cuda()
+    shots = [prop.Shot(src, wav, rec, win_origin=o, win_shape=n) for (o, n, src, rec) in geo]
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    res = [torch.randn((w.nt, s.nrec), device="cuda", generator=gen) for s in shots]
+    pts = sum(int(np.prod(n)) for (_, n, _, _) in geo)
+    # batched (FP16 checkpoints, device FP64 sum)
+    gb = torch.zeros(w.arr_shape, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    p.gradient_batched(shots, res, gb, n_ckpt=48, ckpt_dtype="f16")
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    # plain: sequential per-shot calls, FP32 checkpoints, host FP64 sum
+    gp = np.zeros(w.arr_shape, dtype=np.float64)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, r in zip(shots, res):
+        gw = p.gradient(s, r, n_ckpt=48, ckpt_dtype="f32").cpu().numpy()
+        (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
+        gp[oz:oz + nz, oy:oy + ny, ox:ox + nx] += gw
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    gbh = gb.cpu().numpy()
+    err = float(np.linalg.norm(gbh - gp) / np.linalg.norm(gp))
+    p.close()
+    return {"workload": w.name, "model": list(w.shape), "shots": nshot, "window_points": pts, "time_steps": w.nt,
+            "space_order": w.space_order, "checkpoints": 48,
+            "batched": {"s": round(tb, 2), "GPts/s": round(pts * w.nt / tb / 1e9, 3), "checkpoint_dtype": "f16",
+                        "method_hbm_frac_156B": round(pts * w.nt / tb / 1e9 * 156 / HBM_PEAK_GBS, 4)},
+            "plain": {"s": round(tp, 2), "GPts/s": round(pts * w.nt / tp / 1e9, 3), "checkpoint_dtype": "f32"},
+            "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +250,8 @@ def main():
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps (short runs)")
     ap.add_argument("--size", type=int, default=512)
     ap.add_argument("--only-main", action="store_true", help="skip the adjoint, elastic and gradient paths")
+    ap.add_argument("--batched", type=int, default=0, metavar="NSHOT",
+                    help="also run the batched-vs-plain gradient comparison with NSHOT shots (64 = full)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -287,6 +333,9 @@ def main():
         paths["tti_gradient"] = measure_gradient(torch, prop, nt_gr)
         torch.cuda.empty_cache()
         out["paths"] = paths
+    if args.batched:
+        out.setdefault("paths", {})["batched_vs_plain"] = measure_batched(torch, prop, args.nt or 1500, args.batched)
+        torch.cuda.empty_cache()
 
     if not args.no_cpu:
         log("[bench] CPU baseline (FP64 checker) ...")

@@ -122,3 +122,30 @@ def ttigrad_starting_model(w: Workload) -> dict:
     vp0 = inputs.smooth(mdl["vp"], 10.0).astype(np.float32)
     return {"m": inputs.slowness_squared(vp0), "eps": mdl["eps"], "delta": mdl["delta"], "theta": mdl["theta"],
             "phi": mdl["phi"]}
+
+
+def batch_64(nshot: int = 64, nt: int = 1500, shape=(1024, 1024, 512), seed_model: int = 4, seed_win: int = 5):
+    """64 TTI shots on uneven windows of one seeded model.
+
+    Windows: edges uniform in [128, 320] per axis (seed 5), x-y origin uniform within the model, z
+    origin 0; 32-point absorbing layers inside each window.  Per shot: source at the window centre,
+    4 points below the layer; receivers on every 4th node of the window interior, 2 points below
+    the layer.  Returns (model Workload, list of (origin, shape, src_xyz, rec_xyz)).
+    """
+    h, nbl = (12.5, 12.5, 12.5), 32
+    w = Workload("batch_64", "tti", tuple(shape), h, 8, nt, nbl, 1.116e-3, seed_model, 15.0,
+                 np.zeros((1, 3), np.float32), np.zeros((0, 3), np.float32), v_ref=1500.0)
+    rng = np.random.Generator(np.random.PCG64(seed_win))
+    shots = []
+    for _ in range(nshot):
+        n = [int(rng.integers(128, 321)) for _ in range(3)]
+        n = [min(n[a], shape[a]) for a in range(3)]
+        o = [int(rng.integers(0, shape[0] - n[0] + 1)), int(rng.integers(0, shape[1] - n[1] + 1)), 0]
+        src = np.array([[h[0] * (o[0] + (n[0] - 1) / 2 + 0.3), h[1] * (o[1] + (n[1] - 1) / 2 + 0.3),
+                         h[2] * (nbl + 4)]], np.float32)
+        xs = h[0] * (o[0] + np.arange(nbl, n[0] - nbl, 4))
+        ys = h[1] * (o[1] + np.arange(nbl, n[1] - nbl, 4))
+        X, Y = np.meshgrid(xs, ys)
+        rec = np.stack([X.ravel(), Y.ravel(), np.full(X.size, h[2] * (nbl + 2))], axis=1).astype(np.float32)
+        shots.append((tuple(o), tuple(n), src, rec))
+    return w, shots
