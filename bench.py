@@ -198,13 +198,31 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
     return out
 
 
+def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
+    """Device-to-device copy rate (bytes read + written per second) of torch's copy kernel on 2 GiB."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measure_batched(torch, prop, nt, nshot):
     """Batched checkpointed gradient of many shots vs the plain per-shot baseline (FP32 checkpoints,
     one call per shot, per-shot host FP64 sum)."""
     from paper_2004_10519_amd import configs
     w, geo = configs.batch_64(nshot=nshot, nt=nt)
     log(f"[bench] generating {w.name} model {w.shape} ({nshot} shots) ...")
-    arrs = w.model_list()
+    arrs = w.model_list(progress=lambda msg: log(f"[bench]   model: {msg}"))
     g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
     dev_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
     del arrs
@@ -214,21 +232,28 @@ def measure_batched(torch, prop, nt, nshot):
     gen = torch.Generator(device="cuda").manual_seed(0)
     res = [torch.randn((w.nt, s.nrec), device="cuda", generator=gen) for s in shots]
     pts = sum(int(np.prod(n)) for (_, n, _, _) in geo)
-    # batched (FP16 checkpoints, device FP64 sum)
+    log(f"[bench] {nshot} shots, {pts / 1e6:.1f} M window points, {w.nt} steps")
+    # batched (FP16 checkpoints, device FP64 sum); issued in calls of up to 16 shots so that
+    # progress is reported; each call adds its shots into gb in shot order
+    chunk = 16
     gb = torch.zeros(w.arr_shape, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    p.gradient_batched(shots, res, gb, n_ckpt=48, ckpt_dtype="f16")
-    torch.cuda.synchronize()
+    for c in range(0, nshot, chunk):
+        p.gradient_batched(shots[c:c + chunk], res[c:c + chunk], gb, n_ckpt=48, ckpt_dtype="f16")
+        torch.cuda.synchronize()
+        log(f"[bench]   batched: {min(c + chunk, nshot)}/{nshot} shots, {time.perf_counter() - t0:.1f} s")
     tb = time.perf_counter() - t0
     # plain: sequential per-shot calls, FP32 checkpoints, host FP64 sum
     gp = np.zeros(w.arr_shape, dtype=np.float64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s, r in zip(shots, res):
+    for i, (s, r) in enumerate(zip(shots, res)):
         gw = p.gradient(s, r, n_ckpt=48, ckpt_dtype="f32").cpu().numpy()
         (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
         gp[oz:oz + nz, oy:oy + ny, ox:ox + nx] += gw
+        if (i + 1) % 8 == 0:
+            log(f"[bench]   plain: {i + 1}/{nshot} shots, {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     tp = time.perf_counter() - t0
     gbh = gb.cpu().numpy()
@@ -257,8 +282,9 @@ def main():
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(shots and domains would be sharded across GPUs; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
+              "(several GPUs would each take a shot group and sum the gradient with one all-reduce)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -309,6 +335,10 @@ def main():
                                                              (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
                         for k in kt},
             "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
+    copy_gbs = copy_bandwidth(torch)
+    roof["copy_GBps"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s; dominant kernel {achieved:.0f} GB/s algorithmic")
 
     paths = {}
     if not args.only_main:

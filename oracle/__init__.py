@@ -11,8 +11,8 @@ weights and the checkpoint codec are written here in numpy, following the
 paper's problem statement (Eq. "acou" and the Grid / Function /
 SparseTimeFunction listings), the TTI section (Eq. "rot", the rotated
 derivative listing) and the elastic section (Eq. "elas1", the elastic
-listing).  Every reading of a passage that the paper leaves open is listed in
-DESIGN.md's "Readings" table; the functions below say which one they take.
+listing).  Where the paper leaves a passage open, the function that depends
+on it states the reading it takes in its docstring.
 
 Parity status: every function here is pinned by ``tests/test_oracle_*.py``
 against closed forms, textbook results, invariants or brute force, except the

@@ -1,8 +1,8 @@
 """Workload definitions (sizes, geometry and seeds of the benchmark and parity cases).
 
 Only input recipes live here (they call ``inputs``); the time steps are fixed numbers chosen at
-about 0.8 of the stability bound of each workload (documented in the design doc), so that neither the
-checker nor the library has to supply them to the other.
+about 0.8 of the stability bound of each workload, so that neither the checker nor the library
+has to supply them to the other.
 
   tti2d_101    2D TTI, 101 x 101, h 10 m, space order 4, 500 steps, constant medium (parity case)
   tti3d_512    3D TTI, 512^3, h 12.5 m, space order 12, 3000 steps, 40-point layers (benchmark)
@@ -55,8 +55,8 @@ class Workload:
         w = inputs.ricker(self.f0, self.dt, nt)
         return np.repeat(w[:, None], len(self.src_xyz), axis=1).astype(np.float32)
 
-    def make_model(self) -> dict:
-        """FP32 model arrays in the library's parameter order."""
+    def make_model(self, progress=None) -> dict:
+        """FP32 model arrays keyed by parameter name (``progress`` reports generation stages)."""
         if self.model:
             return self.model
         if self.name == "tti2d_101":
@@ -66,15 +66,16 @@ class Workload:
                           "delta": np.full(shp, 0.05, np.float32), "theta": np.full(shp, math.radians(30), np.float32),
                           "phi": np.zeros(shp, np.float32)}
         elif self.kind == "tti":
-            mdl = inputs.tti_model(self.shape, self.nbl, self.seed)
+            mdl = inputs.tti_model(self.shape, self.nbl, self.seed, progress=progress)
             self.model = {"m": inputs.slowness_squared(mdl["vp"]), "eps": mdl["eps"], "delta": mdl["delta"],
                           "theta": mdl["theta"], "phi": mdl["phi"]}
         else:
             self.model = inputs.elastic_model(self.shape, self.nbl, self.seed)
         return self.model
 
-    def model_list(self):
-        m = self.make_model()
+    def model_list(self, progress=None):
+        """FP32 model arrays in the library's parameter order."""
+        m = self.make_model(progress)
         keys = ("m", "eps", "delta", "theta", "phi") if self.kind == "tti" else ("vp", "vs", "rho")
         return [m[k] for k in keys]
 

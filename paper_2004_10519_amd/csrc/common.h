@@ -30,6 +30,13 @@ struct Weights {
     float wx[8], wy[8], wz[8];
 };
 
+// Global-address-space views of device pointers.  Pointers read from a job table in memory are
+// otherwise treated as generic (flat) pointers; flat loads also count against the LDS wait counter,
+// which would make every LDS wait in the compute phase wait for the next plane's prefetch as well.
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ float gld(const float *p, int64_t i) { return ((const gfloat *)p)[i]; }
+__device__ __forceinline__ void gst(float *p, int64_t i, float v) { ((gfloat *)p)[i] = v; }
+
 __device__ __forceinline__ bool in_win(const Win &w, int x, int y, int z)
 {
     return (unsigned)x < (unsigned)w.nx && (unsigned)y < (unsigned)w.ny && (unsigned)z < (unsigned)w.nz;

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
     const float *__restrict__ Fxz = F[4];
     const float *__restrict__ Fyz = F[5];
     auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
 
     float qzz[Q], qxz[Q], qyz[Q];
@@ -136,14 +136,14 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
         // per-point values of plane z, then the prefetch of plane z+1
         const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
         const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
-        const float v0 = J.v[0][si], v1 = J.v[1][si], v2 = J.v[2][si];
+        const float v0 = gld(J.v[0], si), v1 = gld(J.v[1], si), v2 = gld(J.v[2], si);
         float b0 = 0.f, bxn = 0.f, byn = 0.f, bzn = 0.f, g = 1.f;
         if (MODE == EL_FWD) {
-            b0 = J.b[mi];
-            bxn = J.b[mi + (gx + 1 < w.nx ? 1 : 0)];
-            byn = J.b[mi + (gy + 1 < w.ny ? w.mx : 0)];
-            bzn = J.b[mi + (z + 1 < w.nz ? w.my : 0)];
-            g = J.gx[own ? gx : 0] * J.gy[own ? gy : 0] * J.gz[z];
+            b0 = gld(J.b, mi);
+            bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
+            byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+            bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
+            g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         }
         if (z + 1 < z1) fetch(z + 1);
         const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
@@ -154,13 +154,13 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
                          ds_q<R, true>(qzz, W.wz);
         if (own) {
             if (MODE == EL_FWD) {
-                J.v[0][si] = g * (v0 + dt * (0.5f * (b0 + bxn)) * fx);
-                J.v[1][si] = g * (v1 + dt * (0.5f * (b0 + byn)) * fy);
-                J.v[2][si] = g * (v2 + dt * (0.5f * (b0 + bzn)) * fz);
+                gst(J.v[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
+                gst(J.v[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                gst(J.v[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
             } else {
-                J.v[0][si] = v0 - dt * fx;
-                J.v[1][si] = v1 - dt * fy;
-                J.v[2][si] = v2 - dt * fz;
+                gst(J.v[0], si, v0 - dt * fx);
+                gst(J.v[1], si, v1 - dt * fy);
+                gst(J.v[2], si, v2 - dt * fz);
             }
         }
         b ^= 1;
@@ -191,7 +191,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
     const float *__restrict__ Vy = V[1];
     const float *__restrict__ Vz = V[2];
     auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
 
     float qx[Q], qy[Q], qz[Q];
@@ -273,17 +273,17 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
         const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
         float t[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = J.t[c][si];
+        for (int c = 0; c < 6; ++c) t[c] = gld(J.t[c], si);
         float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f, g = 1.f;
         if (MODE == EL_FWD) {
             const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
-            lam = J.lam[mi];
-            mu0 = J.mu[mi];
-            const float mx_ = J.mu[mi + ox], my_ = J.mu[mi + oy], mz_ = J.mu[mi + oz];
-            mxy = 0.25f * (mu0 + mx_ + my_ + J.mu[mi + ox + oy]);
-            mxz = 0.25f * (mu0 + mx_ + mz_ + J.mu[mi + ox + oz]);
-            myz = 0.25f * (mu0 + my_ + mz_ + J.mu[mi + oy + oz]);
-            g = J.gx[own ? gx : 0] * J.gy[own ? gy : 0] * J.gz[z];
+            lam = gld(J.lam, mi);
+            mu0 = gld(J.mu, mi);
+            const float mx_ = gld(J.mu, mi + ox), my_ = gld(J.mu, mi + oy), mz_ = gld(J.mu, mi + oz);
+            mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
+            mxz = 0.25f * (mu0 + mx_ + mz_ + gld(J.mu, mi + ox + oz));
+            myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
+            g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         }
         if (z + 1 < z1) fetch(z + 1);
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
@@ -295,19 +295,19 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
         if (own) {
             if (MODE == EL_FWD) {
                 const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
-                J.t[0][si] = g * (t[0] + dt * (lt + m2 * exx));
-                J.t[1][si] = g * (t[1] + dt * (lt + m2 * eyy));
-                J.t[2][si] = g * (t[2] + dt * (lt + m2 * ezz));
-                J.t[3][si] = g * (t[3] + dt * mxy * gxy);
-                J.t[4][si] = g * (t[4] + dt * mxz * gxz);
-                J.t[5][si] = g * (t[5] + dt * myz * gyz);
+                gst(J.t[0], si, g * (t[0] + dt * (lt + m2 * exx)));
+                gst(J.t[1], si, g * (t[1] + dt * (lt + m2 * eyy)));
+                gst(J.t[2], si, g * (t[2] + dt * (lt + m2 * ezz)));
+                gst(J.t[3], si, g * (t[3] + dt * mxy * gxy));
+                gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
+                gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
             } else {
-                J.t[0][si] = t[0] - dt * exx;
-                J.t[1][si] = t[1] - dt * eyy;
-                J.t[2][si] = t[2] - dt * ezz;
-                J.t[3][si] = t[3] - dt * gxy;
-                J.t[4][si] = t[4] - dt * gxz;
-                J.t[5][si] = t[5] - dt * gyz;
+                gst(J.t[0], si, t[0] - dt * exx);
+                gst(J.t[1], si, t[1] - dt * eyy);
+                gst(J.t[2], si, t[2] - dt * ezz);
+                gst(J.t[3], si, t[3] - dt * gxy);
+                gst(J.t[4], si, t[4] - dt * gxz);
+                gst(J.t[5], si, t[5] - dt * gyz);
             }
         }
         b ^= 1;
@@ -322,22 +322,22 @@ __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= w.nx) return;
     const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
-    const float g = J.gx[x] * J.gy[y] * J.gz[z];
+    const float g = gld(J.gx, x) * gld(J.gy, y) * gld(J.gz, z);
     float t[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
-        t[c] = g * J.t[c][si];
-        J.t[c][si] = t[c];
+        t[c] = g * gld(J.t[c], si);
+        gst(J.t[c], si, t[c]);
     }
     const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
-    const float lam = J.lam[mi], mu0 = J.mu[mi];
+    const float lam = gld(J.lam, mi), mu0 = gld(J.mu, mi);
     const float lt = lam * (t[0] + t[1] + t[2]), m2 = 2.f * mu0;
-    J.aux[0][si] = lt + m2 * t[0];
-    J.aux[1][si] = lt + m2 * t[1];
-    J.aux[2][si] = lt + m2 * t[2];
-    J.aux[3][si] = 0.25f * (mu0 + J.mu[mi + ox] + J.mu[mi + oy] + J.mu[mi + ox + oy]) * t[3];
-    J.aux[4][si] = 0.25f * (mu0 + J.mu[mi + ox] + J.mu[mi + oz] + J.mu[mi + ox + oz]) * t[4];
-    J.aux[5][si] = 0.25f * (mu0 + J.mu[mi + oy] + J.mu[mi + oz] + J.mu[mi + oy + oz]) * t[5];
+    gst(J.aux[0], si, lt + m2 * t[0]);
+    gst(J.aux[1], si, lt + m2 * t[1]);
+    gst(J.aux[2], si, lt + m2 * t[2]);
+    gst(J.aux[3], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oy) + gld(J.mu, mi + ox + oy)) * t[3]);
+    gst(J.aux[4], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oz) + gld(J.mu, mi + ox + oz)) * t[4]);
+    gst(J.aux[5], si, 0.25f * (mu0 + gld(J.mu, mi + oy) + gld(J.mu, mi + oz) + gld(J.mu, mi + oy + oz)) * t[5]);
 }
 
 // u = bbar (g v~) into aux[0..2]; v~ <- g v~.
@@ -348,18 +348,18 @@ __global__ void el_mix_vel(const ElJob *__restrict__ jobs)
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
     if (x >= w.nx) return;
     const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
-    const float g = J.gx[x] * J.gy[y] * J.gz[z];
-    const float b0 = J.b[mi];
-    const float bx = 0.5f * (b0 + J.b[mi + (x + 1 < w.nx ? 1 : 0)]);
-    const float by = 0.5f * (b0 + J.b[mi + (y + 1 < w.ny ? w.mx : 0)]);
-    const float bz = 0.5f * (b0 + J.b[mi + (z + 1 < w.nz ? w.my : 0)]);
-    const float v0 = g * J.v[0][si], v1 = g * J.v[1][si], v2 = g * J.v[2][si];
-    J.v[0][si] = v0;
-    J.v[1][si] = v1;
-    J.v[2][si] = v2;
-    J.aux[0][si] = bx * v0;
-    J.aux[1][si] = by * v1;
-    J.aux[2][si] = bz * v2;
+    const float g = gld(J.gx, x) * gld(J.gy, y) * gld(J.gz, z);
+    const float b0 = gld(J.b, mi);
+    const float bx = 0.5f * (b0 + gld(J.b, mi + (x + 1 < w.nx ? 1 : 0)));
+    const float by = 0.5f * (b0 + gld(J.b, mi + (y + 1 < w.ny ? w.mx : 0)));
+    const float bz = 0.5f * (b0 + gld(J.b, mi + (z + 1 < w.nz ? w.my : 0)));
+    const float v0 = g * gld(J.v[0], si), v1 = g * gld(J.v[1], si), v2 = g * gld(J.v[2], si);
+    gst(J.v[0], si, v0);
+    gst(J.v[1], si, v1);
+    gst(J.v[2], si, v2);
+    gst(J.aux[0], si, bx * v0);
+    gst(J.aux[1], si, by * v1);
+    gst(J.aux[2], si, bz * v2);
 }
 
 template <int R>

@@ -43,7 +43,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
     const float *__restrict__ U = ADJ ? J.wmix[0] : J.p[par];
     const float *__restrict__ V = ADJ ? J.wmix[1] : J.q[par];
     auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
 
     float qu[NY][Q], qv[NY][Q];                       // z queues of u and v
@@ -124,9 +124,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
             const int y = y0 + ty * NY + r;
             const bool in = gx < w.nx && y < w.ny;
             const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
-            n0[r] = J.nx[mi];
-            n1[r] = J.ny[mi];
-            n2[r] = J.nz[mi];
+            n0[r] = gld(J.nx, mi);
+            n1[r] = gld(J.ny, mi);
+            n2[r] = gld(J.nz, mi);
         }
         if (z + 1 < z1) fetch(z + 1);
 #pragma unroll
@@ -140,12 +140,12 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
                 const float wp = n0[r] * dpx + n1[r] * dpy + n2[r] * dpz;
                 const float wq = n0[r] * dqx + n1[r] * dqy + n2[r] * dqz;
                 const int64_t si = sidx(w, gx, y, z);
-                J.t[0][si] = dpx - n0[r] * wp;
-                J.t[1][si] = dpy - n1[r] * wp;
-                J.t[2][si] = dpz - n2[r] * wp;
-                J.s[0][si] = n0[r] * wq;
-                J.s[1][si] = n1[r] * wq;
-                J.s[2][si] = n2[r] * wq;
+                gst(J.t[0], si, dpx - n0[r] * wp);
+                gst(J.t[1], si, dpy - n1[r] * wp);
+                gst(J.t[2], si, dpz - n2[r] * wp);
+                gst(J.s[0], si, n0[r] * wq);
+                gst(J.s[1], si, n1[r] * wq);
+                gst(J.s[2], si, n2[r] * wq);
             }
         }
         b ^= 1;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     float *__restrict__ pn = J.p[par ^ 1];   // holds the previous level, receives the new one
     float *__restrict__ qn = J.q[par ^ 1];
     auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? f[sidx(w, x, y, z)] : 0.f;
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
 
     float qt[NY][Q], qs[NY][Q];
@@ -263,25 +263,25 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
         __syncthreads();
         // per-point values of plane z first, then the prefetch of plane z+1
         float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
-        const float ezv = J.ez[z];
+        const float ezv = gld(J.ez, z);
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;
             const bool in = gx < w.nx && y < w.ny;
             const int64_t si = sidx(w, in ? gx : 0, in ? y : 0, z);
             const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
-            vp0[r] = pc[si];
-            vq0[r] = qc[si];
-            vp1[r] = pn[si];
-            vq1[r] = qn[si];
-            vm[r] = J.m[mi] * idt2 + 0.f;
-            vA[r] = J.A[mi];
-            vB[r] = J.B[mi];
+            vp0[r] = gld(pc, si);
+            vq0[r] = gld(qc, si);
+            vp1[r] = gld(pn, si);
+            vq1[r] = gld(qn, si);
+            vm[r] = gld(J.m, mi) * idt2 + 0.f;
+            vA[r] = gld(J.A, mi);
+            vB[r] = gld(J.B, mi);
             if (MODE == K2_ADJ_IC) {
                 const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                fpk[r] = sp[si];
-                fqk[r] = sp[J.seg_field + si];
-                vg[r] = J.grad[si];
+                fpk[r] = gld(sp, si);
+                fqk[r] = gld(sp, J.seg_field + si);
+                vg[r] = gld(J.grad, si);
             }
         }
         if (z + 1 < z1) fetch(z + 1);
@@ -302,25 +302,25 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
                     Lq = vB[r] * h0 + hz;
                 }
                 const float mm = vm[r];
-                const float e = J.ex[gx] + J.ey[y] + ezv;
+                const float e = gld(J.ex, gx) + gld(J.ey, y) + ezv;
                 const float ra = 1.0f / (mm + e);
                 const float cc = mm - e;
                 const float np_ = (2.f * mm * vp0[r] - cc * vp1[r] + Lp) * ra;
                 const float nq_ = (2.f * mm * vq0[r] - cc * vq1[r] + Lq) * ra;
-                pn[si] = np_;
-                qn[si] = nq_;
+                gst(pn, si, np_);
+                gst(qn, si, nq_);
                 if (ADJ) {
-                    J.wmix[0][si] = vA[r] * np_ + vB[r] * nq_;
-                    J.wmix[1][si] = vB[r] * np_ + nq_;
+                    gst(J.wmix[0], si, vA[r] * np_ + vB[r] * nq_);
+                    gst(J.wmix[1], si, vB[r] * np_ + nq_);
                 }
                 if (MODE == K2_FWD_STORE) {
                     float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                    sp[si] = np_;
-                    sp[J.seg_field + si] = nq_;
+                    gst(sp, si, np_);
+                    gst(sp, J.seg_field + si, nq_);
                 }
                 if (MODE == K2_ADJ_IC)
-                    J.grad[si] = vg[r] - idt2 * (fpk[r] * (np_ - 2.f * vp0[r] + vp1[r]) +
-                                                 fqk[r] * (nq_ - 2.f * vq0[r] + vq1[r]));
+                    gst(J.grad, si, vg[r] - idt2 * (fpk[r] * (np_ - 2.f * vp0[r] + vp1[r]) +
+                                                    fqk[r] * (nq_ - 2.f * vq0[r] + vq1[r])));
             }
         }
         b ^= 1;

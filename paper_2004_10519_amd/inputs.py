@@ -50,11 +50,38 @@ def ricker(f0: float, dt: float, nt: int, t0: float | None = None) -> np.ndarray
     return ((1.0 - 2.0 * a) * np.exp(-a)).astype(np.float32)
 
 
-def smooth(field: np.ndarray, sigma: float) -> np.ndarray:
-    """Gaussian smoothing (sigma in grid points, reflecting edges), FP64 in, FP64 out."""
+def smooth(field: np.ndarray, sigma: float, threads: int = 8) -> np.ndarray:
+    """Gaussian smoothing (sigma in grid points, kernel truncated at 3 sigma, reflecting edges).
+
+    FP64 in, FP64 out.  The filter is separable: one 1D pass per axis, in axis order, exactly as
+    ``scipy.ndimage.gaussian_filter`` does it; each pass is split into slabs along another axis and
+    run on ``threads`` threads, which gives the same bits as the single-threaded filter.
+    """
+    a = np.asarray(field, dtype=np.float64)
     if sigma <= 0:
-        return np.asarray(field, dtype=np.float64)
-    return ndi.gaussian_filter(np.asarray(field, dtype=np.float64), sigma, truncate=3.0, mode="reflect")
+        return a
+    for ax in range(a.ndim):
+        if a.shape[ax] == 1:
+            a = ndi.gaussian_filter1d(a, sigma, axis=ax, truncate=3.0, mode="reflect")
+            continue
+        split = max((d for d in range(a.ndim) if d != ax), key=lambda d: a.shape[d], default=None)
+        n = a.shape[split] if split is not None else 1
+        nth = max(1, min(threads, n, a.size // (1 << 20)))
+        if nth == 1:
+            a = ndi.gaussian_filter1d(a, sigma, axis=ax, truncate=3.0, mode="reflect")
+            continue
+        out = np.empty_like(a)
+
+        def run(c, a=a, ax=ax, split=split, n=n, nth=nth, out=out):
+            sl = [slice(None)] * a.ndim
+            sl[split] = slice(c * n // nth, (c + 1) * n // nth)
+            sl = tuple(sl)
+            out[sl] = ndi.gaussian_filter1d(a[sl], sigma, axis=ax, truncate=3.0, mode="reflect")
+
+        with ThreadPoolExecutor(nth) as ex:
+            list(ex.map(run, range(nth)))
+        a = out
+    return a
 
 
 def _minmax(a: np.ndarray, lo: float, hi: float) -> np.ndarray:
@@ -79,21 +106,25 @@ def _layer_index(nz: int, nbl: int, seed_rng: np.random.Generator, nlayers: int)
 
 def tti_model(shape_xyz, nbl: int, seed: int, nlayers: int = 10, vmin: float = 1500.0,
               vmax: float = 4500.0, pert: float = 0.05, eps_max: float = 0.3,
-              angle_max_deg: float = 45.0) -> dict:
+              angle_max_deg: float = 45.0, progress=None) -> dict:
     """Seeded TTI model: dict of FP32 arrays vp (m/s), eps, delta, theta, phi (rad), shape (nz, ny, nx).
 
-    For 2D grids pass ny = 1; phi is then zero.
+    For 2D grids pass ny = 1; phi is then zero.  ``progress``, if given, is called with a short
+    message after each generation stage (large models take minutes).
     """
+    say = progress if progress is not None else (lambda msg: None)
     nx, ny, nz = (int(s) for s in shape_xyz)
     shp = (nz, ny, nx)
     rng = _rng(seed)
     layer = _layer_index(nz, nbl, rng, nlayers)
     v_layer = vmin + (vmax - vmin) * layer / (nlayers - 1)
     noises = [_smooth_noise(shp, s, rng) for s in (4.0, 8.0, 8.0, 8.0)]
-    sig = (4.0, 8.0, 8.0, 8.0)
-    with ThreadPoolExecutor(4) as ex:
-        sm = list(ex.map(lambda i: smooth(noises[i], sig[i]), range(4)))
-    del noises
+    say("noise drawn")
+    sm = []
+    for i, sig in enumerate((4.0, 8.0, 8.0, 8.0)):
+        sm.append(smooth(noises[i], sig))
+        noises[i] = None
+        say(f"field {i + 1}/4 smoothed")
     xi_v = _minmax(sm[0], -1.0, 1.0)
     vp = v_layer[:, None, None] * (1.0 + pert * xi_v)
     eps = eps_max * _minmax(sm[1], 0.0, 1.0)
