@@ -436,6 +436,27 @@ def tti_gradient(g: Grid, mod: TTIModel, src_xyz, wavelet, rec_xyz, d_obs, nt=No
     return J, grad, d
 
 
+def tti_image(g: Grid, mod: TTIModel, src_xyz, wavelet, rec_xyz, rec_data, nt=None):
+    """Zero-lag cross-correlation image I = sum_{k=1}^{N} sum_{f in p,q} f^k y_f^k.
+
+    f is the forward state driven by the wavelet, y the adjoint state driven by rec_data at the
+    receivers (the receiver-side wavefield of reverse-time migration).  The paper images its
+    Azure model with the adjoint-state gradient summed over shots (3D imaging section); this
+    zero-lag cross-correlation is the conventional reverse-time-migration imaging condition and
+    is provided beside it (a reading: the paper does not write this condition out).
+    """
+    nt = g.nt if nt is None else nt
+    _, _, states = tti_forward(g, mod, src_xyz, wavelet, rec_xyz, nt=nt, keep=True)
+    img = np.zeros(g.arr_shape)
+
+    def cb(k, yp, yq):
+        fk = states[k]
+        img[...] += yp * fk[0] + yq * fk[1]
+
+    tti_adjoint(g, mod, src_xyz, rec_xyz, rec_data, nt=nt, callback=cb)
+    return img
+
+
 # ---------------------------------------------------------------------------
 # Independent acoustic steppers (for reduction checks)
 # ---------------------------------------------------------------------------

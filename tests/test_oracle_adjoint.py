@@ -98,3 +98,39 @@ def test_tti_gradient_taylor_and_fd(orc, shape):
         jm = _J(orc, g, orc.TTIModel(mod.m - hh * dm, mod.eps, mod.delta, mod.theta, mod.phi), src, wav, rec, dobs)
         fd = (jp - jm) / (2 * hh)
         assert abs(fd - gd) / abs(gd) < 1e-5, (fd, gd)
+
+
+@pytest.mark.parametrize("shape", [(22, 1, 20), (10, 9, 11)])
+def test_tti_image_of_second_difference_is_the_gradient(orc, shape):
+    """The adjoint recursion is time-invariant, so driving it with the second difference of the data,
+    d[n] - 2 d[n+1] + d[n+2], gives the second difference of the adjoint state.  Hence the zero-lag
+    image of that data equals -dt^2 times the gradient for residual d (summation by parts; f^0 = 0 and
+    y^{N+1} = y^{N+2} = 0).  A shifted pairing of f^k with y^{k+-1} breaks this."""
+    g, mod, src, rec = _tti_case(orc, shape, nbl=3, nt=45, seed=4)
+    wav = inputs.ricker(30.0, g.dt, g.nt).astype(np.float64)[:, None].repeat(len(src), axis=1)
+    rng = np.random.default_rng(12)
+    d = rng.standard_normal((g.nt, len(rec)))
+    d2 = d.copy()
+    d2[:-1] -= 2 * d[1:]
+    d2[:-2] += d[2:]
+    img = orc.tti_image(g, mod, src, wav, rec, d2)
+    traces, _, _ = orc.tti_forward(g, mod, src, wav, rec)
+    _, grad, _ = orc.tti_gradient(g, mod, src, wav, rec, traces - d)
+    assert np.linalg.norm(img + g.dt ** 2 * grad) <= 1e-11 * np.linalg.norm(img)
+
+
+def test_tti_image_one_step_closed_form(orc):
+    """N = 1: f^1 = P_s^T s^0 / a in p and q, y^1 = P_r^T d^0 / a in p only, so I = f_p^1 y_p^1 with
+    a = m/dt^2 + eta/(2 dt)."""
+    g, mod, src, rec = _tti_case(orc, (12, 10, 9), nbl=2, nt=1, seed=6)
+    rec = np.concatenate([src + np.array([[3.0, -2.0, 1.5]]), rec])   # receivers beside the sources
+    wav = np.array([[1.7, -0.6]])
+    d = np.array([np.linspace(-1.0, 2.0, len(rec))])
+    img = orc.tti_image(g, mod, src, wav, rec, d)
+    a = mod.m / g.dt ** 2 + orc.tti_eta(g) / (2 * g.dt)
+    fs, fr = np.zeros(g.arr_shape), np.zeros(g.arr_shape)
+    orc.inject(orc.sparse_setup(g, src), fs, wav[0])
+    orc.inject(orc.sparse_setup(g, rec), fr, d[0])
+    expect = (fs / a) * (fr / a)
+    assert np.abs(expect).max() > 0
+    assert np.allclose(img, expect, rtol=1e-13, atol=1e-13 * np.abs(expect).max())
