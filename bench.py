@@ -27,13 +27,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes per grid point of one launch of each stencil kernel (FP32):
-#   tti_pass1: read p, q, n_x, n_y, n_z; write t (3), s (3)                      -> 11 x 4
-#   tti_pass2: read t, s (6), p, q, p-, q- (4), m, 1+2eps, sqrt(1+2delta) (3);
-#              write p+, q+ (2)                                                   -> 15 x 4
+# Algorithmic bytes per grid point of one launch of each stencil kernel (FP32).  TTI, per two-pass
+# scheme (0: six-field temporaries, 1: scalar projections) and direction:
+#   scheme 0 pass 1: read u, v, n_x, n_y, n_z; write t (3), s (3)                         -> 11 x 4
+#   scheme 0 pass 2: read t, s (6), f, f- for p and q (4), m, 1+2eps, sqrt(1+2delta) (3);
+#                    write p+, q+ (2); adjoint also writes w = C y+ (2)                  -> 15 / 17 x 4
+#   scheme 1 pass 1: read u, v, n_x, n_y; write n.grad u, n.grad v                       ->  6 x 4
+#   scheme 1 pass 2: read f, f- for p and q (4), the two projections, n_x, n_y, m, 1+2eps,
+#                    sqrt(1+2delta) (7); write p+, q+ (2); adjoint reads u = w_p too and
+#                    writes w = C y+ (2)                                                 -> 13 / 16 x 4
+# Elastic:
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
-KERNEL_BYTES_PER_PT = {0: 44, 1: 60, 2: 52, 3: 68}
+TTI_KERNEL_BYTES = {(0, 0, False): 44, (0, 1, False): 60, (0, 0, True): 44, (0, 1, True): 68,
+                    (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64}
+KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
+TTI_SCHEME = 0      # two-pass scheme of every TTI handle (--scheme)
+
+
+def kernel_bytes(kclass: int, scheme: int = 0, adjoint: bool = False) -> int:
+    return TTI_KERNEL_BYTES[(scheme, kclass, adjoint)] if kclass in (0, 1) else KERNEL_BYTES_PER_PT[kclass]
+
+
 # minimum bytes per point per time step of the whole method (fused reading, FP32)
 METHOD_BYTES_PER_PT = {"tti": 44, "elastic": 84}
 
@@ -50,7 +65,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kclass: int, npts: int):
+def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/pmc_traffic.json), if they were
     taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -58,7 +73,7 @@ def traffic_from_profiles(kclass: int, npts: int):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get(str(kclass))
+    ent = rec.get(f"{kclass}/{scheme}")
     if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
         return None
     return ent.get("bytes_per_launch")
@@ -70,6 +85,9 @@ def setup_tti(w, torch, prop):
     g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
     p = prop.Propagator(prop.TTI if w.kind == "tti" else prop.ELASTIC, g, dev)
     p._keep = dev
+    if w.kind == "tti":
+        p.set_option("scheme", TTI_SCHEME)
+        p.set_option("autotune", 1)
     shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz, w.rec_kind)
     return p, shot
 
@@ -113,16 +131,17 @@ def cpu_baseline(w, budget_s: float = 15.0):
                                         f"space order {w.space_order}, {steps} FP64 time steps in {el:.1f} s"}
 
 
-def kernel_roof(p, classes, npts):
+def kernel_roof(p, classes, npts, scheme=0, adjoint=False):
     kt = {k: p.kernel_time(k) for k in classes}
     out = {}
     for k, (ms, n, name) in kt.items():
         if n == 0:
             continue
         avg = ms / 1e3 / n
-        out[name] = {"mean_launch_ms": round(avg * 1e3, 4), "launches": n,
-                     "GBps_algorithmic": round(KERNEL_BYTES_PER_PT[k] * npts / avg / 1e9, 1),
-                     "frac_of_8TBs": round(KERNEL_BYTES_PER_PT[k] * npts / avg / 1e9 / HBM_PEAK_GBS, 4)}
+        b = kernel_bytes(k, scheme, adjoint)
+        out[name] = {"mean_launch_ms": round(avg * 1e3, 4), "launches": n, "bytes_per_point": b,
+                     "GBps_algorithmic": round(b * npts / avg / 1e9, 1),
+                     "frac_of_8TBs": round(b * npts / avg / 1e9 / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -132,7 +151,7 @@ def measure_tti_adjoint(torch, prop, w, p, shot):
     torch.cuda.synchronize()
     p.set_timing(True)
     t = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
-    roof = kernel_roof(p, (0, 1), w.npts)
+    roof = kernel_roof(p, (0, 1), w.npts, p.get_option("scheme"), adjoint=True)
     p.set_timing(False)
     g = w.npts * w.nt / t / 1e9
     return {"workload": w.name, "GPts/s": round(g, 3), "ms": round(t * 1e3, 1),
@@ -172,6 +191,8 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
     g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
     dt_ = [torch.from_numpy(a).cuda() for a in true]
     p = prop.Propagator(prop.TTI, g, dt_)
+    p.set_option("scheme", TTI_SCHEME)
+    p.set_option("autotune", 1)
     shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz)
     dobs = p.forward(shot).clone()
     ds_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in start]
@@ -227,6 +248,7 @@ def measure_batched(torch, prop, nt, nshot):
     dev_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
     del arrs
     p = prop.Propagator(prop.TTI, g, dev_)
+    p.set_option("scheme", TTI_SCHEME)
     wav = torch.from_numpy(np.ascontiguousarray(w.wavelet()[:, :1])).cuda()
     shots = [prop.Shot(src, wav, rec, win_origin=o, win_shape=n) for (o, n, src, rec) in geo]
     gen = torch.Generator(device="cuda").manual_seed(0)
@@ -236,6 +258,8 @@ def measure_batched(torch, prop, nt, nshot):
     # batched (FP16 checkpoints, device FP64 sum); issued in calls of up to 16 shots so that
     # progress is reported; each call adds its shots into gb in shot order
     chunk = 16
+    p.set_option("graph", 1)
+    p.set_option("autotune", 1)
     gb = torch.zeros(w.arr_shape, dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -244,7 +268,12 @@ def measure_batched(torch, prop, nt, nshot):
         torch.cuda.synchronize()
         log(f"[bench]   batched: {min(c + chunk, nshot)}/{nshot} shots, {time.perf_counter() - t0:.1f} s")
     tb = time.perf_counter() - t0
-    # plain: sequential per-shot calls, FP32 checkpoints, host FP64 sum
+    tiles_b = {k: p.get_option("info_" + k) for k in ("tile1", "zc1", "tile2", "zc2")}
+    graphs_b = p.get_option("info_graphs")
+    groups_b = p.get_option("info_groups")
+    # plain: sequential per-shot calls, per-step launches, fixed tiles, FP32 checkpoints, host FP64 sum
+    p.set_option("graph", 0)
+    p.set_option("autotune", 0)
     gp = np.zeros(w.arr_shape, dtype=np.float64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -262,12 +291,14 @@ def measure_batched(torch, prop, nt, nshot):
     return {"workload": w.name, "model": list(w.shape), "shots": nshot, "window_points": pts, "time_steps": w.nt,
             "space_order": w.space_order, "checkpoints": 48,
             "batched": {"s": round(tb, 2), "GPts/s": round(pts * w.nt / tb / 1e9, 3), "checkpoint_dtype": "f16",
+                        "graphs": graphs_b, "last_group_tiles": tiles_b, "groups_last_call": groups_b,
                         "method_hbm_frac_156B": round(pts * w.nt / tb / 1e9 * 156 / HBM_PEAK_GBS, 4)},
             "plain": {"s": round(tp, 2), "GPts/s": round(pts * w.nt / tp / 1e9, 3), "checkpoint_dtype": "f32"},
             "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err}
 
 
 def main():
+    global TTI_SCHEME
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -278,9 +309,12 @@ def main():
     ap.add_argument("--batched", type=int, default=0, metavar="NSHOT",
                     help="also run the batched-vs-plain gradient comparison with NSHOT shots (64 = full)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1),
+                    help="TTI two-pass scheme: 0 six-field temporaries, 1 scalar projections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
+    TTI_SCHEME = args.scheme
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(several GPUs would each take a shot group and sum the gradient with one all-reduce)",
@@ -324,17 +358,21 @@ def main():
     dom = max(kt, key=lambda k: kt[k][0])
     ms_tot, nl, name = kt[dom]
     avg_s = ms_tot / 1e3 / max(nl, 1)
-    achieved = KERNEL_BYTES_PER_PT[dom] * npts / avg_s / 1e9
-    traffic = traffic_from_profiles(dom, npts)
+    scheme = p.get_option("scheme")
+    achieved = kernel_bytes(dom, scheme) * npts / avg_s / 1e9
+    traffic = traffic_from_profiles(dom, npts, scheme)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": KERNEL_BYTES_PER_PT[dom] * npts,
+            "algorithmic_bytes_per_launch": kernel_bytes(dom, scheme) * npts, "scheme": scheme,
             "mean_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
             "kernels": {kt[k][2]: {"mean_launch_ms": round(kt[k][0] / max(kt[k][1], 1), 4),
-                                   "GBps_algorithmic": round(KERNEL_BYTES_PER_PT[k] * npts /
+                                   "GBps_algorithmic": round(kernel_bytes(k, scheme) * npts /
                                                              (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
                         for k in kt},
             "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
+    roof["tiles"] = {"pass1": {"variant": p.get_option("info_tile1"), "zc": p.get_option("info_zc1")},
+                     "pass2": {"variant": p.get_option("info_tile2"), "zc": p.get_option("info_zc2")},
+                     "autotuned": True}
     copy_gbs = copy_bandwidth(torch)
     roof["copy_GBps"] = round(copy_gbs, 1)
     roof["frac_of_copy"] = round(achieved / copy_gbs, 4)

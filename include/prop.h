@@ -108,8 +108,8 @@ typedef struct {
 } prop_shot;
 
 /* Create a propagator for a grid and a model.  Validates the grid (even space order 2..16,
- * time order 2 for TTI / 1 for elastic, shape >= 2 space_order + 2 nbl per axis, positive
- * spacing and dt), computes the derived coefficients on the device (TTI: 1+2eps, sqrt(1+2delta),
+ * time order 2 for TTI / 1 for elastic, at least 2 points per active axis, positive spacing and
+ * dt; a shot window needs at least 2 nbl + 2 points per active axis), computes the derived coefficients on the device (TTI: 1+2eps, sqrt(1+2delta),
  * symmetry axis; elastic: lambda, mu, buoyancy) and checks dt against the stability bound for
  * the model's largest velocity (PROP_EUNSTABLE).  stream is a hipStream_t (NULL = default).
  * On success *out owns device memory until prop_destroy. */
@@ -126,8 +126,12 @@ double prop_cfl_dt(prop_kind kind, const prop_grid *grid, double vmax, double ep
 /* Replace the model (same grid); validates like prop_create. */
 int prop_set_model(prop_t h, const prop_model *model);
 
-/* Forward modelling of one shot: rec_out DEVICE nt x nrec receives the traces.
- * TTI: a f^{n+1} = b f^n - c f^{n-1} + C (H0 p^n, Hz q^n) + P_s^T s^n (see the design doc for a, b, c). */
+/* Forward modelling of one shot: rec_out DEVICE nt x nrec receives the traces (row n is recorded
+ * from the new level f^{n+1}).
+ * TTI: a f^{n+1} = b f^n - c f^{n-1} + C (H0 p^n, Hz q^n) + P_s^T s^n for f in (p, q), with
+ * a = m/dt^2 + eta/(2 dt), b = 2 m/dt^2, c = m/dt^2 - eta/(2 dt), eta the damping of the absorbing
+ * layer, C = [[1+2 eps, sqrt(1+2 delta)], [sqrt(1+2 delta), 1]].
+ * Elastic: the staggered velocity-stress scheme of the elastic section. */
 int prop_forward(prop_t h, const prop_shot *shot, float *rec_out);
 
 /* Exact transpose of prop_forward for the same shot (traces -> wavelet):
@@ -145,6 +149,16 @@ int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *sr
 int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float *grad_m,
                   int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype);
 
+/* TTI only.  Zero-lag cross-correlation image of one shot (reverse-time migration imaging
+ * condition; the paper images with the adjoint-state gradient summed over shots, in its 3D
+ * imaging section, and this condition is the conventional alternative):
+ *     I = sum_{k=1}^{N} sum_{f in p,q} f^k y_f^k,
+ * f the forward state driven by the shot's wavelet, y the adjoint state driven by rec_in (DEVICE
+ * nt x nrec, e.g. recorded data) through the receivers.  Same checkpointing as prop_gradient;
+ * image DEVICE window-shaped dense, overwritten. */
+int prop_image(prop_t h, const prop_shot *shot, const float *rec_in, float *image, int32_t n_ckpt,
+               prop_ckpt_dtype ckpt_dtype);
+
 /* Many shots at once (TTI): all shots step in lockstep on their own windows; every stencil launch
  * covers the tiles of all shots of a group.  Shots are processed in groups that fit the device
  * memory.  rec_out[i] DEVICE nt x nrec_i. */
@@ -155,6 +169,11 @@ int prop_forward_batched(prop_t h, int32_t nshot, const prop_shot *shots, float 
 int prop_gradient_batched(prop_t h, int32_t nshot, const prop_shot *shots,
                           const float *const *residual, double *grad_global, int32_t n_ckpt,
                           prop_ckpt_dtype ckpt_dtype);
+
+/* Batched image: per shot as prop_image, accumulated in FP64 into image_global (DEVICE, whole-grid
+ * dense doubles; the call adds), in shot order (the multi-shot image is the sum of the shot images). */
+int prop_image_batched(prop_t h, int32_t nshot, const prop_shot *shots, const float *const *rec_in,
+                       double *image_global, int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype);
 
 /* Copy a final wavefield of the last forward or adjoint call into out (DEVICE, window-shaped
  * dense).  TTI: 0 = p^N, 1 = q^N, 2 = p^{N-1}, 3 = q^{N-1} after prop_forward; after
@@ -167,6 +186,46 @@ int prop_read_state(prop_t h, int32_t field, float *out);
  * milliseconds and the number of launches since the last reset, and names the class. */
 int prop_set_timing(prop_t h, int32_t enable);
 int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name);
+
+/* Run-time options of a handle; they apply to the calls that follow.  None of them changes a
+ * result: every point is computed by the same arithmetic whatever the tiling or launch mode.
+ *   PROP_OPT_GRAPH     0/1 (default 0): record each run of time steps between two host checks
+ *                      (the non-finite watchdog every 500 steps; each gradient segment) in a HIP
+ *                      graph and launch it as one unit.  Ignored while kernel timing is on.
+ *   PROP_OPT_AUTOTUNE  0/1 (default 0): TTI only; on the first call for a set of window shapes
+ *                      and a direction, time both tile variants of each stencil pass at three
+ *                      z-chunk lengths and keep the fastest (cached on the handle).
+ *   PROP_OPT_TILE1/2   0 or 1 (default 1): tile variant of TTI pass 1 / pass 2 when not
+ *                      autotuning (0: 64 x 8 threads, 1: 64 x 16 threads).
+ *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
+ *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
+ *   PROP_OPT_BATCH_MB  device-memory budget of the batched shot-group planner in MiB,
+ *                      0 = 85 % of the free memory (default).
+ *   PROP_OPT_SCHEME    TTI two-pass scheme: 0 = pass 1 stores the six components of
+ *                      (I - n n^T) grad p and n n^T grad q; 1 = pass 1 stores only the two scalars
+ *                      n . grad p and n . grad q and pass 2 re-forms the vectors from p (fewer
+ *                      bytes per step).  Same operators; results agree to FP32 rounding.
+ * Read-only (prop_get_option): PROP_INFO_TILE1/2 and PROP_INFO_ZC1/2, the variant and z-chunk
+ * used by the last TTI call; PROP_INFO_GRAPHS, graphs launched since create; PROP_INFO_GROUPS,
+ * shot groups of the last batched call.  Unknown options give PROP_EINVAL. */
+enum {
+    PROP_OPT_GRAPH = 1,
+    PROP_OPT_AUTOTUNE = 2,
+    PROP_OPT_TILE1 = 3,
+    PROP_OPT_TILE2 = 4,
+    PROP_OPT_ZC = 5,
+    PROP_OPT_XCD = 6,
+    PROP_OPT_BATCH_MB = 7,
+    PROP_OPT_SCHEME = 8,
+    PROP_INFO_TILE1 = 101,
+    PROP_INFO_TILE2 = 102,
+    PROP_INFO_ZC1 = 103,
+    PROP_INFO_ZC2 = 104,
+    PROP_INFO_GRAPHS = 105,
+    PROP_INFO_GROUPS = 106
+};
+int prop_set_option(prop_t h, int32_t option, int64_t value);
+int prop_get_option(prop_t h, int32_t option, int64_t *value);
 
 /* Checkpoint codec (the packing used by prop_gradient), exposed for testing:
  * encode n FP32 values (DEVICE) with scale s = 2^ceil(log2 max|f|) (1 for all-zero input) into

@@ -119,11 +119,12 @@ __global__ void k_tti_rec_adj(BCsr c, const TTIJob *__restrict__ jobs, int par, 
     const float v = bcsr_row_value(c, r, data[sh] + (int64_t)n * npt[sh]) / a;
     const int64_t nd = c.node[r];
     J.p[par ^ 1][nd] += v;
-    J.wmix[0][nd] += J.A[mn] * v;
-    J.wmix[1][nd] += J.B[mn] * v;
-    if (ic) {
+    J.wmix[par ^ 1][0][nd] += J.A[mn] * v;
+    J.wmix[par ^ 1][1][nd] += J.B[mn] * v;
+    if (ic) {   // the injected share of y^k in the imaging condition (f_p^k times it)
         const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-        J.grad[nd] -= idt2 * sp[nd] * v;
+        if (J.image) J.grad[nd] += sp[nd] * v;
+        else J.grad[nd] -= idt2 * sp[nd] * v;
     }
 }
 
@@ -382,9 +383,11 @@ __global__ void k_tti_prep(const float *__restrict__ m, const float *__restrict_
         float st, ct, sp, cp;
         sincosf(t, &st, &ct);
         sincosf(p, &sp, &cp);
-        nx[i] = st * cp;
-        ny[i] = ndim == 3 ? st * sp : 0.f;
-        nz[i] = ct;
+        // the axis is stored with nz >= 0 (n and -n give the same operators)
+        const float sg = ct < 0.f ? -1.f : 1.f;
+        nx[i] = sg * (st * cp);
+        ny[i] = ndim == 3 ? sg * (st * sp) : 0.f;
+        nz[i] = sg * ct;
         if (!(mm > 0.f) || !isfinite(mm) || !isfinite(e) || !isfinite(d) || !isfinite(t) || !isfinite(p)) flags |= 1u;
         else vmax = max(vmax, __float_as_uint(1.0f / sqrtf(mm)));
         if (e < d - 1e-6f) flags |= 2u;

@@ -37,6 +37,10 @@ typedef __attribute__((address_space(1))) float gfloat;
 __device__ __forceinline__ float gld(const float *p, int64_t i) { return ((const gfloat *)p)[i]; }
 __device__ __forceinline__ void gst(float *p, int64_t i, float v) { ((gfloat *)p)[i] = v; }
 
+// Third component of the unit symmetry axis from the other two (the axis is stored with nz >= 0;
+// n and -n give the same operators).
+__device__ __forceinline__ float axis_z(float n0, float n1) { return sqrtf(fmaxf(0.f, 1.f - n0 * n0 - n1 * n1)); }
+
 __device__ __forceinline__ bool in_win(const Win &w, int x, int y, int z)
 {
     return (unsigned)x < (unsigned)w.nx && (unsigned)y < (unsigned)w.ny && (unsigned)z < (unsigned)w.nz;

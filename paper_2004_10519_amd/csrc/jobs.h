@@ -7,12 +7,18 @@
 struct TTIJob {
     Win w;
     float *p[2], *q[2];           // wavefields (state layout)
-    float *wmix[2];               // adjoint only: w = C y of the newest level, the input of pass 1
-    float *t[3], *s[3];           // pass-1 vectors (I - n n^T) grad p and n n^T grad q (state layout)
+    float *wmix[2][2];            // adjoint only: w = C y of the newest level (components p, q), the
+                                  // input of pass 1; double-buffered with the step parity (pass 1
+                                  // reads wmix[par], pass 2 writes wmix[par ^ 1]) because the scalar
+                                  // scheme's pass 2 reads w on tile halos while it writes the new w
+    float *t[3], *s[3];           // pass-1 outputs (state layout): six-field scheme: the vectors
+                                  // (I - n n^T) grad u and n n^T grad v; scalar scheme: t[0] = n . grad u,
+                                  // t[1] = n . grad v
     const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
-    const float *nx, *ny, *nz;    // symmetry axis (model layout)
+    const float *nx, *ny, *nz;    // symmetry axis, nz >= 0 (model layout)
     const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
     float *grad;                  // imaging-condition accumulator (state layout) or null
+    int image;                    // imaging condition: 0 = gradient w.r.t. m, 1 = zero-lag cross-correlation
     float *seg;                   // segment store: per step 2 fields (p then q) of seg_field elems
     int64_t seg_field;            // elements of one stored field (= plane pitch * nz)
 };
@@ -28,12 +34,14 @@ struct ElJob {
 };
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
+// Two-pass schemes of the TTI step: six-field temporaries, or the two scalar projections n . grad.
+enum { TTI_SIX = 0, TTI_SCALAR = 1 };
 
-// shape: tile-shape variant of the pass (see tti.hip); tti_tile_rows gives its tile height.
-void launch_tti_pass1(int R, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
-                      int par, const Weights &W, hipStream_t st);
-void launch_tti_pass2(int R, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc,
-                      int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
+// shape: tile-shape variant of the pass; tti_tile_rows gives its tile height.
+void launch_tti_pass1(int R, int scheme, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles,
+                      int zc, int par, const Weights &W, hipStream_t st);
+void launch_tti_pass2(int R, int scheme, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles,
+                      int zc, int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
 int tti_tile_rows(int R, int pass, int shape);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };

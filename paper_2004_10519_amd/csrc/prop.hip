@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <new>
 #include <string>
@@ -191,7 +192,8 @@ struct Slot {
     int64_t o[3] = {0, 0, 0};
     int64_t plane = 0;          // sy * nz: elements of one state field
     DevBuf fields;              // all wavefields of this window
-    float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq, 15-16 w = C y
+    float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq, 15-18 w = C y
+                                // (two levels of two components)
                                 // elastic: 0-2 v, 3-8 tau, 9-14 aux
     DevBuf tabs;                // damping tables (nx + ny + nz floats)
     Plans src_inj, rec_inj, rec_inj_vz, rec_gat, rec_gat_vz, src_gat;
@@ -228,6 +230,22 @@ struct prop_s {
     int64_t launches[4] = {0, 0, 0, 0};
     int last_state = 0;         // 0 none, 1 forward, 2 adjoint
     int last_groups = 0;        // shot groups used by the last batched call
+    // options (prop_set_option)
+    int opt_graph = 0, opt_autotune = 0, opt_xcd = 0;
+    int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
+    int opt_zc = 0;             // fixed z-chunk length (0: automatic)
+    int opt_scheme = TTI_SIX;   // TTI two-pass scheme (TTI_SIX or TTI_SCALAR)
+    int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
+    // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
+    struct Tune {
+        int shape[2], zc[2];
+    };
+    std::map<std::string, Tune> tuned;
+    Tune last_tune{{1, 1}, {0, 0}};
+    // graph capture of time-step runs
+    hipStream_t cap = nullptr;
+    std::vector<hipGraphExec_t> execs;
+    int64_t graphs_launched = 0;
 };
 
 namespace {
@@ -245,62 +263,44 @@ double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
     return kmax * (d / g.nbl) * (d / g.nbl);
 }
 
-int env_int(const char *name, int dflt)
+int tile_rows(const prop_s *h, int pass, int shape)
 {
-    const char *v = getenv(name);
-    return (v && *v) ? atoi(v) : dflt;
-}
-
-// Tile-shape variants of the two TTI passes (defaults chosen by measurement; PROP_SHAPE1 /
-// PROP_SHAPE2 override them for experiments).
-int shape_of(const prop_s *h, int pass)
-{
-    (void)h;
-    return pass == 1 ? env_int("PROP_SHAPE1", 1) : env_int("PROP_SHAPE2", 1);
-}
-
-int tile_rows(const prop_s *h, int pass = 1)
-{
-    if (h->kind == PROP_TTI) return tti_tile_rows(h->R, pass, shape_of(h, pass));
+    if (h->kind == PROP_TTI) return tti_tile_rows(h->R, pass, shape);
     return el_tile_rows(h->R);
 }
 
-// Tiles of a set of windows in spatial order (x fastest, then y, then z chunk).  Optionally
-// (PROP_XCD=1) the order is dealt round-robin over the 8 XCDs so that each XCD gets a contiguous
-// range of neighbouring tiles.
-void make_tiles(const std::vector<Slot *> &slots, int TY, std::vector<Tile> &out)
+// Tiles of a set of windows in spatial order (x fastest, then y, then z chunk of zc planes).  With
+// the XCD option the order is dealt round-robin over the 8 XCDs so that each XCD gets a contiguous
+// range of neighbouring tiles (measured on the 512^3 workload: plain order is ~3% faster).
+void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std::vector<Tile> &out)
 {
     std::vector<Tile> sp;
     for (size_t j = 0; j < slots.size(); ++j) {
         const Win &w = slots[j]->w;
-        const int zc = slots[j]->zc;
         for (int z0 = 0; z0 < w.nz; z0 += zc)
             for (int y0 = 0; y0 < w.ny; y0 += TY)
                 for (int x0 = 0; x0 < w.nx; x0 += PROP_TX) sp.push_back(Tile{(int)j, x0, y0, z0});
     }
-    // measured on the 512^3 workload: plain order is ~3% faster than the XCD-grouped order
-    const size_t T = sp.size(), X = env_int("PROP_XCD", 0) ? 8 : 1;
+    const size_t T = sp.size(), X = xcd ? 8 : 1;
     out.assign(T, Tile{});
     const size_t per = (T + X - 1) / X;
     size_t b = 0;
     // block b runs on XCD b % 8; give XCD c the spatial range [c*per, (c+1)*per)
-    std::vector<size_t> order;
-    order.reserve(T);
     for (size_t i = 0; i < per; ++i)
         for (size_t c = 0; c < X; ++c) {
             size_t s = c * per + i;
-            if (s < T) order.push_back(s);
+            if (s < T) out[b++] = sp[s];
         }
-    for (size_t k = 0; k < order.size(); ++k) out[b++] = sp[order[k]];
 }
 
-int choose_zc(int nz, int64_t tiles_xy, int R)
+// z-chunk length: enough chunks for ~2048 blocks, but chunks of at least 4R planes (the z halo of
+// a chunk is re-read by its neighbour).
+int choose_zc(const prop_s *h, int nz, int64_t tiles_xy)
 {
-    const char *env = getenv("PROP_ZC");
-    if (env && atoi(env) > 0) return std::min(atoi(env), nz);
+    if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
     const int64_t target = 2048;
     int64_t nch = (target + tiles_xy - 1) / tiles_xy;
-    nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / (4 * R))));
+    nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / (4 * h->R))));
     return (int)((nz + nch - 1) / nch);
 }
 
@@ -459,7 +459,7 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
     sl.w = w;
     for (int a = 0; a < 3; ++a) sl.o[a] = o[a];
     sl.plane = w.sy * w.nz;
-    const int nf = h->kind == PROP_TTI ? 17 : 15;
+    const int nf = h->kind == PROP_TTI ? 19 : 15;
     if (!same) TRY(sl.fields.ensure((size_t)nf * sl.plane * sizeof(float)));
     for (int i = 0; i < nf; ++i) sl.f[i] = sl.fields.as<float>() + (size_t)i * sl.plane;
     // damping tables
@@ -473,9 +473,9 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
                                              : (float)std::exp(-k * h->g.dt);
         }
     TRY(upload(sl.tabs, tab, h->st));
-    const int TY = tile_rows(h, 1);
+    const int TY = tile_rows(h, 1, h->opt_shape[0]);
     const int64_t txy = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY - 1) / TY);
-    sl.zc = choose_zc(w.nz, txy, h->R);
+    sl.zc = choose_zc(h, w.nz, txy);
     return PROP_OK;
 }
 
@@ -488,8 +488,8 @@ TTIJob tti_job(const prop_s *h, const Slot &sl, bool adjoint)
     J.p[1] = sl.f[b + 1];
     J.q[0] = sl.f[adjoint ? 13 : 2];
     J.q[1] = sl.f[adjoint ? 14 : 3];
-    J.wmix[0] = adjoint ? sl.f[15] : nullptr;
-    J.wmix[1] = adjoint ? sl.f[16] : nullptr;
+    for (int l = 0; l < 2; ++l)
+        for (int c = 0; c < 2; ++c) J.wmix[l][c] = adjoint ? sl.f[15 + 2 * l + c] : nullptr;
     for (int i = 0; i < 3; ++i) {
         J.t[i] = sl.f[4 + i];
         J.s[i] = sl.f[7 + i];
@@ -538,10 +538,10 @@ int set_tiles(prop_s *h, Slot &sl)
 {
     std::vector<Slot *> one{&sl};
     std::vector<Tile> tiles;
-    make_tiles(one, tile_rows(h, 1), tiles);
+    make_tiles(one, tile_rows(h, 1, h->opt_shape[0]), sl.zc, h->opt_xcd, tiles);
     sl.ntiles = (int)tiles.size();
     TRY(upload(sl.tiles, tiles, h->st));
-    make_tiles(one, tile_rows(h, 2), tiles);
+    make_tiles(one, tile_rows(h, 2, h->opt_shape[1]), sl.zc, h->opt_xcd, tiles);
     sl.ntiles2 = (int)tiles.size();
     return upload(sl.tiles2, tiles, h->st);
 }
@@ -599,6 +599,12 @@ struct Timed {
     }
 };
 
+void release_graphs(prop_s *h)
+{
+    for (auto e : h->execs) (void)hipGraphExecDestroy(e);
+    h->execs.clear();
+}
+
 int check_finite(prop_s *h, const float *f, const Win &w, const char *what = "wavefield", int step = -1, int shot = 0)
 {
     aux_fill_u32(h->flag.as<unsigned>(), 1, 0u, h->st);
@@ -606,6 +612,7 @@ int check_finite(prop_s *h, const float *f, const Win &w, const char *what = "wa
     unsigned v = 0;
     HIPCHK(hipMemcpyAsync(&v, h->flag.p, sizeof v, hipMemcpyDeviceToHost, h->st));
     HIPCHK(hipStreamSynchronize(h->st));
+    release_graphs(h);
     if (v) return fail(PROP_EUNSTABLE, "non-finite values in %s (shot %d, step %d): instability", what, shot, step);
     return PROP_OK;
 }
@@ -760,9 +767,12 @@ int append_gather(const prop_s *h, const Slot &sl, int shot, const float *xyz, i
 struct Group {
     std::vector<Slot *> slots;
     std::vector<const prop_shot *> shots;
-    DevBuf jobs_f, jobs_a, t1, t2, io;
+    DevBuf jobs_f, jobs_a, io;
     DevBuf pb[16];
-    int nt1 = 0, nt2 = 0, zc = 1;
+    // tile lists per direction (0 forward, 1 adjoint) and pass, with their variant and z-chunk
+    DevBuf tl[2][2];
+    int ntl[2][2] = {}, shape[2][2] = {}, zc[2][2] = {};
+    std::string key;                 // window set, for the autotuner
     BCsr src_inj{}, rec_inj{};
     BGather rec_gat{}, src_gat{};
     const float *const *src_data = nullptr;
@@ -791,6 +801,161 @@ int upload_csr(prop_s *h, Group &G, int base, const HostCsr &hc, BCsr &c)
     return PROP_OK;
 }
 
+// z-chunk of a pass over a set of windows: one value for the group (each job clips it to its own
+// depth), from the total tile count of one plane.
+int group_zc(const prop_s *h, const std::vector<Slot *> &slots, int pass, int shape)
+{
+    const int TY = tile_rows(h, pass, shape);
+    int64_t txy = 0;
+    int nzmax = 1;
+    for (auto *sl : slots) {
+        txy += (int64_t)((sl->w.nx + PROP_TX - 1) / PROP_TX) * ((sl->w.ny + TY - 1) / TY);
+        nzmax = std::max(nzmax, sl->w.nz);
+    }
+    return choose_zc(h, nzmax, txy);
+}
+
+// Untuned choice: the fixed tile variants, one z-chunk for both passes (from pass 1's tiles).
+prop_s::Tune default_tune(const prop_s *h, const std::vector<Slot *> &slots)
+{
+    prop_s::Tune t;
+    t.shape[0] = h->opt_shape[0];
+    t.shape[1] = h->opt_shape[1];
+    t.zc[0] = t.zc[1] = group_zc(h, slots, 1, t.shape[0]);
+    return t;
+}
+
+int apply_tune(prop_s *h, Group &G, int dir, const prop_s::Tune &t)
+{
+    std::vector<Tile> tl;
+    for (int k = 0; k < 2; ++k) {
+        make_tiles(G.slots, tile_rows(h, k + 1, t.shape[k]), t.zc[k], h->opt_xcd, tl);
+        G.ntl[dir][k] = (int)tl.size();
+        G.shape[dir][k] = t.shape[k];
+        G.zc[dir][k] = t.zc[k];
+        TRY(upload(G.tl[dir][k], tl, h->st));
+    }
+    h->last_tune = t;
+    return PROP_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Autotuner: on the first call for a window set and direction, time every tile variant of each
+// pass at three z-chunk lengths (half, one and two times the automatic one) and keep the fastest.
+// The trial launches run on the group's zero state, which they leave zero (no sources yet), so
+// they change no result; the choice is cached on the handle.
+int tune_group(prop_s *h, Group &G, bool adj)
+{
+    if (!h->opt_autotune) return PROP_OK;
+    const int dir = adj ? 1 : 0;
+    const std::string key = std::string(adj ? "A" : "F") + std::to_string(h->opt_scheme) + G.key;
+    auto it = h->tuned.find(key);
+    if (it != h->tuned.end()) return apply_tune(h, G, dir, it->second);
+    prop_s::Tune best = default_tune(h, G.slots);
+    int nzmax = 1;
+    for (auto *sl : G.slots) nzmax = std::max(nzmax, sl->w.nz);
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    const TTIJob *job = adj ? G.jobs_a.as<TTIJob>() : G.jobs_f.as<TTIJob>();
+    const float idt2 = (float)(1.0 / (h->g.dt * h->g.dt));
+    DevBuf tb;
+    std::vector<Tile> tl;
+    for (int pass = 1; pass <= 2; ++pass) {
+        double best_ms = 1e300;
+        for (int shape = 0; shape < 2; ++shape) {
+            const int z0 = group_zc(h, G.slots, pass, shape);
+            int last = -1;
+            for (int zc : {std::max(1, z0 / 2), z0, 2 * z0}) {
+                zc = std::min(zc, nzmax);
+                if (zc == last) continue;
+                last = zc;
+                make_tiles(G.slots, tile_rows(h, pass, shape), zc, h->opt_xcd, tl);
+                TRY(upload(tb, tl, h->st));
+                const int nt = (int)tl.size();
+                auto run = [&]() {
+                    if (pass == 1)
+                        launch_tti_pass1(h->R, h->opt_scheme, shape, adj, job, tb.as<Tile>(), nt, zc, 0, h->W, h->st);
+                    else
+                        launch_tti_pass2(h->R, h->opt_scheme, shape, adj ? K2_ADJ : K2_FWD, job, tb.as<Tile>(), nt, zc,
+                                         0, h->W, idt2, 0, h->st);
+                };
+                run();
+                HIPCHK(hipEventRecord(ev.a, h->st));
+                for (int r = 0; r < 3; ++r) run();
+                HIPCHK(hipEventRecord(ev.b, h->st));
+                HIPCHK(hipEventSynchronize(ev.b));
+                HIPCHK(hipGetLastError());
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.shape[pass - 1] = shape;
+                    best.zc[pass - 1] = zc;
+                }
+            }
+        }
+    }
+    h->tuned[key] = best;
+    return apply_tune(h, G, dir, best);
+}
+
+// A run of time steps recorded into a HIP graph (graph option on, kernel timing off) and launched
+// on the handle's stream when the run ends.  While recording, the handle's stream is an internal
+// capture stream; nothing in a run synchronises with the host.  The executable graphs are freed
+// at the next host synchronisation.
+struct Capture {
+    prop_s *h;
+    hipStream_t orig = nullptr;
+    bool on = false;
+    explicit Capture(prop_s *h_) : h(h_) {}
+    Capture(const Capture &) = delete;
+    Capture &operator=(const Capture &) = delete;
+    int begin()
+    {
+        if (!h->opt_graph || h->timing || on) return PROP_OK;
+        if (!h->cap) HIPCHK(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        orig = h->st;
+        h->st = h->cap;
+        on = true;
+        return PROP_OK;
+    }
+    int end()
+    {
+        if (!on) return PROP_OK;
+        on = false;
+        h->st = orig;
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(h->cap, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PROP_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        h->execs.push_back(ex);
+        HIPCHK(hipGraphLaunch(ex, h->st));
+        h->graphs_launched++;
+        return PROP_OK;
+    }
+    ~Capture()
+    {
+        if (!on) return;
+        h->st = orig;
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(h->cap, &g);
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+    }
+};
+
 // Build a group over `shots` using workspaces `slots` (one per shot).  io pointer tables: wavelets,
 // receiver-side inputs (rec_in / residual), receiver outputs, source outputs (each may be NULL).
 int build_group(prop_s *h, Group &G, const std::vector<const prop_shot *> &shots, const std::vector<Slot *> &slots,
@@ -803,7 +968,7 @@ int build_group(prop_s *h, Group &G, const std::vector<const prop_shot *> &shots
     HostCsr hs, hr;
     HostGather gr, gs;
     std::vector<TTIJob> jf, ja;
-    int64_t txy_min = INT64_MAX;
+    G.key.clear();
     for (int j = 0; j < ns; ++j) {
         const prop_shot *s = shots[j];
         Slot &sl = *slots[j];
@@ -825,21 +990,11 @@ int build_group(prop_s *h, Group &G, const std::vector<const prop_shot *> &shots
         if (src_gat && s->nsrc) TRY(append_gather(h, sl, j, s->src_xyz, s->nsrc, gs));
         jf.push_back(tti_job(h, sl, false));
         ja.push_back(tti_job(h, sl, true));
-        const int TY = tile_rows(h, 1);
-        txy_min = std::min<int64_t>(txy_min, (int64_t)((sl.w.nx + PROP_TX - 1) / PROP_TX) * ((sl.w.ny + TY - 1) / TY) * ns);
+        G.key += std::to_string(sl.w.nx) + "x" + std::to_string(sl.w.ny) + "x" + std::to_string(sl.w.nz) + ";";
     }
-    // one z-chunk size for the group (each job clips it to its own depth)
-    int nzmax = 1;
-    for (auto *sl : slots) nzmax = std::max(nzmax, sl->w.nz);
-    G.zc = choose_zc(nzmax, txy_min, h->R);
-    for (auto *sl : slots) sl->zc = G.zc;
-    std::vector<Tile> tl;
-    make_tiles(slots, tile_rows(h, 1), tl);
-    G.nt1 = (int)tl.size();
-    TRY(upload(G.t1, tl, h->st));
-    make_tiles(slots, tile_rows(h, 2), tl);
-    G.nt2 = (int)tl.size();
-    TRY(upload(G.t2, tl, h->st));
+    const prop_s::Tune t = default_tune(h, slots);
+    TRY(apply_tune(h, G, 0, t));
+    TRY(apply_tune(h, G, 1, t));
     TRY(upload(G.jobs_f, jf, h->st));
     TRY(upload(G.jobs_a, ja, h->st));
     G.src_inj = BCsr{};
@@ -917,13 +1072,17 @@ int build_group(prop_s *h, Group &G, const std::vector<const prop_shot *> &shots
 void tti_step(prop_s *h, Group &G, bool adj, int mode, int par, int seg_step)
 {
     const TTIJob *job = adj ? G.jobs_a.as<TTIJob>() : G.jobs_f.as<TTIJob>();
+    const int d = adj ? 1 : 0;
     {
         Timed t(h, 0);
-        launch_tti_pass1(h->R, shape_of(h, 1), adj, job, G.t1.as<Tile>(), G.nt1, G.zc, par, h->W, h->st);
+        launch_tti_pass1(h->R, h->opt_scheme, G.shape[d][0], adj, job, G.tl[d][0].as<Tile>(), G.ntl[d][0], G.zc[d][0],
+                         par, h->W,
+                         h->st);
     }
     {
         Timed t(h, 1);
-        launch_tti_pass2(h->R, shape_of(h, 2), mode, job, G.t2.as<Tile>(), G.nt2, G.zc, par, h->W,
+        launch_tti_pass2(h->R, h->opt_scheme, G.shape[d][1], mode, job, G.tl[d][1].as<Tile>(), G.ntl[d][1],
+                         G.zc[d][1], par, h->W,
                          (float)(1.0 / (h->g.dt * h->g.dt)), seg_step, h->st);
     }
 }
@@ -940,28 +1099,43 @@ float idt2_of(const prop_s *h) { return (float)(1.0 / (h->g.dt * h->g.dt)); }
 int tti_forward_group(prop_s *h, Group &G)
 {
     for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
+    TRY(tune_group(h, G, false));
     const TTIJob *jf = G.jobs_f.as<TTIJob>();
-    for (int n = 0; n < h->g.nt; ++n) {
+    const int N = h->g.nt;
+    Capture cap(h);
+    TRY(cap.begin());
+    for (int n = 0; n < N; ++n) {
         const int par = n & 1;
         tti_step(h, G, false, K2_FWD, par, 0);
         aux_tti_src(G.src_inj, jf, par, G.src_data, G.nsrc, n, idt2_of(h), -1, h->st);
         aux_tti_gather(G.rec_gat, jf, par, 0, G.rec_out, G.nrec, n, h->st);
-        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) TRY(check_group(h, G, par ^ 1, "p (forward)", n));
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
+            TRY(cap.end());
+            TRY(check_group(h, G, par ^ 1, "p (forward)", n));
+            if (n + 1 < N) TRY(cap.begin());
+        }
     }
     return PROP_OK;
 }
 
 int tti_adjoint_group(prop_s *h, Group &G)
 {
-    for (auto *sl : G.slots) aux_fill(sl->f[11], 6 * sl->plane, 0.f, h->st);   // y (both levels) and w
+    for (auto *sl : G.slots) aux_fill(sl->f[11], 8 * sl->plane, 0.f, h->st);   // y and w (both levels)
+    TRY(tune_group(h, G, true));
     const TTIJob *ja = G.jobs_a.as<TTIJob>();
     const int N = h->g.nt;
+    Capture cap(h);
+    TRY(cap.begin());
     for (int k = N; k >= 1; --k) {
         const int par = (N - k) & 1;
         tti_step(h, G, true, K2_ADJ, par, 0);
         aux_tti_rec_adj(G.rec_inj, ja, par, G.rec_data, G.nrec, k - 1, idt2_of(h), 0, 0, h->st);
         aux_tti_gather(G.src_gat, ja, par, 1, G.src_out, G.nsrc, k - 1, h->st);
-        if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) TRY(check_group(h, G, 11 + (par ^ 1), "y_p (adjoint)", k));
+        if ((N - k + 1) % WATCH_EVERY == 0 || k == 1) {
+            TRY(cap.end());
+            TRY(check_group(h, G, 11 + (par ^ 1), "y_p (adjoint)", k));
+            if (k > 1) TRY(cap.begin());
+        }
     }
     return PROP_OK;
 }
@@ -1016,8 +1190,9 @@ size_t grad_bytes(const Slot &sl, int C, int S, int dtype)
            (size_t)S * 2 * sl.plane * 4 + 1024;
 }
 
-// Checkpointed gradient of a group; each shot's window gradient is left in its slot (field 10).
-int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype)
+// Checkpointed gradient (or zero-lag image) of a group; each shot's window result is left in its
+// slot (field 10).
+int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = false)
 {
     const int N = h->g.nt;
     const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
@@ -1044,6 +1219,7 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype)
     for (int j = 0; j < ns; ++j) {
         TTIJob a = tti_job(h, *G.slots[j], false), b = tti_job(h, *G.slots[j], true);
         a.seg = b.seg = h->seg.as<float>() + G.seg_off[j];
+        b.image = image ? 1 : 0;
         jf.push_back(a);
         ja.push_back(b);
     }
@@ -1056,22 +1232,31 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype)
 
     // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state
     for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
+    TRY(tune_group(h, G, false));
+    Capture cap(h);
+    TRY(cap.begin());
     for (int n = 0; n < N; ++n) {
         const int par = n & 1;
         tti_step(h, G, false, K2_FWD, par, 0);
         aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
         if ((n + 1) % S == 0 && (n + 1) / S < C)
             for (int j = 0; j < ns; ++j) ckpt_save(h, *G.slots[j], ck + G.ck_off[j], sc + G.sc_off[j], (n + 1) / S, par ^ 1, dtype);
-        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) TRY(check_group(h, G, par ^ 1, "p (gradient forward)", n));
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
+            TRY(cap.end());
+            TRY(check_group(h, G, par ^ 1, "p (gradient forward)", n));
+            if (n + 1 < N) TRY(cap.begin());
+        }
     }
     // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
     for (auto *sl : G.slots) {
         aux_fill(sl->f[10], sl->plane, 0.f, h->st);          // gradient accumulator
-        aux_fill(sl->f[11], 6 * sl->plane, 0.f, h->st);      // adjoint state and w
+        aux_fill(sl->f[11], 8 * sl->plane, 0.f, h->st);      // adjoint state and w (both levels)
     }
+    TRY(tune_group(h, G, true));
     for (int j = C - 1; j >= 0; --j) {
         const int start = j * S, end = std::min(N, (j + 1) * S);
         const int par0 = start & 1;
+        TRY(cap.begin());
         for (int i = 0; i < ns; ++i) {
             Slot &sl = *G.slots[i];
             if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
@@ -1087,6 +1272,7 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype)
             tti_step(h, G, true, K2_ADJ_IC, par, k - 1 - start);
             aux_tti_rec_adj(G.rec_inj, dja, par, G.rec_data, G.nrec, k - 1, idt2, 1, k - 1 - start, h->st);
         }
+        TRY(cap.end());
         for (int i = 0; i < ns; ++i) {
             TRY(check_finite(h, G.slots[i]->f[par0], G.slots[i]->w, "restored p", start, i));
             TRY(check_finite(h, G.slots[i]->f[11 + (((N - start - 1) & 1) ^ 1)], G.slots[i]->w, "y_p", start, i));
@@ -1117,15 +1303,16 @@ int tti_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_o
     return PROP_OK;
 }
 
-int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *grad_m, int n_ckpt, int dtype)
+int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *grad_m, int n_ckpt, int dtype,
+                 bool image = false)
 {
     if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
     if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
-    if (!grad_m) return fail(PROP_EINVAL, "grad_m is NULL");
+    if (!grad_m) return fail(PROP_EINVAL, image ? "image is NULL" : "grad_m is NULL");
     Group G;
     const float *ins[1] = {residual};
     TRY(build_group(h, G, {s}, {&h->slot}, true, false, true, false, ins, nullptr, nullptr));
-    TRY(tti_gradient_group(h, G, n_ckpt, dtype));
+    TRY(tti_gradient_group(h, G, n_ckpt, dtype, image));
     aux_copy_out(h->slot.f[10], h->slot.w, grad_m, h->st);
     HIPCHK(hipGetLastError());
     h->last_state = 0;
@@ -1138,7 +1325,7 @@ int plan_groups(prop_s *h, int nshot, const prop_shot *shots, bool grad, int n_c
 {
     size_t freeb = 0, totalb = 0;
     HIPCHK(hipMemGetInfo(&freeb, &totalb));
-    const int64_t budget_env = env_int("PROP_BATCH_MB", 0);
+    const int64_t budget_env = h->opt_batch_mb;
     // memory already held by the batch workspaces is reusable
     size_t held = h->ckpt.bytes + h->ckscale.bytes + h->seg.bytes;
     for (auto &sl : h->bslots) held += sl->fields.bytes;
@@ -1153,7 +1340,7 @@ int plan_groups(prop_s *h, int nshot, const prop_shot *shots, bool grad, int n_c
         int64_t o[3], n[3];
         TRY(shot_window(h, &shots[i], o, n));
         const size_t sx = (n[0] + 63) / 64 * 64, plane = sx * n[1] * n[2];
-        size_t need = 17 * plane * 4 + 4096;
+        size_t need = 19 * plane * 4 + 4096;
         if (grad) {
             Slot tmp;
             tmp.w.nx = (int)n[0];
@@ -1174,7 +1361,7 @@ int plan_groups(prop_s *h, int nshot, const prop_shot *shots, bool grad, int n_c
 }
 
 int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_out, const float *const *residual,
-                double *grad_global, int n_ckpt, int dtype, bool grad)
+                double *grad_global, int n_ckpt, int dtype, bool grad, bool image = false)
 {
     if (nshot < 1 || !shots) return fail(PROP_EINVAL, "need at least one shot");
     if (grad) {
@@ -1200,7 +1387,7 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
         Group G;
         if (grad) {
             TRY(build_group(h, G, sh, sl, true, false, true, false, residual + gr.first, nullptr, nullptr));
-            TRY(tti_gradient_group(h, G, n_ckpt, dtype));
+            TRY(tti_gradient_group(h, G, n_ckpt, dtype, image));
             for (int i = 0; i < ns; ++i) aux_accum_f64(sl[i]->f[10], sl[i]->w, grad_global, h->st);  // shot order
         } else {
             TRY(build_group(h, G, sh, sl, true, true, false, false, nullptr, rec_out + gr.first, nullptr));
@@ -1367,6 +1554,24 @@ int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float 
     return tti_gradient(h, shot, residual, grad_m, n_ckpt, (int)ckpt_dtype);
 }
 
+int prop_image(prop_t h, const prop_shot *shot, const float *rec_in, float *image, int32_t n_ckpt,
+               prop_ckpt_dtype ckpt_dtype)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "images are provided for PROP_TTI only");
+    return tti_gradient(h, shot, rec_in, image, n_ckpt, (int)ckpt_dtype, true);
+}
+
+int prop_image_batched(prop_t h, int32_t nshot, const prop_shot *shots, const float *const *rec_in,
+                       double *image_global, int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "batched calls are provided for PROP_TTI");
+    return tti_batched(h, nshot, shots, nullptr, rec_in, image_global, n_ckpt, (int)ckpt_dtype, true, true);
+}
+
 int prop_forward_batched(prop_t h, int32_t nshot, const prop_shot *shots, float *const *rec_out)
 {
     g_err.clear();
@@ -1419,6 +1624,59 @@ int prop_set_timing(prop_t h, int32_t enable)
     TRY(fold_timing(h));
     h->timing = enable != 0;
     for (int k = 0; k < 4; ++k) h->ms[k] = 0, h->launches[k] = 0;
+    return PROP_OK;
+}
+
+int prop_set_option(prop_t h, int32_t option, int64_t value)
+{
+    g_err.clear();
+    if (!h) return fail(PROP_EINVAL, "handle is NULL");
+    switch (option) {
+    case PROP_OPT_GRAPH: h->opt_graph = value != 0; return PROP_OK;
+    case PROP_OPT_AUTOTUNE: h->opt_autotune = value != 0; return PROP_OK;
+    case PROP_OPT_TILE1:
+    case PROP_OPT_TILE2:
+        if (value != 0 && value != 1) return fail(PROP_EINVAL, "tile variant must be 0 or 1");
+        h->opt_shape[option == PROP_OPT_TILE1 ? 0 : 1] = (int)value;
+        return PROP_OK;
+    case PROP_OPT_ZC:
+        if (value < 0 || value > (1 << 20)) return fail(PROP_EINVAL, "z-chunk must be in [0, 2^20]");
+        h->opt_zc = (int)value;
+        return PROP_OK;
+    case PROP_OPT_XCD: h->opt_xcd = value != 0; return PROP_OK;
+    case PROP_OPT_BATCH_MB:
+        if (value < 0) return fail(PROP_EINVAL, "batch budget must be >= 0");
+        h->opt_batch_mb = value;
+        return PROP_OK;
+    case PROP_OPT_SCHEME:
+        if (value != TTI_SIX && value != TTI_SCALAR) return fail(PROP_EINVAL, "scheme must be 0 or 1");
+        h->opt_scheme = (int)value;
+        return PROP_OK;
+    default: return fail(PROP_EINVAL, "option %d cannot be set", (int)option);
+    }
+}
+
+int prop_get_option(prop_t h, int32_t option, int64_t *value)
+{
+    g_err.clear();
+    if (!h || !value) return fail(PROP_EINVAL, "NULL argument");
+    switch (option) {
+    case PROP_OPT_GRAPH: *value = h->opt_graph; break;
+    case PROP_OPT_AUTOTUNE: *value = h->opt_autotune; break;
+    case PROP_OPT_TILE1: *value = h->opt_shape[0]; break;
+    case PROP_OPT_TILE2: *value = h->opt_shape[1]; break;
+    case PROP_OPT_ZC: *value = h->opt_zc; break;
+    case PROP_OPT_XCD: *value = h->opt_xcd; break;
+    case PROP_OPT_BATCH_MB: *value = h->opt_batch_mb; break;
+    case PROP_OPT_SCHEME: *value = h->opt_scheme; break;
+    case PROP_INFO_TILE1: *value = h->last_tune.shape[0]; break;
+    case PROP_INFO_TILE2: *value = h->last_tune.shape[1]; break;
+    case PROP_INFO_ZC1: *value = h->last_tune.zc[0]; break;
+    case PROP_INFO_ZC2: *value = h->last_tune.zc[1]; break;
+    case PROP_INFO_GRAPHS: *value = h->graphs_launched; break;
+    case PROP_INFO_GROUPS: *value = h->last_groups; break;
+    default: return fail(PROP_EINVAL, "unknown option %d", (int)option);
+    }
     return PROP_OK;
 }
 
@@ -1494,6 +1752,8 @@ int prop_destroy(prop_t h)
     g_err.clear();
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
     (void)hipStreamSynchronize(h->st);
+    release_graphs(h);
+    if (h->cap) (void)hipStreamDestroy(h->cap);
     for (auto e : h->evpool) (void)hipEventDestroy(e);
     delete h;
     return PROP_OK;

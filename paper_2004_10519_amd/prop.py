@@ -21,9 +21,14 @@ TTI, ELASTIC = 1, 2
 CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 
 EXPORTS = ["prop_create", "prop_cfl_dt", "prop_set_model", "prop_forward", "prop_adjoint", "prop_gradient",
-           "prop_forward_batched", "prop_gradient_batched", "prop_read_state", "prop_set_timing",
-           "prop_kernel_time", "prop_ckpt_encode", "prop_ckpt_decode", "prop_dot_f64", "prop_destroy",
-           "prop_last_error"]
+           "prop_image", "prop_forward_batched", "prop_gradient_batched", "prop_image_batched", "prop_read_state", "prop_set_timing",
+           "prop_kernel_time", "prop_set_option", "prop_get_option", "prop_ckpt_encode", "prop_ckpt_decode",
+           "prop_dot_f64", "prop_destroy", "prop_last_error"]
+
+# option / info codes of prop_set_option and prop_get_option
+OPTIONS = {"graph": 1, "autotune": 2, "tile1": 3, "tile2": 4, "zc": 5, "xcd": 6, "batch_mb": 7, "scheme": 8,
+           "info_tile1": 101, "info_tile2": 102, "info_zc1": 103, "info_zc2": 104, "info_graphs": 105,
+           "info_groups": 106}
 
 
 class PropError(RuntimeError):
@@ -66,12 +71,16 @@ def lib() -> ctypes.CDLL:
         L.prop_forward.argtypes = [vp, ctypes.POINTER(CShot), vp]
         L.prop_adjoint.argtypes = [vp, ctypes.POINTER(CShot), vp, vp]
         L.prop_gradient.argtypes = [vp, ctypes.POINTER(CShot), vp, vp, i32, i32]
+        L.prop_image.argtypes = [vp, ctypes.POINTER(CShot), vp, vp, i32, i32]
+        L.prop_image_batched.argtypes = [vp, i32, ctypes.POINTER(CShot), ctypes.POINTER(vp), vp, i32, i32]
         L.prop_forward_batched.argtypes = [vp, i32, ctypes.POINTER(CShot), ctypes.POINTER(vp)]
         L.prop_gradient_batched.argtypes = [vp, i32, ctypes.POINTER(CShot), ctypes.POINTER(vp), vp, i32, i32]
         L.prop_read_state.argtypes = [vp, i32, vp]
         L.prop_set_timing.argtypes = [vp, i32]
         L.prop_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64),
                                        ctypes.POINTER(ctypes.c_char_p)]
+        L.prop_set_option.argtypes = [vp, i32, i64]
+        L.prop_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.prop_ckpt_encode.argtypes = [vp, i64, i32, vp, vp, vp]
         L.prop_ckpt_decode.argtypes = [vp, vp, i64, i32, vp, vp]
         L.prop_dot_f64.argtypes = [vp, vp, i64, ctypes.POINTER(dbl), vp]
@@ -232,6 +241,25 @@ class Propagator:
                                    int(n_ckpt), CKPT[ckpt_dtype]))
         return out
 
+    def image(self, shot: Shot, rec_in: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "bf16",
+              out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Zero-lag cross-correlation image sum_k sum_f f^k y_f^k of one shot (y driven by rec_in)."""
+        if out is None:
+            out = torch.empty(self._win_shape(shot), dtype=torch.float32, device="cuda")
+        cs = shot.c()
+        _check(lib().prop_image(self._h, ctypes.byref(cs), _dev(rec_in) if shot.nrec else None, _dev(out),
+                                int(n_ckpt), CKPT[ckpt_dtype]))
+        return out
+
+    def image_batched(self, shots: Sequence[Shot], rec_in: Sequence[torch.Tensor], image: torch.Tensor,
+                      n_ckpt: int = 48, ckpt_dtype: str = "f16") -> torch.Tensor:
+        """Sum of the shots' zero-lag images, accumulated in FP64 into ``image`` (whole grid)."""
+        arr = (CShot * len(shots))(*[s.c() for s in shots])
+        ptrs = (ctypes.c_void_p * len(shots))(*[_dev(r) for r in rec_in])
+        _check(lib().prop_image_batched(self._h, len(shots), arr, ptrs, _dev(image, torch.float64), int(n_ckpt),
+                                        CKPT[ckpt_dtype]))
+        return image
+
     def forward_batched(self, shots: Sequence[Shot], outs: Optional[list] = None) -> list:
         if outs is None:
             outs = [torch.empty((self.grid.nt, s.nrec), dtype=torch.float32, device="cuda") for s in shots]
@@ -255,6 +283,16 @@ class Propagator:
 
     def set_timing(self, enable: bool):
         _check(lib().prop_set_timing(self._h, int(bool(enable))))
+
+    def set_option(self, name: str, value: int):
+        """Set a run-time option: graph, autotune, tile1, tile2, zc, xcd, batch_mb, scheme."""
+        _check(lib().prop_set_option(self._h, OPTIONS[name], int(value)))
+
+    def get_option(self, name: str) -> int:
+        """Read an option, or info_tile1/2, info_zc1/2 (last TTI launch shape), info_graphs, info_groups."""
+        v = ctypes.c_int64()
+        _check(lib().prop_get_option(self._h, OPTIONS[name], ctypes.byref(v)))
+        return v.value
 
     def kernel_time(self, kclass: int):
         ms, n, name = ctypes.c_double(), ctypes.c_int64(), ctypes.c_char_p()

@@ -63,12 +63,16 @@ def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20):
                 rec=rec.astype(np.float32), kind=kind, wav=np.ascontiguousarray(wav, dtype=np.float32))
 
 
-def make_tti(case, prop):
+def make_tti(case, prop, scheme=0, **options):
+    """TTI propagator for a test case; scheme 0 = six-field pass-1 temporaries, 1 = scalar projections."""
     g = prop.Grid(case["shape"], case["h"], space_order=case["so"], nbl=case["nbl"], dt=case["dt"], nt=case["nt"],
                   v_ref=1500.0)
     mt = [dev(case["model"][k]) for k in ("m", "eps", "delta", "theta", "phi")]
     p = prop.Propagator(prop.TTI, g, mt)
     p._keep_model = mt
+    p.set_option("scheme", scheme)
+    for k, v in options.items():
+        p.set_option(k, v)
     shot = prop.Shot(case["src"], dev(case["wav"]), case["rec"])
     return p, shot
 

@@ -66,17 +66,73 @@ def test_batched_gradient_equals_plain_sum(prop, dtype):
     assert np.array_equal(host(gg), total)
 
 
-def test_batched_groups_split_by_memory_budget(prop, monkeypatch):
+def test_batched_groups_split_by_memory_budget(prop):
     """A tiny budget forces one shot per group; results do not change."""
     p, shots = _setup(prop, nt=60)
     rng = np.random.default_rng(8)
     res = [dev(rng.standard_normal((60, s.nrec))) for s in shots]
     g1 = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
     p.gradient_batched(shots, res, g1, n_ckpt=4, ckpt_dtype="f16")
-    monkeypatch.setenv("PROP_BATCH_MB", "1")
+    assert p.get_option("info_groups") == 1
+    p.set_option("batch_mb", 1)
     g2 = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
     p.gradient_batched(shots, res, g2, n_ckpt=4, ckpt_dtype="f16")
+    assert p.get_option("info_groups") == len(shots)
     assert np.array_equal(host(g1), host(g2))
+
+
+def test_graphs_and_autotuned_tiles_change_no_bit(prop):
+    """HIP-graph launches and autotuned tiles give the same bits as per-step launches with the fixed
+    tiles, for forward, adjoint, gradient and both batched calls; every call is made twice (graphs
+    are recorded again per call) with eager work and host synchronisation in between."""
+    p, shots = _setup(prop, nt=100)
+    rng = np.random.default_rng(9)
+    res = [dev(rng.standard_normal((100, s.nrec))) for s in shots]
+
+    def run_all():
+        out = [host(p.forward(shots[0])).copy(), host(p.adjoint(shots[1], res[1])).copy(),
+               host(p.gradient(shots[2], res[2], n_ckpt=6, ckpt_dtype="f16")).copy()]
+        out += [host(a).copy() for a in p.forward_batched(shots)]
+        gg = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+        p.gradient_batched(shots, res, gg, n_ckpt=6, ckpt_dtype="bf16")
+        out.append(host(gg).copy())
+        return out
+
+    ref = run_all()
+    assert p.get_option("info_graphs") == 0
+    p.set_option("graph", 1)
+    p.set_option("autotune", 1)
+    for rep in range(2):
+        g0 = p.get_option("info_graphs")
+        got = run_all()
+        assert p.get_option("info_graphs") > g0
+        assert p.get_option("info_tile1") in (0, 1) and p.get_option("info_tile2") in (0, 1)
+        assert p.get_option("info_zc1") > 0 and p.get_option("info_zc2") > 0
+        torch.ones(1000, device="cuda").sum().item()       # eager work between the runs
+        for a, b in zip(got, ref):
+            assert np.array_equal(a, b), f"repeat {rep}"
+
+
+def test_graph_runs_span_watchdog_checks(prop):
+    """A forward of 1100 steps is recorded as three graphs (watchdog every 500 steps); same bits."""
+    from paper_2004_10519_amd import inputs
+    shape, h = (48, 40, 36), (10.0, 10.0, 10.0)
+    mdl = inputs.tti_model(shape, 4, 33)
+    mt = [dev(a) for a in (inputs.slowness_squared(mdl["vp"]), mdl["eps"], mdl["delta"], mdl["theta"], mdl["phi"])]
+    g = prop.Grid(shape, h, space_order=4, nbl=4, dt=8e-4, nt=1100, v_ref=1500.0)
+    p = prop.Propagator(prop.TTI, g, mt)
+    src = np.array([[240.0, 200.0, 80.0]], np.float32)
+    rec = np.array([[100.0, 120.0, 30.0], [333.0, 250.0, 60.0]], np.float32)
+    shot = prop.Shot(src, dev(inputs.ricker(25.0, 8e-4, 1100)[:, None]), rec)
+    a = host(p.forward(shot)).copy()
+    p.set_option("graph", 1)
+    b = host(p.forward(shot)).copy()
+    assert p.get_option("info_graphs") == 3
+    assert np.array_equal(a, b)
+    with pytest.raises(prop.PropError):
+        p.set_option("tile1", 2)
+    with pytest.raises(prop.PropError):
+        p.set_option("info_groups", 1)
 
 
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 1e-2)])
@@ -100,3 +156,18 @@ def test_gradient_64cubed_vs_checker(prop, dtype, tol):
     err_masked = rel_l2(gg[mask], gold[mask])
     print(f"64^3 gradient rel-L2 vs FP64 ({dtype} checkpoints): {err:.3e} (masked {err_masked:.3e})")
     assert err <= tol
+
+
+def test_batched_image_equals_plain_sum(prop):
+    p, shots = _setup(prop, nt=90)
+    rng = np.random.default_rng(17)
+    data = [dev(rng.standard_normal((90, s.nrec))) for s in shots]
+    total = np.zeros(p.grid.arr_shape)
+    for s, r in zip(shots, data):
+        im = host(p.image(s, r, n_ckpt=4, ckpt_dtype="f16")).astype(np.float64)
+        (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
+        total[oz:oz + nz, oy:oy + ny, ox:ox + nx] += im
+    gi = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.image_batched(shots, data, gi, n_ckpt=4, ckpt_dtype="f16")
+    assert np.array_equal(host(gi), total)
+    assert np.abs(total).max() > 0

@@ -20,14 +20,18 @@ def prop():
     return P
 
 
-def test_tti2d_101_full_parity(prop, orc):
+SCHEMES = [0, 1]   # six-field temporaries / scalar projections between the two passes
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_tti2d_101_full_parity(prop, orc, scheme):
     """The 2D constant-medium case at full length: 101 x 101, so 4, 500 steps, 101 surface receivers."""
     from paper_2004_10519_amd import configs
     w = configs.tti2d_101()
     mdl = w.make_model()
     case = dict(shape=w.shape, h=w.spacing, so=w.space_order, nbl=w.nbl, nt=w.nt, dt=w.dt, model=mdl,
                 src=w.src_xyz, rec=w.rec_xyz, wav=w.wavelet())
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     d = host(p.forward(shot))
     fields = [host(p.read_state(i)) for i in range(4)]
     g, mod = oracle_tti(case, orc)
@@ -37,11 +41,13 @@ def test_tti2d_101_full_parity(prop, orc):
         assert rel_l2(a, b) <= 1e-4
 
 
-@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (4, (130, 18, 21)), (8, (90, 1, 77))])
-def test_tti_forward_parity(prop, orc, so, shape):
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (4, (130, 18, 21)), (8, (90, 1, 77)),
+                                      (16, (75, 33, 45))])
+def test_tti_forward_parity(prop, orc, so, shape, scheme):
     """Several tiles and ragged tails in x, y and z, absorbing layers, two off-grid sources."""
     case = tti_case(shape, so, 5, 90)
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     d = host(p.forward(shot))
     pf, qf = host(p.read_state(0)), host(p.read_state(1))
     g, mod = oracle_tti(case, orc)
@@ -50,10 +56,11 @@ def test_tti_forward_parity(prop, orc, so, shape):
     assert rel_l2(pf, po) <= 1e-4 and rel_l2(qf, qo) <= 1e-4
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (8, (90, 1, 77))])
-def test_tti_adjoint_parity(prop, orc, so, shape):
+def test_tti_adjoint_parity(prop, orc, so, shape, scheme):
     case = tti_case(shape, so, 5, 80)
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     rng = np.random.default_rng(3)
     rec = rng.standard_normal((case["nt"], len(case["rec"]))).astype(np.float32)
     s = host(p.adjoint(shot, dev(rec)))
@@ -64,10 +71,11 @@ def test_tti_adjoint_parity(prop, orc, so, shape):
     assert rel_l2(yp, ypo) <= 1e-4
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("shape", [(70, 37, 29), (90, 1, 77)])
-def test_tti_gpu_dot_test(prop, shape):
+def test_tti_gpu_dot_test(prop, shape, scheme):
     case = tti_case(shape, 8, 5, 100)
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     rng = np.random.default_rng(11)
     x = dev(rng.standard_normal(case["wav"].shape))
     shot.wavelet = x
@@ -91,10 +99,11 @@ def _bandlimited_residual(case, seed):
     return out.astype(np.float32)
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 5e-3)])
-def test_tti_gradient_parity(prop, orc, dtype, tol):
+def test_tti_gradient_parity(prop, orc, dtype, tol, scheme):
     case = tti_case((40, 36, 32), 8, 5, 150, nrec=30)
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     res = _bandlimited_residual(case, 4)
     gg = host(p.gradient(shot, dev(res), n_ckpt=7, ckpt_dtype=dtype))
     g, mod = oracle_tti(case, orc)
@@ -116,6 +125,27 @@ def test_tti_gradient_single_segment_equals_full_storage(prop, orc):
     d, _, _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
     _, go, _ = orc.tti_gradient(g, mod, case["src"], case["wav"], case["rec"], d - res)
     assert rel_l2(gg, go) <= 1e-4
+
+
+@pytest.mark.parametrize("so", [4, 8, 12, 16])
+def test_scalar_scheme_tiles_and_chunks(prop, so):
+    """Scalar scheme: both tile variants of each pass and short z-chunks (more chunk seams and queue
+    refills) give the traces of its default launch to 1e-6, and the six-field scheme's to 1e-5 (the
+    two schemes round differently: the axis component n_z is re-formed from n_x, n_y, and the
+    vectors are formed in the other pass)."""
+    case = tti_case((83, 29, 41), so, 5, 60)
+    p0, shot = make_tti(case, prop, 0)
+    six = host(p0.forward(shot)).copy()
+    p1, shot = make_tti(case, prop, 1)
+    ref = host(p1.forward(shot)).copy()
+    assert rel_l2(ref, six) <= 1e-5, rel_l2(ref, six)
+    for t1 in (0, 1):
+        for t2 in (0, 1):
+            for zc in (0, 5):
+                p, shot = make_tti(case, prop, 1, tile1=t1, tile2=t2, zc=zc)
+                d = host(p.forward(shot))
+                assert rel_l2(d, ref) <= 1e-6, (t1, t2, zc, rel_l2(d, ref))
+                assert p.get_option("info_zc2") == (zc if zc else p.get_option("info_zc1"))
 
 
 def test_codec_bit_exact(prop, orc):
@@ -181,3 +211,18 @@ def test_error_paths(prop):
     with pytest.raises(prop.PropError) as e:
         p.read_state(0)
     assert e.value.code == prop.PROP_ESTATE
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3)])
+def test_tti_image_parity(prop, orc, dtype, tol, scheme):
+    """Zero-lag cross-correlation image of one shot against the checker's image."""
+    case = tti_case((40, 36, 32), 8, 5, 150, nrec=30)
+    p, shot = make_tti(case, prop, scheme)
+    data = _bandlimited_residual(case, 6)
+    im = host(p.image(shot, dev(data), n_ckpt=7, ckpt_dtype=dtype))
+    g, mod = oracle_tti(case, orc)
+    io = orc.tti_image(g, mod, case["src"], case["wav"], case["rec"], data)
+    err = rel_l2(im, io)
+    print(f"image rel-L2 vs FP64 ({dtype} checkpoints): {err:.3e}")
+    assert err <= tol, err
