@@ -12,9 +12,11 @@
 //   v   <- g (v + dt bbar (D_tau tau))
 //   tau <- g (tau + dt C E v)
 // Adjoint step (exact transpose, applied in reverse): with sigma = C (g tau~) and u = bbar (g v~)
-//   v~ += dt E^T sigma, tau~ <- g tau~;   then   tau~ += dt D_tau^T u, v~ <- g v~,
+//   v~ <- g (v~ + dt E^T sigma);   then   tau~ <- g tau~ + dt D_tau^T u,
 // where E^T = -(the D_tau pattern) and D_tau^T = -(the E pattern), so the adjoint reuses the two
-// forward stencil kernels on the pointwise-weighted fields with a minus sign.
+// forward stencil kernels on the pointwise-weighted fields with a minus sign.  Three launches:
+// el_mix_stress forms sigma; el_vel updates v~ and forms u in its epilogue; el_stress applies g
+// to tau~ while it adds dt D_tau^T u.
 #include "jobs.h"
 
 namespace {
@@ -137,14 +139,11 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
         const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
         const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
         const float v0 = gld(J.v[0], si), v1 = gld(J.v[1], si), v2 = gld(J.v[2], si);
-        float b0 = 0.f, bxn = 0.f, byn = 0.f, bzn = 0.f, g = 1.f;
-        if (MODE == EL_FWD) {
-            b0 = gld(J.b, mi);
-            bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
-            byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
-            bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
-            g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
-        }
+        const float b0 = gld(J.b, mi);
+        const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
+        const float byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+        const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
+        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (z + 1 < z1) fetch(z + 1);
         const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
                          ds_q<R, false>(qxz, W.wz);
@@ -158,9 +157,14 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
                 gst(J.v[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
                 gst(J.v[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
             } else {
-                gst(J.v[0], si, v0 - dt * fx);
-                gst(J.v[1], si, v1 - dt * fy);
-                gst(J.v[2], si, v2 - dt * fz);
+                const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
+                const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
+                gst(J.v[0], si, c0);
+                gst(J.v[1], si, c1);
+                gst(J.v[2], si, c2);
+                gst(J.u[0], si, (0.5f * (b0 + bxn)) * c0);
+                gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
+                gst(J.u[2], si, (0.5f * (b0 + bzn)) * c2);
             }
         }
         b ^= 1;
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
     const int gx = x0 + tx, gy = y0 + ty;
     const bool own = gx < w.nx && gy < w.ny;
-    float *const *V = (MODE == EL_FWD) ? J.v : J.aux;
+    float *const *V = (MODE == EL_FWD) ? J.v : J.u;
     const float *__restrict__ Vx = V[0];
     const float *__restrict__ Vy = V[1];
     const float *__restrict__ Vz = V[2];
@@ -274,7 +278,8 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
         float t[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) t[c] = gld(J.t[c], si);
-        float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f, g = 1.f;
+        float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (MODE == EL_FWD) {
             const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
             lam = gld(J.lam, mi);
@@ -283,7 +288,6 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
             mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
             mxz = 0.25f * (mu0 + mx_ + mz_ + gld(J.mu, mi + ox + oz));
             myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
-            g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         }
         if (z + 1 < z1) fetch(z + 1);
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
@@ -302,19 +306,22 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
                 gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
                 gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
             } else {
-                gst(J.t[0], si, t[0] - dt * exx);
-                gst(J.t[1], si, t[1] - dt * eyy);
-                gst(J.t[2], si, t[2] - dt * ezz);
-                gst(J.t[3], si, t[3] - dt * gxy);
-                gst(J.t[4], si, t[4] - dt * gxz);
-                gst(J.t[5], si, t[5] - dt * gyz);
+                float tg[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) tg[c] = g * t[c];
+                gst(J.t[0], si, tg[0] - dt * exx);
+                gst(J.t[1], si, tg[1] - dt * eyy);
+                gst(J.t[2], si, tg[2] - dt * ezz);
+                gst(J.t[3], si, tg[3] - dt * gxy);
+                gst(J.t[4], si, tg[4] - dt * gxz);
+                gst(J.t[5], si, tg[5] - dt * gyz);
             }
         }
         b ^= 1;
     }
 }
 
-// sigma = C (g tau~) into aux[0..5]; tau~ <- g tau~.
+// sigma = C (g tau~) into aux[0..5] (tau~ itself is scaled by g later, in the stress pass).
 __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
 {
     const ElJob &J = jobs[0];
@@ -325,10 +332,7 @@ __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
     const float g = gld(J.gx, x) * gld(J.gy, y) * gld(J.gz, z);
     float t[6];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-        t[c] = g * gld(J.t[c], si);
-        gst(J.t[c], si, t[c]);
-    }
+    for (int c = 0; c < 6; ++c) t[c] = g * gld(J.t[c], si);
     const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
     const float lam = gld(J.lam, mi), mu0 = gld(J.mu, mi);
     const float lt = lam * (t[0] + t[1] + t[2]), m2 = 2.f * mu0;
@@ -338,28 +342,6 @@ __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
     gst(J.aux[3], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oy) + gld(J.mu, mi + ox + oy)) * t[3]);
     gst(J.aux[4], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oz) + gld(J.mu, mi + ox + oz)) * t[4]);
     gst(J.aux[5], si, 0.25f * (mu0 + gld(J.mu, mi + oy) + gld(J.mu, mi + oz) + gld(J.mu, mi + oy + oz)) * t[5]);
-}
-
-// u = bbar (g v~) into aux[0..2]; v~ <- g v~.
-__global__ void el_mix_vel(const ElJob *__restrict__ jobs)
-{
-    const ElJob &J = jobs[0];
-    const Win w = J.w;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= w.nx) return;
-    const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
-    const float g = gld(J.gx, x) * gld(J.gy, y) * gld(J.gz, z);
-    const float b0 = gld(J.b, mi);
-    const float bx = 0.5f * (b0 + gld(J.b, mi + (x + 1 < w.nx ? 1 : 0)));
-    const float by = 0.5f * (b0 + gld(J.b, mi + (y + 1 < w.ny ? w.mx : 0)));
-    const float bz = 0.5f * (b0 + gld(J.b, mi + (z + 1 < w.nz ? w.my : 0)));
-    const float v0 = g * gld(J.v[0], si), v1 = g * gld(J.v[1], si), v2 = g * gld(J.v[2], si);
-    gst(J.v[0], si, v0);
-    gst(J.v[1], si, v1);
-    gst(J.v[2], si, v2);
-    gst(J.aux[0], si, bx * v0);
-    gst(J.aux[1], si, by * v1);
-    gst(J.aux[2], si, bz * v2);
 }
 
 template <int R>
@@ -412,14 +394,8 @@ void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int
     EL_SWITCH(stress_dispatch, mode, jobs, tiles, ntiles, zc, W, dt, st)
 }
 
-void launch_el_mix_stress(const ElJob *jobs, int, const Win &w0, hipStream_t st, int64_t)
+void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st)
 {
     dim3 blk(256), grd((w0.nx + 255) / 256, w0.ny, w0.nz);
     hipLaunchKernelGGL(el_mix_stress, grd, blk, 0, st, jobs);
-}
-
-void launch_el_mix_vel(const ElJob *jobs, int, const Win &w0, hipStream_t st, int64_t)
-{
-    dim3 blk(256), grd((w0.nx + 255) / 256, w0.ny, w0.nz);
-    hipLaunchKernelGGL(el_mix_vel, grd, blk, 0, st, jobs);
 }

@@ -28,7 +28,8 @@ struct ElJob {
     Win w;
     float *v[3];                  // vx, vy, vz
     float *t[6];                  // txx, tyy, tzz, txy, txz, tyz
-    float *aux[6];                // adjoint temporaries (stiffness-weighted stresses, weighted velocities)
+    float *aux[6];                // adjoint: stiffness-weighted stresses sigma = C (g tau~)
+    float *u[3];                  // adjoint: buoyancy-weighted velocities u = bbar (g v~)
     const float *lam, *mu, *b;    // lambda, mu, buoyancy
     const float *gx, *gy, *gz;    // absorbing layer: exp(-kappa_a dt) per window axis
 };
@@ -49,6 +50,5 @@ void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int nt
                    const Weights &W, float dt, hipStream_t st);
 void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                       const Weights &W, float dt, hipStream_t st);
-void launch_el_mix_stress(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
-void launch_el_mix_vel(const ElJob *jobs, int njobs, const Win &w0, hipStream_t st, int64_t npts_max);
+void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st);
 int el_tile_rows(int R);

@@ -194,7 +194,7 @@ struct Slot {
     DevBuf fields;              // all wavefields of this window
     float *f[24] = {};          // TTI: 0-1 p, 2-3 q, 4-9 t/s, 10 grad, 11-12 yp, 13-14 yq, 15-18 w = C y
                                 // (two levels of two components)
-                                // elastic: 0-2 v, 3-8 tau, 9-14 aux
+                                // elastic: 0-2 v, 3-8 tau, 9-14 sigma, 15-17 u (adjoint)
     DevBuf tabs;                // damping tables (nx + ny + nz floats)
     Plans src_inj, rec_inj, rec_inj_vz, rec_gat, rec_gat_vz, src_gat;
     DevBuf job_fwd, job_adj;    // TTIJob / ElJob on the device
@@ -459,7 +459,7 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
     sl.w = w;
     for (int a = 0; a < 3; ++a) sl.o[a] = o[a];
     sl.plane = w.sy * w.nz;
-    const int nf = h->kind == PROP_TTI ? 19 : 15;
+    const int nf = h->kind == PROP_TTI ? 19 : 18;
     if (!same) TRY(sl.fields.ensure((size_t)nf * sl.plane * sizeof(float)));
     for (int i = 0; i < nf; ++i) sl.f[i] = sl.fields.as<float>() + (size_t)i * sl.plane;
     // damping tables
@@ -517,6 +517,7 @@ ElJob el_job(const prop_s *h, const Slot &sl)
     for (int i = 0; i < 3; ++i) J.v[i] = sl.f[i];
     for (int i = 0; i < 6; ++i) J.t[i] = sl.f[3 + i];
     for (int i = 0; i < 6; ++i) J.aux[i] = sl.f[9 + i];
+    for (int i = 0; i < 3; ++i) J.u[i] = sl.f[15 + i];
     J.lam = h->c[0];
     J.mu = h->c[1];
     J.b = h->c[2];
@@ -1445,7 +1446,7 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
     TRY(prepare_shot(h, sl, s, false, false, true, true));
     if (s->nrec > 0 && !rec_in) return fail(PROP_EINVAL, "rec_in is NULL");
     if (s->nsrc > 0 && !src_out) return fail(PROP_EINVAL, "src_out is NULL");
-    aux_fill(sl.f[0], 15 * sl.plane, 0.f, h->st);
+    aux_fill(sl.f[0], 18 * sl.plane, 0.f, h->st);
     const ElJob *job = sl.job_fwd.as<ElJob>();
     const float dt = (float)h->g.dt;
     for (int n = h->g.nt - 1; n >= 0; --n) {
@@ -1453,12 +1454,11 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
         if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], sl.f[4], sl.f[5], h->st);
         if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
         if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], sl.f[4], sl.f[5], dt, src_out + (size_t)n * s->nsrc, h->st);
-        launch_el_mix_stress(job, 1, sl.w, h->st, 0);
+        launch_el_mix_stress(job, sl.w, h->st);
         {
             Timed t(h, 2);
             launch_el_vel(h->R, EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
         }
-        launch_el_mix_vel(job, 1, sl.w, h->st, 0);
         {
             Timed t(h, 3);
             launch_el_stress(h->R, EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
