@@ -65,9 +65,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0):
+def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tiles=None):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/pmc_traffic.json), if they were
-    taken on the current kernel source; else None."""
+    taken on the current kernel source with the same tiles; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -75,6 +75,8 @@ def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0):
         rec = json.load(fh)
     ent = rec.get(f"{kclass}/{scheme}")
     if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
+        return None
+    if tiles is not None and ent.get("tiles") != tiles:
         return None
     return ent.get("bytes_per_launch")
 
@@ -359,8 +361,9 @@ def main():
     ms_tot, nl, name = kt[dom]
     avg_s = ms_tot / 1e3 / max(nl, 1)
     scheme = p.get_option("scheme")
+    tiles = [p.get_option(k) for k in ("info_tile1", "info_zc1", "info_tile2", "info_zc2")]
     achieved = kernel_bytes(dom, scheme) * npts / avg_s / 1e9
-    traffic = traffic_from_profiles(dom, npts, scheme)
+    traffic = traffic_from_profiles(dom, npts, scheme, tiles)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": kernel_bytes(dom, scheme) * npts, "scheme": scheme,
@@ -370,13 +373,13 @@ def main():
                                                              (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
                         for k in kt},
             "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
-    roof["tiles"] = {"pass1": {"variant": p.get_option("info_tile1"), "zc": p.get_option("info_zc1")},
-                     "pass2": {"variant": p.get_option("info_tile2"), "zc": p.get_option("info_zc2")},
+    roof["tiles"] = {"pass1": {"variant": tiles[0], "zc": tiles[1]}, "pass2": {"variant": tiles[2], "zc": tiles[3]},
                      "autotuned": True}
-    copy_gbs = copy_bandwidth(torch)
-    roof["copy_GBps"] = round(copy_gbs, 1)
-    roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
-    log(f"[bench] device copy {copy_gbs:.0f} GB/s; dominant kernel {achieved:.0f} GB/s algorithmic")
+    if not args.copy_probe:   # (counter runs calibrate on the probe copy alone)
+        copy_gbs = copy_bandwidth(torch)
+        roof["copy_GBps"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
+        log(f"[bench] device copy {copy_gbs:.0f} GB/s; dominant kernel {achieved:.0f} GB/s algorithmic")
 
     paths = {}
     if not args.only_main:
