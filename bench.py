@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per grid point of one launch of each stencil kernel (FP32).  TTI, per two-pass
 # scheme (0: six-field temporaries, 1: scalar projections) and direction:
-#   scheme 0 pass 1: read u, v, n_x, n_y, n_z; write t (3), s (3)                         -> 11 x 4
+#   scheme 0 pass 1: read u, v, n_x, n_y; write t (3), s (3)                              -> 10 x 4
 #   scheme 0 pass 2: read t, s (6), f, f- for p and q (4), m, 1+2eps, sqrt(1+2delta) (3);
 #                    write p+, q+ (2); adjoint also writes w = C y+ (2)                  -> 15 / 17 x 4
 #   scheme 1 pass 1: read u, v, n_x, n_y; write n.grad u, n.grad v                       ->  6 x 4
@@ -39,10 +39,11 @@ HBM_PEAK_GBS = 8000.0
 # Elastic:
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
-TTI_KERNEL_BYTES = {(0, 0, False): 44, (0, 1, False): 60, (0, 0, True): 44, (0, 1, True): 68,
+TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
                     (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64}
 KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
 TTI_SCHEME = 0      # two-pass scheme of every TTI handle (--scheme)
+FIXED_TILES = None  # (tile1, zc1, tile2, zc2) of the main run instead of the autotuner (--tiles)
 
 
 def kernel_bytes(kclass: int, scheme: int = 0, adjoint: bool = False) -> int:
@@ -65,9 +66,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tiles=None):
+def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/pmc_traffic.json), if they were
-    taken on the current kernel source with the same tiles; else None."""
+    taken on the current kernel source with the same tile variant and z-chunk; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
     if not os.path.exists(path):
         return None
@@ -76,7 +77,7 @@ def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tiles=None):
     ent = rec.get(f"{kclass}/{scheme}")
     if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
         return None
-    if tiles is not None and ent.get("tiles") != tiles:
+    if tile is not None and ent.get("tile") != list(tile):
         return None
     return ent.get("bytes_per_launch")
 
@@ -89,7 +90,11 @@ def setup_tti(w, torch, prop):
     p._keep = dev
     if w.kind == "tti":
         p.set_option("scheme", TTI_SCHEME)
-        p.set_option("autotune", 1)
+        if FIXED_TILES:
+            for k, v in zip(("tile1", "zc", "tile2", "zc2"), FIXED_TILES):
+                p.set_option(k, v)
+        else:
+            p.set_option("autotune", 1)
     shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz, w.rec_kind)
     return p, shot
 
@@ -300,7 +305,7 @@ def measure_batched(torch, prop, nt, nshot):
 
 
 def main():
-    global TTI_SCHEME
+    global TTI_SCHEME, FIXED_TILES
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
@@ -311,12 +316,19 @@ def main():
     ap.add_argument("--batched", type=int, default=0, metavar="NSHOT",
                     help="also run the batched-vs-plain gradient comparison with NSHOT shots (64 = full)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tiles", default=None, metavar="T1,Z1,T2,Z2",
+                    help="fixed tile variants and z-chunks of the two TTI passes instead of the autotuner "
+                         "(counter runs: the profiler serialises launches, which would mislead the autotuner)")
     ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1),
                     help="TTI two-pass scheme: 0 six-field temporaries, 1 scalar projections")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     TTI_SCHEME = args.scheme
+    if args.tiles:
+        FIXED_TILES = [int(v) for v in args.tiles.split(",")]
+        if len(FIXED_TILES) != 4:
+            ap.error("--tiles takes four integers")
     if args.gpus != 1:
         print(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
               "(several GPUs would each take a shot group and sum the gradient with one all-reduce)",
@@ -363,7 +375,7 @@ def main():
     scheme = p.get_option("scheme")
     tiles = [p.get_option(k) for k in ("info_tile1", "info_zc1", "info_tile2", "info_zc2")]
     achieved = kernel_bytes(dom, scheme) * npts / avg_s / 1e9
-    traffic = traffic_from_profiles(dom, npts, scheme, tiles)
+    traffic = traffic_from_profiles(dom, npts, scheme, tiles[2 * dom:2 * dom + 2])
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": kernel_bytes(dom, scheme) * npts, "scheme": scheme,
@@ -374,7 +386,7 @@ def main():
                         for k in kt},
             "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
     roof["tiles"] = {"pass1": {"variant": tiles[0], "zc": tiles[1]}, "pass2": {"variant": tiles[2], "zc": tiles[3]},
-                     "autotuned": True}
+                     "autotuned": not FIXED_TILES}
     if not args.copy_probe:   # (counter runs calibrate on the probe copy alone)
         copy_gbs = copy_bandwidth(torch)
         roof["copy_GBps"] = round(copy_gbs, 1)

@@ -198,6 +198,7 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *   PROP_OPT_TILE1/2   0 or 1 (default 1): tile variant of TTI pass 1 / pass 2 when not
  *                      autotuning (0: 64 x 8 threads, 1: 64 x 16 threads).
  *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
+ *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default).
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
  *   PROP_OPT_BATCH_MB  device-memory budget of the batched shot-group planner in MiB,
  *                      0 = 85 % of the free memory (default).
@@ -217,6 +218,7 @@ enum {
     PROP_OPT_XCD = 6,
     PROP_OPT_BATCH_MB = 7,
     PROP_OPT_SCHEME = 8,
+    PROP_OPT_ZC2 = 9,
     PROP_INFO_TILE1 = 101,
     PROP_INFO_TILE2 = 102,
     PROP_INFO_ZC1 = 103,

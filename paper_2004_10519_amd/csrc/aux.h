@@ -80,7 +80,7 @@ void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *s
 void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double *out, hipStream_t st);
 int aux_dot_blocks();
 void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,
-                  int ndim, float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats, hipStream_t st);
+                  int ndim, float *A, float *B, float *nx, float *ny, unsigned *stats, hipStream_t st);
 void aux_el_prep(const float *vp, const float *vs, const float *rho, int64_t n, float *lam, float *mu, float *b,
                  unsigned *stats, hipStream_t st);
 void aux_nonfinite_win(const float *f, const Win &w, unsigned *flag, hipStream_t st);

@@ -373,7 +373,7 @@ __global__ void k_dot_final(const double *__restrict__ part, double *__restrict_
 // bit 1: eps < delta).
 __global__ void k_tti_prep(const float *__restrict__ m, const float *__restrict__ eps, const float *__restrict__ dl,
                            const float *__restrict__ th, const float *__restrict__ ph, int64_t n, int ndim,
-                           float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats)
+                           float *A, float *B, float *nx, float *ny, unsigned *stats)
 {
     unsigned vmax = 0, emax = 0, flags = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -383,11 +383,11 @@ __global__ void k_tti_prep(const float *__restrict__ m, const float *__restrict_
         float st, ct, sp, cp;
         sincosf(t, &st, &ct);
         sincosf(p, &sp, &cp);
-        // the axis is stored with nz >= 0 (n and -n give the same operators)
+        // the axis is stored as (n_x, n_y) of the unit vector with n_z >= 0 (n and -n give the same
+        // operators); the kernels re-form n_z = sqrt(1 - n_x^2 - n_y^2)
         const float sg = ct < 0.f ? -1.f : 1.f;
         nx[i] = sg * (st * cp);
         ny[i] = ndim == 3 ? sg * (st * sp) : 0.f;
-        nz[i] = sg * ct;
         if (!(mm > 0.f) || !isfinite(mm) || !isfinite(e) || !isfinite(d) || !isfinite(t) || !isfinite(p)) flags |= 1u;
         else vmax = max(vmax, __float_as_uint(1.0f / sqrtf(mm)));
         if (e < d - 1e-6f) flags |= 2u;
@@ -562,9 +562,9 @@ void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double
 int aux_dot_blocks() { return DOT_BLOCKS; }
 
 void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,
-                  int ndim, float *A, float *B, float *nx, float *ny, float *nz, unsigned *stats, hipStream_t st)
+                  int ndim, float *A, float *B, float *nx, float *ny, unsigned *stats, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tti_prep, dim3(nblocks(n)), dim3(BS), 0, st, m, eps, dl, th, ph, n, ndim, A, B, nx, ny, nz,
+    hipLaunchKernelGGL(k_tti_prep, dim3(nblocks(n)), dim3(BS), 0, st, m, eps, dl, th, ph, n, ndim, A, B, nx, ny,
                        stats);
 }
 

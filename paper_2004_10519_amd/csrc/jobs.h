@@ -15,7 +15,7 @@ struct TTIJob {
                                   // (I - n n^T) grad u and n n^T grad v; scalar scheme: t[0] = n . grad u,
                                   // t[1] = n . grad v
     const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
-    const float *nx, *ny, *nz;    // symmetry axis, nz >= 0 (model layout)
+    const float *nx, *ny;         // symmetry axis (model layout); n_z = sqrt(1 - n_x^2 - n_y^2) >= 0
     const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
     float *grad;                  // imaging-condition accumulator (state layout) or null
     int image;                    // imaging condition: 0 = gradient w.r.t. m, 1 = zero-lag cross-correlation

@@ -212,7 +212,7 @@ struct prop_s {
     prop_model model;
     int R;
     Weights W;
-    DevBuf coef;                // TTI: A, B, nx, ny, nz; elastic: lam, mu, b (whole grid)
+    DevBuf coef;                // TTI: A, B, nx, ny (axis with nz >= 0); elastic: lam, mu, b (whole grid)
     const float *c[5] = {};
     DevBuf stats, dotpart, dotout, flag;
     Slot slot;
@@ -234,6 +234,7 @@ struct prop_s {
     int opt_graph = 0, opt_autotune = 0, opt_xcd = 0;
     int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
+    int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1)
     int opt_scheme = TTI_SIX;   // TTI two-pass scheme (TTI_SIX or TTI_SCALAR)
     int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
     // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
@@ -499,7 +500,6 @@ TTIJob tti_job(const prop_s *h, const Slot &sl, bool adjoint)
     J.B = h->c[1];
     J.nx = h->c[2];
     J.ny = h->c[3];
-    J.nz = h->c[4];
     const float *tab = sl.tabs.as<float>();
     J.ex = tab;
     J.ey = tab + sl.w.nx;
@@ -628,7 +628,7 @@ int prep_model(prop_s *h, const prop_model *m)
         if (!m->p[i]) return fail(PROP_EINVAL, "model array %d is NULL", i);
     h->model = *m;
     const int64_t n = npts_grid(h->g);
-    const int nc = h->kind == PROP_TTI ? 5 : 3;
+    const int nc = h->kind == PROP_TTI ? 4 : 3;
     TRY(h->coef.ensure((size_t)nc * n * sizeof(float)));
     for (int i = 0; i < nc; ++i) h->c[i] = h->coef.as<float>() + (size_t)i * n;
     TRY(h->stats.ensure(4 * sizeof(unsigned)));
@@ -636,7 +636,7 @@ int prep_model(prop_s *h, const prop_model *m)
     float *cc = h->coef.as<float>();
     if (h->kind == PROP_TTI)
         aux_tti_prep(m->p[0], m->p[1], m->p[2], m->p[3], h->g.ndim == 3 ? m->p[4] : m->p[3], n, h->g.ndim, cc,
-                     cc + n, cc + 2 * n, cc + 3 * n, cc + 4 * n, h->stats.as<unsigned>(), h->st);
+                     cc + n, cc + 2 * n, cc + 3 * n, h->stats.as<unsigned>(), h->st);
     else
         aux_el_prep(m->p[0], m->p[1], m->p[2], n, cc, cc + n, cc + 2 * n, h->stats.as<unsigned>(), h->st);
     HIPCHK(hipGetLastError());
@@ -823,6 +823,11 @@ prop_s::Tune default_tune(const prop_s *h, const std::vector<Slot *> &slots)
     t.shape[0] = h->opt_shape[0];
     t.shape[1] = h->opt_shape[1];
     t.zc[0] = t.zc[1] = group_zc(h, slots, 1, t.shape[0]);
+    if (h->opt_zc2 > 0) {
+        int nzmax = 1;
+        for (auto *sl : slots) nzmax = std::max(nzmax, sl->w.nz);
+        t.zc[1] = std::min(h->opt_zc2, nzmax);
+    }
     return t;
 }
 
@@ -1648,6 +1653,10 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
         if (value < 0 || value > (1 << 20)) return fail(PROP_EINVAL, "z-chunk must be in [0, 2^20]");
         h->opt_zc = (int)value;
         return PROP_OK;
+    case PROP_OPT_ZC2:
+        if (value < 0 || value > (1 << 20)) return fail(PROP_EINVAL, "z-chunk must be in [0, 2^20]");
+        h->opt_zc2 = (int)value;
+        return PROP_OK;
     case PROP_OPT_XCD: h->opt_xcd = value != 0; return PROP_OK;
     case PROP_OPT_BATCH_MB:
         if (value < 0) return fail(PROP_EINVAL, "batch budget must be >= 0");
@@ -1671,6 +1680,7 @@ int prop_get_option(prop_t h, int32_t option, int64_t *value)
     case PROP_OPT_TILE1: *value = h->opt_shape[0]; break;
     case PROP_OPT_TILE2: *value = h->opt_shape[1]; break;
     case PROP_OPT_ZC: *value = h->opt_zc; break;
+    case PROP_OPT_ZC2: *value = h->opt_zc2; break;
     case PROP_OPT_XCD: *value = h->opt_xcd; break;
     case PROP_OPT_BATCH_MB: *value = h->opt_batch_mb; break;
     case PROP_OPT_SCHEME: *value = h->opt_scheme; break;

@@ -126,7 +126,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
             const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
             n0[r] = gld(J.nx, mi);
             n1[r] = gld(J.ny, mi);
-            n2[r] = WS ? axis_z(n0[r], n1[r]) : gld(J.nz, mi);
+            n2[r] = axis_z(n0[r], n1[r]);
         }
         if (z + 1 < z1) fetch(z + 1);
 #pragma unroll

@@ -1,0 +1,185 @@
+"""Parity at the benchmark workloads' full sizes, in the launch configuration bench.py times
+(autotuned tiles), on outputs the FP64 checker can compute, and properties that hold at any size.
+
+* 512^3 so12 TTI and 400^3 so8 elastic: a few time steps from the workload's own source.  After n
+  steps the wavefield is exactly zero beyond n * (stencil reach per step) points from the source, so
+  the checker runs on a sub-grid that contains that support plus a full absorbing layer of its own
+  (where the field is zero, so its damping acts on zeros).  The sub-grid keeps the full grid's top
+  face, so the absorbing layer the source sits next to is the same on both sides.  The GPU fields
+  and traces must match the checker there and be exactly zero everywhere else.
+* 512^3 so12 TTI dot test over 20 steps and 65536 receivers.
+* 256^3 so8 gradient (2000 steps, 48 FP16 checkpoints): central finite difference of the FP64
+  misfit along a smooth model perturbation.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import dev, host, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def prop():
+    from paper_2004_10519_amd import prop as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def tti512_model():
+    """The 512^3 workload's seeded model (generated once for the module)."""
+    from paper_2004_10519_amd import configs
+    return configs.tti3d_512(nt=1).make_model()
+
+
+def _tti512(nt, model):
+    from paper_2004_10519_amd import configs
+    w = configs.tti3d_512(nt=nt)
+    w.model = model
+    return w
+
+
+def _subgrid(w, reach):
+    """Index ranges [lo, hi) per axis (x, y, z) of a sub-grid holding the support after the steps
+    plus an absorbing layer; z starts at the top face."""
+    s = np.asarray(w.src_xyz[0], np.float64) / np.asarray(w.spacing)
+    lo, hi = [], []
+    for a in range(3):
+        l_ = int(math.floor(s[a] - reach)) - w.nbl - 2
+        h_ = int(math.ceil(s[a] + reach)) + w.nbl + 3
+        lo.append(max(l_, 0) if a < 2 else 0)
+        hi.append(min(h_, w.shape[a]))
+    assert lo[0] > w.nbl and lo[1] > w.nbl and hi[0] < w.shape[0] - w.nbl and hi[1] < w.shape[1] - w.nbl
+    return lo, hi
+
+
+def _inside(xyz, lo, hi, h):
+    u = np.asarray(xyz, np.float64) / np.asarray(h)
+    return np.all((u >= np.asarray(lo)) & (u <= np.asarray(hi) - 1), axis=1)
+
+
+def _compare_fields(gpu_full, ref_sub, lo, hi, tol):
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    assert rel_l2(gpu_full[sl], ref_sub) <= tol, rel_l2(gpu_full[sl], ref_sub)
+    rest = gpu_full.copy()
+    rest[sl] = 0
+    assert not rest.any()
+
+
+def test_tti512_so12_first_steps_vs_checker(prop, orc, tti512_model):
+    nt = 6
+    w = _tti512(nt, tti512_model)
+    mdl = w.make_model()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=nt, v_ref=w.v_ref)
+    mt = [dev(mdl[k]) for k in ("m", "eps", "delta", "theta", "phi")]
+    p = prop.Propagator(prop.TTI, g, mt)
+    p.set_option("autotune", 1)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz)
+    d = host(p.forward(shot))
+    pf, qf = host(p.read_state(0)), host(p.read_state(1))
+    lo, hi = _subgrid(w, 2 * (w.space_order // 2) * nt + 2)
+    shp = tuple(hi[a] - lo[a] for a in range(3))
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    gs = orc.Grid(shp, w.spacing, origin=tuple(lo[a] * w.spacing[a] for a in range(3)), space_order=w.space_order,
+                  nbl=w.nbl, dt=w.dt, nt=nt, vref=w.v_ref)
+    mod = orc.TTIModel.from_arrays(gs, *(mdl[k][sl] for k in ("m", "eps", "delta", "theta", "phi")))
+    ins = _inside(w.rec_xyz, lo, hi, w.spacing)
+    do, (po, qo, _, _), _ = orc.tti_forward(gs, mod, w.src_xyz, w.wavelet(), w.rec_xyz[ins])
+    assert np.abs(po).max() > 0
+    _compare_fields(pf, po, lo, hi, 1e-4)
+    _compare_fields(qf, qo, lo, hi, 1e-4)
+    assert rel_l2(d[:, ins], do) <= 1e-4
+    assert not d[:, ~ins].any()
+
+
+def test_el400_so8_first_steps_vs_checker(prop, orc):
+    from paper_2004_10519_amd import configs
+    nt = 8
+    w = configs.el3d_400(nt=nt)
+    mdl = w.make_model()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=nt, v_ref=w.v_ref)
+    mt = [dev(mdl[k]) for k in ("vp", "vs", "rho")]
+    p = prop.Propagator(prop.ELASTIC, g, mt)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz, w.rec_kind)
+    d = host(p.forward(shot))
+    fields = [host(p.read_state(i)) for i in range(9)]
+    lo, hi = _subgrid(w, 2 * (w.space_order // 2) * nt + 2)
+    shp = tuple(hi[a] - lo[a] for a in range(3))
+    sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+    gs = orc.Grid(shp, w.spacing, origin=tuple(lo[a] * w.spacing[a] for a in range(3)), space_order=w.space_order,
+                  nbl=w.nbl, dt=w.dt, nt=nt, vref=w.v_ref)
+    mod = orc.ElasticModel.from_velocities(gs, *(mdl[k][sl] for k in ("vp", "vs", "rho")))
+    ins = _inside(w.rec_xyz, lo, hi, w.spacing)
+    do, fo = orc.elastic_forward(gs, mod, w.src_xyz, w.wavelet(), w.rec_xyz[ins], w.rec_kind[ins])
+    for a, b in zip(fields, fo):
+        if np.abs(b).max() > 1e-30:
+            _compare_fields(a, b, lo, hi, 1e-4)
+        else:
+            # the shear stresses: the source sits in the water layer (mu = 0) and after 8 steps the
+            # wave has only just reached the solid below, where the checker's values are ~1e-47,
+            # beneath FP32's range (smallest normal 1.2e-38)
+            assert np.abs(a).max() < 1e-30
+    assert rel_l2(d[:, ins], do) <= 1e-4
+    assert not d[:, ~ins].any()
+
+
+def test_tti512_so12_dot_test(prop, tti512_model):
+    nt = 20
+    w = _tti512(nt, tti512_model)
+    mdl = w.make_model()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=nt, v_ref=w.v_ref)
+    mt = [dev(mdl[k]) for k in ("m", "eps", "delta", "theta", "phi")]
+    p = prop.Propagator(prop.TTI, g, mt)
+    p.set_option("autotune", 1)
+    rng = np.random.default_rng(21)
+    x = dev(rng.standard_normal((nt, 1)))
+    shot = prop.Shot(w.src_xyz, x, w.rec_xyz)
+    Fx = p.forward(shot)
+    xi = dev(rng.standard_normal((nt, len(w.rec_xyz))))
+    y = (Fx * (xi.norm() / Fx.norm()) + xi).contiguous()
+    FTy = p.adjoint(shot, y)
+    a, b = prop.dot_f64(Fx, y), prop.dot_f64(x, FTy)
+    assert abs(a - b) / abs(a) < 1e-5, (a, b)
+
+
+def test_ttigrad256_finite_difference(prop):
+    """<g, dm> against (J(m + h dm) - J(m - h dm)) / 2h, J = 1/2 ||F(m) s - d_obs||^2 in FP64."""
+    from paper_2004_10519_amd import configs, inputs
+    w = configs.ttigrad()
+    true = w.model_list()
+    m0 = configs.ttigrad_starting_model(w)
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    tt = [dev(a) for a in true]
+    p = prop.Propagator(prop.TTI, g, tt)
+    p.set_option("autotune", 1)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz)
+    dobs = p.forward(shot).clone()
+    base = [m0[k] for k in ("m", "eps", "delta", "theta", "phi")]
+    dm = inputs.random_unit_field(w.arr_shape, 100, 6.0).astype(np.float64)
+    dm[: w.nbl + 4] = 0.0                       # zero above the receivers and in the top layer
+    dm[-w.nbl:] = 0.0
+    dm[:, :w.nbl] = 0.0
+    dm[:, -w.nbl:] = 0.0
+    dm[:, :, :w.nbl] = 0.0
+    dm[:, :, -w.nbl:] = 0.0
+    dm *= 1e-2 * np.abs(base[0]).max() / np.abs(dm).max()
+
+    def J(mm):
+        arrs = [dev(mm)] + [dev(a) for a in base[1:]]
+        p.set_model(arrs)
+        r = (p.forward(shot) - dobs).contiguous()
+        return 0.5 * prop.dot_f64(r, r), r, arrs
+
+    _, res, keep = J(base[0])
+    gr = host(p.gradient(shot, res, n_ckpt=48, ckpt_dtype="f16")).astype(np.float64)
+    gd = float(np.vdot(gr, dm))
+    hh = 0.5
+    jp, _, _ = J((base[0] + hh * dm).astype(np.float32))
+    jm, _, _ = J((base[0] - hh * dm).astype(np.float32))
+    fd = (jp - jm) / (2 * hh)
+    print(f"256^3 gradient: <g, dm> = {gd:.6e}, central FD = {fd:.6e}, rel {abs(fd - gd) / abs(gd):.2e}")
+    assert abs(fd - gd) / abs(gd) < 2e-2
