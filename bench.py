@@ -222,6 +222,18 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
         else:
             ent["rel_l2_vs_f32_checkpoints"] = float(((gr.double() - ref).norm() / ref.norm()).item())
         out[dt] = ent
+    # whole run stored in FP16 (n_ckpt = 1): two sweeps instead of three; method bytes per point and
+    # step: forward 44 + store 4 + adjoint 44 + read 4 + gradient read-modify-write 8 = 104
+    p.gradient(shot, res, 1, "f16")
+    torch.cuda.synchronize()
+    t = timed(torch, lambda: p.gradient(shot, res, 1, "f16"), 1, 0)
+    gr = p.gradient(shot, res, 1, "f16")
+    torch.cuda.synchronize()
+    gp = w.npts * w.nt / t / 1e9
+    out["f16_whole_run"] = {"GPts/s": round(gp, 3), "ms": round(t * 1e3, 1), "checkpoints": 0,
+                            "store_GB": round(w.nt * 2 * w.npts * 2 / 1e9, 1),
+                            "method_hbm_frac_104B": round(gp * 104 / HBM_PEAK_GBS, 4),
+                            "rel_l2_vs_f32_checkpoints": float(((gr.double() - ref).norm() / ref.norm()).item())}
     p.close()
     return out
 

@@ -144,8 +144,12 @@ int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *sr
  * snapshot, then, segment by segment in reverse, an FP32 recomputation from the checkpoint and the
  * adjoint run with the imaging condition
  *     g = -(1/dt^2) sum_k sum_{f in p,q} f^k (y^k - 2 y^{k+1} + y^{k+2}).
- * grad_m DEVICE, window-shaped dense (nz, ny, nx), overwritten.  n_ckpt >= 1 (1 = keep the whole
- * forward wavefield of the single segment, i.e. no recomputation beyond one pass). */
+ * The per-step levels f^k of the segment being processed are kept in FP32.
+ * grad_m DEVICE, window-shaped dense (nz, ny, nx), overwritten.  n_ckpt >= 1; n_ckpt = 1 stores
+ * the whole forward wavefield instead (one segment, no checkpoint), in ckpt_dtype (FP32, or
+ * FP16/BF16 with a power-of-two scale per x-row), and takes two sweeps (forward with storage,
+ * adjoint) instead of three: N x 2 fields x 4 B (FP32) or 2 B (FP16/BF16) per point of device
+ * memory. */
 int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float *grad_m,
                   int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype);
 

@@ -77,6 +77,10 @@ void aux_ckpt_pair_encode(const float *cur, const float *prev, const Win &w, int
                           float *sca, float *scb, hipStream_t st);
 void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *sca, const float *scb, const Win &w,
                           int dtype, float *cur, float *prev, hipStream_t st);
+// 16-bit segment store of one step: p, q rounded to FP16 (dtype 1) / BF16 (dtype 2) with per-x-row
+// power-of-two scales; codes dense (nz, ny, nx).
+void aux_encode_rows2(const float *p, const float *q, const Win &w, int dtype, uint16_t *cp, uint16_t *cq, float *sp,
+                      float *sq, hipStream_t st);
 void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double *out, hipStream_t st);
 int aux_dot_blocks();
 void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,

@@ -100,7 +100,7 @@ __global__ void k_tti_src(BCsr c, const TTIJob *__restrict__ jobs, int par, cons
     const int64_t nd = c.node[r];
     J.p[par ^ 1][nd] += v;
     J.q[par ^ 1][nd] += v;
-    if (seg_step >= 0) {
+    if (seg_step >= 0 && J.seg_dtype == 0) {   // (a 16-bit store is encoded after the injection)
         float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
         sp[nd] += v;
         sp[J.seg_field + nd] += v;
@@ -122,9 +122,11 @@ __global__ void k_tti_rec_adj(BCsr c, const TTIJob *__restrict__ jobs, int par, 
     J.wmix[par ^ 1][0][nd] += J.A[mn] * v;
     J.wmix[par ^ 1][1][nd] += J.B[mn] * v;
     if (ic) {   // the injected share of y^k in the imaging condition (f_p^k times it)
-        const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-        if (J.image) J.grad[nd] += sp[nd] * v;
-        else J.grad[nd] -= idt2 * sp[nd] * v;
+        const int64_t z = nd / J.w.sy, rem = nd - z * J.w.sy, y = rem / J.w.sx, x = rem - y * J.w.sx;
+        float fp, fq;
+        seg_load(J, seg_step, (int)x, (int)y, (int)z, nd, fp, fq);
+        if (J.image) J.grad[nd] += fp * v;
+        else J.grad[nd] -= idt2 * fp * v;
     }
 }
 
@@ -314,6 +316,46 @@ __global__ void k_encode_pair_rows(const float *__restrict__ cur, const float *_
         const float va = c * r1, vb = d * r2;
         ca[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(va)) : f32_to_bf16_rne(va);
         cb[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(vb)) : f32_to_bf16_rne(vb);
+    }
+}
+
+// 16-bit segment store of one time step: p and q each rounded to nearest-even FP16/BF16 with a
+// power-of-two scale per x-row (one block per row, both row maxima reduced in LDS).
+__global__ void k_encode_rows2(const float *__restrict__ p, const float *__restrict__ q, Win w, int dtype,
+                               uint16_t *__restrict__ cp, uint16_t *__restrict__ cq, float *__restrict__ sp,
+                               float *__restrict__ sq)
+{
+    __shared__ unsigned sa[BS], sb[BS];
+    const int y = blockIdx.y, z = blockIdx.z;
+    unsigned xa = 0, xb = 0;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const int64_t i = sidx(w, x, y, z);
+        xa = max(xa, __float_as_uint(p[i]) & 0x7fffffffu);
+        xb = max(xb, __float_as_uint(q[i]) & 0x7fffffffu);
+    }
+    sa[threadIdx.x] = xa;
+    sb[threadIdx.x] = xb;
+    __syncthreads();
+    for (int s = BS / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            sa[threadIdx.x] = max(sa[threadIdx.x], sa[threadIdx.x + s]);
+            sb[threadIdx.x] = max(sb[threadIdx.x], sb[threadIdx.x + s]);
+        }
+        __syncthreads();
+    }
+    const float s1 = pow2_scale(sa[0]), s2 = pow2_scale(sb[0]);
+    const float r1 = 1.0f / s1, r2 = 1.0f / s2;
+    const int64_t r = (int64_t)z * w.ny + y;
+    if (threadIdx.x == 0) {
+        sp[r] = s1;
+        sq[r] = s2;
+    }
+    const int64_t row = r * w.nx;
+    for (int x = threadIdx.x; x < w.nx; x += BS) {
+        const int64_t i = sidx(w, x, y, z);
+        const float va = p[i] * r1, vb = q[i] * r2;
+        cp[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(va)) : f32_to_bf16_rne(va);
+        cq[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(vb)) : f32_to_bf16_rne(vb);
     }
 }
 
@@ -544,6 +586,12 @@ void aux_ckpt_pair_encode(const float *cur, const float *prev, const Win &w, int
                           float *sca, float *scb, hipStream_t st)
 {
     hipLaunchKernelGGL(k_encode_pair_rows, dim3(1, w.ny, w.nz), dim3(BS), 0, st, cur, prev, w, dtype, ca, cb, sca, scb);
+}
+
+void aux_encode_rows2(const float *p, const float *q, const Win &w, int dtype, uint16_t *cp, uint16_t *cq, float *sp,
+                      float *sq, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_encode_rows2, dim3(1, w.ny, w.nz), dim3(BS), 0, st, p, q, w, dtype, cp, cq, sp, sq);
 }
 
 void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *sca, const float *scb, const Win &w,

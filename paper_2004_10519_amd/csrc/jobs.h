@@ -2,6 +2,8 @@
 #pragma once
 #include "common.h"
 
+#include <hip/hip_fp16.h>
+
 // One TTI shot window.  cur/prev wavefields ping-pong between p[0]/p[1] (and q) with the step
 // parity: the new level overwrites the level two steps back.
 struct TTIJob {
@@ -19,9 +21,35 @@ struct TTIJob {
     const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
     float *grad;                  // imaging-condition accumulator (state layout) or null
     int image;                    // imaging condition: 0 = gradient w.r.t. m, 1 = zero-lag cross-correlation
-    float *seg;                   // segment store: per step 2 fields (p then q) of seg_field elems
+    float *seg;                   // segment store (FP32): per step 2 fields (p then q) of seg_field elems
     int64_t seg_field;            // elements of one stored field (= plane pitch * nz)
+    int seg_dtype;                // segment store type: 0 FP32 (seg), 1 FP16 / 2 BF16 (seg16, segsc)
+    uint16_t *seg16;              // 16-bit store: per step 2 fields of seg16_field codes, dense (nz, ny, nx)
+    float *segsc;                 // ... and 2 x segsc_field power-of-two scales, one per x-row
+    int64_t seg16_field, segsc_field;
 };
+
+__device__ __forceinline__ float code16_to_f32(uint16_t c, int dtype)
+{
+    return dtype == 1 ? __half2float(__ushort_as_half(c)) : __uint_as_float((unsigned)c << 16);
+}
+
+// The stored forward levels (p, q) of segment step s at window point (x, y, z), state index si.
+__device__ __forceinline__ void seg_load(const TTIJob &J, int s, int x, int y, int z, int64_t si, float &fp, float &fq)
+{
+    if (J.seg_dtype == 0) {
+        const float *sp = J.seg + (int64_t)s * 2 * J.seg_field;
+        fp = gld(sp, si);
+        fq = gld(sp, J.seg_field + si);
+    } else {
+        typedef __attribute__((address_space(1))) const uint16_t gu16;
+        const int64_t r = (int64_t)z * J.w.ny + y, di = r * J.w.nx + x;
+        const gu16 *c = (const gu16 *)(J.seg16 + (int64_t)s * 2 * J.seg16_field);
+        const float *sc = J.segsc + (int64_t)s * 2 * J.segsc_field;
+        fp = gld(sc, r) * code16_to_f32(c[di], J.seg_dtype);
+        fq = gld(sc, J.segsc_field + r) * code16_to_f32(c[J.seg16_field + di], J.seg_dtype);
+    }
+}
 
 // One elastic shot window (fields in state layout; parameters in model layout).
 struct ElJob {

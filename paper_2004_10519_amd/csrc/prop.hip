@@ -1194,11 +1194,20 @@ void ckpt_load(prop_s *h, Slot &sl, const char *ck, const float *sc, int j, int 
 }
 
 // Device bytes of one shot's gradient workspace beyond its wavefields (checkpoints, scales, segment).
+// Segment store of one shot: S steps of (p, q); FP32 in state layout, or 16-bit codes (dense) plus
+// one FP32 scale per x-row, in the checkpoint type.
+size_t seg_bytes(const Slot &sl, int S, int dtype)
+{
+    const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz, rows = (size_t)sl.w.ny * sl.w.nz;
+    if (dtype == 0) return (size_t)S * 2 * sl.plane * 4;
+    return ((size_t)S * 2 * pts * 2 + 255) / 256 * 256 + (size_t)S * 2 * rows * 4;
+}
+
 size_t grad_bytes(const Slot &sl, int C, int S, int dtype)
 {
     const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz;
-    return (size_t)C * 4 * pts * (dtype == 0 ? 4 : 2) + (size_t)C * 4 * sl.w.ny * sl.w.nz * 4 +
-           (size_t)S * 2 * sl.plane * 4 + 1024;
+    const size_t ck = C > 1 ? (size_t)C * 4 * pts * (dtype == 0 ? 4 : 2) + (size_t)C * 4 * sl.w.ny * sl.w.nz * 4 : 0;
+    return ck + seg_bytes(sl, S, C > 1 ? 0 : dtype) + 1024;
 }
 
 // Checkpointed gradient (or zero-lag image) of a group; each shot's window result is left in its
@@ -1210,6 +1219,11 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
     const int C = (N + S - 1) / S;                // checkpoints used (c_j = j S < N)
     const int ns = (int)G.slots.size();
     size_t ck_total = 0, sc_total = 0, seg_total = 0;
+    const int Cs = C > 1 ? C : 0;                 // no checkpoint is stored when one segment covers all
+    // segment store: FP32 between checkpoints (it costs the same bytes as a 16-bit store that is
+    // encoded after each step, and keeps f^k exact); in the checkpoint type when one segment holds
+    // the whole run (the memory then matters)
+    const int sdt = C > 1 ? 0 : dtype;
     G.ck_off.assign(ns, 0);
     G.sc_off.assign(ns, 0);
     G.seg_off.assign(ns, 0);
@@ -1217,19 +1231,32 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
         const Slot &sl = *G.slots[j];
         const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz;
         G.ck_off[j] = ck_total;
-        ck_total += ((size_t)C * 4 * pts * (dtype == 0 ? 4 : 2) + 255) / 256 * 256;
+        ck_total += ((size_t)Cs * 4 * pts * (dtype == 0 ? 4 : 2) + 255) / 256 * 256;
         G.sc_off[j] = sc_total;
-        sc_total += (size_t)C * 4 * sl.w.ny * sl.w.nz;
+        sc_total += (size_t)Cs * 4 * sl.w.ny * sl.w.nz;
         G.seg_off[j] = seg_total;
-        seg_total += (size_t)S * 2 * sl.plane;
+        seg_total += (seg_bytes(sl, S, sdt) + 255) / 256 * 256;
     }
     TRY(h->ckpt.ensure(std::max<size_t>(ck_total, 16)));
     TRY(h->ckscale.ensure(std::max<size_t>(sc_total * sizeof(float), 16)));
-    TRY(h->seg.ensure(std::max<size_t>(seg_total * sizeof(float), 16)));
+    TRY(h->seg.ensure(std::max<size_t>(seg_total, 16)));
     std::vector<TTIJob> jf, ja;
     for (int j = 0; j < ns; ++j) {
-        TTIJob a = tti_job(h, *G.slots[j], false), b = tti_job(h, *G.slots[j], true);
-        a.seg = b.seg = h->seg.as<float>() + G.seg_off[j];
+        const Slot &sl = *G.slots[j];
+        TTIJob a = tti_job(h, sl, false), b = tti_job(h, sl, true);
+        char *base = h->seg.as<char>() + G.seg_off[j];
+        for (TTIJob *J : {&a, &b}) {
+            J->seg_dtype = sdt;
+            if (sdt == 0) {
+                J->seg = (float *)base;
+            } else {
+                const size_t pts = (size_t)sl.w.nx * sl.w.ny * sl.w.nz;
+                J->seg16 = (uint16_t *)base;
+                J->segsc = (float *)(base + ((size_t)S * 2 * pts * 2 + 255) / 256 * 256);
+                J->seg16_field = (int64_t)pts;
+                J->segsc_field = (int64_t)sl.w.ny * sl.w.nz;
+            }
+        }
         b.image = image ? 1 : 0;
         jf.push_back(a);
         ja.push_back(b);
@@ -1241,12 +1268,13 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
     char *ck = h->ckpt.as<char>();
     float *sc = h->ckscale.as<float>();
 
-    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state
+    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state.  With a single
+    //    segment there is nothing to checkpoint: the recomputation below is the only forward sweep.
     for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
     TRY(tune_group(h, G, false));
     Capture cap(h);
-    TRY(cap.begin());
-    for (int n = 0; n < N; ++n) {
+    if (C > 1) TRY(cap.begin());
+    for (int n = 0; n < (C > 1 ? N : 0); ++n) {
         const int par = n & 1;
         tti_step(h, G, false, K2_FWD, par, 0);
         aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
@@ -1275,8 +1303,21 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
         }
         for (int n = start; n < end; ++n) {
             const int par = n & 1;
-            tti_step(h, G, false, K2_FWD_STORE, par, n - start);
-            aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, n - start, h->st);
+            if (sdt == 0) {     // FP32 store: written by the update pass, the source added in place
+                tti_step(h, G, false, K2_FWD_STORE, par, n - start);
+                aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, n - start, h->st);
+            } else {            // 16-bit store: encoded once the step (with its source) is complete
+                tti_step(h, G, false, K2_FWD, par, 0);
+                aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
+                for (int i = 0; i < ns; ++i) {
+                    const TTIJob &J = jf[i];
+                    const Slot &sl = *G.slots[i];
+                    const int64_t k = n - start;
+                    aux_encode_rows2(sl.f[par ^ 1], sl.f[2 + (par ^ 1)], sl.w, sdt, J.seg16 + k * 2 * J.seg16_field,
+                                     J.seg16 + (k * 2 + 1) * J.seg16_field, J.segsc + k * 2 * J.segsc_field,
+                                     J.segsc + (k * 2 + 1) * J.segsc_field, h->st);
+                }
+            }
         }
         for (int k = end; k > start; --k) {
             const int par = (N - k) & 1;

@@ -283,9 +283,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
             vA[r] = gld(J.A, mi);
             vB[r] = gld(J.B, mi);
             if (MODE == K2_ADJ_IC) {
-                const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                fpk[r] = gld(sp, si);
-                fqk[r] = gld(sp, J.seg_field + si);
+                seg_load(J, seg_step, in ? gx : 0, in ? y : 0, z, si, fpk[r], fqk[r]);
                 vg[r] = gld(J.grad, si);
             }
         }
@@ -318,7 +316,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
                     gst(J.wmix[par ^ 1][0], si, vA[r] * np_ + vB[r] * nq_);
                     gst(J.wmix[par ^ 1][1], si, vB[r] * np_ + nq_);
                 }
-                if (MODE == K2_FWD_STORE) {
+                if (MODE == K2_FWD_STORE && J.seg_dtype == 0) {
                     float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
                     gst(sp, si, np_);
                     gst(sp, J.seg_field + si, nq_);
@@ -513,9 +511,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2s(const TTIJob *__restr
             vA = gld(J.A, mi);
             vB = gld(J.B, mi);
             if (MODE == K2_ADJ_IC) {
-                const float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                fpk = gld(sp, si);
-                fqk = gld(sp, J.seg_field + si);
+                seg_load(J, seg_step, own_in ? gx : 0, own_in ? gy : 0, z, si, fpk, fqk);
                 vg = gld(J.grad, si);
             }
         }
@@ -582,7 +578,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2s(const TTIJob *__restr
                 gst(J.wmix[par ^ 1][0], si, vA * np_ + vB * nq_);
                 gst(J.wmix[par ^ 1][1], si, vB * np_ + nq_);
             }
-            if (MODE == K2_FWD_STORE) {
+            if (MODE == K2_FWD_STORE && J.seg_dtype == 0) {
                 float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
                 gst(sp, si, np_);
                 gst(sp, J.seg_field + si, nq_);

@@ -51,18 +51,18 @@ def test_batched_forward_equals_plain(prop):
         assert np.array_equal(host(a), b)
 
 
-@pytest.mark.parametrize("dtype", ["f16", "f32"])
-def test_batched_gradient_equals_plain_sum(prop, dtype):
+@pytest.mark.parametrize("dtype,n_ckpt", [("f16", 5), ("f32", 5), ("f16", 1)])
+def test_batched_gradient_equals_plain_sum(prop, dtype, n_ckpt):
     p, shots = _setup(prop, nt=100)
     rng = np.random.default_rng(7)
     res = [dev(rng.standard_normal((100, s.nrec))) for s in shots]
     total = np.zeros(p.grid.arr_shape)
     for s, r in zip(shots, res):
-        g = host(p.gradient(s, r, n_ckpt=5, ckpt_dtype=dtype)).astype(np.float64)
+        g = host(p.gradient(s, r, n_ckpt=n_ckpt, ckpt_dtype=dtype)).astype(np.float64)
         (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
         total[oz:oz + nz, oy:oy + ny, ox:ox + nx] += g
     gg = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
-    p.gradient_batched(shots, res, gg, n_ckpt=5, ckpt_dtype=dtype)
+    p.gradient_batched(shots, res, gg, n_ckpt=n_ckpt, ckpt_dtype=dtype)
     assert np.array_equal(host(gg), total)
 
 

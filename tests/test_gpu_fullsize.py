@@ -8,8 +8,8 @@
   face, so the absorbing layer the source sits next to is the same on both sides.  The GPU fields
   and traces must match the checker there and be exactly zero everywhere else.
 * 512^3 so12 TTI dot test over 20 steps and 65536 receivers.
-* 256^3 so8 gradient (2000 steps, 48 FP16 checkpoints): central finite difference of the FP64
-  misfit along a smooth model perturbation.
+* 256^3 so8 gradient (2000 steps; 48 FP16 checkpoints, or the whole run stored in FP16): central
+  finite difference of the FP64 misfit along a smooth model perturbation.
 """
 import math
 
@@ -146,8 +146,10 @@ def test_tti512_so12_dot_test(prop, tti512_model):
     assert abs(a - b) / abs(a) < 1e-5, (a, b)
 
 
-def test_ttigrad256_finite_difference(prop):
-    """<g, dm> against (J(m + h dm) - J(m - h dm)) / 2h, J = 1/2 ||F(m) s - d_obs||^2 in FP64."""
+@pytest.mark.parametrize("n_ckpt", [48, 1])
+def test_ttigrad256_finite_difference(prop, n_ckpt):
+    """<g, dm> against (J(m + h dm) - J(m - h dm)) / 2h, J = 1/2 ||F(m) s - d_obs||^2 in FP64; FP16
+    storage: 48 checkpoints, or the whole run (n_ckpt = 1, 134 GB)."""
     from paper_2004_10519_amd import configs, inputs
     w = configs.ttigrad()
     true = w.model_list()
@@ -175,7 +177,7 @@ def test_ttigrad256_finite_difference(prop):
         return 0.5 * prop.dot_f64(r, r), r, arrs
 
     _, res, keep = J(base[0])
-    gr = host(p.gradient(shot, res, n_ckpt=48, ckpt_dtype="f16")).astype(np.float64)
+    gr = host(p.gradient(shot, res, n_ckpt=n_ckpt, ckpt_dtype="f16")).astype(np.float64)
     gd = float(np.vdot(gr, dm))
     hh = 0.5
     jp, _, _ = J((base[0] + hh * dm).astype(np.float32))

@@ -115,6 +115,25 @@ def test_tti_gradient_parity(prop, orc, dtype, tol, scheme):
     assert err <= tol, err
 
 
+@pytest.mark.parametrize("dtype,tol", [("f16", 1e-3), ("bf16", 1e-2)])
+def test_tti_gradient_whole_run_16bit_storage(prop, orc, dtype, tol):
+    """n_ckpt = 1 with a 16-bit type stores every forward level in FP16/BF16 (per-row scales) and
+    runs two sweeps."""
+    case = tti_case((40, 36, 32), 8, 5, 150, nrec=30)
+    p, shot = make_tti(case, prop)
+    res = _bandlimited_residual(case, 4)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=1, ckpt_dtype=dtype))
+    g, mod = oracle_tti(case, orc)
+    d, _, _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
+    _, go, _ = orc.tti_gradient(g, mod, case["src"], case["wav"], case["rec"], d - res)
+    err = rel_l2(gg, go)
+    print(f"gradient rel-L2 vs FP64 (whole run stored in {dtype}): {err:.3e}")
+    assert err <= tol, err
+    im = host(p.image(shot, dev(res), n_ckpt=1, ckpt_dtype=dtype))
+    io = orc.tti_image(g, mod, case["src"], case["wav"], case["rec"], res)
+    assert rel_l2(im, io) <= tol, rel_l2(im, io)
+
+
 def test_tti_gradient_single_segment_equals_full_storage(prop, orc):
     """n_ckpt = 1 keeps the whole forward wavefield (no checkpoint rounding): FP32-level agreement."""
     case = tti_case((40, 36, 32), 8, 5, 120, nrec=30)
