@@ -67,6 +67,8 @@ def lib():
         pp = ctypes.POINTER(dp)
         L.orc_el_step.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, pp, pp]
         L.orc_el_step_T.argtypes = [gp, ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_double, pp, pp]
+        L.orc_el_force.argtypes = [gp, ctypes.c_int, dp, pp, pp]
+        L.orc_el_strain.argtypes = [gp, ctypes.c_int, dp, pp, pp]
         _lib = L
     return _lib
 
@@ -590,6 +592,108 @@ def elastic_adjoint(g: Grid, mod: ElasticModel, src_xyz, rec_xyz, rec_data, rec_
             out[n] = g.dt * interp(src, t[0] + t[1] + t[2])
         _el_call(lib().orc_el_step_T, g, mod, damp, v, t)
     return out, v + t
+
+
+def _el_apply(fn, g, fields, nout):
+    c = _wf(fd_staggered(g.space_order))
+    cg = g.c()
+    src = [np.ascontiguousarray(f, dtype=np.float64) for f in fields]
+    out = [np.empty(g.arr_shape) for _ in range(nout)]
+    fn(ctypes.byref(cg), g.r, _p(c), _pp(src), _pp(out))
+    return out
+
+
+def elastic_force(g: Grid, t) -> list:
+    """D_tau tau: the stress divergence at the three velocity positions (the velocity update's force)."""
+    return _el_apply(lib().orc_el_force, g, t, 3)
+
+
+def elastic_strain(g: Grid, v) -> list:
+    """E v: (exx, eyy, ezz) at the nodes and (gxy, gxz, gyz) at the shear-stress positions."""
+    return _el_apply(lib().orc_el_strain, g, v, 6)
+
+
+def _spread_avg(g: Grid, acc: np.ndarray, axes) -> np.ndarray:
+    """Transpose of the half-node average over ``axes`` (R9: the mean of the 2 or 4 neighbouring
+    nodes, the upper neighbour clamped to the last index): each node collects the share of ``acc``
+    at every averaged position that it enters."""
+    out = np.zeros(g.arr_shape)
+    nz, ny, nx = g.arr_shape
+    n = {0: nx, 1: ny, 2: nz}
+    dim = {0: 2, 1: 1, 2: 0}                      # array dimension of each axis
+    idx = np.indices(g.arr_shape)
+    share = acc / (2 ** len(axes))
+    for corner in range(2 ** len(axes)):
+        tgt = [idx[0], idx[1], idx[2]]
+        for b, ax in enumerate(axes):
+            if (corner >> b) & 1:
+                d = dim[ax]
+                tgt[d] = np.minimum(tgt[d] + 1, n[ax] - 1)
+        np.add.at(out, (tgt[0], tgt[1], tgt[2]), share)
+    return out
+
+
+def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec_kind=None, nt=None):
+    """Gradient of J = 1/2 sum_n ||d^n - d_obs^n||^2 with respect to vp, vs and rho per node
+    (discretise-then-differentiate, like the TTI gradient; a reading, the paper gives no elastic
+    gradient).  Adjoint state of the two sub-steps of step n,
+        v' = g (v + dt bbar D_tau tau),     tau' = g (tau + dt C(lambda, mubar) E v'):
+    with (v~', tau~') the adjoint of the state after step n (receiver residuals injected),
+        dJ/dlambda  += dt g (tau~'_xx + tau~'_yy + tau~'_zz) tr(E v')
+        dJ/dmu      += 2 dt g sum_a tau~'_aa (E v')_aa  +  spread of dt g tau~'_s (E v')_s to the
+                       four nodes of mubar for each shear component s
+        dJ/db       += spread of dt v~_c (D_tau tau^n)_c to the two nodes of bbar, where
+                       v~ = g v~'' is the velocity adjoint after the transposed step (v~'' is the
+                       adjoint of v' once the stress sub-step is transposed);
+    then lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho give
+        dJ/dvp = 2 rho vp dJ/dlambda,   dJ/dvs = 2 rho vs (dJ/dmu - 2 dJ/dlambda),
+        dJ/drho = (vp^2 - 2 vs^2) dJ/dlambda + vs^2 dJ/dmu - dJ/db / rho^2.
+    Returns (J, (g_vp, g_vs, g_rho), traces)."""
+    nt = g.nt if nt is None else nt
+    c = lambda a: np.asarray(a, dtype=np.float64).reshape(g.arr_shape)
+    vp, vs, rho = c(vp), c(vs), c(rho)
+    mod = ElasticModel.from_velocities(g, vp, vs, rho)
+    states = [[np.zeros(g.arr_shape) for _ in range(9)]]
+    d, _ = elastic_forward(g, mod, src_xyz, wavelet, rec_xyz, rec_kind, nt=nt,
+                           callback=lambda n, f: states.append([a.copy() for a in f]))
+    res = d - np.asarray(d_obs, dtype=np.float64).reshape(d.shape)
+    J = 0.5 * float(np.sum(res * res))
+    damp = np.ascontiguousarray(elastic_damp(g))
+    iP, iV, spP, spV = _el_receivers(g, rec_xyz, rec_kind)
+    v = [np.zeros(g.arr_shape) for _ in range(3)]
+    t = [np.zeros(g.arr_shape) for _ in range(6)]
+    g_lam, g_mu = np.zeros(g.arr_shape), np.zeros(g.arr_shape)
+    acc_s = [np.zeros(g.arr_shape) for _ in range(3)]     # shear positions xy, xz, yz
+    acc_b = [np.zeros(g.arr_shape) for _ in range(3)]     # velocity positions x, y, z
+    for n in range(nt - 1, -1, -1):
+        if spP is not None:
+            for k in range(3):
+                inject(spP, t[k], res[n, iP])
+        if spV is not None:
+            inject(spV, v[2], res[n, iV])
+        e = elastic_strain(g, states[n + 1][:3])
+        gdt = g.dt * damp
+        g_lam += gdt * (t[0] + t[1] + t[2]) * (e[0] + e[1] + e[2])
+        g_mu += 2.0 * gdt * (t[0] * e[0] + t[1] * e[1] + t[2] * e[2])
+        for k in range(3):
+            acc_s[k] += gdt * t[3 + k] * e[3 + k]
+        _el_call(lib().orc_el_step_T, g, mod, damp, v, t)
+        f = elastic_force(g, states[n][3:])
+        for k in range(3):
+            acc_b[k] += g.dt * v[k] * f[k]
+    for k, axes in enumerate(((0, 1), (0, 2), (1, 2))):
+        if g.ndim == 2 and 1 in axes:
+            continue
+        g_mu += _spread_avg(g, acc_s[k], axes)
+    g_b = np.zeros(g.arr_shape)
+    for k in range(3):
+        if g.ndim == 2 and k == 1:
+            continue
+        g_b += _spread_avg(g, acc_b[k], (k,))
+    g_vp = 2.0 * rho * vp * g_lam
+    g_vs = 2.0 * rho * vs * (g_mu - 2.0 * g_lam)
+    g_rho = (vp * vp - 2.0 * vs * vs) * g_lam + vs * vs * g_mu - g_b / (rho * rho)
+    return J, (g_vp, g_vs, g_rho), d
 
 
 def acoustic_staggered_forward(g: Grid, lam, b, src_xyz, wavelet, nt=None):

@@ -375,6 +375,22 @@ static void el_stiff(const orc_grid *g, const double *lam, const double *mu, dou
     }
 }
 
+/* The force D_tau tau at the velocity positions (3 outputs) and the strains E v (6 outputs), as
+ * used by the step below; exported for the adjoint-state gradient. */
+void orc_el_force(const orc_grid *g, int r, const double *cw, double **t, double **out)
+{
+    double *tmp = malloc(sizeof(double) * npts(g));
+    el_force(g, r, cw, t, out, tmp);
+    free(tmp);
+}
+
+void orc_el_strain(const orc_grid *g, int r, const double *cw, double **v, double **out)
+{
+    double *tmp = malloc(sizeof(double) * npts(g));
+    el_strain(g, r, cw, v, out, tmp);
+    free(tmp);
+}
+
 /* Forward step, in place:  v <- g (v + dt b D_tau tau);  tau <- g (tau + dt C E v). */
 void orc_el_step(const orc_grid *g, int r, const double *cw, const double *lam, const double *mu,
                  const double *b, const double *damp, double dt, double **v, double **t)

@@ -102,3 +102,47 @@ def test_elastic_dot_dense_map(orc):
                         callback=lambda n, f: adj.__setitem__(n, np.stack(f)))
     lhs, rhs = np.vdot(out, Y), np.vdot(X, adj)
     assert abs(lhs - rhs) / abs(lhs) < 1e-12
+
+
+def _el_J(orc, g, vp, vs, rho, src, wav, rec, kind, dobs):
+    mod = orc.ElasticModel.from_velocities(g, vp, vs, rho)
+    d, _ = orc.elastic_forward(g, mod, src, wav, rec, kind)
+    r = d - dobs
+    return 0.5 * float(np.sum(r * r))
+
+
+@pytest.mark.parametrize("shape", [(12, 11, 13), (22, 1, 20)])
+def test_elastic_gradient_taylor_and_fd(orc, shape):
+    """Gradient with respect to vp, vs and rho: central finite differences along smooth directions
+    (one parameter at a time) and the second-order Taylor remainder.  vs is perturbed only where
+    it is positive (the water layer keeps vs = 0)."""
+    nx, ny, nz = shape
+    g = _grid(orc, shape, 3, 50)
+    mdl = inputs.elastic_model(shape, 3, 8)
+    vp, vs, rho = (mdl[k].astype(np.float64) for k in ("vp", "vs", "rho"))
+    h = g.spacing
+    _, _, src, rec, kind = _el_case(orc, shape, 50, 8)
+    wav = inputs.ricker(45.0, g.dt, g.nt).astype(np.float64)[:, None].repeat(len(src), axis=1)
+    # observed data from a perturbed "true" model
+    pert = 1 + 0.04 * inputs.random_unit_field(g.arr_shape, 2, 1.5)
+    tmod = orc.ElasticModel.from_velocities(g, vp * pert, vs * pert, rho)
+    dobs, _ = orc.elastic_forward(g, tmod, src, wav, rec, kind)
+    J0, (gvp, gvs, grho), _ = orc.elastic_gradient(g, vp, vs, rho, src, wav, rec, dobs, kind)
+    for which, seed in (("vp", 30), ("vs", 31), ("rho", 32)):
+        dm = inputs.random_unit_field(g.arr_shape, seed, 1.5).astype(np.float64)
+        base = {"vp": vp, "vs": vs, "rho": rho}[which]
+        if which == "vs":
+            dm *= vs > 0
+        dm *= 1e-2 * np.abs(base).max() / np.abs(dm).max()
+        grad = {"vp": gvp, "vs": gvs, "rho": grho}[which]
+        gd = float(np.vdot(grad, dm))
+
+        def J(hh):
+            m = {"vp": vp, "vs": vs, "rho": rho}
+            m = dict(m, **{which: base + hh * dm})
+            return _el_J(orc, g, m["vp"], m["vs"], m["rho"], src, wav, rec, kind, dobs)
+
+        rem = [abs(J(hh) - J0 - hh * gd) for hh in (1.0, 0.5, 0.25)]
+        assert rem[0] / rem[1] > 3.5 and rem[1] / rem[2] > 3.5, (which, rem)
+        fd = (J(0.01) - J(-0.01)) / 0.02
+        assert abs(fd - gd) / abs(gd) < 1e-5, (which, fd, gd)
