@@ -181,9 +181,15 @@ def measure_elastic(torch, prop, nt):
     torch.cuda.synchronize()
     ta = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
     g, ga = w.npts * w.nt / t / 1e9, w.npts * w.nt / ta / 1e9
+    # gradient with respect to (vp, vs, rho), 48 FP32 checkpoints (a residual-shaped random input:
+    # the cost does not depend on the values)
+    log("[bench] elastic gradient ...")
+    tg = timed(torch, lambda: p.gradient(shot, rec, n_ckpt=48, ckpt_dtype="f32"), 1, 0)
+    gg = w.npts * w.nt / tg / 1e9
     p.close()
     return {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
             "forward_GPts/s": round(g, 3), "adjoint_GPts/s": round(ga, 3),
+            "gradient_vp_vs_rho_GPts/s": round(gg, 3), "gradient_checkpoints": 48,
             "forward_method_hbm_frac": round(g * METHOD_BYTES_PER_PT["elastic"] / HBM_PEAK_GBS, 4),
             "forward_kernels": roof}
 
@@ -306,6 +312,23 @@ def measure_batched(torch, prop, nt, nshot):
     tp = time.perf_counter() - t0
     gbh = gb.cpu().numpy()
     err = float(np.linalg.norm(gbh - gp) / np.linalg.norm(gp))
+    del gb
+    torch.cuda.empty_cache()
+    # batched with the whole run stored in FP16 (n_ckpt = 1; the planner fits fewer shots per group)
+    p.set_option("graph", 1)
+    p.set_option("autotune", 1)
+    gw_ = torch.zeros(w.arr_shape, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    groups_w = 0
+    for c in range(0, nshot, chunk):
+        p.gradient_batched(shots[c:c + chunk], res[c:c + chunk], gw_, n_ckpt=1, ckpt_dtype="f16")
+        torch.cuda.synchronize()
+        groups_w += p.get_option("info_groups")
+        log(f"[bench]   batched, whole run stored: {min(c + chunk, nshot)}/{nshot} shots, "
+            f"{time.perf_counter() - t0:.1f} s")
+    tw = time.perf_counter() - t0
+    errw = float(np.linalg.norm(gw_.cpu().numpy() - gp) / np.linalg.norm(gp))
     p.close()
     return {"workload": w.name, "model": list(w.shape), "shots": nshot, "window_points": pts, "time_steps": w.nt,
             "space_order": w.space_order, "checkpoints": 48,
@@ -313,7 +336,10 @@ def measure_batched(torch, prop, nt, nshot):
                         "graphs": graphs_b, "last_group_tiles": tiles_b, "groups_last_call": groups_b,
                         "method_hbm_frac_156B": round(pts * w.nt / tb / 1e9 * 156 / HBM_PEAK_GBS, 4)},
             "plain": {"s": round(tp, 2), "GPts/s": round(pts * w.nt / tp / 1e9, 3), "checkpoint_dtype": "f32"},
-            "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err}
+            "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err,
+            "batched_whole_run_f16": {"s": round(tw, 2), "GPts/s": round(pts * w.nt / tw / 1e9, 3),
+                                      "shot_groups": groups_w, "speedup_vs_plain": round(tp / tw, 3),
+                                      "rel_l2_vs_plain": errw}}
 
 
 def main():

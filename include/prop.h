@@ -138,7 +138,12 @@ int prop_forward(prop_t h, const prop_shot *shot, float *rec_out);
  * rec_in DEVICE nt x nrec, src_out DEVICE nt x nsrc (overwritten). */
 int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *src_out);
 
-/* TTI only.  Gradient of J = 1/2 sum_n ||d^n - d_obs^n||^2 with respect to m over the shot's
+/* Gradient of J = 1/2 sum_n ||d^n - d_obs^n||^2 over the shot's window.
+ * PROP_ELASTIC: with respect to (vp, vs, rho); grad_m DEVICE receives three window-shaped dense
+ * fields in that order; FP32 checkpoints of the nine fields every ceil(N / n_ckpt) steps
+ * (ckpt_dtype must be PROP_CKPT_F32); the stored forward velocities of each segment give the
+ * strains and the force of the adjoint-state imaging condition.
+ * PROP_TTI: with respect to m over the shot's
  * window, given residual = d - d_obs (DEVICE nt x nrec): a forward run that stores n_ckpt evenly
  * spaced checkpoints of (p, q) at two time levels in ckpt_dtype with a power-of-two scale per
  * snapshot, then, segment by segment in reverse, an FP32 recomputation from the checkpoint and the

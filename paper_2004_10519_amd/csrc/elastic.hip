@@ -344,6 +344,209 @@ __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
     gst(J.aux[5], si, 0.25f * (mu0 + gld(J.mu, mi + oy) + gld(J.mu, mi + oz) + gld(J.mu, mi + oy + oz)) * t[5]);
 }
 
+// Imaging condition of the elastic gradient for one adjoint step (after the transposed velocity
+// update, before the transposed stress update).  The strains of the stored forward velocities
+// v^{n+1} are formed exactly as in the forward stress pass (LDS planes with x and y halos, z
+// queues); then, per storage point,
+//   acc_lambda += dt g tr(tau~) tr(E v),  acc_mu += 2 dt g sum_a tau~_aa (E v)_aa,
+//   acc_s      += dt g tau~_s (E v)_s for the shear components s (at their staggered positions),
+//   acc_b,c    += v~_c dt (D_tau tau^n)_c = v~_c (v^{n+1}_c - g v^n_c) / (g bbar_c)
+// (the velocity update v^{n+1} = g (v^n + dt bbar D_tau tau^n) gives the force from two stored
+// velocity levels).
+template <int R>
+__global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__restrict__ jobs,
+                                                           const Tile *__restrict__ tiles, int zc, Weights W, float dt)
+{
+    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
+    using P = Plane<R, TY>;
+    using H = Halo<R, TY, NT>;
+    constexpr int LX = P::LX;
+    __shared__ float Lx[2][P::SIZE], Ly[2][P::SIZE], Lz[2][P::SIZE];
+
+    const Tile tl = tiles[blockIdx.x];
+    const ElGradJob &J = jobs[tl.job];
+    const Win w = J.w;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
+    const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
+    const int gx = x0 + tx, gy = y0 + ty;
+    const bool own = gx < w.nx && gy < w.ny;
+    const float *__restrict__ Vx = J.vn1[0];
+    const float *__restrict__ Vy = J.vn1[1];
+    const float *__restrict__ Vz = J.vn1[2];
+    auto ld = [&](const float *f, int x, int y, int z) -> float {
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
+    };
+
+    float qx[Q], qy[Q], qz[Q];
+    float nx_, ny_, nz_;
+    float hx[3][H::NXH], hy[3][H::NYH];
+#pragma unroll
+    for (int s = 1; s < Q; ++s) {
+        const int z = z0 - R + s - 1;
+        qx[s] = ld(Vx, gx, gy, z);
+        qy[s] = ld(Vy, gx, gy, z);
+        qz[s] = ld(Vz, gx, gy, z);
+    }
+    auto fetch = [&](int z) {
+        nx_ = ld(Vx, gx, gy, z + R);
+        ny_ = ld(Vy, gx, gy, z + R);
+        nz_ = ld(Vz, gx, gy, z + R);
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            const bool v = i < H::NXI;
+            hx[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
+            hx[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
+            hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            const bool v = i < H::NYI;
+            hy[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
+            hy[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
+            hy[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+        }
+    };
+    fetch(z0);
+    int b = 0;
+    for (int z = z0; z < z1; ++z) {
+        float *lx = Lx[b], *ly = Ly[b], *lz = Lz[b];
+#pragma unroll
+        for (int s = 0; s < Q - 1; ++s) {
+            qx[s] = qx[s + 1];
+            qy[s] = qy[s + 1];
+            qz[s] = qz[s + 1];
+        }
+        qx[Q - 1] = nx_;
+        qy[Q - 1] = ny_;
+        qz[Q - 1] = nz_;
+        const int li = P::at(ty, tx);
+        lx[li] = qx[R];
+        ly[li] = qy[R];
+        lz[li] = qz[R];
+#pragma unroll
+        for (int k = 0; k < H::NXH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NXI) {
+                int yy, xx;
+                H::xitem(i, yy, xx);
+                lx[P::at(yy, xx)] = hx[0][k];
+                ly[P::at(yy, xx)] = hx[1][k];
+                lz[P::at(yy, xx)] = hx[2][k];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < H::NYH; ++k) {
+            const int i = tid + k * NT;
+            if (i < H::NYI) {
+                int yy, xx;
+                H::yitem(i, yy, xx);
+                lx[P::at(yy, xx)] = hy[0][k];
+                ly[P::at(yy, xx)] = hy[1][k];
+                lz[P::at(yy, xx)] = hy[2][k];
+            }
+        }
+        __syncthreads();
+        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+        float t[6], vt[3], v0[3];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) t[c] = gld(J.tt[c], si);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            vt[c] = gld(J.vt[c], si);
+            v0[c] = gld(J.vn0[c], si);
+        }
+        const float b0 = gld(J.b, mi);
+        const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
+        const float byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+        const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
+        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
+        const float v1[3] = {qx[R], qy[R], qz[R]};
+        if (z + 1 < z1) fetch(z + 1);
+        const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
+        const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
+        const float ezz = ds_q<R, false>(qz, W.wz);
+        const float gxy = ds_lds<R, true>(lx, li, LX, W.wy) + ds_lds<R, true>(ly, li, 1, W.wx);
+        const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
+        const float gyz = ds_q<R, true>(qy, W.wz) + ds_lds<R, true>(lz, li, LX, W.wy);
+        if (own) {
+            const float gdt = g * dt;
+            const float bb[3] = {0.5f * (b0 + bxn), 0.5f * (b0 + byn), 0.5f * (b0 + bzn)};
+            gst(J.acc[0], si, gld(J.acc[0], si) + gdt * (t[0] + t[1] + t[2]) * (exx + eyy + ezz));
+            gst(J.acc[1], si, gld(J.acc[1], si) + 2.f * gdt * (t[0] * exx + t[1] * eyy + t[2] * ezz));
+            gst(J.acc[2], si, gld(J.acc[2], si) + gdt * t[3] * gxy);
+            gst(J.acc[3], si, gld(J.acc[3], si) + gdt * t[4] * gxz);
+            gst(J.acc[4], si, gld(J.acc[4], si) + gdt * t[5] * gyz);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                gst(J.acc[5 + c], si, gld(J.acc[5 + c], si) + vt[c] * (v1[c] - g * v0[c]) / (g * bb[c]));
+        }
+        b ^= 1;
+    }
+}
+
+// Transpose of the half-node averages, gathered at each node, and the chain rule to (vp, vs, rho):
+// a position p enters the average at nodes p and min(p + 1, n - 1) along each averaged axis, so a
+// node i collects from p = i - 1 (weight 1) and p = i (weight 1 + [i = n - 1]), times 1/2 per axis.
+__device__ __forceinline__ float spread_w(int p, int i, int n) { return (p == i ? 1.f : 0.f) + (min(p + 1, n - 1) == i ? 1.f : 0.f); }
+
+__global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, const float *__restrict__ vp,
+                               const float *__restrict__ vs, const float *__restrict__ rho, float *__restrict__ out)
+{
+    const ElGradJob &J = jobs[0];
+    const Win w = J.w;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= w.nx) return;
+    const int n[3] = {w.nx, w.ny, w.nz};
+    const int c3[3] = {x, y, z};
+    auto at = [&](const float *f, int px, int py, int pz) { return gld(f, sidx(w, px, py, pz)); };
+    const int64_t si = sidx(w, x, y, z);
+    const float gl = gld(J.acc[0], si);
+    float gm = gld(J.acc[1], si);
+    // shear positions: (x, y) for xy, (x, z) for xz, (y, z) for yz
+    const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int k = 0; k < 3; ++k) {
+        const int a1 = pairs[k][0], a2 = pairs[k][1];
+        if (ndim == 2 && (a1 == 1 || a2 == 1)) continue;
+        for (int d1 = -1; d1 <= 0; ++d1) {
+            const int p1 = c3[a1] + d1;
+            if (p1 < 0) continue;
+            for (int d2 = -1; d2 <= 0; ++d2) {
+                const int p2 = c3[a2] + d2;
+                if (p2 < 0) continue;
+                int p[3] = {x, y, z};
+                p[a1] = p1;
+                p[a2] = p2;
+                const float wgt = 0.25f * spread_w(p1, c3[a1], n[a1]) * spread_w(p2, c3[a2], n[a2]);
+                gm += wgt * at(J.acc[2 + k], p[0], p[1], p[2]);
+            }
+        }
+    }
+    float gb = 0.f;
+    for (int a = 0; a < 3; ++a) {
+        if (ndim == 2 && a == 1) continue;
+        for (int d = -1; d <= 0; ++d) {
+            const int pa = c3[a] + d;
+            if (pa < 0) continue;
+            int p[3] = {x, y, z};
+            p[a] = pa;
+            gb += 0.5f * spread_w(pa, c3[a], n[a]) * at(J.acc[5 + a], p[0], p[1], p[2]);
+        }
+    }
+    const int64_t mi = midx(w, x, y, z);
+    const float a = gld(vp, mi), s = gld(vs, mi), r = gld(rho, mi);
+    const int64_t o = ((int64_t)z * w.ny + y) * w.nx + x, np_ = (int64_t)w.nx * w.ny * w.nz;
+    gst(out, o, 2.f * r * a * gl);
+    gst(out, np_ + o, 2.f * r * s * (gm - 2.f * gl));
+    gst(out, 2 * np_ + o, (a * a - 2.f * s * s) * gl + s * s * gm - gb / (r * r));
+}
+
 template <int R>
 void vel_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                   float dt, hipStream_t st)
@@ -398,4 +601,24 @@ void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st)
 {
     dim3 blk(256), grd((w0.nx + 255) / 256, w0.ny, w0.nz);
     hipLaunchKernelGGL(el_mix_stress, grd, blk, 0, st, jobs);
+}
+
+template <int R>
+void gic_dispatch(const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                  hipStream_t st)
+{
+    hipLaunchKernelGGL((el_grad_ic<R>), dim3(ntiles), dim3(PROP_TX, EBY), 0, st, job, tiles, zc, W, dt);
+}
+
+void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                       hipStream_t st)
+{
+    EL_SWITCH(gic_dispatch, job, tiles, ntiles, zc, W, dt, st)
+}
+
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, const float *vp, const float *vs,
+                           const float *rho, float *out, hipStream_t st)
+{
+    dim3 blk(256), grd((w.nx + 255) / 256, w.ny, w.nz);
+    hipLaunchKernelGGL(el_grad_finish, grd, blk, 0, st, job, ndim, vp, vs, rho, out);
 }

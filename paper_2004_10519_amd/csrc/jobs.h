@@ -62,6 +62,19 @@ struct ElJob {
     const float *gx, *gy, *gz;    // absorbing layer: exp(-kappa_a dt) per window axis
 };
 
+// Elastic gradient: the imaging condition of one adjoint step, and the final spread to the nodes.
+struct ElGradJob {
+    Win w;
+    const float *vn1[3];          // forward velocities after the step (stored), v^{n+1}
+    const float *vn0[3];          // forward velocities before the step, v^n
+    const float *tt[6];           // adjoint stresses after the step (receiver residuals injected)
+    const float *vt[3];           // adjoint velocities after the transposed velocity update, g v~''
+    const float *b;               // buoyancy (model layout)
+    const float *gx, *gy, *gz;    // absorbing layer factors per window axis
+    float *acc[8];                // accumulators: lambda, mu (normal part) at nodes; mubar at the xy,
+                                  // xz, yz shear positions; bbar at the x, y, z velocity positions
+};
+
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
 // Two-pass schemes of the TTI step: six-field temporaries, or the two scalar projections n . grad.
 enum { TTI_SIX = 0, TTI_SCALAR = 1 };
@@ -79,4 +92,10 @@ void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int nt
 void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                       const Weights &W, float dt, hipStream_t st);
 void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st);
+void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                       hipStream_t st);
+// Spread the accumulators to the nodes (transpose of the half-node averages) and convert to
+// (vp, vs, rho): out = three dense window fields.
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, const float *vp, const float *vs,
+                           const float *rho, float *out, hipStream_t st);
 int el_tile_rows(int R);

@@ -72,6 +72,13 @@ struct DevBuf {
         bytes = n;
         return PROP_OK;
     }
+    // like ensure, but also gives memory back when the buffer is more than twice the need (large
+    // workspaces of an earlier call would otherwise stay allocated beside the new ones)
+    int fit(size_t n)
+    {
+        if (p && bytes > 2 * std::max<size_t>(n, 16)) release();
+        return ensure(n);
+    }
     template <class T> T *as() const { return (T *)p; }
 };
 
@@ -218,6 +225,8 @@ struct prop_s {
     Slot slot;
     // gradient workspace
     DevBuf ckpt, ckscale, seg;
+    // elastic gradient workspace: forward fields, accumulators, jobs
+    DevBuf elfwd, elacc, eljob_f, eljob_g;
     // batched workspace
     std::vector<std::unique_ptr<Slot>> bslots;
     DevBuf bjobs_fwd, bjobs_adj, btiles;
@@ -1237,9 +1246,9 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
         G.seg_off[j] = seg_total;
         seg_total += (seg_bytes(sl, S, sdt) + 255) / 256 * 256;
     }
-    TRY(h->ckpt.ensure(std::max<size_t>(ck_total, 16)));
-    TRY(h->ckscale.ensure(std::max<size_t>(sc_total * sizeof(float), 16)));
-    TRY(h->seg.ensure(std::max<size_t>(seg_total, 16)));
+    TRY(h->ckpt.fit(std::max<size_t>(ck_total, 16)));
+    TRY(h->ckscale.fit(std::max<size_t>(sc_total * sizeof(float), 16)));
+    TRY(h->seg.fit(std::max<size_t>(seg_total, 16)));
     std::vector<TTIJob> jf, ja;
     for (int j = 0; j < ns; ++j) {
         const Slot &sl = *G.slots[j];
@@ -1523,6 +1532,113 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
     return PROP_OK;
 }
 
+// Elastic gradient with respect to (vp, vs, rho): forward run with C = ceil(N/S) checkpoints of the
+// nine fields (FP32), then segment by segment in reverse: restore, recompute the segment storing
+// the velocities of every level, and run the adjoint steps with the imaging condition between the
+// transposed velocity and stress updates.  out: three dense window fields (vp, vs, rho).
+int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out, int n_ckpt, int dtype)
+{
+    if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
+    if (dtype != PROP_CKPT_F32) return fail(PROP_EINVAL, "elastic gradients keep FP32 checkpoints");
+    if (!out) return fail(PROP_EINVAL, "grad_m is NULL");
+    Slot &sl = h->slot;
+    TRY(prepare_shot(h, sl, s, true, false, true, false));
+    if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
+    if (s->nrec > 0 && !residual) return fail(PROP_EINVAL, "residual is NULL");
+    const int N = h->g.nt;
+    const int S = (N + n_ckpt - 1) / n_ckpt;
+    const int C = (N + S - 1) / S;
+    const size_t P = sl.plane;
+    // forward fields (9) + accumulators (8) + checkpoints (9 per stored checkpoint) + velocity store
+    TRY(h->elfwd.ensure((size_t)9 * P * sizeof(float)));
+    TRY(h->elacc.ensure((size_t)8 * P * sizeof(float)));
+    TRY(h->ckpt.fit(std::max<size_t>((size_t)(C - 1) * 9 * P * sizeof(float), 16)));
+    TRY(h->seg.fit((size_t)(S + 1) * 3 * P * sizeof(float)));
+    float *fw = h->elfwd.as<float>(), *acc = h->elacc.as<float>(), *ck = h->ckpt.as<float>();
+    float *vs_ = h->seg.as<float>();
+    ElJob jf = el_job(h, sl);
+    for (int i = 0; i < 3; ++i) jf.v[i] = fw + (size_t)i * P;
+    for (int i = 0; i < 6; ++i) jf.t[i] = fw + (size_t)(3 + i) * P;
+    TRY(upload_one(h->eljob_f, jf, h->st));
+    const ElJob *djf = h->eljob_f.as<ElJob>();
+    const ElJob *dja = sl.job_fwd.as<ElJob>();   // adjoint fields: the slot's own
+    ElGradJob gj{};
+    gj.w = sl.w;
+    for (int i = 0; i < 6; ++i) gj.tt[i] = sl.f[3 + i];
+    for (int i = 0; i < 3; ++i) gj.vt[i] = sl.f[i];
+    gj.b = h->c[2];
+    const float *tab = sl.tabs.as<float>();
+    gj.gx = tab;
+    gj.gy = tab + sl.w.nx;
+    gj.gz = tab + sl.w.nx + sl.w.ny;
+    for (int i = 0; i < 8; ++i) gj.acc[i] = acc + (size_t)i * P;
+    std::vector<ElGradJob> gjs(S);   // one job per segment step (which stored levels it reads)
+    for (int k = 0; k < S; ++k) {
+        gjs[k] = gj;
+        for (int i = 0; i < 3; ++i) {
+            gjs[k].vn0[i] = vs_ + ((size_t)k * 3 + i) * P;
+            gjs[k].vn1[i] = vs_ + ((size_t)(k + 1) * 3 + i) * P;
+        }
+    }
+    TRY(upload(h->eljob_g, gjs, h->st));
+    const ElGradJob *dgj = h->eljob_g.as<ElGradJob>();
+    const float dt = (float)h->g.dt;
+    auto fwd_step = [&](int n) {
+        el_step_fwd(h, sl, djf);
+        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, jf.t[0], jf.t[1],
+                                   jf.t[2], h->st);
+    };
+    auto copy = [&](float *dst, const float *src, size_t nflt) -> int {
+        HIPCHK(hipMemcpyAsync(dst, src, nflt * sizeof(float), hipMemcpyDeviceToDevice, h->st));
+        return PROP_OK;
+    };
+    // 1) forward with checkpoints (state after step jS, j >= 1)
+    aux_fill(fw, 9 * P, 0.f, h->st);
+    for (int n = 0; n < (C > 1 ? N : 0); ++n) {
+        fwd_step(n);
+        if ((n + 1) % S == 0 && (n + 1) / S < C) TRY(copy(ck + (size_t)((n + 1) / S - 1) * 9 * P, fw, 9 * P));
+        if ((n + 1) % WATCH_EVERY == 0) {
+            HIPCHK(hipGetLastError());
+            TRY(check_finite(h, jf.t[2], sl.w, "tau_zz (gradient forward)", n));
+        }
+    }
+    // 2) reverse sweep
+    aux_fill(sl.f[0], 18 * P, 0.f, h->st);
+    aux_fill(acc, 8 * P, 0.f, h->st);
+    for (int j = C - 1; j >= 0; --j) {
+        const int start = j * S, end = std::min(N, (j + 1) * S);
+        if (j == 0) aux_fill(fw, 9 * P, 0.f, h->st);
+        else TRY(copy(fw, ck + (size_t)(j - 1) * 9 * P, 9 * P));
+        TRY(copy(vs_, fw, 3 * P));
+        for (int n = start; n < end; ++n) {
+            fwd_step(n);
+            TRY(copy(vs_ + (size_t)(n + 1 - start) * 3 * P, fw, 3 * P));
+        }
+        for (int n = end - 1; n >= start; --n) {
+            const float *row = s->nrec ? residual + (size_t)n * s->nrec : nullptr;
+            if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], sl.f[4], sl.f[5], h->st);
+            if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
+            launch_el_mix_stress(dja, sl.w, h->st);
+            {
+                Timed t(h, 2);
+                launch_el_vel(h->R, EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            }
+            launch_el_grad_ic(h->R, dgj + (n - start), sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            {
+                Timed t(h, 3);
+                launch_el_stress(h->R, EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            }
+        }
+        HIPCHK(hipGetLastError());
+        TRY(check_finite(h, sl.f[5], sl.w, "adjoint tau_zz (gradient)", start));
+    }
+    launch_el_grad_finish(dgj, sl.w, h->g.ndim, h->model.p[0], h->model.p[1], h->model.p[2], out, h->st);
+    HIPCHK(hipGetLastError());
+    TRY(check_finite(h, acc, sl.w, "gradient accumulator", 0));
+    h->last_state = 0;
+    return PROP_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -1601,7 +1717,7 @@ int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float 
 {
     g_err.clear();
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
-    if (h->kind != PROP_TTI) return fail(PROP_EINVAL, "gradients are provided for PROP_TTI only");
+    if (h->kind == PROP_ELASTIC) return el_gradient(h, shot, residual, grad_m, n_ckpt, (int)ckpt_dtype);
     return tti_gradient(h, shot, residual, grad_m, n_ckpt, (int)ckpt_dtype);
 }
 

@@ -234,8 +234,9 @@ class Propagator:
 
     def gradient(self, shot: Shot, residual: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "bf16",
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        if out is None:
-            out = torch.empty(self._win_shape(shot), dtype=torch.float32, device="cuda")
+        if out is None:   # elastic: the gradients with respect to vp, vs and rho, stacked
+            shp = self._win_shape(shot)
+            out = torch.empty(((3,) + shp) if self.kind == ELASTIC else shp, dtype=torch.float32, device="cuda")
         cs = shot.c()
         _check(lib().prop_gradient(self._h, ctypes.byref(cs), _dev(residual) if shot.nrec else None, _dev(out),
                                    int(n_ckpt), CKPT[ckpt_dtype]))

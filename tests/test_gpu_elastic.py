@@ -27,6 +27,29 @@ def test_elastic_forward_parity(prop, orc, so, shape):
         assert rel_l2(a, b) <= 1e-4
 
 
+def _to_2d(case):
+    case["src"] = np.ascontiguousarray(case["src"][:, [0, 2]])
+    case["rec"] = np.ascontiguousarray(case["rec"][:, [0, 2]])
+    return case
+
+
+@pytest.mark.parametrize("so", [4, 8])
+def test_elastic_forward_parity_2d(prop, orc, so):
+    """2D (x, z): ny = 1; vy, txy and tyz stay exactly zero, tyy follows the normal strains."""
+    case = _to_2d(el_case((90, 1, 61), so, 5, 80))
+    p, shot = make_el(case, prop)
+    d = host(p.forward(shot))
+    fields = [host(p.read_state(i)) for i in range(9)]
+    g, mod = oracle_el(case, orc)
+    do, fo = orc.elastic_forward(g, mod, case["src"], case["wav"], case["rec"], case["kind"])
+    assert rel_l2(d, do) <= 1e-4, rel_l2(d, do)
+    for i, (a, b) in enumerate(zip(fields, fo)):
+        if np.abs(b).max() > 0:
+            assert rel_l2(a, b) <= 1e-4, (i, rel_l2(a, b))
+        else:
+            assert not a.any(), i
+
+
 @pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (4, (66, 20, 40))])
 def test_elastic_adjoint_parity(prop, orc, so, shape):
     case = el_case(shape, so, 5, 60)
@@ -55,3 +78,31 @@ def test_elastic_gpu_dot_test(prop):
     FTy = p.adjoint(shot, y)
     a, b = prop.dot_f64(Fx, y), prop.dot_f64(x, FTy)
     assert abs(a - b) / abs(a) < 1e-5, (a, b)
+
+
+@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (4, (66, 1, 40))])
+def test_elastic_gradient_parity(prop, orc, so, shape):
+    """Gradient with respect to (vp, vs, rho) against the checker's adjoint-state gradient (residual
+    from a perturbed model), with FP32 checkpoints every 12 steps."""
+    from paper_2004_10519_amd import inputs
+    case = el_case(shape, so, 5, 60)
+    if shape[1] == 1:
+        case = _to_2d(case)
+    p, shot = make_el(case, prop)
+    g, mod = oracle_el(case, orc)
+    m = case["model"]
+    pert = 1 + 0.03 * inputs.random_unit_field(g.arr_shape, 5, 2.0)
+    dobs, _ = orc.elastic_forward(g, orc.ElasticModel.from_velocities(g, m["vp"] * pert, m["vs"] * pert, m["rho"]),
+                                  case["src"], case["wav"], case["rec"], case["kind"])
+    d = host(p.forward(shot)).astype(np.float64)
+    res = (d - dobs).astype(np.float32)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=5, ckpt_dtype="f32"))
+    _, go, _ = orc.elastic_gradient(g, m["vp"], m["vs"], m["rho"], case["src"], case["wav"], case["rec"],
+                                    d - res.astype(np.float64), case["kind"])
+    for name, a, b in zip(("vp", "vs", "rho"), gg, go):
+        err = rel_l2(a, b)
+        print(f"elastic gradient {name}: rel-L2 {err:.3e}")
+        assert err <= 1e-3, (name, err)
+    # checkpoints are exact FP32 copies: any segmentation gives the same bits
+    g1 = host(p.gradient(shot, dev(res), n_ckpt=1, ckpt_dtype="f32"))
+    assert np.array_equal(g1, gg)
