@@ -504,6 +504,13 @@ class ElasticModel:
 VZ_STAGGER = (0.0, 0.0, 0.5)
 
 
+def _normal(g: Grid):
+    """The normal-stress components of the stress tensor: (xx, yy, zz) in 3D; (xx, zz) in 2D, where
+    the tensor is 2 x 2 (reading: the explosive source enters them and the pressure is their sum,
+    the trace of the tensor, as in the paper's 2D example)."""
+    return (0, 2) if g.ndim == 2 else (0, 1, 2)
+
+
 def _el_call(fn, g, mod, damp, v, t):
     c = _wf(fd_staggered(g.space_order))
     cg = g.c()
@@ -525,9 +532,9 @@ def elastic_forward(g: Grid, mod: ElasticModel, src_xyz, wavelet, rec_xyz, rec_k
                     force=None, callback=None):
     """Velocity-stress forward modelling (velocities, then stresses from the new velocities).
 
-    After the stress update of step n the explosive source adds dt * P_s^T s^n to txx, tyy, tzz
-    (reading), then receivers record pressure = P_r (txx + tyy + tzz) (kind 0; the trace of the
-    stress tensor, no -1/3 factor) or vz on its staggered grid (kind 1).
+    After the stress update of step n the explosive source adds dt * P_s^T s^n to the normal
+    stresses (txx, tyy, tzz; in 2D txx, tzz) (reading), then receivers record pressure = P_r (their
+    sum, the trace of the stress tensor, no -1/3 factor) (kind 0) or vz on its staggered grid (kind 1).
     ``force(n)`` may return 9 dense arrays added to the fields after step n (dot tests) and
     ``callback(n, fields)`` sees the fields after step n.
     Returns (traces (nt, nrec), final fields [vx, vy, vz, txx, tyy, tzz, txy, txz, tyz]).
@@ -543,7 +550,7 @@ def elastic_forward(g: Grid, mod: ElasticModel, src_xyz, wavelet, rec_xyz, rec_k
     for n in range(nt):
         _el_call(lib().orc_el_step, g, mod, damp, v, t)
         if src is not None:
-            for c in range(3):
+            for c in _normal(g):
                 inject(src, t[c], g.dt * wav[n])
         if force is not None:
             fr = force(n)
@@ -553,7 +560,7 @@ def elastic_forward(g: Grid, mod: ElasticModel, src_xyz, wavelet, rec_xyz, rec_k
         if callback is not None:
             callback(n, v + t)
         if spP is not None:
-            traces[n, iP] = interp(spP, t[0] + t[1] + t[2])
+            traces[n, iP] = interp(spP, sum(t[c] for c in _normal(g)))
         if spV is not None:
             traces[n, iV] = interp(spV, v[2])
     return traces, v + t
@@ -577,7 +584,7 @@ def elastic_adjoint(g: Grid, mod: ElasticModel, src_xyz, rec_xyz, rec_data, rec_
     out = np.zeros((nt, 0 if src is None else src.idx.shape[0]))
     for n in range(nt - 1, -1, -1):
         if spP is not None:
-            for c in range(3):
+            for c in _normal(g):
                 inject(spP, t[c], dat[n, iP])
         if spV is not None:
             inject(spV, v[2], dat[n, iV])
@@ -589,7 +596,7 @@ def elastic_adjoint(g: Grid, mod: ElasticModel, src_xyz, rec_xyz, rec_data, rec_
         if callback is not None:
             callback(n, v + t)
         if src is not None:
-            out[n] = g.dt * interp(src, t[0] + t[1] + t[2])
+            out[n] = g.dt * interp(src, sum(t[c] for c in _normal(g)))
         _el_call(lib().orc_el_step_T, g, mod, damp, v, t)
     return out, v + t
 
@@ -667,7 +674,7 @@ def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec
     acc_b = [np.zeros(g.arr_shape) for _ in range(3)]     # velocity positions x, y, z
     for n in range(nt - 1, -1, -1):
         if spP is not None:
-            for k in range(3):
+            for k in _normal(g):
                 inject(spP, t[k], res[n, iP])
         if spV is not None:
             inject(spV, v[2], res[n, iV])
