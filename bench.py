@@ -245,7 +245,8 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
 
 
 def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
-    """Device-to-device copy rate (bytes read + written per second) of torch's copy kernel on 2 GiB."""
+    """Device-to-device copy rate (bytes read + written per second) of torch's copy kernel on 2 GiB,
+    and the read-only rate of torch's sum over the same 2 GiB."""
     a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
@@ -257,9 +258,18 @@ def copy_bandwidth(torch, nbytes=1 << 31, reps=10):
     e1.record()
     torch.cuda.synchronize()
     gbs = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    # read-only rate of the same buffer (torch's sum reduction)
+    a.sum()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        a.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    rgbs = nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del a, b
     torch.cuda.empty_cache()
-    return gbs
+    return gbs, rgbs
 
 
 def measure_batched(torch, prop, nt, nshot):
@@ -426,8 +436,9 @@ def main():
     roof["tiles"] = {"pass1": {"variant": tiles[0], "zc": tiles[1]}, "pass2": {"variant": tiles[2], "zc": tiles[3]},
                      "autotuned": not FIXED_TILES}
     if not args.copy_probe:   # (counter runs calibrate on the probe copy alone)
-        copy_gbs = copy_bandwidth(torch)
+        copy_gbs, read_gbs = copy_bandwidth(torch)
         roof["copy_GBps"] = round(copy_gbs, 1)
+        roof["read_GBps"] = round(read_gbs, 1)
         roof["frac_of_copy"] = round(achieved / copy_gbs, 4)
         log(f"[bench] device copy {copy_gbs:.0f} GB/s; dominant kernel {achieved:.0f} GB/s algorithmic")
 

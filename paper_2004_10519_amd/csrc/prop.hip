@@ -1221,7 +1221,7 @@ size_t grad_bytes(const Slot &sl, int C, int S, int dtype)
 
 // Checkpointed gradient (or zero-lag image) of a group; each shot's window result is left in its
 // slot (field 10).
-int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = false)
+int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = false, bool grow_only = false)
 {
     const int N = h->g.nt;
     const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
@@ -1246,9 +1246,11 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
         G.seg_off[j] = seg_total;
         seg_total += (seg_bytes(sl, S, sdt) + 255) / 256 * 256;
     }
-    TRY(h->ckpt.fit(std::max<size_t>(ck_total, 16)));
-    TRY(h->ckscale.fit(std::max<size_t>(sc_total * sizeof(float), 16)));
-    TRY(h->seg.fit(std::max<size_t>(seg_total, 16)));
+    // a batched call keeps its workspaces at the largest group's size (no re-allocation per group)
+    auto want = [&](DevBuf &b, size_t n) { return grow_only ? b.ensure(n) : b.fit(n); };
+    TRY(want(h->ckpt, std::max<size_t>(ck_total, 16)));
+    TRY(want(h->ckscale, std::max<size_t>(sc_total * sizeof(float), 16)));
+    TRY(want(h->seg, std::max<size_t>(seg_total, 16)));
     std::vector<TTIJob> jf, ja;
     for (int j = 0; j < ns; ++j) {
         const Slot &sl = *G.slots[j];
@@ -1436,6 +1438,11 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
     std::vector<std::pair<int, int>> groups;
     TRY(plan_groups(h, nshot, shots, grad, n_ckpt, dtype, groups));
     h->last_groups = (int)groups.size();
+    if (grad) {   // the planner counted these as reusable: give them back before the groups grow them
+        h->ckpt.release();
+        h->ckscale.release();
+        h->seg.release();
+    }
     for (auto &gr : groups) {
         const int ns = gr.second - gr.first;
         while ((int)h->bslots.size() < ns) h->bslots.emplace_back(new Slot());
@@ -1448,7 +1455,7 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
         Group G;
         if (grad) {
             TRY(build_group(h, G, sh, sl, true, false, true, false, residual + gr.first, nullptr, nullptr));
-            TRY(tti_gradient_group(h, G, n_ckpt, dtype, image));
+            TRY(tti_gradient_group(h, G, n_ckpt, dtype, image, true));
             for (int i = 0; i < ns; ++i) aux_accum_f64(sl[i]->f[10], sl[i]->w, grad_global, h->st);  // shot order
         } else {
             TRY(build_group(h, G, sh, sl, true, true, false, false, nullptr, rec_out + gr.first, nullptr));
@@ -1462,6 +1469,10 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
 }
 
 // -------------------------------------------------------------------------- elastic time loops
+// The normal stresses that the explosive source and the pressure receivers act on: txx, tyy, tzz in
+// 3D; txx, tzz in 2D, where the stress tensor is 2 x 2 (tyy is then not part of it).
+float *tyy_of(const prop_s *h, const Slot &sl) { return h->g.ndim == 3 ? sl.f[4] : nullptr; }
+
 void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
 {
     const float dt = (float)h->g.dt;
@@ -1486,10 +1497,10 @@ int el_forward(prop_s *h, const prop_shot *s, float *rec_out)
     const float dt = (float)h->g.dt;
     for (int n = 0; n < h->g.nt; ++n) {
         el_step_fwd(h, sl, job);
-        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, sl.f[3], sl.f[4],
+        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, sl.f[3], tyy_of(h, sl),
                                    sl.f[5], h->st);
         float *row = s->nrec ? rec_out + (size_t)n * s->nrec : nullptr;
-        if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, sl.f[3], sl.f[4], sl.f[5], 1.f, row, h->st);
+        if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], 1.f, row, h->st);
         if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, sl.f[2], nullptr, nullptr, 1.f, row, h->st);
         if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) {
             HIPCHK(hipGetLastError());
@@ -1511,9 +1522,10 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
     const float dt = (float)h->g.dt;
     for (int n = h->g.nt - 1; n >= 0; --n) {
         const float *row = s->nrec ? rec_in + (size_t)n * s->nrec : nullptr;
-        if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], sl.f[4], sl.f[5], h->st);
+        if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
         if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
-        if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], sl.f[4], sl.f[5], dt, src_out + (size_t)n * s->nsrc, h->st);
+        if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], dt, src_out + (size_t)n * s->nsrc,
+                                h->st);
         launch_el_mix_stress(job, sl.w, h->st);
         {
             Timed t(h, 2);
@@ -1585,8 +1597,8 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
     const float dt = (float)h->g.dt;
     auto fwd_step = [&](int n) {
         el_step_fwd(h, sl, djf);
-        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, jf.t[0], jf.t[1],
-                                   jf.t[2], h->st);
+        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, jf.t[0],
+                                   h->g.ndim == 3 ? jf.t[1] : nullptr, jf.t[2], h->st);
     };
     auto copy = [&](float *dst, const float *src, size_t nflt) -> int {
         HIPCHK(hipMemcpyAsync(dst, src, nflt * sizeof(float), hipMemcpyDeviceToDevice, h->st));
@@ -1616,7 +1628,7 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
         }
         for (int n = end - 1; n >= start; --n) {
             const float *row = s->nrec ? residual + (size_t)n * s->nrec : nullptr;
-            if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], sl.f[4], sl.f[5], h->st);
+            if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
             if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
             launch_el_mix_stress(dja, sl.w, h->st);
             {

@@ -245,3 +245,59 @@ def test_tti_image_parity(prop, orc, dtype, tol, scheme):
     err = rel_l2(im, io)
     print(f"image rel-L2 vs FP64 ({dtype} checkpoints): {err:.3e}")
     assert err <= tol, err
+
+
+def test_isotropic_reduction_vs_acoustic_stepper(prop, orc):
+    """eps = delta = 0 and a vertical axis: p = q and the TTI scheme is the acoustic leapfrog with the
+    composed Laplacian -sum_a D_a^T D_a; compare with the checker's independent acoustic stepper."""
+    from paper_2004_10519_amd import inputs
+    shape, h, so, nt = (60, 44, 52), (10.0, 11.0, 9.0), 8, 120
+    mdl = inputs.tti_model(shape, 0, 12)
+    m = inputs.slowness_squared(mdl["vp"])
+    z = np.zeros_like(m)
+    case = tti_case(shape, so, 0, nt)
+    case["model"] = {"m": m, "eps": z, "delta": z, "theta": z, "phi": z}
+    p, shot = make_tti(case, prop)
+    d = host(p.forward(shot))
+    pf, qf = host(p.read_state(0)), host(p.read_state(1))
+    g = orc.Grid(shape, h, space_order=so, nbl=0, dt=case["dt"], nt=nt)
+    da, ua = orc.acoustic_wide_forward(g, m, case["src"], case["wav"], case["rec"])
+    assert rel_l2(d, da) <= 1e-4, rel_l2(d, da)
+    assert rel_l2(pf, ua) <= 1e-4 and np.array_equal(pf, qf)
+
+
+def test_degenerate_shots(prop, orc):
+    """No source: all-zero traces; no receivers: the state still evolves; one time step; a window of
+    the smallest allowed size (2 nbl + 2 points per axis) inside a larger grid."""
+    case = tti_case((70, 37, 29), 8, 5, 40)
+    p, shot = make_tti(case, prop)
+    silent = prop.Shot(np.zeros((0, 3), np.float32), None, case["rec"])
+    assert not host(p.forward(silent)).any()
+    blind = prop.Shot(case["src"], dev(case["wav"]), np.zeros((0, 3), np.float32))
+    p.forward(blind)
+    pf = host(p.read_state(0))
+    g, mod = oracle_tti(case, orc)
+    _, (po, _, _, _), _ = orc.tti_forward(g, mod, case["src"], case["wav"], None)
+    assert rel_l2(pf, po) <= 1e-4
+    one = tti_case((70, 37, 29), 8, 5, 1)
+    p1, s1 = make_tti(one, prop)
+    d1 = host(p1.forward(s1))
+    g1, mod1 = oracle_tti(one, orc)
+    do1, _, _ = orc.tti_forward(g1, mod1, one["src"], one["wav"], one["rec"])
+    assert rel_l2(d1, do1) <= 1e-6
+    # smallest window: 12 x 12 x 12 with nbl 5, at an offset inside the 70 x 37 x 29 grid
+    o, n = (30, 11, 9), (12, 12, 12)
+    hh = case["h"]
+    src = np.array([[hh[0] * (o[0] + 5.5), hh[1] * (o[1] + 6.2), hh[2] * (o[2] + 5.7)]], np.float32)
+    rec = np.array([[hh[0] * (o[0] + 2.0), hh[1] * (o[1] + 9.0), hh[2] * (o[2] + 3.3)],
+                    [hh[0] * (o[0] + 11.0), hh[1] * (o[1] + 11.0), hh[2] * (o[2] + 11.0)]], np.float32)
+    wav = dev(case["wav"][:, :1])
+    dw = host(p.forward(prop.Shot(src, wav, rec, win_origin=o, win_shape=n)))
+    sub = (slice(o[2], o[2] + n[2]), slice(o[1], o[1] + n[1]), slice(o[0], o[0] + n[0]))
+    gw = orc.Grid(n, hh, origin=tuple(o[a] * hh[a] for a in range(3)), space_order=8, nbl=5, dt=case["dt"],
+                  nt=case["nt"], vref=1500.0)
+    mw = orc.TTIModel.from_arrays(gw, *(case["model"][k][sub] for k in ("m", "eps", "delta", "theta", "phi")))
+    dow, _, _ = orc.tti_forward(gw, mw, src, case["wav"][:, :1], rec)
+    assert rel_l2(dw, dow) <= 1e-4, rel_l2(dw, dow)
+    with pytest.raises(prop.PropError):       # one point short of 2 nbl + 2
+        p.forward(prop.Shot(src, wav, rec, win_origin=o, win_shape=(11, 12, 12)))
