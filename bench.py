@@ -36,13 +36,17 @@ HBM_PEAK_GBS = 8000.0
 #   scheme 1 pass 2: read f, f- for p and q (4), the two projections, n_x, n_y, m, 1+2eps,
 #                    sqrt(1+2delta) (7); write p+, q+ (2); adjoint reads u = w_p too and
 #                    writes w = C y+ (2)                                                 -> 13 / 16 x 4
+#   scheme 2 (one fused pass, class 1): read u, v, f- for p and q (4), n_x, n_y, m, 1+2eps,
+#                    sqrt(1+2delta) (5); write p+, q+ (2); adjoint reads y too and writes
+#                    w = C y+ (2)                                                         -> 11 / 15 x 4
 # Elastic:
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
 TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
-                    (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64}
+                    (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64,
+                    (2, 1, False): 44, (2, 1, True): 60}
 KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
-TTI_SCHEME = 0      # two-pass scheme of every TTI handle (--scheme)
+TTI_SCHEME = None   # step scheme of every TTI handle (--scheme); None = the library default
 FIXED_TILES = None  # (tile1, zc1, tile2, zc2) of the main run instead of the autotuner (--tiles)
 
 
@@ -60,7 +64,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "tti.hip"):
+    for f in ("common.h", "tti.hip", "tti_fused.hip"):
         with open(os.path.join(ROOT, "paper_2004_10519_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -89,7 +93,8 @@ def setup_tti(w, torch, prop):
     p = prop.Propagator(prop.TTI if w.kind == "tti" else prop.ELASTIC, g, dev)
     p._keep = dev
     if w.kind == "tti":
-        p.set_option("scheme", TTI_SCHEME)
+        if TTI_SCHEME is not None:
+            p.set_option("scheme", TTI_SCHEME)
         if FIXED_TILES:
             for k, v in zip(("tile1", "zc", "tile2", "zc2"), FIXED_TILES):
                 p.set_option(k, v)
@@ -204,7 +209,8 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
     g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
     dt_ = [torch.from_numpy(a).cuda() for a in true]
     p = prop.Propagator(prop.TTI, g, dt_)
-    p.set_option("scheme", TTI_SCHEME)
+    if TTI_SCHEME is not None:
+        p.set_option("scheme", TTI_SCHEME)
     p.set_option("autotune", 1)
     shot = prop.Shot(w.src_xyz, torch.from_numpy(w.wavelet()).cuda(), w.rec_xyz)
     dobs = p.forward(shot).clone()
@@ -240,6 +246,7 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
                             "store_GB": round(w.nt * 2 * w.npts * 2 / 1e9, 1),
                             "method_hbm_frac_104B": round(gp * 104 / HBM_PEAK_GBS, 4),
                             "rel_l2_vs_f32_checkpoints": float(((gr.double() - ref).norm() / ref.norm()).item())}
+    out["scheme"] = p.get_option("scheme")
     p.close()
     return out
 
@@ -283,7 +290,8 @@ def measure_batched(torch, prop, nt, nshot):
     dev_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
     del arrs
     p = prop.Propagator(prop.TTI, g, dev_)
-    p.set_option("scheme", TTI_SCHEME)
+    if TTI_SCHEME is not None:
+        p.set_option("scheme", TTI_SCHEME)
     wav = torch.from_numpy(np.ascontiguousarray(w.wavelet()[:, :1])).cuda()
     shots = [prop.Shot(src, wav, rec, win_origin=o, win_shape=n) for (o, n, src, rec) in geo]
     gen = torch.Generator(device="cuda").manual_seed(0)
@@ -339,9 +347,10 @@ def measure_batched(torch, prop, nt, nshot):
             f"{time.perf_counter() - t0:.1f} s")
     tw = time.perf_counter() - t0
     errw = float(np.linalg.norm(gw_.cpu().numpy() - gp) / np.linalg.norm(gp))
+    scheme = p.get_option("scheme")
     p.close()
     return {"workload": w.name, "model": list(w.shape), "shots": nshot, "window_points": pts, "time_steps": w.nt,
-            "space_order": w.space_order, "checkpoints": 48,
+            "space_order": w.space_order, "checkpoints": 48, "scheme": scheme,
             "batched": {"s": round(tb, 2), "GPts/s": round(pts * w.nt / tb / 1e9, 3), "checkpoint_dtype": "f16",
                         "graphs": graphs_b, "last_group_tiles": tiles_b, "groups_last_call": groups_b,
                         "method_hbm_frac_156B": round(pts * w.nt / tb / 1e9 * 156 / HBM_PEAK_GBS, 4)},
@@ -367,8 +376,10 @@ def main():
     ap.add_argument("--tiles", default=None, metavar="T1,Z1,T2,Z2",
                     help="fixed tile variants and z-chunks of the two TTI passes instead of the autotuner "
                          "(counter runs: the profiler serialises launches, which would mislead the autotuner)")
-    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1),
-                    help="TTI two-pass scheme: 0 six-field temporaries, 1 scalar projections")
+    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2),
+                    help="TTI step scheme: 0 two passes with six-field temporaries, 1 two passes with "
+                         "scalar projections, 2 one fused pass (default: the library's choice per space "
+                         "order, fused up to 8)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -413,6 +424,7 @@ def main():
     p.set_timing(True)
     t_step = timed(torch, run, args.steps, 0)
     kt = {k: p.kernel_time(k) for k in (0, 1)}
+    kt = {k: v for k, v in kt.items() if v[1] > 0}   # the fused scheme launches class 1 only
     p.set_timing(False)
     gpts = npts * w.nt / t_step / 1e9
     log(f"[bench] {w.name}: {t_step * 1e3:.1f} ms/step, {gpts:.2f} GPts/s")

@@ -211,10 +211,13 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
  *   PROP_OPT_BATCH_MB  device-memory budget of the batched shot-group planner in MiB,
  *                      0 = 85 % of the free memory (default).
- *   PROP_OPT_SCHEME    TTI two-pass scheme: 0 = pass 1 stores the six components of
- *                      (I - n n^T) grad p and n n^T grad q; 1 = pass 1 stores only the two scalars
- *                      n . grad p and n . grad q and pass 2 re-forms the vectors from p (fewer
- *                      bytes per step).  Same operators; results agree to FP32 rounding.
+ *   PROP_OPT_SCHEME    TTI step scheme: 0 = two passes, pass 1 stores the six components of
+ *                      (I - n n^T) grad p and n n^T grad q; 1 = two passes, pass 1 stores only the
+ *                      two scalars n . grad p and n . grad q and pass 2 re-forms the vectors from p;
+ *                      2 = one fused pass, the projections stay on chip (space order <= 12, else
+ *                      PROP_EINVAL; kernel class 1 then times the fused pass and class 0 is
+ *                      unused).  Default: 2 up to space order 8, 0 above.  Same operators;
+ *                      results agree to FP32 rounding.
  * Read-only (prop_get_option): PROP_INFO_TILE1/2 and PROP_INFO_ZC1/2, the variant and z-chunk
  * used by the last TTI call; PROP_INFO_GRAPHS, graphs launched since create; PROP_INFO_GROUPS,
  * shot groups of the last batched call.  Unknown options give PROP_EINVAL. */

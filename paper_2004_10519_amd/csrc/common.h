@@ -63,6 +63,20 @@ struct Plane {
     __device__ static __forceinline__ int at(int yy, int xx) { return (yy + R) * LX + xx + R; }
 };
 
+// LDS planes of the x and y components of a vector field for its divergence: the x component on
+// the tile rows with an R-wide x-halo, the y component on the tile columns with an R-wide y-halo.
+template <int R, int TY>
+struct XPlane {
+    static constexpr int LX = PROP_TX + 2 * R;
+    static constexpr int SIZE = LX * TY;
+    __device__ static __forceinline__ int at(int yy, int xx) { return yy * LX + xx + R; }
+};
+template <int R, int TY>
+struct YPlane {
+    static constexpr int SIZE = PROP_TX * (TY + 2 * R);
+    __device__ static __forceinline__ int at(int yy, int xx) { return (yy + R) * PROP_TX + xx; }
+};
+
 // Stage the halo of one plane into LDS.  `get(x, y)` returns the (window-local) value at
 // (x, y) of the current plane, zero outside the window.  HX: x-halo rows [0, TY), columns
 // [-R, 0) and [TX, TX+R); HY: y-halo rows [-R, 0) and [TY, TY+R), columns [0, TX).

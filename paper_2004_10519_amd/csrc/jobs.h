@@ -76,15 +76,20 @@ struct ElGradJob {
 };
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
-// Two-pass schemes of the TTI step: six-field temporaries, or the two scalar projections n . grad.
-enum { TTI_SIX = 0, TTI_SCALAR = 1 };
+// Schemes of the TTI step: two passes with six-field temporaries, two passes with the two scalar
+// projections n . grad, or one fused pass (projections kept on chip).
+enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2 };
 
 // shape: tile-shape variant of the pass; tti_tile_rows gives its tile height.
 void launch_tti_pass1(int R, int scheme, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles,
                       int zc, int par, const Weights &W, hipStream_t st);
 void launch_tti_pass2(int R, int scheme, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles,
                       int zc, int par, const Weights &W, float idt2, int seg_step, hipStream_t st);
-int tti_tile_rows(int R, int pass, int shape);
+// The fused scheme runs only the second launch (pass 1 is a no-op).
+int tti_tile_rows(int R, int scheme, int pass, int shape);
+int tti_fused_max_radius();
+void launch_tti_fused(int R, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+                      const Weights &W, float idt2, int seg_step, hipStream_t st);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };
 void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,

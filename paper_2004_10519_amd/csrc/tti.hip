@@ -331,20 +331,6 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     }
 }
 
-// LDS planes of the scalar scheme's divergence pass: t0 and s0 on the tile rows with an R-wide
-// x-halo, t1 and s1 on the tile columns with an R-wide y-halo.
-template <int R, int TY>
-struct XPlane {
-    static constexpr int LX = PROP_TX + 2 * R;
-    static constexpr int SIZE = LX * TY;
-    __device__ static __forceinline__ int at(int yy, int xx) { return yy * LX + xx + R; }
-};
-template <int R, int TY>
-struct YPlane {
-    static constexpr int SIZE = PROP_TX * (TY + 2 * R);
-    __device__ static __forceinline__ int at(int yy, int xx) { return (yy + R) * PROP_TX + xx; }
-};
-
 // Scalar scheme, pass 2.  Pass 1 stored only wp = n . grad u and wq = n . grad v; here
 //     H0 u = div t,  t = grad u - n wp,        Hz v = div s,  s = n wq,
 // with every intermediate zero outside the window (the same operators as the six-field scheme).
@@ -672,8 +658,9 @@ void p2_dispatch(int scheme, int shape, int mode, const TTIJob *jobs, const Tile
 
 }  // namespace
 
-int tti_tile_rows(int R, int pass, int shape)
+int tti_tile_rows(int R, int scheme, int pass, int shape)
 {
+    if (scheme == TTI_FUSED) return 16;
     const int by = shape == 1 ? 16 : 8;
     return pass == 1 ? by * (R <= 6 ? 2 : 1) : by;
 }
@@ -693,11 +680,13 @@ int tti_tile_rows(int R, int pass, int shape)
 void launch_tti_pass1(int R, int scheme, int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles,
                       int zc, int par, const Weights &W, hipStream_t st)
 {
+    if (scheme == TTI_FUSED) return;
     R_SWITCH(p1_dispatch, scheme, shape, adj, jobs, tiles, ntiles, zc, par, W, st)
 }
 
 void launch_tti_pass2(int R, int scheme, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles,
                       int zc, int par, const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
+    if (scheme == TTI_FUSED) return launch_tti_fused(R, shape, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     R_SWITCH(p2_dispatch, scheme, shape, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st)
 }

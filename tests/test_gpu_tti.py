@@ -20,7 +20,7 @@ def prop():
     return P
 
 
-SCHEMES = [0, 1]   # six-field temporaries / scalar projections between the two passes
+SCHEMES = [0, 1, 2]   # two passes (six-field temporaries / scalar projections), one fused pass
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -165,6 +165,31 @@ def test_scalar_scheme_tiles_and_chunks(prop, so):
                 d = host(p.forward(shot))
                 assert rel_l2(d, ref) <= 1e-6, (t1, t2, zc, rel_l2(d, ref))
                 assert p.get_option("info_zc2") == (zc if zc else p.get_option("info_zc1"))
+
+
+@pytest.mark.parametrize("so", [2, 4, 8, 12])
+def test_fused_scheme_tiles_and_chunks(prop, so):
+    """Fused scheme: both tile variants and short z-chunks (chunk seams, warm-up of the queues and
+    accumulators at every chunk start) give the traces of its default launch to 1e-6 and the
+    six-field scheme's to 1e-5 (the z divergence is summed in another order)."""
+    case = tti_case((83, 29, 41), so, 5, 60)
+    p0, shot = make_tti(case, prop, 0)
+    six = host(p0.forward(shot)).copy()
+    p2, shot = make_tti(case, prop, 2)
+    ref = host(p2.forward(shot)).copy()
+    assert rel_l2(ref, six) <= 1e-5, rel_l2(ref, six)
+    for t2 in (0, 1):
+        for zc in (0, 3, 17):
+            p, shot = make_tti(case, prop, 2, tile2=t2, zc=zc, zc2=zc)
+            d = host(p.forward(shot))
+            assert rel_l2(d, ref) <= 1e-6, (t2, zc, rel_l2(d, ref))
+
+
+def test_fused_scheme_rejects_wide_stencils(prop):
+    case = tti_case((40, 20, 30), 16, 5, 10)
+    p, _ = make_tti(case, prop, 0)
+    with pytest.raises(prop.PropError, match="space orders up to 12"):
+        p.set_option("scheme", 2)
 
 
 def test_codec_bit_exact(prop, orc):
