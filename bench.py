@@ -15,6 +15,7 @@ The JSON line also carries
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -70,7 +71,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None):
+def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None, space_order: int = 12):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/pmc_traffic.json), if they were
     taken on the current kernel source with the same tile variant and z-chunk; else None."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
@@ -78,7 +79,7 @@ def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    ent = rec.get(f"{kclass}/{scheme}")
+    ent = rec.get(f"{kclass}/{scheme}/so{space_order}")
     if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
         return None
     if tile is not None and ent.get("tile") != list(tile):
@@ -369,6 +370,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--nt", type=int, default=None, help="override the number of time steps (short runs)")
     ap.add_argument("--size", type=int, default=512)
+    ap.add_argument("--space-order", type=int, default=None,
+                    help="space order of the main TTI run instead of 12 (profiles of other stencil widths)")
     ap.add_argument("--only-main", action="store_true", help="skip the adjoint, elastic and gradient paths")
     ap.add_argument("--batched", type=int, default=0, metavar="NSHOT",
                     help="also run the batched-vs-plain gradient comparison with NSHOT shots (64 = full)")
@@ -409,6 +412,8 @@ def main():
         del a, b
 
     w = configs.tti3d_512(nt=args.nt or 3000, n=args.size)
+    if args.space_order:
+        w = dataclasses.replace(w, space_order=args.space_order)
     log(f"[bench] generating {w.name} model {w.shape} ...")
     t0 = time.perf_counter()
     p, shot = setup_tti(w, torch, prop)
@@ -435,7 +440,7 @@ def main():
     scheme = p.get_option("scheme")
     tiles = [p.get_option(k) for k in ("info_tile1", "info_zc1", "info_tile2", "info_zc2")]
     achieved = kernel_bytes(dom, scheme) * npts / avg_s / 1e9
-    traffic = traffic_from_profiles(dom, npts, scheme, tiles[2 * dom:2 * dom + 2])
+    traffic = traffic_from_profiles(dom, npts, scheme, tiles[2 * dom:2 * dom + 2], w.space_order)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "algorithmic_bytes_per_launch": kernel_bytes(dom, scheme) * npts, "scheme": scheme,
@@ -458,7 +463,7 @@ def main():
     if not args.only_main:
         log("[bench] TTI adjoint ...")
         paths["tti_adjoint"] = measure_tti_adjoint(torch, prop, w, p, shot)
-    out = {"metric": "GPts/s (TTI forward, 512^3, so12)", "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
+    out = {"metric": f"GPts/s (TTI forward, {w.shape[0]}^3, so{w.space_order})", "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 2),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded layered TTI model, Ricker source)",
