@@ -205,7 +205,9 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *                      and a direction, time both tile variants of each stencil pass at three
  *                      z-chunk lengths and keep the fastest (cached on the handle).
  *   PROP_OPT_TILE1/2   0 or 1 (default 1): tile variant of TTI pass 1 / pass 2 when not
- *                      autotuning (0: 64 x 8 threads, 1: 64 x 16 threads).
+ *                      autotuning (0: 64 x 8 threads, 1: 64 x 16 threads; the fused pass uses
+ *                      TILE2 and a 64 x 16 tile either way, 0: 512 threads of two rows,
+ *                      1: 1024 threads of one row).
  *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
  *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default).
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.

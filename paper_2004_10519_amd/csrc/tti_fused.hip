@@ -440,15 +440,15 @@ void pf_launch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int 
     }
 }
 
-// Tile variants, both 64 x 16: 0 = 1024 threads of one row each, 1 = 512 threads of two rows each.
-// (A 64 x 32 tile would halve the y-halo work per point, but two rows of queues and accumulators
-// per thread exceed the 128 registers a thread of a 1024-thread block may hold.)  Space orders up
-// to 12 (R <= 6): beyond that the halo queues outgrow the LDS of a CU.
+// Tile variants, both 64 x 16: 1 (the default) = 1024 threads of one row each, 0 = 512 threads of
+// two rows each.  (A 64 x 32 tile would halve the y-halo work per point, but two rows of queues and
+// accumulators per thread exceed the 128 registers a thread of a 1024-thread block may hold.)
+// Space orders up to 12 (R <= 6): beyond that the halo queues outgrow the LDS of a CU.
 template <int R>
 void pf_dispatch(int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
-    if (shape == 0) pf_launch<R, 16, 1>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+    if (shape == 1) pf_launch<R, 16, 1>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     else            pf_launch<R, 8, 2>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
 }
 
