@@ -226,6 +226,29 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
             hys[k] = i < H::NYI ? ld(S1, x0 + xx, y0 + yy, z) : 0.f;
         }
     };
+    float nvp0[NY], nvq0[NY], nvp1[NY], nvq1[NY], nvm[NY], nvA[NY], nvB[NY], nfpk[NY], nfqk[NY], nvg[NY];
+    auto pload = [&](int z) {
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            const int y = y0 + ty * NY + r;
+            const bool in = gx < w.nx && y < w.ny;
+            const int64_t si = sidx(w, in ? gx : 0, in ? y : 0, z);
+            const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
+            nvp0[r] = gld(pc, si);
+            nvq0[r] = gld(qc, si);
+            nvp1[r] = gld(pn, si);
+            nvq1[r] = gld(qn, si);
+            nvm[r] = gld(J.m, mi);
+            nvA[r] = gld(J.A, mi);
+            nvB[r] = gld(J.B, mi);
+            nfpk[r] = nfqk[r] = nvg[r] = 0.f;
+            if (MODE == K2_ADJ_IC) {
+                seg_load(J, seg_step, in ? gx : 0, in ? y : 0, z, si, nfpk[r], nfqk[r]);
+                nvg[r] = gld(J.grad, si);
+            }
+        }
+    };
+    pload(z0);
     fetch(z0);
     int b = 0;
     for (int z = z0; z < z1; ++z) {
@@ -266,28 +289,27 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
             }
         }
         __syncthreads();
-        // per-point values of plane z first, then the prefetch of plane z+1
+        // per-point values of plane z were loaded one plane earlier; those of plane z+1 are issued
+        // before the prefetch of plane z+1, so that waiting for them next time does not wait for it
         float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
         const float ezv = gld(J.ez, z);
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
-            const int y = y0 + ty * NY + r;
-            const bool in = gx < w.nx && y < w.ny;
-            const int64_t si = sidx(w, in ? gx : 0, in ? y : 0, z);
-            const int64_t mi = midx(w, in ? gx : 0, in ? y : 0, z);
-            vp0[r] = gld(pc, si);
-            vq0[r] = gld(qc, si);
-            vp1[r] = gld(pn, si);
-            vq1[r] = gld(qn, si);
-            vm[r] = gld(J.m, mi) * idt2 + 0.f;
-            vA[r] = gld(J.A, mi);
-            vB[r] = gld(J.B, mi);
-            if (MODE == K2_ADJ_IC) {
-                seg_load(J, seg_step, in ? gx : 0, in ? y : 0, z, si, fpk[r], fqk[r]);
-                vg[r] = gld(J.grad, si);
-            }
+            vp0[r] = nvp0[r];
+            vq0[r] = nvq0[r];
+            vp1[r] = nvp1[r];
+            vq1[r] = nvq1[r];
+            vm[r] = nvm[r] * idt2 + 0.f;
+            vA[r] = nvA[r];
+            vB[r] = nvB[r];
+            fpk[r] = nfpk[r];
+            fqk[r] = nfqk[r];
+            vg[r] = nvg[r];
         }
-        if (z + 1 < z1) fetch(z + 1);
+        if (z + 1 < z1) {
+            pload(z + 1);
+            fetch(z + 1);
+        }
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;

@@ -233,6 +233,34 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
             }
         }
     };
+    // update operands: current plane (v*) and next plane (nv*)
+    float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
+    float nvp0[NY], nvq0[NY], nvp1[NY], nvq1[NY], nvm[NY], nvA[NY], nvB[NY], nfpk[NY], nfqk[NY], nvg[NY];
+    auto load_upd = [&](int zo) {
+        const bool v = zo >= z0 && zo < z1;   // block-uniform
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            const uint32_t uos = fresh(os[r]), uom = fresh(om[r]);
+            nvp0[r] = nvq0[r] = nvp1[r] = nvq1[r] = nvm[r] = nvA[r] = nvB[r] = nfpk[r] = nfqk[r] = nvg[r] = 0.f;
+            if (v) {
+                if (ADJ) {
+                    nvp0[r] = ldo(sp(J.p[par], zo), uos);
+                    nvq0[r] = ldo(sp(J.q[par], zo), uos);
+                }
+                nvp1[r] = ldo(sp(J.p[par ^ 1], zo), uos);
+                nvq1[r] = ldo(sp(J.q[par ^ 1], zo), uos);
+                nvm[r] = ldo(mp(J.m, zo), uom);
+                nvA[r] = ldo(mp(J.A, zo), uom);
+                nvB[r] = ldo(mp(J.B, zo), uom);
+                if (MODE == K2_ADJ_IC) {
+                    const int y = ok[r] ? y0 + ty * NY + r : 0, x = ok[r] ? gx : 0;
+                    seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), nfpk[r], nfqk[r]);
+                    nvg[r] = ldo(sp(J.grad, zo), uos);
+                }
+            }
+        }
+    };
+    load_upd(zs - R);
     fetch(zs);
     for (int zf = zs; zf < ze; ++zf) {
         // 1. advance the queues (plane zf + R enters) and stage plane zf
@@ -278,38 +306,27 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
 #pragma unroll
         for (int k = 0; k < NH; ++k) b0[k] = hn0[k], b1[k] = hn1[k];
         __syncthreads();
-        if (zf + 1 < ze) fetch(zf + 1);
 
-        // operands of the update of plane zo = zf - R (block-uniform condition)
+        // plane zo = zf - R is updated in this iteration with the operands loaded one plane earlier;
+        // the operands of plane zo + 1 are issued before the next plane's prefetch, so that the
+        // wait for them in the next iteration does not wait for that prefetch as well
         const int zo = zf - R;
         const bool out = zo >= z0;
-        float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
-        uint32_t uos[NY], uom[NY];
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
-            uos[r] = fresh(os[r]);
-            uom[r] = fresh(om[r]);
-            vp0[r] = vq0[r] = vp1[r] = vq1[r] = vm[r] = vA[r] = vB[r] = fpk[r] = fqk[r] = vg[r] = 0.f;
-            if (out) {
-                if (ADJ) {
-                    vp0[r] = ldo(sp(J.p[par], zo), uos[r]);
-                    vq0[r] = ldo(sp(J.q[par], zo), uos[r]);
-                } else {
-                    vp0[r] = qu[r][0];
-                    vq0[r] = qv[r][0];
-                }
-                vp1[r] = ldo(sp(J.p[par ^ 1], zo), uos[r]);
-                vq1[r] = ldo(sp(J.q[par ^ 1], zo), uos[r]);
-                vm[r] = ldo(mp(J.m, zo), uom[r]) * idt2 + 0.f;
-                vA[r] = ldo(mp(J.A, zo), uom[r]);
-                vB[r] = ldo(mp(J.B, zo), uom[r]);
-                if (MODE == K2_ADJ_IC) {
-                    const int y = ok[r] ? y0 + ty * NY + r : 0, x = ok[r] ? gx : 0;
-                    seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), fpk[r], fqk[r]);
-                    vg[r] = ldo(sp(J.grad, zo), uos[r]);
-                }
-            }
+            vp0[r] = ADJ ? nvp0[r] : qu[r][0];
+            vq0[r] = ADJ ? nvq0[r] : qv[r][0];
+            vp1[r] = nvp1[r];
+            vq1[r] = nvq1[r];
+            vm[r] = nvm[r];
+            vA[r] = nvA[r];
+            vB[r] = nvB[r];
+            fpk[r] = nfpk[r];
+            fqk[r] = nfqk[r];
+            vg[r] = nvg[r];
         }
+        load_upd(zo + 1);
+        if (zf + 1 < ze) fetch(zf + 1);
 
         // 2. t and s of plane zf: own columns (all components), halo (x or y components)
         const bool zin = zok(zf);
@@ -375,6 +392,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
             at[r][R] += dc_lds_x<R>(Lt0, XP::at(row, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(row, tx), W.wy);
             as[r][R] += dc_lds_x<R>(Ls0, XP::at(row, tx), W.wx) + dc_lds_y<R, PROP_TX>(Ls1, YP::at(row, tx), W.wy);
             if (out && ok[r]) {
+                const uint32_t uos = fresh(os[r]);
                 const float h0 = at[r][0], hz = as[r][0];
                 float Lp, Lq;
                 if (ADJ) {
@@ -384,25 +402,25 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
                     Lp = vA[r] * h0 + vB[r] * hz;
                     Lq = vB[r] * h0 + hz;
                 }
-                const float mm = vm[r];
+                const float mm = vm[r] * idt2 + 0.f;
                 const float e = exy[r] + ezo;
                 const float ra = 1.0f / (mm + e);
                 const float cc = mm - e;
                 const float np_ = (2.f * mm * vp0[r] - cc * vp1[r] + Lp) * ra;
                 const float nq_ = (2.f * mm * vq0[r] - cc * vq1[r] + Lq) * ra;
-                sto(spw(J.p[par ^ 1], zo), uos[r], np_);
-                sto(spw(J.q[par ^ 1], zo), uos[r], nq_);
+                sto(spw(J.p[par ^ 1], zo), uos, np_);
+                sto(spw(J.q[par ^ 1], zo), uos, nq_);
                 if (ADJ) {
-                    sto(spw(J.wmix[par ^ 1][0], zo), uos[r], vA[r] * np_ + vB[r] * nq_);
-                    sto(spw(J.wmix[par ^ 1][1], zo), uos[r], vB[r] * np_ + nq_);
+                    sto(spw(J.wmix[par ^ 1][0], zo), uos, vA[r] * np_ + vB[r] * nq_);
+                    sto(spw(J.wmix[par ^ 1][1], zo), uos, vB[r] * np_ + nq_);
                 }
                 if (MODE == K2_FWD_STORE && J.seg_dtype == 0) {
                     float *sg = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                    sto(spw(sg, zo), uos[r], np_);
-                    sto(spw(sg + J.seg_field, zo), uos[r], nq_);
+                    sto(spw(sg, zo), uos, np_);
+                    sto(spw(sg + J.seg_field, zo), uos, nq_);
                 }
                 if (MODE == K2_ADJ_IC)
-                    sto(spw(J.grad, zo), uos[r],
+                    sto(spw(J.grad, zo), uos,
                         J.image ? vg[r] + (fpk[r] * np_ + fqk[r] * nq_)
                                 : vg[r] - idt2 * (fpk[r] * (np_ - 2.f * vp0[r] + vp1[r]) +
                                                   fqk[r] * (nq_ - 2.f * vq0[r] + vq1[r])));
