@@ -92,6 +92,11 @@ class Grid:
 
     shape = (nx, ny, nz) with ny = 1 in 2D; arrays are (nz, ny, nx).  z is depth.
     nbl = width (points) of the absorbing layer, counted inside ``shape``.
+    free_surface (elastic only): the top face carries no absorbing layer; its nbl rows are vacuum
+    (lambda = mu = 0, the given density kept) and the surface is the normal-stress plane of row nbl
+    (reading: the paper only names a free surface as an equation on a sub-domain; the vacuum
+    formulation keeps the propagator a plain velocity-stress step in a heterogeneous medium, so its
+    transpose, dot test and gradients are those of that step).
     """
     shape: tuple
     spacing: tuple
@@ -101,6 +106,7 @@ class Grid:
     dt: float = 1e-3
     nt: int = 1
     vref: float = 1500.0
+    free_surface: bool = False
 
     @property
     def ndim(self) -> int:
@@ -226,14 +232,16 @@ def tti_H(g: Grid, theta, phi, f, group: int) -> np.ndarray:
 # ---------------------------------------------------------------------------
 def damping_kappa(g: Grid) -> np.ndarray:
     """kappa(x) = sum_a kmax_a (d_a / nbl)^2 (1/s), d_a = depth in points into the layer along axis a,
-    kmax_a = 3 vref ln(1000) / (2 nbl h_a).  Zero when nbl = 0."""
+    kmax_a = 3 vref ln(1000) / (2 nbl h_a).  Zero when nbl = 0.  With a free surface the top face
+    (small z) has no layer."""
     k = np.zeros(g.arr_shape, dtype=np.float64)
     if g.nbl <= 0:
         return k
     for ax in g.axes():
         n = g.shape[ax]
         i = np.arange(n, dtype=np.float64)
-        d = np.maximum(np.maximum(g.nbl - i, i - (n - 1 - g.nbl)), 0.0)
+        top = np.zeros(n) if (ax == 2 and g.free_surface) else g.nbl - i
+        d = np.maximum(np.maximum(top, i - (n - 1 - g.nbl)), 0.0)
         kmax = 3.0 * g.vref * math.log(1000.0) / (2.0 * g.nbl * g.spacing[ax])
         prof = kmax * (d / g.nbl) ** 2
         shp = [1, 1, 1]
@@ -495,10 +503,15 @@ class ElasticModel:
 
     @staticmethod
     def from_velocities(g: Grid, vp, vs, rho) -> "ElasticModel":
+        """lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho; with a free surface the rows above
+        it (z index < nbl) are vacuum, lambda = mu = 0."""
         c = lambda a: np.asarray(a, dtype=np.float64).reshape(g.arr_shape)
         vp, vs, rho = c(vp), c(vs), c(rho)
-        return ElasticModel(np.ascontiguousarray(rho * (vp * vp - 2 * vs * vs)),
-                            np.ascontiguousarray(rho * vs * vs), np.ascontiguousarray(1.0 / rho))
+        lam, mu = rho * (vp * vp - 2 * vs * vs), rho * vs * vs
+        if g.free_surface:
+            lam[:g.nbl] = 0.0
+            mu[:g.nbl] = 0.0
+        return ElasticModel(np.ascontiguousarray(lam), np.ascontiguousarray(mu), np.ascontiguousarray(1.0 / rho))
 
 
 VZ_STAGGER = (0.0, 0.0, 0.5)
@@ -652,7 +665,8 @@ def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec
         dJ/db       += spread of dt v~_c (D_tau tau^n)_c to the two nodes of bbar, where
                        v~ = g v~'' is the velocity adjoint after the transposed step (v~'' is the
                        adjoint of v' once the stress sub-step is transposed);
-    then lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho give
+    then lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho (fixed at lambda = mu = 0 in the vacuum
+    rows of a free surface, where only b depends on the model) give
         dJ/dvp = 2 rho vp dJ/dlambda,   dJ/dvs = 2 rho vs (dJ/dmu - 2 dJ/dlambda),
         dJ/drho = (vp^2 - 2 vs^2) dJ/dlambda + vs^2 dJ/dmu - dJ/db / rho^2.
     Returns (J, (g_vp, g_vs, g_rho), traces)."""
@@ -697,6 +711,9 @@ def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec
         if g.ndim == 2 and k == 1:
             continue
         g_b += _spread_avg(g, acc_b[k], (k,))
+    if g.free_surface:   # the vacuum rows' lambda and mu do not depend on (vp, vs, rho)
+        g_lam[:g.nbl] = 0.0
+        g_mu[:g.nbl] = 0.0
     g_vp = 2.0 * rho * vp * g_lam
     g_vs = 2.0 * rho * vs * (g_mu - 2.0 * g_lam)
     g_rho = (vp * vp - 2.0 * vs * vs) * g_lam + vs * vs * g_mu - g_b / (rho * rho)
