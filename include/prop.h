@@ -75,6 +75,14 @@ typedef struct {
     double  dt;           /* time step in seconds; must not exceed prop_cfl_dt() */
     int32_t nt;           /* number of time steps */
     double  v_ref;        /* m/s: reference velocity of the absorbing-layer profile */
+    int32_t free_surface; /* 0 = absorbing layer on every face; 1 = free surface on the top face
+                             (small z; PROP_ELASTIC only, nbl >= space_order / 2): that face has no
+                             absorbing layer, its nbl rows are vacuum (lambda = mu = 0, the given
+                             density kept) and the surface is the normal-stress plane of row nbl.
+                             Shot windows must then start at z index 0; the gradient is zero for vp
+                             and vs in the vacuum rows.  (The paper names a free surface as an
+                             equation on a sub-domain, the elastic section; the vacuum form keeps
+                             the step, its transpose and its gradient unchanged in form.) */
 } prop_grid;
 
 /* Model parameters, DEVICE, dense (nz, ny, nx) over the whole grid.

@@ -496,7 +496,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__r
 // node i collects from p = i - 1 (weight 1) and p = i (weight 1 + [i = n - 1]), times 1/2 per axis.
 __device__ __forceinline__ float spread_w(int p, int i, int n) { return (p == i ? 1.f : 0.f) + (min(p + 1, n - 1) == i ? 1.f : 0.f); }
 
-__global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, const float *__restrict__ vp,
+__global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, int nvac, const float *__restrict__ vp,
                                const float *__restrict__ vs, const float *__restrict__ rho, float *__restrict__ out)
 {
     const ElGradJob &J = jobs[0];
@@ -507,7 +507,7 @@ __global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, con
     const int c3[3] = {x, y, z};
     auto at = [&](const float *f, int px, int py, int pz) { return gld(f, sidx(w, px, py, pz)); };
     const int64_t si = sidx(w, x, y, z);
-    const float gl = gld(J.acc[0], si);
+    float gl = gld(J.acc[0], si);
     float gm = gld(J.acc[1], si);
     // shear positions: (x, y) for xy, (x, z) for xz, (y, z) for yz
     const int pairs[3][2] = {{0, 1}, {0, 2}, {1, 2}};
@@ -538,6 +538,10 @@ __global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, con
             p[a] = pa;
             gb += 0.5f * spread_w(pa, c3[a], n[a]) * at(J.acc[5 + a], p[0], p[1], p[2]);
         }
+    }
+    if (z < nvac) {   // vacuum: lambda and mu are fixed at zero; only the buoyancy depends on rho
+        gl = 0.f;
+        gm = 0.f;
     }
     const int64_t mi = midx(w, x, y, z);
     const float a = gld(vp, mi), s = gld(vs, mi), r = gld(rho, mi);
@@ -616,9 +620,9 @@ void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntile
     EL_SWITCH(gic_dispatch, job, tiles, ntiles, zc, W, dt, st)
 }
 
-void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, const float *vp, const float *vs,
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,
                            const float *rho, float *out, hipStream_t st)
 {
     dim3 blk(256), grd((w.nx + 255) / 256, w.ny, w.nz);
-    hipLaunchKernelGGL(el_grad_finish, grd, blk, 0, st, job, ndim, vp, vs, rho, out);
+    hipLaunchKernelGGL(el_grad_finish, grd, blk, 0, st, job, ndim, nvac, vp, vs, rho, out);
 }

@@ -100,7 +100,8 @@ void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st);
 void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
                        hipStream_t st);
 // Spread the accumulators to the nodes (transpose of the half-node averages) and convert to
-// (vp, vs, rho): out = three dense window fields.
-void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, const float *vp, const float *vs,
+// (vp, vs, rho): out = three dense window fields.  Rows z < nvac are vacuum (lambda = mu = 0 there,
+// independent of vp, vs and rho).
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,
                            const float *rho, float *out, hipStream_t st);
 int el_tile_rows(int R);

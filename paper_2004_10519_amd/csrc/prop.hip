@@ -158,6 +158,10 @@ int check_grid(prop_kind kind, const prop_grid *g)
     if (g->nbl < 0) return fail(PROP_EINVAL, "nbl must be >= 0");
     if (!(g->dt > 0) || g->nt < 1) return fail(PROP_EINVAL, "dt must be > 0 and nt >= 1");
     if (g->nbl > 0 && !(g->v_ref > 0)) return fail(PROP_EINVAL, "v_ref must be > 0 with an absorbing layer");
+    if (g->free_surface != 0 && g->free_surface != 1) return fail(PROP_EINVAL, "free_surface must be 0 or 1");
+    if (g->free_surface && kind != PROP_ELASTIC) return fail(PROP_EINVAL, "a free surface is elastic only");
+    if (g->free_surface && g->nbl < g->space_order / 2)
+        return fail(PROP_EINVAL, "a free surface needs nbl >= space_order / 2 vacuum rows");
     for (int a = 0; a < 3; ++a) {
         if (g->ndim == 2 && a == 1) continue;
         if (!(g->spacing[a] > 0)) return fail(PROP_EINVAL, "spacing must be > 0");
@@ -268,7 +272,8 @@ double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
 {
     if (g.nbl <= 0) return 0.0;
     if (g.ndim == 2 && axis == 1) return 0.0;
-    double d = std::max<double>(std::max<double>(g.nbl - (double)i, (double)i - (double)(n - 1 - g.nbl)), 0.0);
+    const double top = (axis == 2 && g.free_surface) ? 0.0 : g.nbl - (double)i;   // free surface: no top layer
+    double d = std::max<double>(std::max<double>(top, (double)i - (double)(n - 1 - g.nbl)), 0.0);
     double kmax = 3.0 * g.v_ref * std::log(1000.0) / (2.0 * g.nbl * g.spacing[axis]);
     return kmax * (d / g.nbl) * (d / g.nbl);
 }
@@ -303,12 +308,13 @@ void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std:
         }
 }
 
-// z-chunk length: enough chunks for ~2048 blocks, but chunks of at least 4R planes (the z halo of
-// a chunk is re-read by its neighbour).
+// z-chunk length: enough chunks for ~2048 blocks (elastic: ~4096; its two passes have no
+// autotuner, and 17-plane chunks measured 4 % faster than 34-plane ones at 400^3 so8), but chunks
+// of at least 4R planes (the z halo of a chunk is re-read by its neighbour).
 int choose_zc(const prop_s *h, int nz, int64_t tiles_xy)
 {
     if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
-    const int64_t target = 2048;
+    const int64_t target = h->kind == PROP_TTI ? 2048 : 4096;
     int64_t nch = (target + tiles_xy - 1) / tiles_xy;
     nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / (4 * h->R))));
     return (int)((nz + nch - 1) / nch);
@@ -328,6 +334,7 @@ int shot_window(const prop_s *h, const prop_shot *s, int64_t o[3], int64_t n[3])
         if (!(h->g.ndim == 2 && a == 1) && n[a] < 2) return fail(PROP_EINVAL, "window needs >= 2 points per axis");
         if (!(h->g.ndim == 2 && a == 1) && n[a] < 2 * (int64_t)h->g.nbl + 2)
             return fail(PROP_EINVAL, "window smaller than its absorbing layers");
+    if (h->g.free_surface && o[2] != 0) return fail(PROP_EINVAL, "with a free surface a window starts at z index 0");
     }
     return PROP_OK;
 }
@@ -648,6 +655,11 @@ int prep_model(prop_s *h, const prop_model *m)
                      cc + n, cc + 2 * n, cc + 3 * n, h->stats.as<unsigned>(), h->st);
     else
         aux_el_prep(m->p[0], m->p[1], m->p[2], n, cc, cc + n, cc + 2 * n, h->stats.as<unsigned>(), h->st);
+    if (h->kind == PROP_ELASTIC && h->g.free_surface) {   // vacuum rows above the free surface
+        const int64_t nv = (int64_t)h->g.nbl * h->g.shape[1] * h->g.shape[0];
+        aux_fill(cc, nv, 0.f, h->st);
+        aux_fill(cc + n, nv, 0.f, h->st);
+    }
     HIPCHK(hipGetLastError());
     unsigned s[4];
     HIPCHK(hipMemcpyAsync(s, h->stats.p, sizeof s, hipMemcpyDeviceToHost, h->st));
@@ -1644,7 +1656,8 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
         HIPCHK(hipGetLastError());
         TRY(check_finite(h, sl.f[5], sl.w, "adjoint tau_zz (gradient)", start));
     }
-    launch_el_grad_finish(dgj, sl.w, h->g.ndim, h->model.p[0], h->model.p[1], h->model.p[2], out, h->st);
+    launch_el_grad_finish(dgj, sl.w, h->g.ndim, h->g.free_surface ? h->g.nbl : 0, h->model.p[0], h->model.p[1],
+                          h->model.p[2], out, h->st);
     HIPCHK(hipGetLastError());
     TRY(check_finite(h, acc, sl.w, "gradient accumulator", 0));
     h->last_state = 0;

@@ -40,7 +40,8 @@ class PropError(RuntimeError):
 class CGrid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("shape", ctypes.c_int64 * 3), ("spacing", ctypes.c_double * 3),
                 ("origin", ctypes.c_double * 3), ("space_order", ctypes.c_int32), ("time_order", ctypes.c_int32),
-                ("nbl", ctypes.c_int32), ("dt", ctypes.c_double), ("nt", ctypes.c_int32), ("v_ref", ctypes.c_double)]
+                ("nbl", ctypes.c_int32), ("dt", ctypes.c_double), ("nt", ctypes.c_int32), ("v_ref", ctypes.c_double),
+                ("free_surface", ctypes.c_int32)]
 
 
 class CModel(ctypes.Structure):
@@ -122,6 +123,7 @@ class Grid:
     dt: float = 1e-3
     nt: int = 1
     v_ref: float = 1500.0
+    free_surface: bool = False   # elastic: free surface on the top face (vacuum rows above row nbl)
 
     @property
     def ndim(self) -> int:
@@ -144,6 +146,7 @@ class Grid:
         g.dt = float(self.dt)
         g.nt = int(self.nt)
         g.v_ref = float(self.v_ref)
+        g.free_surface = int(bool(self.free_surface))
         return g
 
 

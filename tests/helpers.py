@@ -48,7 +48,7 @@ def _sd(so):
     return oracle.symbol_max_sq(so)
 
 
-def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20):
+def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20, free_surface=False):
     nx, ny, nz = shape
     model = inputs.elastic_model(shape, nbl, seed)
     rng = np.random.default_rng(seed + 7)
@@ -60,7 +60,8 @@ def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20):
     dt = 0.8 * min(h) / (4725.0 * np.sqrt(3) * {4: 1.16667, 8: 1.28631, 12: 1.33906}[so])
     wav = inputs.ricker(30.0, dt, nt)[:, None]
     return dict(shape=shape, h=h, so=so, nbl=nbl, nt=nt, dt=float(dt), model=model, src=src.astype(np.float32),
-                rec=rec.astype(np.float32), kind=kind, wav=np.ascontiguousarray(wav, dtype=np.float32))
+                rec=rec.astype(np.float32), kind=kind, wav=np.ascontiguousarray(wav, dtype=np.float32),
+                free_surface=free_surface)
 
 
 def make_tti(case, prop, scheme=0, **options):
@@ -83,7 +84,7 @@ def make_tti(case, prop, scheme=0, **options):
 
 def make_el(case, prop):
     g = prop.Grid(case["shape"], case["h"], space_order=case["so"], nbl=case["nbl"], dt=case["dt"], nt=case["nt"],
-                  v_ref=1500.0)
+                  v_ref=1500.0, free_surface=case.get("free_surface", False))
     mt = [dev(case["model"][k]) for k in ("vp", "vs", "rho")]
     p = prop.Propagator(prop.ELASTIC, g, mt)
     p._keep_model = mt
@@ -101,6 +102,6 @@ def oracle_tti(case, orc):
 
 def oracle_el(case, orc):
     g = orc.Grid(case["shape"], case["h"], space_order=case["so"], nbl=case["nbl"], dt=case["dt"], nt=case["nt"],
-                 vref=1500.0)
+                 vref=1500.0, free_surface=case.get("free_surface", False))
     m = case["model"]
     return g, orc.ElasticModel.from_velocities(g, m["vp"], m["vs"], m["rho"])

@@ -106,3 +106,96 @@ def test_elastic_gradient_parity(prop, orc, so, shape):
     # checkpoints are exact FP32 copies: any segmentation gives the same bits
     g1 = host(p.gradient(shot, dev(res), n_ckpt=1, ckpt_dtype="f32"))
     assert np.array_equal(g1, gg)
+
+
+# ---- free surface on the top face (vacuum rows above row nbl, no absorbing layer on that face)
+FS_CASES = [((70, 37, 29), 8), ((90, 1, 61), 8), ((66, 20, 40), 4)]
+
+
+def _fs_case(shape, so, nt):
+    case = el_case(shape, so, 5, nt, free_surface=True)
+    if shape[1] == 1:
+        case = _to_2d(case)
+    # source below the surface, near it (the ghost and the surface waves matter)
+    case["src"][0, -1] = case["h"][2] * (case["nbl"] + 3.4)
+    return case
+
+
+@pytest.mark.parametrize("shape,so", FS_CASES)
+def test_free_surface_forward_parity(prop, orc, shape, so):
+    case = _fs_case(shape, so, 80)
+    p, shot = make_el(case, prop)
+    d = host(p.forward(shot))
+    fields = [host(p.read_state(i)) for i in range(9)]
+    g, mod = oracle_el(case, orc)
+    do, fo = orc.elastic_forward(g, mod, case["src"], case["wav"], case["rec"], case["kind"])
+    assert rel_l2(d, do) <= 1e-4, rel_l2(d, do)
+    for i, (a, b) in enumerate(zip(fields, fo)):
+        if np.abs(b).max() > 0:
+            assert rel_l2(a, b) <= 1e-4, (i, rel_l2(a, b))
+        else:
+            assert not a.any(), i
+    nb = case["nbl"]
+    for c in (3, 4, 5):   # normal stresses vanish in the vacuum rows
+        assert not fields[c][:nb].any()
+
+
+@pytest.mark.parametrize("shape,so", FS_CASES[:2])
+def test_free_surface_adjoint_parity_and_dot(prop, orc, shape, so):
+    case = _fs_case(shape, so, 60)
+    p, shot = make_el(case, prop)
+    rng = np.random.default_rng(3)
+    rec = rng.standard_normal((case["nt"], len(case["rec"]))).astype(np.float32)
+    s = host(p.adjoint(shot, dev(rec)))
+    g, mod = oracle_el(case, orc)
+    so_, _ = orc.elastic_adjoint(g, mod, case["src"], case["rec"], rec, case["kind"])
+    assert rel_l2(s, so_) <= 1e-4, rel_l2(s, so_)
+    x = dev(rng.standard_normal(case["wav"].shape))
+    shot.wavelet = x
+    Fx = p.forward(shot)
+    xi = dev(rng.standard_normal((case["nt"], len(case["rec"]))))
+    y = (Fx * (xi.norm() / Fx.norm()) + xi).contiguous()
+    FTy = p.adjoint(shot, y)
+    a, b = prop.dot_f64(Fx, y), prop.dot_f64(x, FTy)
+    assert abs(a - b) / abs(a) < 1e-5, (a, b)
+
+
+@pytest.mark.parametrize("shape,so", FS_CASES[:2])
+def test_free_surface_gradient_parity(prop, orc, shape, so):
+    from paper_2004_10519_amd import inputs
+    case = _fs_case(shape, so, 60)
+    p, shot = make_el(case, prop)
+    g, mod = oracle_el(case, orc)
+    m = case["model"]
+    pert = 1 + 0.03 * inputs.random_unit_field(g.arr_shape, 5, 2.0)
+    dobs, _ = orc.elastic_forward(g, orc.ElasticModel.from_velocities(g, m["vp"] * pert, m["vs"] * pert, m["rho"]),
+                                  case["src"], case["wav"], case["rec"], case["kind"])
+    d = host(p.forward(shot)).astype(np.float64)
+    res = (d - dobs).astype(np.float32)
+    gg = host(p.gradient(shot, dev(res), n_ckpt=5, ckpt_dtype="f32"))
+    _, go, _ = orc.elastic_gradient(g, m["vp"], m["vs"], m["rho"], case["src"], case["wav"], case["rec"],
+                                    d - res.astype(np.float64), case["kind"])
+    for name, a, b in zip(("vp", "vs", "rho"), gg, go):
+        err = rel_l2(a, b)
+        print(f"free-surface elastic gradient {name}: rel-L2 {err:.3e}")
+        assert err <= 1e-3, (name, err)
+    nb = case["nbl"]
+    assert not gg[0][:nb].any() and not gg[1][:nb].any()
+
+
+def test_free_surface_rejections(prop):
+    from helpers import tti_case
+    case = el_case((40, 20, 30), 8, 3, 10, free_surface=True)
+    with pytest.raises(prop.PropError, match="nbl >= space_order"):
+        make_el(case, prop)
+    tcase = tti_case((40, 20, 30), 8, 5, 10)
+    g = prop.Grid(tcase["shape"], tcase["h"], space_order=8, nbl=5, dt=tcase["dt"], nt=10, free_surface=True)
+    mt = [dev(tcase["model"][k]) for k in ("m", "eps", "delta", "theta", "phi")]
+    with pytest.raises(prop.PropError, match="elastic only"):
+        prop.Propagator(prop.TTI, g, mt)
+    case = el_case((40, 20, 30), 8, 5, 10, free_surface=True)
+    p, shot = make_el(case, prop)
+    off = prop.Shot(case["src"], dev(case["wav"]), case["rec"], case["kind"], win_origin=(0, 0, 1),
+                    win_shape=(40, 20, 29))
+    with pytest.raises(prop.PropError, match="starts at z index 0"):
+        p.forward(off)
