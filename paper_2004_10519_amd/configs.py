@@ -9,6 +9,9 @@ has to supply them to the other.
   el3d_400     3D elastic, 400^3, h 10 m, space order 8, 2000 steps, 40-point layers
   ttigrad_256  3D TTI gradient, 256^3, h 12.5 m, space order 8, 2000 steps (and a 64^3 check)
   batch_64     64 TTI shots on windows of a 1024 x 1024 x 512 model, space order 8, 1500 steps
+  el2d_marine  2D elastic, 1701 x 391, h 10 m, space order 8, 5 s, free surface over a 450 m water
+               layer; pressure 5 m below the surface and vz on the sea bed (the paper's 2D example's
+               geometry on a seeded layered model)
 """
 from __future__ import annotations
 
@@ -36,6 +39,7 @@ class Workload:
     rec_xyz: np.ndarray
     rec_kind: np.ndarray = None
     v_ref: float = 1500.0
+    free_surface: bool = False
     model: dict = field(default_factory=dict, repr=False)
 
     @property
@@ -69,6 +73,8 @@ class Workload:
             mdl = inputs.tti_model(self.shape, self.nbl, self.seed, progress=progress)
             self.model = {"m": inputs.slowness_squared(mdl["vp"]), "eps": mdl["eps"], "delta": mdl["delta"],
                           "theta": mdl["theta"], "phi": mdl["phi"]}
+        elif self.name == "el2d_marine":
+            self.model = inputs.marine_elastic_model(self.shape, self.nbl, MARINE_WATER_ROWS, self.seed)
         else:
             self.model = inputs.elastic_model(self.shape, self.nbl, self.seed)
         return self.model
@@ -150,3 +156,22 @@ def batch_64(nshot: int = 64, nt: int = 1500, shape=(1024, 1024, 512), seed_mode
         rec = np.stack([X.ravel(), Y.ravel(), np.full(X.size, h[2] * (nbl + 2))], axis=1).astype(np.float32)
         shots.append((tuple(o), tuple(n), src, rec))
     return w, shots
+
+
+MARINE_WATER_ROWS = 45   # 450 m of water at 10 m
+
+
+def el2d_marine(nt: int = 5556) -> Workload:
+    """Free surface on the top face at row nbl (the rows above it are vacuum), explosive source 10 m
+    below it at x = 5 km of the physical frame, pressure receivers 5 m below the surface and vz
+    receivers on the sea bed, every 10 m across the physical width; dt 0.9 ms (5 s in 5556 steps)."""
+    shape, h, nbl = (1701, 1, 391), (10.0, 1.0, 10.0), 40
+    z0 = nbl * h[2]
+    src = np.array([[nbl * h[0] + 5000.0, z0 + 10.0]], dtype=np.float32)
+    xs = nbl * h[0] + np.arange(0, shape[0] - 2 * nbl) * h[0]
+    rp = np.stack([xs, np.full(xs.size, z0 + 5.0)], axis=1)
+    rv = np.stack([xs, np.full(xs.size, z0 + MARINE_WATER_ROWS * h[2])], axis=1)
+    rec = np.concatenate([rp, rv], axis=0).astype(np.float32)
+    kind = np.concatenate([np.zeros(xs.size, np.int32), np.ones(xs.size, np.int32)])
+    return Workload("el2d_marine", "elastic", shape, h, 8, nt, nbl, 0.9e-3, 9, 12.0, src, rec, kind,
+                    v_ref=1500.0, free_surface=True)

@@ -154,6 +154,29 @@ def elastic_model(shape_xyz, nbl: int, seed: int, nlayers: int = 10, vmin: float
     return {k: np.ascontiguousarray(v, dtype=np.float32) for k, v in (("vp", vp), ("vs", vs), ("rho", rho))}
 
 
+def marine_elastic_model(shape_xyz, surface_row: int, water_rows: int, seed: int, nlayers: int = 9,
+                         vmin: float = 1600.0, vmax: float = 4500.0, pert: float = 0.05,
+                         vp_vs: float = 1.8) -> dict:
+    """Seeded marine elastic model: FP32 vp, vs (m/s), rho (kg/m^3), shape (nz, ny, nx).  Water
+    (vp 1500 m/s, vs 0) from the top down to surface_row + water_rows (the rows above surface_row
+    become vacuum under a free surface), then nlayers elastic layers between vmin and vmax with a
+    smoothed +-pert perturbation, vs = vp / vp_vs, Gardner density 310 vp^0.25."""
+    nx, ny, nz = (int(s) for s in shape_xyz)
+    shp = (nz, ny, nx)
+    rng = _rng(seed)
+    bed = surface_row + water_rows
+    depths = np.sort(rng.uniform(0.0, 0.9, nlayers - 1)) * (nz - bed) + bed
+    k = np.arange(nz, dtype=np.float64)
+    layer = np.searchsorted(depths, k, side="right")
+    v_layer = vmin + (vmax - vmin) * layer / max(nlayers - 1, 1)
+    xi = _minmax(smooth(rng.standard_normal(shp), 4.0), -1.0, 1.0)
+    water = (k < bed)[:, None, None]
+    vp = np.where(water, 1500.0, v_layer[:, None, None] * (1.0 + pert * xi))
+    vs = np.where(water, 0.0, vp / vp_vs)
+    rho = 310.0 * vp ** 0.25
+    return {k_: np.ascontiguousarray(v, dtype=np.float32) for k_, v in (("vp", vp), ("vs", vs), ("rho", rho))}
+
+
 def slowness_squared(vp: np.ndarray) -> np.ndarray:
     """The model parameter m = 1/vp^2 (s^2/m^2) as FP32, computed in FP64 from the FP32 velocities."""
     v = np.asarray(vp, dtype=np.float64)

@@ -10,6 +10,8 @@
 * 512^3 so12 TTI dot test over 20 steps and 65536 receivers.
 * 256^3 so8 gradient (2000 steps; 48 FP16 checkpoints, or the whole run stored in FP16): central
   finite difference of the FP64 misfit along a smooth model perturbation.
+* 2D marine elastic workload (1701 x 391, free surface over the water layer): the first 800 steps,
+  all 3242 traces, against the checker on the whole grid.
 """
 import math
 
@@ -185,3 +187,33 @@ def test_ttigrad256_finite_difference(prop, n_ckpt):
     fd = (jp - jm) / (2 * hh)
     print(f"256^3 gradient: <g, dm> = {gd:.6e}, central FD = {fd:.6e}, rel {abs(fd - gd) / abs(gd):.2e}")
     assert abs(fd - gd) / abs(gd) < 2e-2
+
+
+def test_el2d_marine_free_surface_vs_checker(prop, orc):
+    """Full shape of the 2D marine workload, first 800 steps (0.72 s: the direct wave and its surface
+    ghost, the sea-bed reflection back near the surface, the transmitted waves at the sea bed):
+    traces of both receiver lines and the final fields against the checker; the normal stresses
+    stay zero in the vacuum rows."""
+    from paper_2004_10519_amd import configs
+    w = configs.el2d_marine(nt=800)
+    m = w.make_model()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref,
+                  free_surface=True)
+    mt = [dev(m[k]) for k in ("vp", "vs", "rho")]
+    p = prop.Propagator(prop.ELASTIC, g, mt)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz, w.rec_kind)
+    d = host(p.forward(shot))
+    fields = [host(p.read_state(i)) for i in range(9)]
+    og = orc.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, vref=w.v_ref,
+                  free_surface=True)
+    mod = orc.ElasticModel.from_velocities(og, m["vp"], m["vs"], m["rho"])
+    do, fo = orc.elastic_forward(og, mod, w.src_xyz, w.wavelet(), w.rec_xyz, w.rec_kind)
+    npr = int((w.rec_kind == 0).sum())
+    for name, sl in (("pressure", slice(0, npr)), ("vz", slice(npr, None))):
+        err = rel_l2(d[:, sl], do[:, sl])
+        print(f"el2d_marine {name} traces rel-L2 {err:.2e}")
+        assert np.abs(do[:, sl]).max() > 0 and err <= 1e-4, (name, err)
+    for i in (0, 2, 3, 5, 7):   # vx, vz, txx, tzz, txz (2D)
+        assert rel_l2(fields[i], fo[i]) <= 1e-4, i
+    for c in (3, 5):
+        assert not fields[c][:w.nbl].any()
