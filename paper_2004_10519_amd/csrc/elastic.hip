@@ -21,17 +21,20 @@
 
 namespace {
 
-constexpr int EBY = 16;   // block = 64 x 16 threads, one row each
+// Tile rows (= threads in y, one row each): 16 on 3D grids; 2D grids (ny = 1) use one row, so a
+// block is a single wavefront and no y-halo work is done (its y derivatives are zero).
+constexpr int EBY = 16;
 
 // Velocity pass.  Fields read: F[0..5] = (xx, yy, zz, xy, xz, yz) stresses (forward: tau;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
 // register queues: zz, xz, yz.  Pipelined like the TTI passes: the loads of plane z+1 are in
 // flight while plane z is computed; LDS is double-buffered.
-template <int R, int MODE>
-__global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict__ jobs,
+template <int R, int MODE, int BY>
+__global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
-    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
+    constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
+    constexpr bool TWO_D = BY == 1;
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -83,7 +86,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
             hxz[k] = v ? ld(Fxz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
             }
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             if (i < H::NYI) {
                 int yy, xx;
@@ -145,11 +148,11 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
         const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
         const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (z + 1 < z1) fetch(z + 1);
-        const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
+        const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lxy, li, LX, W.wy)) +
                          ds_q<R, false>(qxz, W.wz);
-        const float fy = ds_lds<R, false>(lxy, li, 1, W.wx) + ds_lds<R, true>(lyy, li, LX, W.wy) +
+        const float fy = ds_lds<R, false>(lxy, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, true>(lyy, li, LX, W.wy)) +
                          ds_q<R, false>(qyz, W.wz);
-        const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + ds_lds<R, false>(lyz, li, LX, W.wy) +
+        const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lyz, li, LX, W.wy)) +
                          ds_q<R, true>(qzz, W.wz);
         if (own) {
             if (MODE == EL_FWD) {
@@ -173,11 +176,12 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_vel(const ElJob *__restrict_
 
 // Stress pass.  Fields read: V[0..2] (forward: v; adjoint: u = bbar g v~), each staged in LDS
 // with x and y halos and queued in z.
-template <int R, int MODE>
-__global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restrict__ jobs,
+template <int R, int MODE, int BY>
+__global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restrict__ jobs,
                                                           const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
-    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
+    constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
+    constexpr bool TWO_D = BY == 1;
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
             hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
             }
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             if (i < H::NYI) {
                 int yy, xx;
@@ -291,11 +295,11 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_stress(const ElJob *__restri
         }
         if (z + 1 < z1) fetch(z + 1);
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
-        const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
+        const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
         const float ezz = ds_q<R, false>(qz, W.wz);
-        const float gxy = ds_lds<R, true>(lx, li, LX, W.wy) + ds_lds<R, true>(ly, li, 1, W.wx);
+        const float gxy = (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
         const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
-        const float gyz = ds_q<R, true>(qy, W.wz) + ds_lds<R, true>(lz, li, LX, W.wy);
+        const float gyz = ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
         if (own) {
             if (MODE == EL_FWD) {
                 const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
@@ -353,11 +357,12 @@ __global__ void el_mix_stress(const ElJob *__restrict__ jobs)
 //   acc_b,c    += v~_c dt (D_tau tau^n)_c = v~_c (v^{n+1}_c - g v^n_c) / (g bbar_c)
 // (the velocity update v^{n+1} = g (v^n + dt bbar D_tau tau^n) gives the force from two stored
 // velocity levels).
-template <int R>
-__global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__restrict__ jobs,
+template <int R, int BY>
+__global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__restrict__ jobs,
                                                            const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
-    constexpr int TY = EBY, Q = 2 * R + 1, NT = PROP_TX * EBY;
+    constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
+    constexpr bool TWO_D = BY == 1;
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -402,7 +407,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__r
             hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
@@ -441,7 +446,7 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__r
             }
         }
 #pragma unroll
-        for (int k = 0; k < H::NYH; ++k) {
+        for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
             const int i = tid + k * NT;
             if (i < H::NYI) {
                 int yy, xx;
@@ -470,11 +475,11 @@ __global__ __launch_bounds__(PROP_TX * EBY) void el_grad_ic(const ElGradJob *__r
         const float v1[3] = {qx[R], qy[R], qz[R]};
         if (z + 1 < z1) fetch(z + 1);
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
-        const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
+        const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
         const float ezz = ds_q<R, false>(qz, W.wz);
-        const float gxy = ds_lds<R, true>(lx, li, LX, W.wy) + ds_lds<R, true>(ly, li, 1, W.wx);
+        const float gxy = (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
         const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
-        const float gyz = ds_q<R, true>(qy, W.wz) + ds_lds<R, true>(lz, li, LX, W.wy);
+        const float gyz = ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
         if (own) {
             const float gdt = g * dt;
             const float bb[3] = {0.5f * (b0 + bxn), 0.5f * (b0 + byn), 0.5f * (b0 + bzn)};
@@ -551,30 +556,46 @@ __global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, int
     gst(out, 2 * np_ + o, (a * a - 2.f * s * s) * gl + s * s * gm - gb / (r * r));
 }
 
-template <int R>
-void vel_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
-                  float dt, hipStream_t st)
+template <int R, int BY>
+void vel_launch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                hipStream_t st)
 {
-    dim3 blk(PROP_TX, EBY), grd(ntiles);
-    if (mode == EL_FWD) hipLaunchKernelGGL((el_vel<R, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
-    else                hipLaunchKernelGGL((el_vel<R, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    dim3 blk(PROP_TX, BY), grd(ntiles);
+    if (mode == EL_FWD) hipLaunchKernelGGL((el_vel<R, EL_FWD, BY>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    else                hipLaunchKernelGGL((el_vel<R, EL_ADJ, BY>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
 }
 
 template <int R>
-void stress_dispatch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
+void vel_dispatch(int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
+                  float dt, hipStream_t st)
+{
+    if (by == 1) vel_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else         vel_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+}
+
+template <int R, int BY>
+void stress_launch(int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                   hipStream_t st)
+{
+    dim3 blk(PROP_TX, BY), grd(ntiles);
+    if (mode == EL_FWD) hipLaunchKernelGGL((el_stress<R, EL_FWD, BY>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    else                hipLaunchKernelGGL((el_stress<R, EL_ADJ, BY>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+}
+
+template <int R>
+void stress_dispatch(int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                      float dt, hipStream_t st)
 {
-    dim3 blk(PROP_TX, EBY), grd(ntiles);
-    if (mode == EL_FWD) hipLaunchKernelGGL((el_stress<R, EL_FWD>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
-    else                hipLaunchKernelGGL((el_stress<R, EL_ADJ>), grd, blk, 0, st, jobs, tiles, zc, W, dt);
+    if (by == 1) stress_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else         stress_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
 }
 
 }  // namespace
 
-int el_tile_rows(int R)
+int el_tile_rows(int R, int ndim)
 {
     (void)R;
-    return EBY;
+    return ndim == 2 ? 1 : EBY;
 }
 
 #define EL_SWITCH(FN, ...)                                  \
@@ -589,16 +610,16 @@ int el_tile_rows(int R)
     default: FN<8>(__VA_ARGS__); break;                     \
     }
 
-void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
-                   float dt, hipStream_t st)
+void launch_el_vel(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+                   const Weights &W, float dt, hipStream_t st)
 {
-    EL_SWITCH(vel_dispatch, mode, jobs, tiles, ntiles, zc, W, dt, st)
+    EL_SWITCH(vel_dispatch, by, mode, jobs, tiles, ntiles, zc, W, dt, st)
 }
 
-void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+void launch_el_stress(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                       const Weights &W, float dt, hipStream_t st)
 {
-    EL_SWITCH(stress_dispatch, mode, jobs, tiles, ntiles, zc, W, dt, st)
+    EL_SWITCH(stress_dispatch, by, mode, jobs, tiles, ntiles, zc, W, dt, st)
 }
 
 void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st)
@@ -608,16 +629,17 @@ void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st)
 }
 
 template <int R>
-void gic_dispatch(const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+void gic_dispatch(int by, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
                   hipStream_t st)
 {
-    hipLaunchKernelGGL((el_grad_ic<R>), dim3(ntiles), dim3(PROP_TX, EBY), 0, st, job, tiles, zc, W, dt);
+    if (by == 1) hipLaunchKernelGGL((el_grad_ic<R, 1>), dim3(ntiles), dim3(PROP_TX, 1), 0, st, job, tiles, zc, W, dt);
+    else hipLaunchKernelGGL((el_grad_ic<R, EBY>), dim3(ntiles), dim3(PROP_TX, EBY), 0, st, job, tiles, zc, W, dt);
 }
 
-void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
-                       hipStream_t st)
+void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W,
+                       float dt, hipStream_t st)
 {
-    EL_SWITCH(gic_dispatch, job, tiles, ntiles, zc, W, dt, st)
+    EL_SWITCH(gic_dispatch, by, job, tiles, ntiles, zc, W, dt, st)
 }
 
 void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,

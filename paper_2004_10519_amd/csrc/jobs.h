@@ -92,16 +92,17 @@ void launch_tti_fused(int R, int shape, int mode, const TTIJob *jobs, const Tile
                       const Weights &W, float idt2, int seg_step, hipStream_t st);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };
-void launch_el_vel(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+// by: tile rows of the launch (el_tile_rows); the tiles must have been made with that height.
+void launch_el_vel(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                    const Weights &W, float dt, hipStream_t st);
-void launch_el_stress(int R, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
+void launch_el_stress(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                       const Weights &W, float dt, hipStream_t st);
 void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st);
-void launch_el_grad_ic(int R, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
-                       hipStream_t st);
+void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W,
+                       float dt, hipStream_t st);
 // Spread the accumulators to the nodes (transpose of the half-node averages) and convert to
 // (vp, vs, rho): out = three dense window fields.  Rows z < nvac are vacuum (lambda = mu = 0 there,
 // independent of vp, vs and rho).
 void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,
                            const float *rho, float *out, hipStream_t st);
-int el_tile_rows(int R);
+int el_tile_rows(int R, int ndim);
