@@ -90,7 +90,8 @@ def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None, sp
 def setup_tti(w, torch, prop):
     arrs = w.model_list()
     dev = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrs]
-    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref,
+                  free_surface=w.free_surface)
     p = prop.Propagator(prop.TTI if w.kind == "tti" else prop.ELASTIC, g, dev)
     p._keep = dev
     if w.kind == "tti":
@@ -198,6 +199,24 @@ def measure_elastic(torch, prop, nt):
             "gradient_vp_vs_rho_GPts/s": round(gg, 3), "gradient_checkpoints": 48,
             "forward_method_hbm_frac": round(g * METHOD_BYTES_PER_PT["elastic"] / HBM_PEAK_GBS, 4),
             "forward_kernels": roof}
+
+
+def measure_marine(torch, prop):
+    """The 2D marine elastic workload (free surface over a water layer), 5 s of modelling."""
+    from paper_2004_10519_amd import configs
+    w = configs.el2d_marine()
+    p, shot = setup_tti(w, torch, prop)
+    p.forward(shot)
+    torch.cuda.synchronize()
+    t = timed(torch, lambda: p.forward(shot), 1, 0)
+    d = p.forward(shot)
+    npr = int((w.rec_kind == 0).sum())
+    peak = [float(d[:, :npr].abs().max()), float(d[:, npr:].abs().max())]
+    p.close()
+    return {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
+            "free_surface": True, "s": round(t, 4), "GPts/s": round(w.npts * w.nt / t / 1e9, 3),
+            "receivers": {"pressure_5m": npr, "vz_seabed": len(w.rec_xyz) - npr},
+            "peak_pressure": peak[0], "peak_vz": peak[1]}
 
 
 def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
@@ -477,6 +496,9 @@ def main():
     if not args.only_main:
         nt_el = 2000 if args.nt is None else min(args.nt, 2000)
         paths["elastic"] = measure_elastic(torch, prop, nt_el)
+        torch.cuda.empty_cache()
+        log("[bench] 2D marine elastic (free surface) ...")
+        paths["elastic_2d_marine"] = measure_marine(torch, prop)
         torch.cuda.empty_cache()
         nt_gr = 2000 if args.nt is None else min(args.nt, 2000)
         paths["tti_gradient"] = measure_gradient(torch, prop, nt_gr)
