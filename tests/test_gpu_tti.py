@@ -291,11 +291,13 @@ def test_isotropic_reduction_vs_acoustic_stepper(prop, orc):
     assert rel_l2(pf, ua) <= 1e-4 and np.array_equal(pf, qf)
 
 
-def test_degenerate_shots(prop, orc):
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_degenerate_shots(prop, orc, scheme):
     """No source: all-zero traces; no receivers: the state still evolves; one time step; a window of
-    the smallest allowed size (2 nbl + 2 points per axis) inside a larger grid."""
+    the smallest allowed size (2 nbl + 2 points per axis) inside a larger grid; a grid thinner than
+    the stencil (5 x 3 x 2 points at space order 12, no absorbing layer)."""
     case = tti_case((70, 37, 29), 8, 5, 40)
-    p, shot = make_tti(case, prop)
+    p, shot = make_tti(case, prop, scheme)
     silent = prop.Shot(np.zeros((0, 3), np.float32), None, case["rec"])
     assert not host(p.forward(silent)).any()
     blind = prop.Shot(case["src"], dev(case["wav"]), np.zeros((0, 3), np.float32))
@@ -305,7 +307,7 @@ def test_degenerate_shots(prop, orc):
     _, (po, _, _, _), _ = orc.tti_forward(g, mod, case["src"], case["wav"], None)
     assert rel_l2(pf, po) <= 1e-4
     one = tti_case((70, 37, 29), 8, 5, 1)
-    p1, s1 = make_tti(one, prop)
+    p1, s1 = make_tti(one, prop, scheme)
     d1 = host(p1.forward(s1))
     g1, mod1 = oracle_tti(one, orc)
     do1, _, _ = orc.tti_forward(g1, mod1, one["src"], one["wav"], one["rec"])
@@ -326,3 +328,9 @@ def test_degenerate_shots(prop, orc):
     assert rel_l2(dw, dow) <= 1e-4, rel_l2(dw, dow)
     with pytest.raises(prop.PropError):       # one point short of 2 nbl + 2
         p.forward(prop.Shot(src, wav, rec, win_origin=o, win_shape=(11, 12, 12)))
+    thin = tti_case((5, 3, 2), 12, 0, 12, nsrc=1, nrec=3)
+    pt, st = make_tti(thin, prop, scheme)
+    dt_ = host(pt.forward(st))
+    gt, mt = oracle_tti(thin, orc)
+    dot_, _, _ = orc.tti_forward(gt, mt, thin["src"], thin["wav"], thin["rec"])
+    assert np.abs(dot_).max() > 0 and rel_l2(dt_, dot_) <= 1e-4, rel_l2(dt_, dot_)
