@@ -63,3 +63,6 @@ def test_workload_time_steps_are_stable(orc):
     w = configs.el3d_400()
     og = orc.Grid(w.shape, w.spacing, space_order=w.space_order)
     assert w.dt <= orc.elastic_dt_max(og, 4725.0) * 0.81
+    w = configs.el2d_marine()   # layers up to 4.5 km/s with a +5 % perturbation
+    og = orc.Grid(w.shape, w.spacing, space_order=w.space_order)
+    assert w.dt <= orc.elastic_dt_max(og, 4725.0) * 0.81
