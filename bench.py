@@ -57,6 +57,9 @@ def kernel_bytes(kclass: int, scheme: int = 0, adjoint: bool = False) -> int:
 
 # minimum bytes per point per time step of the whole method (fused reading, FP32)
 METHOD_BYTES_PER_PT = {"tti": 44, "elastic": 84}
+# TTI FLOPs per point after the paper's symbolic optimisation (Table ttiFLOPs), used only to quote a
+# FLOP-rate equivalent beside the paper's own figures
+TTI_PAPER_FLOPS_PER_PT = {4: 95, 8: 102, 12: 160, 16: 276}
 
 
 def log(*a):
@@ -490,6 +493,10 @@ def main():
                       "space_order": w.space_order, "time_steps": w.nt, "nbl": w.nbl, "receivers": len(w.rec_xyz),
                       "parallelism": "single GPU"},
            "roofline": roof}
+    if w.space_order in TTI_PAPER_FLOPS_PER_PT:
+        fpp = TTI_PAPER_FLOPS_PER_PT[w.space_order]
+        out["flop_equivalent"] = {"TFLOP/s": round(gpts * fpp / 1e3, 2), "flop_per_point": fpp,
+                                  "basis": "the paper's optimised TTI FLOP count per point (Table ttiFLOPs)"}
     p.close()
     del p
     torch.cuda.empty_cache()
