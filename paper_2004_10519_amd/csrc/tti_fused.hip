@@ -110,6 +110,17 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
     const int gx = x0 + tx;
     const float *U = ADJ ? J.wmix[par][0] : J.p[par];
     const float *V = ADJ ? J.wmix[par][1] : J.q[par];
+    // the job fields the march uses, read once before it (the loop's stores could alias the job table,
+    // which would otherwise make the compiler reload them on every plane)
+    const float *const Pc = J.p[par], *const Qc = J.q[par];
+    float *const Pn = J.p[par ^ 1], *const Qn = J.q[par ^ 1];
+    float *const Wn0 = ADJ ? J.wmix[par ^ 1][0] : nullptr, *const Wn1 = ADJ ? J.wmix[par ^ 1][1] : nullptr;
+    const float *const Mm = J.m, *const MA = J.A, *const MB = J.B, *const Nx = J.nx, *const Ny = J.ny;
+    const float *const Ez = J.ez;
+    float *const Grad = J.grad;
+    const int image = J.image;
+    float *const SegP = (MODE == K2_FWD_STORE && J.seg_dtype == 0) ? J.seg + (int64_t)seg_step * 2 * J.seg_field : nullptr;
+    float *const SegQ = SegP ? SegP + J.seg_field : nullptr;
     auto sp = [&](const float *f, int z) { return (gcchar *)(f + (int64_t)z * w.sy); };
     auto mp = [&](const float *f, int z) { return (gcchar *)(f + w.moff + (int64_t)z * w.my); };
     auto spw = [&](float *f, int z) { return (gchar *)(f + (int64_t)z * w.sy); };
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
 #pragma unroll
         for (int k = 0; k < NO; ++k) frs[k] = fresh(rs[k]);
         gcchar *bu = sp(U, zf + R), *bv = sp(V, zf + R), *cu = sp(U, zf), *cv = sp(V, zf);
-        gcchar *bn0 = mp(J.nx, zf), *bn1 = mp(J.ny, zf);
+        gcchar *bn0 = mp(Nx, zf), *bn1 = mp(Ny, zf);
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             nu[r] = nv[r] = on0[r] = on1[r] = 0.f;
@@ -244,18 +255,18 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
             nvp0[r] = nvq0[r] = nvp1[r] = nvq1[r] = nvm[r] = nvA[r] = nvB[r] = nfpk[r] = nfqk[r] = nvg[r] = 0.f;
             if (v) {
                 if (ADJ) {
-                    nvp0[r] = ldo(sp(J.p[par], zo), uos);
-                    nvq0[r] = ldo(sp(J.q[par], zo), uos);
+                    nvp0[r] = ldo(sp(Pc, zo), uos);
+                    nvq0[r] = ldo(sp(Qc, zo), uos);
                 }
-                nvp1[r] = ldo(sp(J.p[par ^ 1], zo), uos);
-                nvq1[r] = ldo(sp(J.q[par ^ 1], zo), uos);
-                nvm[r] = ldo(mp(J.m, zo), uom);
-                nvA[r] = ldo(mp(J.A, zo), uom);
-                nvB[r] = ldo(mp(J.B, zo), uom);
+                nvp1[r] = ldo(sp(Pn, zo), uos);
+                nvq1[r] = ldo(sp(Qn, zo), uos);
+                nvm[r] = ldo(mp(Mm, zo), uom);
+                nvA[r] = ldo(mp(MA, zo), uom);
+                nvB[r] = ldo(mp(MB, zo), uom);
                 if (MODE == K2_ADJ_IC) {
                     const int y = ok[r] ? y0 + ty * NY + r : 0, x = ok[r] ? gx : 0;
                     seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), nfpk[r], nfqk[r]);
-                    nvg[r] = ldo(sp(J.grad, zo), uos);
+                    nvg[r] = ldo(sp(Grad, zo), uos);
                 }
             }
         }
@@ -385,7 +396,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
         __syncthreads();
 
         // 3. x-y divergence of plane zf; update of plane zo
-        const float ezo = out ? gld(J.ez, zo) : 0.f;
+        const float ezo = out ? gld(Ez, zo) : 0.f;
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int row = ty * NY + r;
@@ -408,20 +419,19 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
                 const float cc = mm - e;
                 const float np_ = (2.f * mm * vp0[r] - cc * vp1[r] + Lp) * ra;
                 const float nq_ = (2.f * mm * vq0[r] - cc * vq1[r] + Lq) * ra;
-                sto(spw(J.p[par ^ 1], zo), uos, np_);
-                sto(spw(J.q[par ^ 1], zo), uos, nq_);
+                sto(spw(Pn, zo), uos, np_);
+                sto(spw(Qn, zo), uos, nq_);
                 if (ADJ) {
-                    sto(spw(J.wmix[par ^ 1][0], zo), uos, vA[r] * np_ + vB[r] * nq_);
-                    sto(spw(J.wmix[par ^ 1][1], zo), uos, vB[r] * np_ + nq_);
+                    sto(spw(Wn0, zo), uos, vA[r] * np_ + vB[r] * nq_);
+                    sto(spw(Wn1, zo), uos, vB[r] * np_ + nq_);
                 }
-                if (MODE == K2_FWD_STORE && J.seg_dtype == 0) {
-                    float *sg = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                    sto(spw(sg, zo), uos, np_);
-                    sto(spw(sg + J.seg_field, zo), uos, nq_);
+                if (MODE == K2_FWD_STORE && SegP) {
+                    sto(spw(SegP, zo), uos, np_);
+                    sto(spw(SegQ, zo), uos, nq_);
                 }
                 if (MODE == K2_ADJ_IC)
-                    sto(spw(J.grad, zo), uos,
-                        J.image ? vg[r] + (fpk[r] * np_ + fqk[r] * nq_)
+                    sto(spw(Grad, zo), uos,
+                        image ? vg[r] + (fpk[r] * np_ + fqk[r] * nq_)
                                 : vg[r] - idt2 * (fpk[r] * (np_ - 2.f * vp0[r] + vp1[r]) +
                                                   fqk[r] * (nq_ - 2.f * vq0[r] + vq1[r])));
             }
