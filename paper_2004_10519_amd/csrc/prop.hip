@@ -278,6 +278,14 @@ double kappa(const prop_grid &g, int axis, int64_t i, int64_t n)
     return kmax * (d / g.nbl) * (d / g.nbl);
 }
 
+// The fused TTI pass addresses a point within its x-y plane by a 32-bit byte offset (state and
+// model layouts); planes of 4 GiB or more take the two-pass scheme.
+bool fused_fits(const prop_grid &g)
+{
+    const double plane = (double)((g.shape[0] + 63) / 64 * 64) * (double)g.shape[1] * 4.0;
+    return plane < 4294967296.0 && (double)g.shape[0] * (double)g.shape[1] * 4.0 < 4294967296.0;
+}
+
 int tile_rows(const prop_s *h, int pass, int shape)
 {
     if (h->kind == PROP_TTI) return tti_tile_rows(h->R, h->opt_scheme, pass, shape);
@@ -1700,7 +1708,7 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
     // default TTI scheme: the fused pass up to space order 8, two passes beyond (measured on the
     // 512^3 workload: fused 1.62 / 2.10 ms per step at space order 4 / 8 against 2.84 / 2.94 ms;
     // at space order 12 the fused pass is register-bound and slower, 4.65 against 2.98 ms)
-    h->opt_scheme = kind == PROP_TTI && h->R <= 4 ? TTI_FUSED : TTI_SIX;
+    h->opt_scheme = kind == PROP_TTI && h->R <= 4 && fused_fits(*grid) ? TTI_FUSED : TTI_SIX;
     double w[8] = {0};
     if (kind == PROP_TTI) centred_weights(h->R, w);
     else staggered_weights(h->R, w);
@@ -1856,6 +1864,8 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
             return fail(PROP_EINVAL, "scheme must be 0, 1 or 2");
         if (value == TTI_FUSED && h->R > tti_fused_max_radius())
             return fail(PROP_EINVAL, "the fused scheme supports space orders up to %d", 2 * tti_fused_max_radius());
+        if (value == TTI_FUSED && !fused_fits(h->g))
+            return fail(PROP_EINVAL, "the fused scheme needs x-y planes below 4 GiB");
         h->opt_scheme = (int)value;
         return PROP_OK;
     default: return fail(PROP_EINVAL, "option %d cannot be set", (int)option);
