@@ -246,13 +246,13 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
     };
     // update operands: current plane (v*) and next plane (nv*)
     float vp0[NY], vq0[NY], vp1[NY], vq1[NY], vm[NY], vA[NY], vB[NY], fpk[NY], fqk[NY], vg[NY];
-    float nvp0[NY], nvq0[NY], nvp1[NY], nvq1[NY], nvm[NY], nvA[NY], nvB[NY], nfpk[NY], nfqk[NY], nvg[NY];
+    float nvp0[NY], nvq0[NY], nvp1[NY], nvq1[NY], nvm[NY], nvA[NY], nvB[NY];
     auto load_upd = [&](int zo) {
         const bool v = zo >= z0 && zo < z1;   // block-uniform
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const uint32_t uos = fresh(os[r]), uom = fresh(om[r]);
-            nvp0[r] = nvq0[r] = nvp1[r] = nvq1[r] = nvm[r] = nvA[r] = nvB[r] = nfpk[r] = nfqk[r] = nvg[r] = 0.f;
+            nvp0[r] = nvq0[r] = nvp1[r] = nvq1[r] = nvm[r] = nvA[r] = nvB[r] = 0.f;
             if (v) {
                 if (ADJ) {
                     nvp0[r] = ldo(sp(Pc, zo), uos);
@@ -263,11 +263,6 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
                 nvm[r] = ldo(mp(Mm, zo), uom);
                 nvA[r] = ldo(mp(MA, zo), uom);
                 nvB[r] = ldo(mp(MB, zo), uom);
-                if (MODE == K2_ADJ_IC) {
-                    const int y = ok[r] ? y0 + ty * NY + r : 0, x = ok[r] ? gx : 0;
-                    seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), nfpk[r], nfqk[r]);
-                    nvg[r] = ldo(sp(Grad, zo), uos);
-                }
             }
         }
     };
@@ -332,9 +327,17 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
             vm[r] = nvm[r];
             vA[r] = nvA[r];
             vB[r] = nvB[r];
-            fpk[r] = nfpk[r];
-            fqk[r] = nfqk[r];
-            vg[r] = nvg[r];
+        }
+        // imaging-condition operands of plane zo: issued here, before the loads of the next planes
+        // (a plane ahead they would cost three more registers than this mode has)
+#pragma unroll
+        for (int r = 0; r < NY; ++r) {
+            fpk[r] = fqk[r] = vg[r] = 0.f;
+            if (MODE == K2_ADJ_IC && out) {
+                const int y = ok[r] ? y0 + ty * NY + r : 0, x = ok[r] ? gx : 0;
+                seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), fpk[r], fqk[r]);
+                vg[r] = ldo(sp(Grad, zo), fresh(os[r]));
+            }
         }
         load_upd(zo + 1);
         if (zf + 1 < ze) fetch(zf + 1);
