@@ -1,0 +1,50 @@
+"""Host-side logic of bench.py (no GPU): the algorithmic byte counts per kernel, the lookup of the
+counter-measured traffic in profiles/, and the single-GPU contract."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+@pytest.fixture(scope="module")
+def bench():
+    import bench as b
+    return b
+
+
+def test_kernel_bytes(bench):
+    # fields moved per point by each TTI launch (FP32): two-pass six-field, two-pass scalar, fused
+    assert bench.kernel_bytes(0, 0) == 10 * 4 and bench.kernel_bytes(1, 0) == 15 * 4
+    assert bench.kernel_bytes(1, 0, adjoint=True) == 17 * 4
+    assert bench.kernel_bytes(0, 1) == 6 * 4 and bench.kernel_bytes(1, 1) == 13 * 4
+    assert bench.kernel_bytes(1, 2) == 11 * 4 == bench.METHOD_BYTES_PER_PT["tti"]
+    assert bench.kernel_bytes(1, 2, adjoint=True) == 15 * 4
+    assert bench.kernel_bytes(2) == 13 * 4 and bench.kernel_bytes(3) == 17 * 4
+
+
+def test_traffic_lookup_follows_the_committed_counters(bench):
+    with open(os.path.join(ROOT, "profiles", "pmc_traffic.json")) as fh:
+        rec = json.load(fh)
+    npts = 512 ** 3
+    for key, ent in rec.items():
+        if key == "calibration":
+            continue
+        kclass, scheme, so = key.split("/")
+        got = bench.traffic_from_profiles(int(kclass), npts, int(scheme), ent["tile"], int(so[2:]))
+        # counters taken on another kernel source are not reported
+        fresh = ent["source_hash"] == bench.kernel_source_hash()
+        assert got == (ent["bytes_per_launch"] if fresh else None), key
+        assert ent["bytes_per_launch"] > bench.kernel_bytes(int(kclass), int(scheme)) * npts   # halos
+        assert bench.traffic_from_profiles(int(kclass), npts, int(scheme), [9, 9], int(so[2:])) is None
+        assert bench.traffic_from_profiles(int(kclass), npts + 1, int(scheme), ent["tile"], int(so[2:])) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
