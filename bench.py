@@ -45,7 +45,8 @@ HBM_PEAK_GBS = 8000.0
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
 TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
                     (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64,
-                    (2, 1, False): 44, (2, 1, True): 60}
+                    (2, 1, False): 44, (2, 1, True): 60,
+                    (3, 0, False): 32, (3, 1, False): 60, (3, 0, True): 32, (3, 1, True): 68}
 KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
 TTI_SCHEME = None   # step scheme of every TTI handle (--scheme); None = the library default
 FIXED_TILES = None  # (tile1, zc1, tile2, zc2) of the main run instead of the autotuner (--tiles)
@@ -401,7 +402,7 @@ def main():
     ap.add_argument("--tiles", default=None, metavar="T1,Z1,T2,Z2",
                     help="fixed tile variants and z-chunks of the two TTI passes instead of the autotuner "
                          "(counter runs: the profiler serialises launches, which would mislead the autotuner)")
-    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2),
+    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2, 3),
                     help="TTI step scheme: 0 two passes with six-field temporaries, 1 two passes with "
                          "scalar projections, 2 one fused pass (default: the library's choice per space "
                          "order, fused up to 8)")

@@ -226,7 +226,10 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *                      two scalars n . grad p and n . grad q and pass 2 re-forms the vectors from p;
  *                      2 = one fused pass, the projections stay on chip (space order <= 12 and x-y
  *                      planes below 4 GiB, else PROP_EINVAL; kernel class 1 then times the fused
- *                      pass and class 0 is unused).  Default: 2 up to space order 8, 0 above.
+ *                      pass and class 0 is unused); 3 = two passes, pass 1 stores the three
+ *                      components of (I - n n^T) grad p and the scalar n . grad q, and pass 2
+ *                      re-forms n n^T grad q from it and the axis (bitwise equal to 0, 8 bytes
+ *                      a point fewer).  Default: 2 up to space order 8, 3 up to 12, 0 above.
  *                      Same operators; results agree to FP32 rounding.
  * Read-only (prop_get_option): PROP_INFO_TILE1/2 and PROP_INFO_ZC1/2, the variant and z-chunk
  * used by the last TTI call; PROP_INFO_GRAPHS, graphs launched since create; PROP_INFO_GROUPS,

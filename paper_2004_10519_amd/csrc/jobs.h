@@ -15,7 +15,7 @@ struct TTIJob {
                                   // scheme's pass 2 reads w on tile halos while it writes the new w
     float *t[3], *s[3];           // pass-1 outputs (state layout): six-field scheme: the vectors
                                   // (I - n n^T) grad u and n n^T grad v; scalar scheme: t[0] = n . grad u,
-                                  // t[1] = n . grad v
+                                  // t[1] = n . grad v; four-field scheme: t as six-field, s[0] = n . grad v
     const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
     const float *nx, *ny;         // symmetry axis (model layout); n_z = sqrt(1 - n_x^2 - n_y^2) >= 0
     const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
@@ -77,8 +77,9 @@ struct ElGradJob {
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
 // Schemes of the TTI step: two passes with six-field temporaries, two passes with the two scalar
-// projections n . grad, or one fused pass (projections kept on chip).
-enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2 };
+// projections n . grad, one fused pass (projections kept on chip), or two passes with four
+// temporaries: t and the scalar n . grad v, from which pass 2 re-forms s = n (n . grad v).
+enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2, TTI_FOUR = 3 };
 
 // shape: tile-shape variant of the pass; tti_tile_rows gives its tile height.
 void launch_tti_pass1(int R, int scheme, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles,

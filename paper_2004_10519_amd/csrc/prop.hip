@@ -248,7 +248,7 @@ struct prop_s {
     int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
     int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1)
-    int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_SCALAR or TTI_FUSED); set at create
+    int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_SCALAR, TTI_FUSED or TTI_FOUR); set at create
     int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
     // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
     struct Tune {
@@ -1709,8 +1709,11 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
     h->R = grid->space_order / 2;
     // default TTI scheme: the fused pass up to space order 8, two passes beyond (measured on the
     // 512^3 workload: fused 1.62 / 2.10 ms per step at space order 4 / 8 against 2.84 / 2.94 ms;
-    // at space order 12 the fused pass is register-bound and slower, 4.65 against 2.98 ms)
-    h->opt_scheme = kind == PROP_TTI && h->R <= 4 && fused_fits(*grid) ? TTI_FUSED : TTI_SIX;
+    // at space order 12 the fused pass is register-bound and slower, 4.65 against 2.98 ms).  Of the
+    // two-pass schemes the four-field one moves 8 bytes a point less (space order 12: 2.95 against
+    // 3.02 ms per step, bitwise the same results); its pass 2 spills beyond space order 12.
+    if (kind == PROP_TTI)
+        h->opt_scheme = h->R <= 4 && fused_fits(*grid) ? TTI_FUSED : h->R <= 6 ? TTI_FOUR : TTI_SIX;
     double w[8] = {0};
     if (kind == PROP_TTI) centred_weights(h->R, w);
     else staggered_weights(h->R, w);
@@ -1862,8 +1865,8 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
         h->opt_batch_mb = value;
         return PROP_OK;
     case PROP_OPT_SCHEME:
-        if (value != TTI_SIX && value != TTI_SCALAR && value != TTI_FUSED)
-            return fail(PROP_EINVAL, "scheme must be 0, 1 or 2");
+        if (value != TTI_SIX && value != TTI_SCALAR && value != TTI_FUSED && value != TTI_FOUR)
+            return fail(PROP_EINVAL, "scheme must be 0, 1, 2 or 3");
         if (value == TTI_FUSED && h->R > tti_fused_max_radius())
             return fail(PROP_EINVAL, "the fused scheme supports space orders up to %d", 2 * tti_fused_max_radius());
         if (value == TTI_FUSED && !fused_fits(h->g))

@@ -8,6 +8,8 @@
 // derivative D (D^T = -D).  One time step is two passes over the grid:
 //   pass 1: t = (I - n n^T) grad u,  s = n (n . grad v)
 //           forward: (u, v) = (p, q); adjoint: (u, v) = w = C y (mix first, the transpose order)
+//           (four-field scheme: s is stored as the scalar n . grad v and re-formed in pass 2 from
+//           it and the axis, which pass 2 reads; the products are the same, so is every bit)
 //   pass 2: H0 = div t, Hz = div s; forward L = C (H0, Hz), adjoint L = (H0, Hz);
 //           a f+ = b f - c f- + L,  a = m/dt^2 + eta/(2dt), b = 2m/dt^2, c = m/dt^2 - eta/(2dt),
 //           with C = [[1+2eps, sqrt(1+2delta)], [sqrt(1+2delta), 1]]; the adjoint pass also writes
@@ -25,7 +27,8 @@ namespace {
 // Rows per thread drop to 1 for the widest stencils to keep the register queues in budget.
 template <int R> constexpr int ny1_of() { return R <= 6 ? 2 : 1; }
 
-template <int R, int NY, int BY, bool ADJ, bool WS>
+// SCH: TTI_SIX (t and s), TTI_SCALAR (n . grad u and n . grad v), TTI_FOUR (t and n . grad v)
+template <int R, int NY, int BY, bool ADJ, int SCH>
 __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W)
 {
@@ -140,16 +143,20 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
                 const float wp = n0[r] * dpx + n1[r] * dpy + n2[r] * dpz;
                 const float wq = n0[r] * dqx + n1[r] * dqy + n2[r] * dqz;
                 const int64_t si = sidx(w, gx, y, z);
-                if (WS) {
+                if (SCH == TTI_SCALAR) {
                     gst(J.t[0], si, wp);
                     gst(J.t[1], si, wq);
                 } else {
                     gst(J.t[0], si, dpx - n0[r] * wp);
                     gst(J.t[1], si, dpy - n1[r] * wp);
                     gst(J.t[2], si, dpz - n2[r] * wp);
-                    gst(J.s[0], si, n0[r] * wq);
-                    gst(J.s[1], si, n1[r] * wq);
-                    gst(J.s[2], si, n2[r] * wq);
+                    if (SCH == TTI_FOUR) {
+                        gst(J.s[0], si, wq);
+                    } else {
+                        gst(J.s[0], si, n0[r] * wq);
+                        gst(J.s[1], si, n1[r] * wq);
+                        gst(J.s[2], si, n2[r] * wq);
+                    }
                 }
             }
         }
@@ -157,7 +164,11 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
     }
 }
 
-template <int R, int NY, int BY, int MODE>
+// FOUR: pass 1 stored t and the scalar wq = n . grad v (in s[0]); s = n wq is formed here, at the
+// front plane for the z queue and the centre plane, and at the halo points, from wq and the axis.
+// The centre products of the own columns are formed at the front and wait R planes in a delay
+// ring in LDS, private to the thread (plane z in slot z mod (R + 1)); registers are the limit here.
+template <int R, int NY, int BY, int MODE, bool FOUR>
 __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W,
                                                        float idt2, int seg_step)
@@ -166,7 +177,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     constexpr bool ADJ = (MODE == K2_ADJ || MODE == K2_ADJ_IC);
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
+    constexpr int ND = FOUR ? (R + 1) * NY * NT : 1;
     __shared__ float Ltx[2][P::SIZE], Lty[2][P::SIZE], Lsx[2][P::SIZE], Lsy[2][P::SIZE];
+    __shared__ float Dsx[ND], Dsy[ND];
 
     const Tile tl = tiles[blockIdx.x];
     const TTIJob &J = jobs[tl.job];
@@ -174,6 +187,8 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
     const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
     const int gx = x0 + tx;
+    // delay-ring slot of plane z, row r of this thread
+    auto dslot = [&](int z, int r) { return ((((z % (R + 1)) + (R + 1)) % (R + 1)) * NY + r) * NT + tid; };
     const float *__restrict__ T0 = J.t[0];
     const float *__restrict__ T1 = J.t[1];
     const float *__restrict__ T2 = J.t[2];
@@ -187,27 +202,48 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
+    auto ldm = [&](const float *f, int x, int y, int z) -> float {
+        return in_win(w, x, y, z) ? gld(f, midx(w, x, y, z)) : 0.f;
+    };
+    const float *__restrict__ AX = J.nx;
+    const float *__restrict__ AY = J.ny;
 
     float qt[NY][Q], qs[NY][Q];
     float nt[NY], ns[NY], itx[NY], ity[NY], isx[NY], isy[NY];
-    float hxt[H::NXH], hxs[H::NXH], hyt[H::NYH], hys[H::NYH];
+    float hxt[H::NXH], hxs[H::NXH], hyt[H::NYH], hys[H::NYH], hxn[H::NXH], hyn[H::NYH];
 #pragma unroll
     for (int r = 0; r < NY; ++r)
 #pragma unroll
         for (int s = 1; s < Q; ++s) {
-            qt[r][s] = ld(T2, gx, y0 + ty * NY + r, z0 - R + s - 1);
-            qs[r][s] = ld(S2, gx, y0 + ty * NY + r, z0 - R + s - 1);
+            const int y = y0 + ty * NY + r, zz = z0 - R + s - 1;
+            qt[r][s] = ld(T2, gx, y, zz);
+            if (FOUR) {
+                const float wq = ld(S0, gx, y, zz), ax = ldm(AX, gx, y, zz), ay = ldm(AY, gx, y, zz);
+                qs[r][s] = axis_z(ax, ay) * wq;
+                if (s > R) {   // planes z0 .. z0 + R - 1, centres of the first R planes
+                    Dsx[dslot(zz, r)] = ax * wq;
+                    Dsy[dslot(zz, r)] = ay * wq;
+                }
+            } else {
+                qs[r][s] = ld(S2, gx, y, zz);
+            }
         }
     auto fetch = [&](int z) {
 #pragma unroll
         for (int r = 0; r < NY; ++r) {
             const int y = y0 + ty * NY + r;
             nt[r] = ld(T2, gx, y, z + R);
-            ns[r] = ld(S2, gx, y, z + R);
             itx[r] = ld(T0, gx, y, z);
             ity[r] = ld(T1, gx, y, z);
-            isx[r] = ld(S0, gx, y, z);
-            isy[r] = ld(S1, gx, y, z);
+            if (FOUR) {   // wq and the axis of the front plane
+                ns[r] = ld(S0, gx, y, z + R);
+                isx[r] = ldm(AX, gx, y, z + R);
+                isy[r] = ldm(AY, gx, y, z + R);
+            } else {
+                ns[r] = ld(S2, gx, y, z + R);
+                isx[r] = ld(S0, gx, y, z);
+                isy[r] = ld(S1, gx, y, z);
+            }
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
@@ -216,6 +252,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
             if (i < H::NXI) H::xitem(i, yy, xx);
             hxt[k] = i < H::NXI ? ld(T0, x0 + xx, y0 + yy, z) : 0.f;
             hxs[k] = i < H::NXI ? ld(S0, x0 + xx, y0 + yy, z) : 0.f;
+            hxn[k] = FOUR && i < H::NXI ? ldm(AX, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < H::NYH; ++k) {
@@ -223,7 +260,8 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
             int yy = 0, xx = 0;
             if (i < H::NYI) H::yitem(i, yy, xx);
             hyt[k] = i < H::NYI ? ld(T1, x0 + xx, y0 + yy, z) : 0.f;
-            hys[k] = i < H::NYI ? ld(S1, x0 + xx, y0 + yy, z) : 0.f;
+            hys[k] = i < H::NYI ? ld(FOUR ? S0 : S1, x0 + xx, y0 + yy, z) : 0.f;
+            hyn[k] = FOUR && i < H::NYI ? ldm(AY, x0 + xx, y0 + yy, z) : 0.f;
         }
     };
     float nvp0[NY], nvq0[NY], nvp1[NY], nvq1[NY], nvm[NY], nvA[NY], nvB[NY], nfpk[NY], nfqk[NY], nvg[NY];
@@ -261,12 +299,21 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
                 qs[r][s] = qs[r][s + 1];
             }
             qt[r][Q - 1] = nt[r];
-            qs[r][Q - 1] = ns[r];
             const int li = P::at(ty * NY + r, tx);
             ltx[li] = itx[r];
             lty[li] = ity[r];
-            lsx[li] = isx[r];
-            lsy[li] = isy[r];
+            if (FOUR) {
+                // plane z + R enters the slot of plane z - 1, which the previous plane consumed
+                qs[r][Q - 1] = axis_z(isx[r], isy[r]) * ns[r];
+                Dsx[dslot(z + R, r)] = isx[r] * ns[r];
+                Dsy[dslot(z + R, r)] = isy[r] * ns[r];
+                lsx[li] = Dsx[dslot(z, r)];
+                lsy[li] = Dsy[dslot(z, r)];
+            } else {
+                qs[r][Q - 1] = ns[r];
+                lsx[li] = isx[r];
+                lsy[li] = isy[r];
+            }
         }
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
@@ -275,7 +322,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
                 int yy, xx;
                 H::xitem(i, yy, xx);
                 ltx[P::at(yy, xx)] = hxt[k];
-                lsx[P::at(yy, xx)] = hxs[k];
+                lsx[P::at(yy, xx)] = FOUR ? hxn[k] * hxs[k] : hxs[k];
             }
         }
 #pragma unroll
@@ -285,7 +332,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
                 int yy, xx;
                 H::yitem(i, yy, xx);
                 lty[P::at(yy, xx)] = hyt[k];
-                lsy[P::at(yy, xx)] = hys[k];
+                lsy[P::at(yy, xx)] = FOUR ? hyn[k] * hys[k] : hys[k];
             }
         }
         __syncthreads();
@@ -598,47 +645,54 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2s(const TTIJob *__restr
     }
 }
 
-template <int R, int BY, bool WS>
+template <int R, int BY, int SCH>
 void p1_launch(bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
                hipStream_t st)
 {
     constexpr int NY = ny1_of<R>();
     dim3 blk(PROP_TX, BY), grd(ntiles);
-    if (adj) hipLaunchKernelGGL((tti_pass1<R, NY, BY, true, WS>), grd, blk, 0, st, jobs, tiles, zc, par, W);
-    else     hipLaunchKernelGGL((tti_pass1<R, NY, BY, false, WS>), grd, blk, 0, st, jobs, tiles, zc, par, W);
+    if (adj) hipLaunchKernelGGL((tti_pass1<R, NY, BY, true, SCH>), grd, blk, 0, st, jobs, tiles, zc, par, W);
+    else     hipLaunchKernelGGL((tti_pass1<R, NY, BY, false, SCH>), grd, blk, 0, st, jobs, tiles, zc, par, W);
+}
+
+template <int R, int SCH>
+void p1_shape(int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+              const Weights &W, hipStream_t st)
+{
+    if (shape == 1) p1_launch<R, 16, SCH>(adj, jobs, tiles, ntiles, zc, par, W, st);
+    else            p1_launch<R, 8, SCH>(adj, jobs, tiles, ntiles, zc, par, W, st);
 }
 
 template <int R>
 void p1_dispatch(int scheme, int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, hipStream_t st)
 {
-    if (scheme == TTI_SCALAR) {
-        if (shape == 1) p1_launch<R, 16, true>(adj, jobs, tiles, ntiles, zc, par, W, st);
-        else            p1_launch<R, 8, true>(adj, jobs, tiles, ntiles, zc, par, W, st);
-    } else {
-        if (shape == 1) p1_launch<R, 16, false>(adj, jobs, tiles, ntiles, zc, par, W, st);
-        else            p1_launch<R, 8, false>(adj, jobs, tiles, ntiles, zc, par, W, st);
-    }
+    if (scheme == TTI_SCALAR)    p1_shape<R, TTI_SCALAR>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
+    else if (scheme == TTI_FOUR) p1_shape<R, TTI_FOUR>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
+    else                         p1_shape<R, TTI_SIX>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
 }
 
-template <int R, int BY>
+template <int R, int BY, bool FOUR>
 void p2_launch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
                float idt2, int seg_step, hipStream_t st)
 {
     dim3 blk(PROP_TX, BY), grd(ntiles);
     switch (mode) {
     case K2_FWD:
-        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD, FOUR>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
+                           seg_step);
         break;
     case K2_FWD_STORE:
-        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD_STORE>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_FWD_STORE, FOUR>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
                            seg_step);
         break;
     case K2_ADJ:
-        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ, FOUR>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
+                           seg_step);
         break;
     default:
-        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ_IC>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
+        hipLaunchKernelGGL((tti_pass2<R, 1, BY, K2_ADJ_IC, FOUR>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
+                           seg_step);
         break;
     }
 }
@@ -672,9 +726,12 @@ void p2_dispatch(int scheme, int shape, int mode, const TTIJob *jobs, const Tile
     if (scheme == TTI_SCALAR) {
         if (shape == 1) p2s_launch<R, 16>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
         else            p2s_launch<R, 8>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+    } else if (scheme == TTI_FOUR) {
+        if (shape == 1) p2_launch<R, 16, true>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+        else            p2_launch<R, 8, true>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     } else {
-        if (shape == 1) p2_launch<R, 16>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
-        else            p2_launch<R, 8>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+        if (shape == 1) p2_launch<R, 16, false>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+        else            p2_launch<R, 8, false>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     }
 }
 

@@ -66,7 +66,8 @@ def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20, free_surfac
 
 def make_tti(case, prop, scheme=0, **options):
     """TTI propagator for a test case; scheme 0 = six-field pass-1 temporaries, 1 = scalar projections,
-    2 = one fused pass (space orders up to 12: the test is skipped beyond)."""
+    2 = one fused pass (space orders up to 12: the test is skipped beyond), 3 = four-field
+    temporaries (t and n . grad q)."""
     if scheme == 2 and case["so"] > 12:
         import pytest
         pytest.skip("the fused scheme supports space orders up to 12")

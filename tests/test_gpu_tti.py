@@ -20,7 +20,7 @@ def prop():
     return P
 
 
-SCHEMES = [0, 1, 2]   # two passes (six-field temporaries / scalar projections), one fused pass
+SCHEMES = [0, 1, 2, 3]   # two passes (six-field / scalar / four-field temporaries), one fused pass
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -144,6 +144,26 @@ def test_tti_gradient_single_segment_equals_full_storage(prop, orc):
     d, _, _ = orc.tti_forward(g, mod, case["src"], case["wav"], case["rec"])
     _, go, _ = orc.tti_gradient(g, mod, case["src"], case["wav"], case["rec"], d - res)
     assert rel_l2(gg, go) <= 1e-4
+
+
+@pytest.mark.parametrize("so,shape", [(4, (83, 29, 41)), (8, (70, 37, 29)), (12, (67, 20, 40)), (16, (75, 33, 45)),
+                                      (8, (90, 1, 77))])
+def test_four_field_scheme_bitwise_equals_six(prop, so, shape):
+    """Four-field scheme: pass 1 stores t and the scalar n . grad q, pass 2 forms n (n . grad q) from
+    it and the axis. Those products are the floats the six-field pass 1 stores, so forward traces,
+    adjoint traces and the gradient (FP32 checkpoints) are equal bit for bit, for every tile variant
+    and short z-chunks."""
+    case = tti_case(shape, so, 5, 60)
+    p0, shot = make_tti(case, prop, 0)
+    d0 = host(p0.forward(shot)).copy()
+    rec = np.random.default_rng(3).standard_normal(d0.shape).astype(np.float32)
+    a0 = host(p0.adjoint(shot, dev(rec))).copy()
+    g0 = host(p0.gradient(shot, dev(rec), n_ckpt=4, ckpt_dtype="f32")).copy()
+    for t1, t2, zc in ((1, 1, 0), (0, 0, 5), (1, 0, 3)):
+        p3, shot3 = make_tti(case, prop, 3, tile1=t1, tile2=t2, zc=zc)
+        assert np.array_equal(host(p3.forward(shot3)), d0), (t1, t2, zc)
+        assert np.array_equal(host(p3.adjoint(shot3, dev(rec))), a0), (t1, t2, zc)
+        assert np.array_equal(host(p3.gradient(shot3, dev(rec), n_ckpt=4, ckpt_dtype="f32")), g0), (t1, t2, zc)
 
 
 @pytest.mark.parametrize("so", [4, 8, 12, 16])
