@@ -29,12 +29,17 @@ constexpr int EBY = 16;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
 // register queues: zz, xz, yz.  Pipelined like the TTI passes: the loads of plane z+1 are in
 // flight while plane z is computed; LDS is double-buffered.
+// 2D forward (SKIPY): v_y, tau_xy and tau_yz start at zero, have no source and stay exactly zero
+// (their only drivers are y derivatives and each other), so that pass neither loads nor stores
+// them; the fields keep the zeros they were filled with.  tau_yy is still formed (it is part of
+// the final state), but in 2D nothing reads it back: its y derivative is zero.
 template <int R, int MODE, int BY>
 __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
     constexpr bool TWO_D = BY == 1;
+    constexpr bool SKIPY = TWO_D && MODE == EL_FWD;
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -66,15 +71,15 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         const int z = z0 - R + s - 1;
         qzz[s] = ld(Fzz, gx, gy, z);
         qxz[s] = ld(Fxz, gx, gy, z);
-        qyz[s] = ld(Fyz, gx, gy, z);
+        qyz[s] = SKIPY ? 0.f : ld(Fyz, gx, gy, z);
     }
     auto fetch = [&](int z) {
         nzz = ld(Fzz, gx, gy, z + R);
         nxz = ld(Fxz, gx, gy, z + R);
-        nyz = ld(Fyz, gx, gy, z + R);
+        nyz = SKIPY ? 0.f : ld(Fyz, gx, gy, z + R);
         ixx = ld(Fxx, gx, gy, z);
-        iyy = ld(Fyy, gx, gy, z);
-        ixy = ld(Fxy, gx, gy, z);
+        iyy = TWO_D ? 0.f : ld(Fyy, gx, gy, z);   // read only by the y derivative
+        ixy = SKIPY ? 0.f : ld(Fxy, gx, gy, z);
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
             const int i = tid + k * NT;
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
             if (i < H::NXI) H::xitem(i, yy, xx);
             const bool v = i < H::NXI;
             hxx[k] = v ? ld(Fxx, x0 + xx, y0 + yy, z) : 0.f;
-            hxy_x[k] = v ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
+            hxy_x[k] = v && !SKIPY ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
             hxz[k] = v ? ld(Fxz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
@@ -111,10 +116,10 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         qyz[Q - 1] = nyz;
         const int li = P::at(ty, tx);
         lxx[li] = ixx;
-        lyy[li] = iyy;
-        lxy[li] = ixy;
+        if (!TWO_D) lyy[li] = iyy;
+        if (!SKIPY) lxy[li] = ixy;
         lxz[li] = qxz[R];
-        lyz[li] = qyz[R];
+        if (!TWO_D) lyz[li] = qyz[R];
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
             const int i = tid + k * NT;
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
                 int yy, xx;
                 H::xitem(i, yy, xx);
                 lxx[P::at(yy, xx)] = hxx[k];
-                lxy[P::at(yy, xx)] = hxy_x[k];
+                if (!SKIPY) lxy[P::at(yy, xx)] = hxy_x[k];
                 lxz[P::at(yy, xx)] = hxz[k];
             }
         }
@@ -141,23 +146,24 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         // per-point values of plane z, then the prefetch of plane z+1
         const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
         const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
-        const float v0 = gld(J.v[0], si), v1 = gld(J.v[1], si), v2 = gld(J.v[2], si);
+        const float v0 = gld(J.v[0], si), v1 = SKIPY ? 0.f : gld(J.v[1], si), v2 = gld(J.v[2], si);
         const float b0 = gld(J.b, mi);
         const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
-        const float byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+        const float byn = SKIPY ? 0.f : gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
         const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
         const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (z + 1 < z1) fetch(z + 1);
         const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lxy, li, LX, W.wy)) +
                          ds_q<R, false>(qxz, W.wz);
-        const float fy = ds_lds<R, false>(lxy, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, true>(lyy, li, LX, W.wy)) +
-                         ds_q<R, false>(qyz, W.wz);
+        const float fy = SKIPY ? 0.f
+                               : ds_lds<R, false>(lxy, li, 1, W.wx) +
+                                     (TWO_D ? 0.f : ds_lds<R, true>(lyy, li, LX, W.wy)) + ds_q<R, false>(qyz, W.wz);
         const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lyz, li, LX, W.wy)) +
                          ds_q<R, true>(qzz, W.wz);
         if (own) {
             if (MODE == EL_FWD) {
                 gst(J.v[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
-                gst(J.v[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                if (!SKIPY) gst(J.v[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
                 gst(J.v[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
             } else {
                 const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
@@ -182,6 +188,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
     constexpr bool TWO_D = BY == 1;
+    constexpr bool SKIPY = TWO_D && MODE == EL_FWD;   // 2D forward: v_y, tau_xy, tau_yz stay zero
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -209,12 +216,12 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
     for (int s = 1; s < Q; ++s) {
         const int z = z0 - R + s - 1;
         qx[s] = ld(Vx, gx, gy, z);
-        qy[s] = ld(Vy, gx, gy, z);
+        qy[s] = SKIPY ? 0.f : ld(Vy, gx, gy, z);
         qz[s] = ld(Vz, gx, gy, z);
     }
     auto fetch = [&](int z) {
         nx_ = ld(Vx, gx, gy, z + R);
-        ny_ = ld(Vy, gx, gy, z + R);
+        ny_ = SKIPY ? 0.f : ld(Vy, gx, gy, z + R);
         nz_ = ld(Vz, gx, gy, z + R);
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
@@ -223,7 +230,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
             if (i < H::NXI) H::xitem(i, yy, xx);
             const bool v = i < H::NXI;
             hx[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
-            hx[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
+            hx[1][k] = v && !SKIPY ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
             hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
@@ -252,7 +259,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
         qz[Q - 1] = nz_;
         const int li = P::at(ty, tx);
         lx[li] = qx[R];
-        ly[li] = qy[R];
+        if (!SKIPY) ly[li] = qy[R];
         lz[li] = qz[R];
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
@@ -261,7 +268,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
                 int yy, xx;
                 H::xitem(i, yy, xx);
                 lx[P::at(yy, xx)] = hx[0][k];
-                ly[P::at(yy, xx)] = hx[1][k];
+                if (!SKIPY) ly[P::at(yy, xx)] = hx[1][k];
                 lz[P::at(yy, xx)] = hx[2][k];
             }
         }
@@ -281,34 +288,38 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
         const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
         float t[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = gld(J.t[c], si);
+        for (int c = 0; c < 6; ++c) t[c] = SKIPY && (c == 3 || c == 5) ? 0.f : gld(J.t[c], si);
         float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
         const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (MODE == EL_FWD) {
             const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
             lam = gld(J.lam, mi);
             mu0 = gld(J.mu, mi);
-            const float mx_ = gld(J.mu, mi + ox), my_ = gld(J.mu, mi + oy), mz_ = gld(J.mu, mi + oz);
-            mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
+            const float mx_ = gld(J.mu, mi + ox), mz_ = gld(J.mu, mi + oz);
             mxz = 0.25f * (mu0 + mx_ + mz_ + gld(J.mu, mi + ox + oz));
-            myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
+            if (!SKIPY) {
+                const float my_ = gld(J.mu, mi + oy);
+                mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
+                myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
+            }
         }
         if (z + 1 < z1) fetch(z + 1);
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
         const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
         const float ezz = ds_q<R, false>(qz, W.wz);
-        const float gxy = (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
+        const float gxy =
+            SKIPY ? 0.f : (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
         const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
-        const float gyz = ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
+        const float gyz = SKIPY ? 0.f : ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
         if (own) {
             if (MODE == EL_FWD) {
                 const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
                 gst(J.t[0], si, g * (t[0] + dt * (lt + m2 * exx)));
                 gst(J.t[1], si, g * (t[1] + dt * (lt + m2 * eyy)));
                 gst(J.t[2], si, g * (t[2] + dt * (lt + m2 * ezz)));
-                gst(J.t[3], si, g * (t[3] + dt * mxy * gxy));
+                if (!SKIPY) gst(J.t[3], si, g * (t[3] + dt * mxy * gxy));
                 gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
-                gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
+                if (!SKIPY) gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
             } else {
                 float tg[6];
 #pragma unroll
