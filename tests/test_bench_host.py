@@ -18,12 +18,18 @@ def bench():
 
 
 def test_kernel_bytes(bench):
-    # fields moved per point by each TTI launch (FP32): two-pass six-field, two-pass scalar, fused
+    # fields moved per point by each TTI launch (FP32): two-pass six-field, two-pass scalar, fused,
+    # two-pass four-field
     assert bench.kernel_bytes(0, 0) == 10 * 4 and bench.kernel_bytes(1, 0) == 15 * 4
     assert bench.kernel_bytes(1, 0, adjoint=True) == 17 * 4
     assert bench.kernel_bytes(0, 1) == 6 * 4 and bench.kernel_bytes(1, 1) == 13 * 4
     assert bench.kernel_bytes(1, 2) == 11 * 4 == bench.METHOD_BYTES_PER_PT["tti"]
     assert bench.kernel_bytes(1, 2, adjoint=True) == 15 * 4
+    # four-field: pass 1 reads u, v, n_x, n_y and writes t (3) and n . grad v; pass 2 reads n_x, n_y
+    # in place of s_x, s_y, so it moves what the six-field pass 2 moves
+    assert bench.kernel_bytes(0, 3) == 8 * 4 and bench.kernel_bytes(0, 3, adjoint=True) == 8 * 4
+    assert bench.kernel_bytes(1, 3) == bench.kernel_bytes(1, 0)
+    assert bench.kernel_bytes(1, 3, adjoint=True) == bench.kernel_bytes(1, 0, adjoint=True)
     assert bench.kernel_bytes(2) == 13 * 4 and bench.kernel_bytes(3) == 17 * 4
 
 
