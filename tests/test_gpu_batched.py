@@ -19,7 +19,9 @@ def prop():
     return P
 
 
-def _setup(prop, nt=120):
+def _setup(prop, nt=120, scheme=None):
+    """Three shots on uneven windows of a 100 x 80 x 60 model, space order 8 (default scheme: the
+    fused pass), or the given step scheme."""
     from paper_2004_10519_amd import inputs
     shape, h, so, nbl = (100, 80, 60), (10.0, 10.0, 10.0), 8, 6
     mdl = inputs.tti_model(shape, nbl, 31)
@@ -29,6 +31,8 @@ def _setup(prop, nt=120):
     mt = [dev(a) for a in arrs]
     p = prop.Propagator(prop.TTI, g, mt)
     p._keep_model = mt
+    if scheme is not None:
+        p.set_option("scheme", scheme)
     wins = [((3, 5, 0), (70, 41, 50)), ((20, 0, 4), (80, 77, 56)), ((0, 30, 0), (37, 50, 60))]
     shots = []
     for k, (o, n) in enumerate(wins):
@@ -43,8 +47,9 @@ def _setup(prop, nt=120):
     return p, shots
 
 
-def test_batched_forward_equals_plain(prop):
-    p, shots = _setup(prop)
+@pytest.mark.parametrize("scheme", [None, 3])
+def test_batched_forward_equals_plain(prop, scheme):
+    p, shots = _setup(prop, scheme=scheme)
     plain = [host(p.forward(s)).copy() for s in shots]
     outs = p.forward_batched(shots)
     for a, b in zip(outs, plain):
@@ -81,11 +86,13 @@ def test_batched_groups_split_by_memory_budget(prop):
     assert np.array_equal(host(g1), host(g2))
 
 
-def test_graphs_and_autotuned_tiles_change_no_bit(prop):
+@pytest.mark.parametrize("scheme", [None, 3])
+def test_graphs_and_autotuned_tiles_change_no_bit(prop, scheme):
     """HIP-graph launches and autotuned tiles give the same bits as per-step launches with the fixed
     tiles, for forward, adjoint, gradient and both batched calls; every call is made twice (graphs
-    are recorded again per call) with eager work and host synchronisation in between."""
-    p, shots = _setup(prop, nt=100)
+    are recorded again per call) with eager work and host synchronisation in between.  For the
+    default (fused) scheme and the four-field two-pass scheme (its pass 2 keeps a delay ring in LDS)."""
+    p, shots = _setup(prop, nt=100, scheme=scheme)
     rng = np.random.default_rng(9)
     res = [dev(rng.standard_normal((100, s.nrec))) for s in shots]
 
