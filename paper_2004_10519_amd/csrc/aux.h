@@ -59,6 +59,11 @@ void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m,
 void aux_tti_inject_adj(const Csr &c, const float *data, float idt2, const float *m, const float *A, const float *B,
                         float *yp, float *wp, float *wq, float *grad, const float *fpk, hipStream_t st);
 void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, float *d1, float *d2, hipStream_t st);
+// Elastic adjoint: sigma_ii = lambda tr(g tau~) + 2 mu g tau~_ii at the plan's nodes (after an injection
+// into tau~_ii there); g = gx[x] gy[y] gz[z] of the window, lambda and mu at the plan's model nodes.
+void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, const float *gz, const float *lam,
+                  const float *mu, const float *t0, const float *t1, const float *t2, float *a0, float *a1, float *a2,
+                  hipStream_t st);
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
                 hipStream_t st);
 void aux_fill(float *p, int64_t n, float v, hipStream_t st);

@@ -64,6 +64,27 @@ __global__ void k_el_inject(Csr c, const float *__restrict__ data, float scale, 
     if (d2) d2[n] += v;
 }
 
+// Elastic adjoint: the diagonal of sigma = C (g tau~) at the nodes of an injection plan, recomputed
+// from tau~ after receiver residuals were added there (the stress pass formed sigma from tau~ before
+// the injection; the shear components are not injected).  Same arithmetic as the stress pass.
+__global__ void k_el_remix(Csr c, Win w, const float *__restrict__ gx, const float *__restrict__ gy,
+                           const float *__restrict__ gz, const float *__restrict__ lam, const float *__restrict__ mu,
+                           const float *t0, const float *t1, const float *t2, float *a0, float *a1, float *a2)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= c.nrows) return;
+    const int64_t si = c.node[r], mi = c.mnode[r];
+    const int z = (int)(si / w.sy);
+    const int64_t rem = si - (int64_t)z * w.sy;
+    const int y = (int)(rem / w.sx), x = (int)(rem - (int64_t)y * w.sx);
+    const float g = gx[x] * gy[y] * gz[z];
+    const float s0 = g * t0[si], s1 = g * t1[si], s2 = g * t2[si];
+    const float lt = lam[mi] * (s0 + s1 + s2), m2 = 2.f * mu[mi];
+    a0[si] = lt + m2 * s0;
+    a1[si] = lt + m2 * s1;
+    a2[si] = lt + m2 * s2;
+}
+
 // Multilinear gather: out[pos_o] = scale * sum_c w_oc (f0 + f1 + f2)[idx_oc].  One point per lane.
 __global__ void k_gather(Gather g, const float *__restrict__ f0, const float *__restrict__ f1,
                          const float *__restrict__ f2, float scale, float *__restrict__ out)
@@ -530,6 +551,15 @@ void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, floa
 {
     if (c.nrows <= 0) return;
     hipLaunchKernelGGL(k_el_inject, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, data, scale, d0, d1, d2);
+}
+
+void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, const float *gz, const float *lam,
+                  const float *mu, const float *t0, const float *t1, const float *t2, float *a0, float *a1, float *a2,
+                  hipStream_t st)
+{
+    if (c.nrows <= 0) return;
+    hipLaunchKernelGGL(k_el_remix, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, w, gx, gy, gz, lam, mu, t0, t1,
+                       t2, a0, a1, a2);
 }
 
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,

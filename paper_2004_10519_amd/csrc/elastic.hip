@@ -14,9 +14,10 @@
 // Adjoint step (exact transpose, applied in reverse): with sigma = C (g tau~) and u = bbar (g v~)
 //   v~ <- g (v~ + dt E^T sigma);   then   tau~ <- g tau~ + dt D_tau^T u,
 // where E^T = -(the D_tau pattern) and D_tau^T = -(the E pattern), so the adjoint reuses the two
-// forward stencil kernels on the pointwise-weighted fields with a minus sign.  Three launches:
-// el_mix_stress forms sigma; el_vel updates v~ and forms u in its epilogue; el_stress applies g
-// to tau~ while it adds dt D_tau^T u.
+// forward stencil kernels on the pointwise-weighted fields with a minus sign.  Two launches a
+// step: el_vel updates v~ from sigma and forms u in its epilogue; el_stress applies g to tau~ while
+// it adds dt D_tau^T u, and forms sigma of the new tau~ for the next step in its epilogue (the
+// diagonal components are recomputed at the receiver-injection nodes after the injection).
 #include "jobs.h"
 
 namespace {
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
         for (int c = 0; c < 6; ++c) t[c] = SKIPY && (c == 3 || c == 5) ? 0.f : gld(J.t[c], si);
         float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
         const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
-        if (MODE == EL_FWD) {
+        {   // (the adjoint needs them for sigma of the new tau~)
             const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
             lam = gld(J.lam, mi);
             mu0 = gld(J.mu, mi);
@@ -321,42 +322,34 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
                 gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
                 if (!SKIPY) gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
             } else {
-                float tg[6];
+                float tg[6], tn[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c) tg[c] = g * t[c];
-                gst(J.t[0], si, tg[0] - dt * exx);
-                gst(J.t[1], si, tg[1] - dt * eyy);
-                gst(J.t[2], si, tg[2] - dt * ezz);
-                gst(J.t[3], si, tg[3] - dt * gxy);
-                gst(J.t[4], si, tg[4] - dt * gxz);
-                gst(J.t[5], si, tg[5] - dt * gyz);
+                tn[0] = tg[0] - dt * exx;
+                tn[1] = tg[1] - dt * eyy;
+                tn[2] = tg[2] - dt * ezz;
+                tn[3] = tg[3] - dt * gxy;
+                tn[4] = tg[4] - dt * gxz;
+                tn[5] = tg[5] - dt * gyz;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) gst(J.t[c], si, tn[c]);
+                // sigma = C (g tau~) of the new tau~, which the velocity pass of the next (earlier)
+                // step reads; where that step injects receiver residuals into tau~, el_remix
+                // recomputes the diagonal components after the injection
+                float sg[6];
+#pragma unroll
+                for (int c = 0; c < 6; ++c) sg[c] = g * tn[c];
+                const float lt = lam * (sg[0] + sg[1] + sg[2]), m2 = 2.f * mu0;
+                gst(J.aux[0], si, lt + m2 * sg[0]);
+                gst(J.aux[1], si, lt + m2 * sg[1]);
+                gst(J.aux[2], si, lt + m2 * sg[2]);
+                gst(J.aux[3], si, mxy * sg[3]);
+                gst(J.aux[4], si, mxz * sg[4]);
+                gst(J.aux[5], si, myz * sg[5]);
             }
         }
         b ^= 1;
     }
-}
-
-// sigma = C (g tau~) into aux[0..5] (tau~ itself is scaled by g later, in the stress pass).
-__global__ void el_mix_stress(const ElJob *__restrict__ jobs)
-{
-    const ElJob &J = jobs[0];
-    const Win w = J.w;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
-    if (x >= w.nx) return;
-    const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
-    const float g = gld(J.gx, x) * gld(J.gy, y) * gld(J.gz, z);
-    float t[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) t[c] = g * gld(J.t[c], si);
-    const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
-    const float lam = gld(J.lam, mi), mu0 = gld(J.mu, mi);
-    const float lt = lam * (t[0] + t[1] + t[2]), m2 = 2.f * mu0;
-    gst(J.aux[0], si, lt + m2 * t[0]);
-    gst(J.aux[1], si, lt + m2 * t[1]);
-    gst(J.aux[2], si, lt + m2 * t[2]);
-    gst(J.aux[3], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oy) + gld(J.mu, mi + ox + oy)) * t[3]);
-    gst(J.aux[4], si, 0.25f * (mu0 + gld(J.mu, mi + ox) + gld(J.mu, mi + oz) + gld(J.mu, mi + ox + oz)) * t[4]);
-    gst(J.aux[5], si, 0.25f * (mu0 + gld(J.mu, mi + oy) + gld(J.mu, mi + oz) + gld(J.mu, mi + oy + oz)) * t[5]);
 }
 
 // Imaging condition of the elastic gradient for one adjoint step (after the transposed velocity
@@ -633,11 +626,6 @@ void launch_el_stress(int R, int by, int mode, const ElJob *jobs, const Tile *ti
     EL_SWITCH(stress_dispatch, by, mode, jobs, tiles, ntiles, zc, W, dt, st)
 }
 
-void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st)
-{
-    dim3 blk(256), grd((w0.nx + 255) / 256, w0.ny, w0.nz);
-    hipLaunchKernelGGL(el_mix_stress, grd, blk, 0, st, jobs);
-}
 
 template <int R>
 void gic_dispatch(int by, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,

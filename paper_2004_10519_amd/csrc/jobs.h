@@ -98,7 +98,6 @@ void launch_el_vel(int R, int by, int mode, const ElJob *jobs, const Tile *tiles
                    const Weights &W, float dt, hipStream_t st);
 void launch_el_stress(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                       const Weights &W, float dt, hipStream_t st);
-void launch_el_mix_stress(const ElJob *jobs, const Win &w0, hipStream_t st);
 void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, int ntiles, int zc, const Weights &W,
                        float dt, hipStream_t st);
 // Spread the accumulators to the nodes (transpose of the half-node averages) and convert to

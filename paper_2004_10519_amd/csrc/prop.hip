@@ -1511,6 +1511,16 @@ void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
     }
 }
 
+// After the adjoint receiver injection into tau~ (the diagonal at the pressure nodes): sigma there,
+// which the stress pass of the previous adjoint step formed from tau~ before the injection.
+void el_remix(prop_s *h, Slot &sl)
+{
+    if (!sl.rec_inj.csr.nrows) return;
+    const float *tab = sl.tabs.as<float>();
+    aux_el_remix(sl.rec_inj.csr, sl.w, tab, tab + sl.w.nx, tab + sl.w.nx + sl.w.ny, h->c[0], h->c[1], sl.f[3], sl.f[4],
+                 sl.f[5], sl.f[9], sl.f[10], sl.f[11], h->st);
+}
+
 int el_forward(prop_s *h, const prop_shot *s, float *rec_out)
 {
     Slot &sl = h->slot;
@@ -1549,9 +1559,9 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
         const float *row = s->nrec ? rec_in + (size_t)n * s->nrec : nullptr;
         if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
         if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
+        el_remix(h, sl);
         if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], dt, src_out + (size_t)n * s->nsrc,
                                 h->st);
-        launch_el_mix_stress(job, sl.w, h->st);
         {
             Timed t(h, 2);
             launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
@@ -1655,7 +1665,7 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
             const float *row = s->nrec ? residual + (size_t)n * s->nrec : nullptr;
             if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
             if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
-            launch_el_mix_stress(dja, sl.w, h->st);
+            el_remix(h, sl);
             {
                 Timed t(h, 2);
                 launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
