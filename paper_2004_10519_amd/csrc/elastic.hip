@@ -30,17 +30,19 @@ constexpr int EBY = 16;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
 // register queues: zz, xz, yz.  Pipelined like the TTI passes: the loads of plane z+1 are in
 // flight while plane z is computed; LDS is double-buffered.
-// 2D forward (SKIPY): v_y, tau_xy and tau_yz start at zero, have no source and stay exactly zero
-// (their only drivers are y derivatives and each other), so that pass neither loads nor stores
-// them; the fields keep the zeros they were filled with.  tau_yy is still formed (it is part of
-// the final state), but in 2D nothing reads it back: its y derivative is zero.
+// 2D (SKIPY): v_y, tau_xy and tau_yz start at zero, have no source and stay exactly zero (their
+// only drivers are y derivatives and each other), and so do their adjoint counterparts (v~_y,
+// u_y, tau~_xy, tau~_yz, sigma_xy, sigma_yz: no receiver injects into them); the 2D passes neither
+// load nor store them, and the fields keep the zeros they were filled with.  tau_yy is still
+// formed (it is part of the final state), but in 2D nothing reads it back: its y derivative is
+// zero.
 template <int R, int MODE, int BY>
 __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
     constexpr bool TWO_D = BY == 1;
-    constexpr bool SKIPY = TWO_D && MODE == EL_FWD;
+    constexpr bool SKIPY = TWO_D;
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -170,10 +172,10 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
                 const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
                 const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
                 gst(J.v[0], si, c0);
-                gst(J.v[1], si, c1);
+                if (!SKIPY) gst(J.v[1], si, c1);
                 gst(J.v[2], si, c2);
                 gst(J.u[0], si, (0.5f * (b0 + bxn)) * c0);
-                gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
+                if (!SKIPY) gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
                 gst(J.u[2], si, (0.5f * (b0 + bzn)) * c2);
             }
         }
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
     constexpr bool TWO_D = BY == 1;
-    constexpr bool SKIPY = TWO_D && MODE == EL_FWD;   // 2D forward: v_y, tau_xy, tau_yz stay zero
+    constexpr bool SKIPY = TWO_D;   // 2D: v_y, tau_xy, tau_yz (and their adjoints) stay zero
     using P = Plane<R, TY>;
     using H = Halo<R, TY, NT>;
     constexpr int LX = P::LX;
@@ -332,7 +334,8 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
                 tn[4] = tg[4] - dt * gxz;
                 tn[5] = tg[5] - dt * gyz;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) gst(J.t[c], si, tn[c]);
+                for (int c = 0; c < 6; ++c)
+                    if (!(SKIPY && (c == 3 || c == 5))) gst(J.t[c], si, tn[c]);
                 // sigma = C (g tau~) of the new tau~, which the velocity pass of the next (earlier)
                 // step reads; where that step injects receiver residuals into tau~, el_remix
                 // recomputes the diagonal components after the injection
@@ -343,9 +346,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
                 gst(J.aux[0], si, lt + m2 * sg[0]);
                 gst(J.aux[1], si, lt + m2 * sg[1]);
                 gst(J.aux[2], si, lt + m2 * sg[2]);
-                gst(J.aux[3], si, mxy * sg[3]);
+                if (!SKIPY) gst(J.aux[3], si, mxy * sg[3]);
                 gst(J.aux[4], si, mxz * sg[4]);
-                gst(J.aux[5], si, myz * sg[5]);
+                if (!SKIPY) gst(J.aux[5], si, myz * sg[5]);
             }
         }
         b ^= 1;
