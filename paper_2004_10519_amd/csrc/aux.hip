@@ -341,40 +341,56 @@ __global__ void k_encode_pair_rows(const float *__restrict__ cur, const float *_
 }
 
 // 16-bit segment store of one time step: p and q each rounded to nearest-even FP16/BF16 with a
-// power-of-two scale per x-row (one block per row, both row maxima reduced in LDS).
+// power-of-two scale per x-row.  One wavefront per row: the row's values stay in registers between
+// the two row maxima (reduced across the wavefront with lane shuffles) and the encode; rows longer
+// than 64 KR points re-read the rest.
+template <int KR>
 __global__ void k_encode_rows2(const float *__restrict__ p, const float *__restrict__ q, Win w, int dtype,
                                uint16_t *__restrict__ cp, uint16_t *__restrict__ cq, float *__restrict__ sp,
                                float *__restrict__ sq)
 {
-    __shared__ unsigned sa[BS], sb[BS];
-    const int y = blockIdx.y, z = blockIdx.z;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+    if (r >= (int64_t)w.ny * w.nz) return;   // whole wavefronts
+    const int z = (int)(r / w.ny), y = (int)(r - (int64_t)z * w.ny);
+    const int64_t base = sidx(w, 0, y, z);
+    float vp[KR], vq[KR];
     unsigned xa = 0, xb = 0;
-    for (int x = threadIdx.x; x < w.nx; x += BS) {
-        const int64_t i = sidx(w, x, y, z);
-        xa = max(xa, __float_as_uint(p[i]) & 0x7fffffffu);
-        xb = max(xb, __float_as_uint(q[i]) & 0x7fffffffu);
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int x = lane + 64 * k;
+        vp[k] = x < w.nx ? p[base + x] : 0.f;
+        vq[k] = x < w.nx ? q[base + x] : 0.f;
+        xa = max(xa, __float_as_uint(vp[k]) & 0x7fffffffu);
+        xb = max(xb, __float_as_uint(vq[k]) & 0x7fffffffu);
     }
-    sa[threadIdx.x] = xa;
-    sb[threadIdx.x] = xb;
-    __syncthreads();
-    for (int s = BS / 2; s > 0; s >>= 1) {
-        if (threadIdx.x < s) {
-            sa[threadIdx.x] = max(sa[threadIdx.x], sa[threadIdx.x + s]);
-            sb[threadIdx.x] = max(sb[threadIdx.x], sb[threadIdx.x + s]);
-        }
-        __syncthreads();
+    for (int x = lane + 64 * KR; x < w.nx; x += 64) {
+        xa = max(xa, __float_as_uint(p[base + x]) & 0x7fffffffu);
+        xb = max(xb, __float_as_uint(q[base + x]) & 0x7fffffffu);
     }
-    const float s1 = pow2_scale(sa[0]), s2 = pow2_scale(sb[0]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        xa = max(xa, (unsigned)__shfl_xor((int)xa, o));
+        xb = max(xb, (unsigned)__shfl_xor((int)xb, o));
+    }
+    const float s1 = pow2_scale(xa), s2 = pow2_scale(xb);
     const float r1 = 1.0f / s1, r2 = 1.0f / s2;
-    const int64_t r = (int64_t)z * w.ny + y;
-    if (threadIdx.x == 0) {
+    if (lane == 0) {
         sp[r] = s1;
         sq[r] = s2;
     }
     const int64_t row = r * w.nx;
-    for (int x = threadIdx.x; x < w.nx; x += BS) {
-        const int64_t i = sidx(w, x, y, z);
-        const float va = p[i] * r1, vb = q[i] * r2;
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+        const int x = lane + 64 * k;
+        if (x < w.nx) {
+            const float va = vp[k] * r1, vb = vq[k] * r2;
+            cp[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(va)) : f32_to_bf16_rne(va);
+            cq[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(vb)) : f32_to_bf16_rne(vb);
+        }
+    }
+    for (int x = lane + 64 * KR; x < w.nx; x += 64) {
+        const float va = p[base + x] * r1, vb = q[base + x] * r2;
         cp[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(va)) : f32_to_bf16_rne(va);
         cq[row + x] = dtype == 1 ? __half_as_ushort(__float2half_rn(vb)) : f32_to_bf16_rne(vb);
     }
@@ -621,7 +637,9 @@ void aux_ckpt_pair_encode(const float *cur, const float *prev, const Win &w, int
 void aux_encode_rows2(const float *p, const float *q, const Win &w, int dtype, uint16_t *cp, uint16_t *cq, float *sp,
                       float *sq, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_encode_rows2, dim3(1, w.ny, w.nz), dim3(BS), 0, st, p, q, w, dtype, cp, cq, sp, sq);
+    const int64_t rows = (int64_t)w.ny * w.nz, per = BS / 64;
+    hipLaunchKernelGGL(k_encode_rows2<8>, dim3((unsigned)((rows + per - 1) / per)), dim3(BS), 0, st, p, q, w, dtype, cp,
+                       cq, sp, sq);
 }
 
 void aux_ckpt_pair_decode(const uint16_t *ca, const uint16_t *cb, const float *sca, const float *scb, const Win &w,
