@@ -824,3 +824,63 @@ def elastic_dt_max(g: Grid, vpmax: float) -> float:
     c = _wf(fd_staggered(g.space_order))
     hmin = min(g.spacing[ax] for ax in g.axes())
     return hmin / (vpmax * math.sqrt(len(g.axes())) * float(np.sum(np.abs(c))))
+
+
+# ---------------------------------------------------------------------------
+# Row codecs of the gradient's stores (reading R15, per x-row scales)
+# ---------------------------------------------------------------------------
+def row_scales(f: np.ndarray) -> np.ndarray:
+    """One power-of-two scale per x-row (the last axis) of an FP32 array: s = 2^k, k = ceil(log2 max|row|)
+    clamped to [-126, 127], and 1 for an all-zero row -- the rule of ``ckpt_scale`` applied per row."""
+    f = np.asarray(f, dtype=np.float32)
+    mx = np.max(np.abs(f), axis=-1).astype(np.float64) if f.shape[-1] else np.zeros(f.shape[:-1])
+    mant, e = np.frexp(mx)                       # mx = mant 2^e, mant in [0.5, 1)
+    k = np.where(mant == 0.5, e - 1, e)
+    s = np.ldexp(1.0, np.clip(k, -126, 127))
+    return np.where(mx == 0.0, 1.0, s).astype(np.float32)
+
+
+def round16(x32: np.ndarray, dtype: str) -> np.ndarray:
+    """Bit patterns of the FP16 ('f16') or BF16 ('bf16') values nearest to FP32 values, ties to even."""
+    x32 = np.asarray(x32, dtype=np.float32)
+    if dtype == "f16":
+        return x32.astype(np.float16).view(np.uint16)
+    if dtype == "bf16":
+        return bf16_bits_rne(x32)
+    raise ValueError(dtype)
+
+
+def value16(codes: np.ndarray, dtype: str) -> np.ndarray:
+    """FP32 values of FP16 / BF16 bit patterns (exact)."""
+    c = np.asarray(codes, dtype=np.uint16)
+    if dtype == "f16":
+        return c.view(np.float16).astype(np.float32)
+    return (c.astype(np.uint32) << 16).view(np.float32)
+
+
+def encode_rows(f: np.ndarray, dtype: str):
+    """Per-row codec: codes of f / s_row (FP32 product with the exact reciprocal of the power-of-two
+    scale, then nearest-even 16-bit rounding) and the scales.  Returns (codes, scales)."""
+    f = np.asarray(f, dtype=np.float32)
+    s = row_scales(f)
+    x = f * (np.float32(1.0) / s)[..., None]
+    return round16(x, dtype), s
+
+
+def ckpt_pair_encode_rows(cur: np.ndarray, prev: np.ndarray, dtype: str):
+    """Checkpoint codec of one field at two time levels: a = f^c and b = f^c - f^{c-1} (FP32
+    difference), each coded with ``encode_rows`` (quantising the two levels independently would
+    destroy their difference, the time derivative, which is much smaller than either level).
+    Returns (codes_a, codes_b, scales_a, scales_b)."""
+    cur = np.asarray(cur, dtype=np.float32)
+    b = cur - np.asarray(prev, dtype=np.float32)
+    ca, sa = encode_rows(cur, dtype)
+    cb, sb = encode_rows(b, dtype)
+    return ca, cb, sa, sb
+
+
+def ckpt_pair_decode_rows(ca, cb, sa, sb, dtype: str):
+    """Inverse of ``ckpt_pair_encode_rows``: f^c = s_a a, f^{c-1} = f^c - s_b b (FP32)."""
+    cur = np.asarray(sa, dtype=np.float32)[..., None] * value16(ca, dtype)
+    prev = cur - np.asarray(sb, dtype=np.float32)[..., None] * value16(cb, dtype)
+    return cur, prev

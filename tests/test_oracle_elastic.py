@@ -7,6 +7,8 @@
 * dot tests of the exact transpose (user map with pressure and vz receivers, and a dense
   space-time map), with absorbing layers.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -146,3 +148,48 @@ def test_elastic_gradient_taylor_and_fd(orc, shape):
         assert rem[0] / rem[1] > 3.5 and rem[1] / rem[2] > 3.5, (which, rem)
         fd = (J(0.01) - J(-0.01)) / 0.02
         assert abs(fd - gd) / abs(gd) < 1e-5, (which, fd, gd)
+
+
+def _el_stiffness(orc, g, mod, v):
+    """K v for the velocity-stress step without damping: from the state (v, tau = 0), two steps give
+    v'' = v + dt^2 bbar D_tau (C E v) = v - dt^2 K v (the first step only forms tau = dt C E v)."""
+    vv = [a.copy() for a in v]
+    t = [np.zeros(g.arr_shape) for _ in range(6)]
+    damp = np.ones(g.arr_shape)
+    for _ in range(2):
+        orc._el_call(orc.lib().orc_el_step, g, mod, damp, vv, t)
+    return [(a - b) / g.dt ** 2 for a, b in zip(v, vv)]
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_elastic_time_step_bound_vs_power_iteration(orc, ndim):
+    """The staggered velocity-stress step is a leapfrog for v, v+ - 2v + v- = -dt^2 K v, stable iff
+    dt^2 lambda_max(K) / 4 <= 1.  Power iteration on the oracle's own step gives lambda_max: the bound
+    elastic_dt_max must not exceed 2 / sqrt(lambda_max), and in a homogeneous medium (where the P-wave
+    Nyquist mode along every axis attains it) it must be tight, so a dropped sqrt(d) or a sum of the
+    weights instead of their magnitudes fails."""
+    shape = (30, 1, 28) if ndim == 2 else (16, 15, 14)
+    g = orc.Grid(shape, (10.0, 10.0, 10.0), space_order=8, dt=1e-4)
+    rng = np.random.default_rng(11)
+    mdl = inputs.elastic_model(shape, 0, 21)
+    cases = {"homogeneous": (np.full(g.arr_shape, 3000.0), np.full(g.arr_shape, 3000.0 / 1.8),
+                             np.full(g.arr_shape, 2200.0)),
+             "layered": (mdl["vp"].astype(np.float64), mdl["vs"].astype(np.float64), mdl["rho"].astype(np.float64))}
+    for name, (vp, vs, rho) in cases.items():
+        mod = orc.ElasticModel.from_velocities(g, vp, vs, rho)
+        v = [rng.standard_normal(g.arr_shape) for _ in range(3)]
+        if ndim == 2:
+            v[1][...] = 0.0
+        lam, prev = 0.0, -1.0
+        for it in range(600):
+            kv = _el_stiffness(orc, g, mod, v)
+            nrm = math.sqrt(sum(float(np.vdot(a, a)) for a in kv))
+            lam = nrm / math.sqrt(sum(float(np.vdot(a, a)) for a in v))
+            v = [a / nrm for a in kv]
+            if abs(lam - prev) <= 1e-9 * lam:
+                break
+            prev = lam
+        r = lam * orc.elastic_dt_max(g, float(vp.max())) ** 2 / 4
+        assert r <= 1.0 + 1e-9, (name, r)
+        if name == "homogeneous":
+            assert r >= 0.93, (name, r)

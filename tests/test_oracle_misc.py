@@ -6,6 +6,8 @@ import pytest
 
 from paper_2004_10519_amd import inputs
 
+from codec_cases import rows_fixture
+
 
 @pytest.mark.parametrize("shape", [(9, 7, 6), (12, 1, 10)])
 def test_interpolation_exact_on_multilinear_and_injection_is_transpose(orc, shape):
@@ -134,3 +136,73 @@ def test_codec_subnormal_maximum(orc):
         assert s == 2.0 ** -126
         dec = orc.ckpt_decode(s, codes, dt)
         assert np.all(np.isfinite(dec)) and np.abs(dec - f).max() <= 2.0 ** -126 * 2.0 ** -9
+
+
+def _nearest_even_f16(x):
+    """Brute force: the FP16 value nearest to each float64 |x| (all finite FP16 values enumerated), ties to
+    the even code; returned with the sign of x."""
+    tab = _all_f16()
+    ax = np.abs(x)
+    i = np.clip(np.searchsorted(tab, ax), 1, len(tab) - 1)
+    lo, hi = tab[i - 1], tab[i]
+    best = np.where(ax - lo < hi - ax, lo, hi)
+    even = np.where((np.arange(0x7C00)[i - 1] % 2) == 0, lo, hi)
+    best = np.where((ax - lo) == (hi - ax), even, best)
+    return best * np.sign(x)
+
+
+def _nearest_even_bf16(x):
+    ax = np.abs(x)
+    e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    ulp = 2.0 ** (e - 7)
+    lo = np.floor(ax / ulp) * ulp
+    hi = lo + ulp
+    pick = np.where(ax - lo < hi - ax, lo, hi)
+    lo_even = (np.round(lo / ulp) % 2) == 0
+    pick = np.where((ax - lo) == (hi - ax), np.where(lo_even, lo, hi), pick)
+    return np.where(ax > 0, pick, 0.0) * np.sign(x)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_row_codec_scales_and_nearest_even(orc, dtype):
+    f = rows_fixture()
+    codes, s = orc.encode_rows(f, dtype)
+    mx = np.abs(f).max(axis=-1).astype(np.float64)
+    assert s[0, 1] == 1.0 and not codes[0, 1].any()
+    assert s[1, 2] == 2.0 ** -126
+    nz_ = mx > 0
+    # power-of-two scales with max/2 < max|row| <= s (normal maxima)
+    assert np.all(np.log2(s) == np.round(np.log2(s)))
+    norm = nz_ & (mx >= 2.0 ** -126)
+    assert np.all((s[norm] / 2 < mx[norm]) & (mx[norm] <= s[norm]))
+    x = f.astype(np.float64) / s[..., None].astype(np.float64)
+    want = _nearest_even_f16(x) if dtype == "f16" else _nearest_even_bf16(x)
+    got = orc.value16(codes, dtype).astype(np.float64)
+    assert np.array_equal(got, want)
+    if dtype == "f16":   # the exact ties round to the even FP16 mantissa
+        assert got[2, 3, 0] == 1.0 / 2 and got[2, 3, 1] == (1 + 4 * 2 ** -11) / 2
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16"])
+def test_checkpoint_pair_codec(orc, dtype):
+    """Level + level difference: the difference is coded with its own row scales, so the decoded
+    time difference f^c - f^{c-1} carries the 16-bit relative accuracy of the difference itself."""
+    rng = np.random.default_rng(23)
+    cur = rows_fixture()
+    prev = (cur * (1 + 0.05 * rng.standard_normal(cur.shape))).astype(np.float32)
+    ca, cb, sa, sb = orc.ckpt_pair_encode_rows(cur, prev, dtype)
+    ref_a, ref_sa = orc.encode_rows(cur, dtype)
+    ref_b, ref_sb = orc.encode_rows(cur - prev, dtype)
+    assert np.array_equal(ca, ref_a) and np.array_equal(cb, ref_b)
+    assert np.array_equal(sa, ref_sa) and np.array_equal(sb, ref_sb)
+    c2, p2 = orc.ckpt_pair_decode_rows(ca, cb, sa, sb, dtype)
+    u = 2.0 ** -11 if dtype == "f16" else 2.0 ** -8   # half an ulp of a value in [1/2, 1), relative to s
+    big = np.abs(cur).max(axis=-1) >= 2.0 ** -100    # rows whose codes stay in the normal range
+    da = np.abs(c2.astype(np.float64) - cur)
+    db = np.abs((c2.astype(np.float64) - p2) - (cur.astype(np.float64) - prev))
+    assert np.all(da[big] <= u * sa[big][..., None] * (1 + 1e-6))
+    # the decoded difference: its own rounding plus the FP32 roundings of the difference and the decode
+    tol_b = u * sb[..., None] + 2.0 ** -23 * (np.abs(cur) + np.abs(prev)) * 2
+    assert np.all(db[big] <= tol_b[big])
+    # decode is the stated arithmetic: prev = cur - s_b b in FP32
+    assert np.array_equal(p2, c2 - sb[..., None] * orc.value16(cb, dtype))
