@@ -3,14 +3,18 @@
 
 One "step" is one whole modelling run of the 3D TTI workload tti3d_512 (512^3 grid, 12.5 m,
 space order 12, 3000 time steps, 40-point absorbing layers, 15 Hz source, 256 x 256 receivers),
-with all inputs resident in HBM: every time step's two stencil passes, source injection and
-receiver interpolation.  Metric: grid points updated per second (GPts/s = 512^3 * 3000 / time).
+with all inputs resident in HBM: every time step's stencil launches, source injection and
+receiver interpolation.  Metric: grid points updated per second (GPts/s = 512^3 * 3000 / time);
+ms_per_step is one whole run, ms_per_time_step one of its 3000 time steps.
 
 The JSON line also carries
-  roofline      dominant kernel's algorithmic bytes per launch / its mean launch time (HIP events on
-                the library's stream during the timed steps), against the 8 TB/s HBM peak;
-  cpu_baseline  the FP64 checker timed on this host on a bounded sample of the same workload;
-  paths         other measured paths when --all is given (elastic, adjoint, gradient).
+  roofline      the method's algorithmic bytes of one time step (44 B/pt) times the points of one
+                launch of the dominant kernel, over that kernel's mean launch time (HIP events on the
+                library's stream during the timed steps), against the 8 TB/s HBM peak; step_frac is
+                the same bytes over the whole time step;
+  cpu_baseline  the FP64 checker timed on this host on bounded samples of the TTI and elastic workloads;
+  paths         the other measured paths (TTI adjoint, elastic forward / adjoint / gradient, 2D marine
+                elastic, TTI gradient, 64 batched shots against 64 plain calls); --only-main skips them.
 """
 from __future__ import annotations
 
@@ -40,13 +44,17 @@ HBM_PEAK_GBS = 8000.0
 #   scheme 2 (one fused pass, class 1): read u, v, f- for p and q (4), n_x, n_y, m, 1+2eps,
 #                    sqrt(1+2delta) (5); write p+, q+ (2); adjoint reads y too and writes
 #                    w = C y+ (2)                                                         -> 11 / 15 x 4
+#   scheme 4 pass A: read u, n_x, n_y; write h = H0 u                                    ->  4 x 4
+#   scheme 4 pass B: read v, n_x, n_y, h, f and f- of p (2), f- of q, m, 1+2eps, sqrt(1+2delta);
+#                    write p+, q+ (2); adjoint reads f of q too and writes w = C y+ (2)  -> 12 / 15 x 4
 # Elastic:
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
 TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
                     (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64,
                     (2, 1, False): 44, (2, 1, True): 60,
-                    (3, 0, False): 32, (3, 1, False): 60, (3, 0, True): 32, (3, 1, True): 68}
+                    (3, 0, False): 32, (3, 1, False): 60, (3, 0, True): 32, (3, 1, True): 68,
+                    (4, 0, False): 16, (4, 1, False): 48, (4, 0, True): 16, (4, 1, True): 60}
 KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
 TTI_SCHEME = None   # step scheme of every TTI handle (--scheme); None = the library default
 FIXED_TILES = None  # (tile1, zc1, tile2, zc2) of the main run instead of the autotuner (--tiles)
@@ -121,9 +129,22 @@ def timed(torch, fn, steps, warmup):
     return (time.perf_counter() - t0) / steps
 
 
-def cpu_baseline(w, budget_s: float = 15.0):
-    """The FP64 checker on a sub-volume of the same model (a bounded sample of the workload)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, budget_s: float = 12.0, el_budget_s: float = 8.0):
+    """The FP64 checker on sub-volumes of the benchmark model (the TTI step of the headline) and of the
+    elastic 400^3 model (a bounded sample of each workload)."""
     import oracle
+    from paper_2004_10519_amd import configs
     n = min(192, w.shape[0])
     mdl = w.make_model()
     sl = tuple(slice(s // 2 - n // 2, s // 2 - n // 2 + n) if s > 1 else slice(None) for s in w.arr_shape)
@@ -144,9 +165,33 @@ def cpu_baseline(w, budget_s: float = 15.0):
         if el > budget_s or steps >= 50:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    return {"value": round(int(np.prod(shape)) * steps / el / 1e9, 5), "unit": "GPts/s", "cores": cores,
-            "kind": "oracle", "sample": f"{shape[0]}x{shape[1]}x{shape[2]} centre sub-volume of the {w.name} model, "
-                                        f"space order {w.space_order}, {steps} FP64 time steps in {el:.1f} s"}
+    out = {"value": round(int(np.prod(shape)) * steps / el / 1e9, 5), "unit": "GPts/s", "cores": cores,
+           "kind": "oracle", "cpu_model": cpu_model(),
+           "sample": f"{shape[0]}x{shape[1]}x{shape[2]} centre sub-volume of the {w.name} model, "
+                     f"space order {w.space_order}, {steps} FP64 time steps in {el:.1f} s"}
+    # elastic: the velocity-stress step of the el3d_400 workload on a centre sub-volume
+    we = configs.el3d_400(nt=1)
+    ne = 160
+    me = we.make_model()
+    sle = tuple(slice(s // 2 - ne // 2, s // 2 - ne // 2 + ne) for s in we.arr_shape)
+    ge = oracle.Grid((ne, ne, ne), we.spacing, space_order=we.space_order, nbl=we.nbl // 4, dt=we.dt, nt=1,
+                     vref=we.v_ref)
+    emod = oracle.ElasticModel.from_velocities(ge, *(np.ascontiguousarray(me[k][sle]) for k in ("vp", "vs", "rho")))
+    damp = np.ascontiguousarray(oracle.elastic_damp(ge))
+    v = [rng.standard_normal(ge.arr_shape) for _ in range(3)]
+    t = [np.zeros(ge.arr_shape) for _ in range(6)]
+    oracle._el_call(oracle.lib().orc_el_step, ge, emod, damp, v, t)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        oracle._el_call(oracle.lib().orc_el_step, ge, emod, damp, v, t)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > el_budget_s or steps >= 50:
+            break
+    out["elastic"] = {"value": round(ne ** 3 * steps / el / 1e9, 5), "unit": "GPts/s",
+                      "sample": f"{ne}^3 centre sub-volume of the {we.name} model, space order {we.space_order}, "
+                                f"{steps} FP64 velocity-stress steps in {el:.1f} s"}
+    return out
 
 
 def kernel_roof(p, classes, npts, scheme=0, adjoint=False):
@@ -276,6 +321,24 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
                             "store_GB": round(w.nt * 2 * w.npts * 2 / 1e9, 1),
                             "method_hbm_frac_104B": round(gp * 104 / HBM_PEAK_GBS, 4),
                             "rel_l2_vs_f32_checkpoints": float(((gr.double() - ref).norm() / ref.norm()).item())}
+    # one FWI iteration: modelling (for the residual), then the gradient.  A saving forward keeps the
+    # checkpoints (or, with n_ckpt = 1, the whole run in FP16) and the gradient reuses them: one
+    # forward sweep less (48 checkpoints: 3 sweeps instead of 4; whole run: 2 instead of 3)
+    fwi = {}
+    for label, n in (("48_f16_checkpoints", 48), ("whole_run_f16", 1)):
+        def plain(n=n):
+            p.forward(shot)
+            p.gradient(shot, res, n, "f16")
+
+        def saved(n=n):
+            p.forward(shot, save_ckpt=n, ckpt_dtype="f16")
+            p.gradient(shot, res, 0)
+
+        t_plain = timed(torch, plain, 1, 0)
+        t_saved = timed(torch, saved, 1, 0)
+        fwi[label] = {"forward_then_gradient_s": round(t_plain, 4), "saving_forward_then_reuse_s": round(t_saved, 4),
+                      "speedup": round(t_plain / t_saved, 3)}
+    out["fwi_iteration"] = fwi
     out["scheme"] = p.get_option("scheme")
     p.close()
     return out
@@ -362,21 +425,6 @@ def measure_batched(torch, prop, nt, nshot):
     err = float(np.linalg.norm(gbh - gp) / np.linalg.norm(gp))
     del gb
     torch.cuda.empty_cache()
-    # batched with the whole run stored in FP16 (n_ckpt = 1; the planner fits fewer shots per group)
-    p.set_option("graph", 1)
-    p.set_option("autotune", 1)
-    gw_ = torch.zeros(w.arr_shape, dtype=torch.float64, device="cuda")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    groups_w = 0
-    for c in range(0, nshot, chunk):
-        p.gradient_batched(shots[c:c + chunk], res[c:c + chunk], gw_, n_ckpt=1, ckpt_dtype="f16")
-        torch.cuda.synchronize()
-        groups_w += p.get_option("info_groups")
-        log(f"[bench]   batched, whole run stored: {min(c + chunk, nshot)}/{nshot} shots, "
-            f"{time.perf_counter() - t0:.1f} s")
-    tw = time.perf_counter() - t0
-    errw = float(np.linalg.norm(gw_.cpu().numpy() - gp) / np.linalg.norm(gp))
     scheme = p.get_option("scheme")
     p.close()
     return {"workload": w.name, "model": list(w.shape), "shots": nshot, "window_points": pts, "time_steps": w.nt,
@@ -385,10 +433,7 @@ def measure_batched(torch, prop, nt, nshot):
                         "graphs": graphs_b, "last_group_tiles": tiles_b, "groups_last_call": groups_b,
                         "method_hbm_frac_156B": round(pts * w.nt / tb / 1e9 * 156 / HBM_PEAK_GBS, 4)},
             "plain": {"s": round(tp, 2), "GPts/s": round(pts * w.nt / tp / 1e9, 3), "checkpoint_dtype": "f32"},
-            "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err,
-            "batched_whole_run_f16": {"s": round(tw, 2), "GPts/s": round(pts * w.nt / tw / 1e9, 3),
-                                      "shot_groups": groups_w, "speedup_vs_plain": round(tp / tw, 3),
-                                      "rel_l2_vs_plain": errw}}
+            "speedup": round(tp / tb, 3), "rel_l2_batched_vs_plain": err}
 
 
 def main():
@@ -402,15 +447,19 @@ def main():
     ap.add_argument("--space-order", type=int, default=None,
                     help="space order of the main TTI run instead of 12 (profiles of other stencil widths)")
     ap.add_argument("--only-main", action="store_true", help="skip the adjoint, elastic and gradient paths")
-    ap.add_argument("--batched", type=int, default=0, metavar="NSHOT",
-                    help="also run the batched-vs-plain gradient comparison with NSHOT shots (64 = full)")
+    ap.add_argument("--batched", type=int, default=64, metavar="NSHOT",
+                    help="shots of the batched-vs-plain gradient comparison (default 64, the full workload; "
+                         "0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--budget", type=float, default=540.0,
+                    help="wall-time budget in seconds: a measured leg that would end past it is skipped")
     ap.add_argument("--tiles", default=None, metavar="T1,Z1,T2,Z2",
                     help="fixed tile variants and z-chunks of the two TTI passes instead of the autotuner "
                          "(counter runs: the profiler serialises launches, which would mislead the autotuner)")
-    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2, 3),
+    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2, 3, 4),
                     help="TTI step scheme: 0 two passes with six-field temporaries, 1 two passes with "
-                         "scalar projections, 2 one fused pass (default: the library's choice per space "
+                         "scalar projections, 2 one fused pass, 3 two passes with four-field temporaries, "
+                         "4 two fused single-field passes (default: the library's choice per space "
                          "order, fused up to 8)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one device copy of 512 MiB (calibrates rocprofv3 FETCH_SIZE / WRITE_SIZE)")
@@ -426,6 +475,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    T0 = time.perf_counter()
     import torch
     from paper_2004_10519_amd import configs, prop
     prop.lib()
@@ -468,17 +518,24 @@ def main():
     avg_s = ms_tot / 1e3 / max(nl, 1)
     scheme = p.get_option("scheme")
     tiles = [p.get_option(k) for k in ("info_tile1", "info_zc1", "info_tile2", "info_zc2")]
-    achieved = kernel_bytes(dom, scheme) * npts / avg_s / 1e9
+    # achieved: the method's algorithmic bytes of one time step (44 B per point, FP32) times the points
+    # one launch of the dominant kernel updates, over its mean launch time
+    method_b = METHOD_BYTES_PER_PT["tti"]
+    achieved = method_b * npts / avg_s / 1e9
     traffic = traffic_from_profiles(dom, npts, scheme, tiles[2 * dom:2 * dom + 2], w.space_order)
+    t_ts = t_step / w.nt
     roof = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "algorithmic_bytes_per_launch": kernel_bytes(dom, scheme) * npts, "scheme": scheme,
+            "basis": f"{method_b} B/pt (one TTI time step: read p, q at two levels and m, eps, delta, theta, "
+                     f"phi; write p+, q+) x {npts} points per launch",
+            "algorithmic_bytes_per_launch": method_b * npts, "scheme": scheme,
             "mean_launch_ms": round(avg_s * 1e3, 4), "launches": nl,
+            "step_frac": round(method_b * npts / t_ts / 1e9 / HBM_PEAK_GBS, 4),
             "kernels": {kt[k][2]: {"mean_launch_ms": round(kt[k][0] / max(kt[k][1], 1), 4),
-                                   "GBps_algorithmic": round(kernel_bytes(k, scheme) * npts /
-                                                             (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
-                        for k in kt},
-            "method_hbm_frac": round(gpts * METHOD_BYTES_PER_PT["tti"] / HBM_PEAK_GBS, 4)}
+                                   "own_bytes_per_point": kernel_bytes(k, scheme),
+                                   "GBps_own_bytes": round(kernel_bytes(k, scheme) * npts /
+                                                           (kt[k][0] / 1e3 / max(kt[k][1], 1)) / 1e9, 1)}
+                        for k in kt}}
     roof["tiles"] = {"pass1": {"variant": tiles[0], "zc": tiles[1]}, "pass2": {"variant": tiles[2], "zc": tiles[3]},
                      "autotuned": not FIXED_TILES}
     if not args.copy_probe:   # (counter runs calibrate on the probe copy alone)
@@ -494,6 +551,7 @@ def main():
         paths["tti_adjoint"] = measure_tti_adjoint(torch, prop, w, p, shot)
     out = {"metric": f"GPts/s (TTI forward, {w.shape[0]}^3, so{w.space_order})", "value": round(gpts, 3), "unit": "GPts/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_step * 1e3, 2),
+           "time_steps_per_step": w.nt, "ms_per_time_step": round(t_ts * 1e3, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded layered TTI model, Ricker source)",
            "config": {"workload": w.name, "grid": list(w.shape), "spacing_m": w.spacing[0],
@@ -507,24 +565,31 @@ def main():
     p.close()
     del p
     torch.cuda.empty_cache()
-    if not args.only_main:
-        nt_el = 2000 if args.nt is None else min(args.nt, 2000)
-        paths["elastic"] = measure_elastic(torch, prop, nt_el)
-        torch.cuda.empty_cache()
-        log("[bench] 2D marine elastic (free surface) ...")
-        paths["elastic_2d_marine"] = measure_marine(torch, prop)
-        torch.cuda.empty_cache()
-        nt_gr = 2000 if args.nt is None else min(args.nt, 2000)
-        paths["tti_gradient"] = measure_gradient(torch, prop, nt_gr)
-        torch.cuda.empty_cache()
-        out["paths"] = paths
-    if args.batched:
-        out.setdefault("paths", {})["batched_vs_plain"] = measure_batched(torch, prop, args.nt or 1500, args.batched)
+    # the remaining legs, each started only while the whole run stays inside the time budget (the
+    # estimates are generous wall times on one MI355X; a skipped leg is recorded as such)
+    def leg(name, est_s, fn, where):
+        left = args.budget - (time.perf_counter() - T0)
+        if left < est_s:
+            where[name] = {"skipped": f"time budget: {left:.0f} s left, the leg takes about {est_s:.0f} s"}
+            log(f"[bench] {name}: skipped ({left:.0f} s left)")
+            return
+        where[name] = fn()
         torch.cuda.empty_cache()
 
+    if not args.only_main:
+        nt_el = 2000 if args.nt is None else min(args.nt, 2000)
+        nt_gr = 2000 if args.nt is None else min(args.nt, 2000)
+        leg("elastic", 60, lambda: measure_elastic(torch, prop, nt_el), paths)
+        leg("tti_gradient", 60, lambda: measure_gradient(torch, prop, nt_gr), paths)
+        out["paths"] = paths
     if not args.no_cpu:
         log("[bench] CPU baseline (FP64 checker) ...")
         out["cpu_baseline"] = cpu_baseline(w)
+    if not args.only_main:
+        if args.batched:
+            leg("batched_vs_plain", 230, lambda: measure_batched(torch, prop, args.nt or 1500, args.batched), paths)
+        log("[bench] 2D marine elastic (free surface) ...")
+        leg("elastic_2d_marine", 15, lambda: measure_marine(torch, prop), paths)
     print(json.dumps(out), flush=True)
 
 

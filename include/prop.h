@@ -131,7 +131,8 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
  * Returns a negative value for an invalid grid. */
 double prop_cfl_dt(prop_kind kind, const prop_grid *grid, double vmax, double eps_max);
 
-/* Replace the model (same grid); validates like prop_create. */
+/* Replace the model (same grid); validates like prop_create.  Invalidates the checkpoints that a
+ * saving prop_forward left on the handle (the model arrays may have new values). */
 int prop_set_model(prop_t h, const prop_model *model);
 
 /* Forward modelling of one shot: rec_out DEVICE nt x nrec receives the traces (row n is recorded
@@ -139,8 +140,16 @@ int prop_set_model(prop_t h, const prop_model *model);
  * TTI: a f^{n+1} = b f^n - c f^{n-1} + C (H0 p^n, Hz q^n) + P_s^T s^n for f in (p, q), with
  * a = m/dt^2 + eta/(2 dt), b = 2 m/dt^2, c = m/dt^2 - eta/(2 dt), eta the damping of the absorbing
  * layer, C = [[1+2 eps, sqrt(1+2 delta)], [sqrt(1+2 delta), 1]].
- * Elastic: the staggered velocity-stress scheme of the elastic section. */
-int prop_forward(prop_t h, const prop_shot *shot, float *rec_out);
+ * Elastic: the staggered velocity-stress scheme of the elastic section.
+ * save_ckpt = 0: modelling only.  save_ckpt = n >= 1: the run also keeps, on the handle, the forward
+ * checkpoints that prop_gradient / prop_image with n_ckpt = n and this ckpt_dtype would store (TTI:
+ * n = 1 keeps the whole run in ckpt_dtype; elastic: ckpt_dtype must be PROP_CKPT_F32), so that a
+ * gradient or image of the same shot under the same model skips its own forward sweep (the usual
+ * FWI iteration: modelling, residual, gradient).  The traces are the same as with save_ckpt = 0.
+ * The saved checkpoints stay valid until prop_set_model, the next saving prop_forward, or a gradient,
+ * image or batched call that stores checkpoints of its own; prop_adjoint and plain forward calls
+ * keep them.  ckpt_dtype is ignored when save_ckpt = 0. */
+int prop_forward(prop_t h, const prop_shot *shot, float *rec_out, int32_t save_ckpt, prop_ckpt_dtype ckpt_dtype);
 
 /* Exact transpose of prop_forward for the same shot (traces -> wavelet):
  * rec_in DEVICE nt x nrec, src_out DEVICE nt x nsrc (overwritten). */
@@ -162,7 +171,13 @@ int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *sr
  * the whole forward wavefield instead (one segment, no checkpoint), in ckpt_dtype (FP32, or
  * FP16/BF16 with a power-of-two scale per x-row), and takes two sweeps (forward with storage,
  * adjoint) instead of three: N x 2 fields x 4 B (FP32) or 2 B (FP16/BF16) per point of device
- * memory. */
+ * memory.
+ * Checkpoint reuse (both kinds): when the last saving prop_forward ran this shot (same window, the
+ * same source points and the same wavelet array, left unchanged) under the current model with
+ * save_ckpt = n_ckpt and the same ckpt_dtype, its checkpoints are used and the forward sweep is
+ * skipped (with n_ckpt = 1 only the adjoint sweep remains).  n_ckpt = 0 asks for exactly that reuse,
+ * whatever n and dtype the forward saved with, and returns PROP_ESTATE when the handle holds no valid
+ * checkpoints of this shot (none saved, or invalidated since; see prop_forward). */
 int prop_gradient(prop_t h, const prop_shot *shot, const float *residual, float *grad_m,
                   int32_t n_ckpt, prop_ckpt_dtype ckpt_dtype);
 
@@ -204,8 +219,11 @@ int prop_read_state(prop_t h, int32_t field, float *out);
 int prop_set_timing(prop_t h, int32_t enable);
 int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name);
 
-/* Run-time options of a handle; they apply to the calls that follow.  None of them changes a
- * result: every point is computed by the same arithmetic whatever the tiling or launch mode.
+/* Run-time options of a handle; they apply to the calls that follow.  They change how the work is
+ * launched.  GRAPH, AUTOTUNE, TILE1/2, ZC, ZC2, XCD and BATCH_MB leave every result bitwise unchanged:
+ * each point is computed by the same arithmetic whatever the tiling or launch mode.  SCHEME selects
+ * another arrangement of the same operators: schemes 0 and 3 give bitwise equal results, and the
+ * others agree with them to FP32 rounding (sums formed in another order).
  *   PROP_OPT_GRAPH     0/1 (default 0): record each run of time steps between two host checks
  *                      (the non-finite watchdog every 500 steps; each gradient segment) in a HIP
  *                      graph and launch it as one unit.  Ignored while kernel timing is on.
@@ -262,6 +280,24 @@ int prop_ckpt_encode(const float *f, int64_t n, prop_ckpt_dtype dtype, void *cod
                      void *stream);
 int prop_ckpt_decode(const void *codes, const float *scale_dev, int64_t n, prop_ckpt_dtype dtype,
                      float *f, void *stream);
+
+/* Row codecs of the gradient's stores, exposed for testing.  Fields are dense (nz, ny, nx) FP32
+ * arrays (DEVICE); every x-row (fixed y, z) gets its own power-of-two scale s = 2^k,
+ * k = ceil(log2 max|row|) clamped to [-126, 127] (1 for an all-zero row), and its values f * (1/s)
+ * (an exact FP32 product) round to nearest even FP16 (dtype F16) or BF16 (dtype BF16).
+ *   pair = 1: the checkpoint pair of one field at two time levels: a = cur, b = cur - prev (the FP32
+ *             difference; the time derivative it carries is much smaller than either level);
+ *   pair = 0: two independent fields a = cur, b = prev (the per-step store of p and q when the
+ *             gradient keeps the whole run).
+ * codes_a, codes_b DEVICE nz*ny*nx uint16; scale_a, scale_b DEVICE nz*ny floats.  Requires
+ * 1 <= ny, nz <= 65535 and 1 <= nx <= 2^31 - 1 (PROP_EINVAL otherwise).  Enqueued on stream. */
+int prop_ckpt_encode_rows(const float *cur, const float *prev, int64_t nx, int64_t ny, int64_t nz, int32_t pair,
+                          prop_ckpt_dtype dtype, uint16_t *codes_a, uint16_t *codes_b, float *scale_a,
+                          float *scale_b, void *stream);
+/* Inverse of the pair codec: cur = s_a a, prev = cur - s_b b (FP32), dense (nz, ny, nx) DEVICE. */
+int prop_ckpt_decode_rows(const uint16_t *codes_a, const uint16_t *codes_b, const float *scale_a,
+                          const float *scale_b, int64_t nx, int64_t ny, int64_t nz, prop_ckpt_dtype dtype,
+                          float *cur, float *prev, void *stream);
 
 /* FP64 inner product of two FP32 device vectors (deterministic order); blocks until done. */
 int prop_dot_f64(const float *a, const float *b, int64_t n, double *result, void *stream);

@@ -77,9 +77,10 @@ struct ElGradJob {
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
 // Schemes of the TTI step: two passes with six-field temporaries, two passes with the two scalar
-// projections n . grad, one fused pass (projections kept on chip), or two passes with four
-// temporaries: t and the scalar n . grad v, from which pass 2 re-forms s = n (n . grad v).
-enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2, TTI_FOUR = 3 };
+// projections n . grad, one fused pass (projections kept on chip), two passes with four
+// temporaries: t and the scalar n . grad v, from which pass 2 re-forms s = n (n . grad v), or two
+// fused single-field passes (h = H0 u, then Hz v and the update; one temporary, h).
+enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2, TTI_FOUR = 3, TTI_SPLIT = 4 };
 
 // shape: tile-shape variant of the pass; tti_tile_rows gives its tile height.
 void launch_tti_pass1(int R, int scheme, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles,
@@ -89,6 +90,10 @@ void launch_tti_pass2(int R, int scheme, int shape, int mode, const TTIJob *jobs
 // The fused scheme runs only the second launch (pass 1 is a no-op).
 int tti_tile_rows(int R, int scheme, int pass, int shape);
 int tti_fused_max_radius();
+// The split scheme: part 0 = pass A (h = H0 u, written to t[0]), part 1 = pass B (Hz v, update).
+int tti_split_max_radius();
+void launch_tti_split(int R, int part, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
+                      const Weights &W, float idt2, int seg_step, hipStream_t st);
 void launch_tti_fused(int R, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                       const Weights &W, float idt2, int seg_step, hipStream_t st);
 

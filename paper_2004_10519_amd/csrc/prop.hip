@@ -256,6 +256,14 @@ struct prop_s {
     };
     std::map<std::string, Tune> tuned;
     Tune last_tune{{1, 1}, {0, 0}};
+    // checkpoints left by a saving prop_forward (shot identity, count and type)
+    struct Saved {
+        bool valid = false;
+        int n_ckpt = 0, dtype = 0, nsrc = 0;
+        int64_t o[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+        const float *wav = nullptr;
+        std::vector<float> src;
+    } saved;
     // graph capture of time-step runs
     hipStream_t cap = nullptr;
     std::vector<hipGraphExec_t> execs;
@@ -326,7 +334,8 @@ void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std:
 int choose_zc(const prop_s *h, int nz, int64_t tiles_xy)
 {
     if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
-    const int64_t target = h->kind == PROP_TTI ? (h->opt_scheme == TTI_FUSED ? 512 : 2048) : 4096;
+    const bool one_block_per_cu = h->opt_scheme == TTI_FUSED || h->opt_scheme == TTI_SPLIT;
+    const int64_t target = h->kind == PROP_TTI ? (one_block_per_cu ? 512 : 2048) : 4096;
     const int minlen = h->kind == PROP_ELASTIC && h->g.ndim == 2 ? h->R : 4 * h->R;
     int64_t nch = (target + tiles_xy - 1) / tiles_xy;
     nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / minlen)));
@@ -687,6 +696,7 @@ int prep_model(prop_s *h, const prop_model *m)
     if (h->g.dt > bound * (1 + 1e-9))
         return fail(PROP_EUNSTABLE, "dt = %g exceeds the stability bound %g (vmax %g)", h->g.dt, bound, (double)vmax);
     h->last_state = 0;
+    h->saved.valid = false;
     return PROP_OK;
 }
 
@@ -914,7 +924,7 @@ int tune_group(prop_s *h, Group &G, bool adj)
     std::vector<Tile> tl;
     for (int pass = h->opt_scheme == TTI_FUSED ? 2 : 1; pass <= 2; ++pass) {
         std::vector<std::pair<int, int>> cand{{dflt.shape[pass - 1], dflt.zc[pass - 1]}};
-        for (int shape = 0; shape < 2; ++shape) {
+        for (int shape = h->opt_scheme == TTI_SPLIT ? 1 : 0; shape < 2; ++shape) {
             const int z0 = group_zc(h, G.slots, pass, shape);
             for (int zc : {std::max(1, z0 / 2), z0, 2 * z0}) {
                 const std::pair<int, int> c{shape, std::min(zc, nzmax)};
@@ -1244,9 +1254,16 @@ size_t grad_bytes(const Slot &sl, int C, int S, int dtype)
     return ck + seg_bytes(sl, S, C > 1 ? 0 : dtype) + 1024;
 }
 
-// Checkpointed gradient (or zero-lag image) of a group; each shot's window result is left in its
-// slot (field 10).
-int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = false, bool grow_only = false)
+// Checkpointed gradient (or zero-lag image) of a group, in three parts: the plan (segment length,
+// checkpoint count, workspaces, job tables), the forward sweep that stores the checkpoints (or, with
+// a single segment, the whole run) and the reverse sweep.  A saving prop_forward runs the first two
+// (gathering traces as it goes); a gradient reusing them runs the plan and the reverse sweep.
+struct GradPlan {
+    int N = 0, S = 0, C = 0, sdt = 0, dtype = 0;
+    std::vector<TTIJob> jf;          // host copies of the forward job table (segment-store pointers)
+};
+
+int tti_grad_setup(prop_s *h, Group &G, int n_ckpt, int dtype, bool image, bool grow_only, GradPlan &P)
 {
     const int N = h->g.nt;
     const int S = (N + n_ckpt - 1) / n_ckpt;      // segment length
@@ -1258,6 +1275,11 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
     // encoded after each step, and keeps f^k exact); in the checkpoint type when one segment holds
     // the whole run (the memory then matters)
     const int sdt = C > 1 ? 0 : dtype;
+    P.N = N;
+    P.S = S;
+    P.C = C;
+    P.sdt = sdt;
+    P.dtype = dtype;
     G.ck_off.assign(ns, 0);
     G.sc_off.assign(ns, 0);
     G.seg_off.assign(ns, 0);
@@ -1276,7 +1298,8 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
     TRY(want(h->ckpt, std::max<size_t>(ck_total, 16)));
     TRY(want(h->ckscale, std::max<size_t>(sc_total * sizeof(float), 16)));
     TRY(want(h->seg, std::max<size_t>(seg_total, 16)));
-    std::vector<TTIJob> jf, ja;
+    std::vector<TTIJob> ja;
+    P.jf.clear();
     for (int j = 0; j < ns; ++j) {
         const Slot &sl = *G.slots[j];
         TTIJob a = tti_job(h, sl, false), b = tti_job(h, sl, true);
@@ -1294,66 +1317,110 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
             }
         }
         b.image = image ? 1 : 0;
-        jf.push_back(a);
+        P.jf.push_back(a);
         ja.push_back(b);
     }
-    TRY(upload(G.jobs_f, jf, h->st));
+    TRY(upload(G.jobs_f, P.jf, h->st));
     TRY(upload(G.jobs_a, ja, h->st));
-    const TTIJob *djf = G.jobs_f.as<TTIJob>(), *dja = G.jobs_a.as<TTIJob>();
+    return PROP_OK;
+}
+
+// Forward steps [start, end) of the segment that starts at `start`, storing each new level in the
+// segment store (FP32: written by the update pass, the source added in place; 16-bit: encoded once
+// the step, with its source, is complete); traces are gathered when the group has receiver plans.
+void tti_seg_forward(prop_s *h, Group &G, const GradPlan &P, int start, int end)
+{
+    const TTIJob *djf = G.jobs_f.as<TTIJob>();
+    const float idt2 = idt2_of(h);
+    const int ns = (int)G.slots.size();
+    for (int n = start; n < end; ++n) {
+        const int par = n & 1;
+        if (P.sdt == 0) {
+            tti_step(h, G, false, K2_FWD_STORE, par, n - start);
+            aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, n - start, h->st);
+        } else {
+            tti_step(h, G, false, K2_FWD, par, 0);
+            aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
+            for (int i = 0; i < ns; ++i) {
+                const TTIJob &J = P.jf[i];
+                const Slot &sl = *G.slots[i];
+                const int64_t k = n - start;
+                aux_encode_rows2(sl.f[par ^ 1], sl.f[2 + (par ^ 1)], sl.w, P.sdt, J.seg16 + k * 2 * J.seg16_field,
+                                 J.seg16 + (k * 2 + 1) * J.seg16_field, J.segsc + k * 2 * J.segsc_field,
+                                 J.segsc + (k * 2 + 1) * J.segsc_field, h->st);
+            }
+        }
+        aux_tti_gather(G.rec_gat, djf, par, 0, G.rec_out, G.nrec, n, h->st);
+    }
+}
+
+// The forward sweep: checkpoints at c_j = j S (j >= 1; c_0 = 0 is the zero state), or with a single
+// segment the whole run in the segment store.
+int tti_grad_forward(prop_s *h, Group &G, const GradPlan &P)
+{
+    const int N = P.N, S = P.S, C = P.C, ns = (int)G.slots.size();
+    const TTIJob *djf = G.jobs_f.as<TTIJob>();
     const float idt2 = idt2_of(h);
     char *ck = h->ckpt.as<char>();
     float *sc = h->ckscale.as<float>();
-
-    // 1) forward with checkpoints at c_j = j S (j >= 1); c_0 = 0 is the zero state.  With a single
-    //    segment there is nothing to checkpoint: the recomputation below is the only forward sweep.
     for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
     TRY(tune_group(h, G, false));
     Capture cap(h);
-    if (C > 1) TRY(cap.begin());
-    for (int n = 0; n < (C > 1 ? N : 0); ++n) {
+    if (C == 1) {
+        TRY(cap.begin());
+        tti_seg_forward(h, G, P, 0, N);
+        TRY(cap.end());
+        return check_group(h, G, N & 1, "p (forward with storage)", N - 1);
+    }
+    TRY(cap.begin());
+    for (int n = 0; n < N; ++n) {
         const int par = n & 1;
         tti_step(h, G, false, K2_FWD, par, 0);
         aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
+        aux_tti_gather(G.rec_gat, djf, par, 0, G.rec_out, G.nrec, n, h->st);
         if ((n + 1) % S == 0 && (n + 1) / S < C)
-            for (int j = 0; j < ns; ++j) ckpt_save(h, *G.slots[j], ck + G.ck_off[j], sc + G.sc_off[j], (n + 1) / S, par ^ 1, dtype);
+            for (int j = 0; j < ns; ++j)
+                ckpt_save(h, *G.slots[j], ck + G.ck_off[j], sc + G.sc_off[j], (n + 1) / S, par ^ 1, P.dtype);
         if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
             TRY(cap.end());
-            TRY(check_group(h, G, par ^ 1, "p (gradient forward)", n));
+            TRY(check_group(h, G, par ^ 1, "p (forward with checkpoints)", n));
             if (n + 1 < N) TRY(cap.begin());
         }
     }
-    // 2) reverse sweep over segments: restore, recompute and store, adjoint with imaging condition
+    return PROP_OK;
+}
+
+// The reverse sweep over segments: restore, recompute and store, then the adjoint steps with the
+// imaging condition.  Each shot's window result is left in its slot (field 10).  With a single
+// segment the forward sweep has already stored the whole run.
+int tti_grad_reverse(prop_s *h, Group &G, const GradPlan &P)
+{
+    const int N = P.N, S = P.S, C = P.C, ns = (int)G.slots.size();
+    const TTIJob *dja = G.jobs_a.as<TTIJob>();
+    const float idt2 = idt2_of(h);
+    char *ck = h->ckpt.as<char>();
+    float *sc = h->ckscale.as<float>();
     for (auto *sl : G.slots) {
         aux_fill(sl->f[10], sl->plane, 0.f, h->st);          // gradient accumulator
         aux_fill(sl->f[11], 8 * sl->plane, 0.f, h->st);      // adjoint state and w (both levels)
     }
+    if (C > 1) {   // the recomputation uses the forward tiles (the tuner's trials run on a zero state)
+        for (auto *sl : G.slots) aux_fill(sl->f[0], 4 * sl->plane, 0.f, h->st);
+        TRY(tune_group(h, G, false));
+    }
     TRY(tune_group(h, G, true));
+    Capture cap(h);
     for (int j = C - 1; j >= 0; --j) {
         const int start = j * S, end = std::min(N, (j + 1) * S);
         const int par0 = start & 1;
         TRY(cap.begin());
-        for (int i = 0; i < ns; ++i) {
-            Slot &sl = *G.slots[i];
-            if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
-            else ckpt_load(h, sl, ck + G.ck_off[i], sc + G.sc_off[i], j, par0, dtype);
-        }
-        for (int n = start; n < end; ++n) {
-            const int par = n & 1;
-            if (sdt == 0) {     // FP32 store: written by the update pass, the source added in place
-                tti_step(h, G, false, K2_FWD_STORE, par, n - start);
-                aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, n - start, h->st);
-            } else {            // 16-bit store: encoded once the step (with its source) is complete
-                tti_step(h, G, false, K2_FWD, par, 0);
-                aux_tti_src(G.src_inj, djf, par, G.src_data, G.nsrc, n, idt2, -1, h->st);
-                for (int i = 0; i < ns; ++i) {
-                    const TTIJob &J = jf[i];
-                    const Slot &sl = *G.slots[i];
-                    const int64_t k = n - start;
-                    aux_encode_rows2(sl.f[par ^ 1], sl.f[2 + (par ^ 1)], sl.w, sdt, J.seg16 + k * 2 * J.seg16_field,
-                                     J.seg16 + (k * 2 + 1) * J.seg16_field, J.segsc + k * 2 * J.segsc_field,
-                                     J.segsc + (k * 2 + 1) * J.segsc_field, h->st);
-                }
+        if (C > 1) {
+            for (int i = 0; i < ns; ++i) {
+                Slot &sl = *G.slots[i];
+                if (j == 0) aux_fill(sl.f[0], 4 * sl.plane, 0.f, h->st);
+                else ckpt_load(h, sl, ck + G.ck_off[i], sc + G.sc_off[i], j, par0, P.dtype);
             }
+            tti_seg_forward(h, G, P, start, end);
         }
         for (int k = end; k > start; --k) {
             const int par = (N - k) & 1;
@@ -1362,7 +1429,7 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
         }
         TRY(cap.end());
         for (int i = 0; i < ns; ++i) {
-            TRY(check_finite(h, G.slots[i]->f[par0], G.slots[i]->w, "restored p", start, i));
+            if (C > 1) TRY(check_finite(h, G.slots[i]->f[par0], G.slots[i]->w, "restored p", start, i));
             TRY(check_finite(h, G.slots[i]->f[11 + (((N - start - 1) & 1) ^ 1)], G.slots[i]->w, "y_p", start, i));
         }
         TRY(check_group(h, G, 10, "gradient", start));
@@ -1370,12 +1437,68 @@ int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = 
     return PROP_OK;
 }
 
-int tti_forward(prop_s *h, const prop_shot *s, float *rec_out)
+int tti_gradient_group(prop_s *h, Group &G, int n_ckpt, int dtype, bool image = false, bool grow_only = false)
+{
+    GradPlan P;
+    TRY(tti_grad_setup(h, G, n_ckpt, dtype, image, grow_only, P));
+    TRY(tti_grad_forward(h, G, P));
+    return tti_grad_reverse(h, G, P);
+}
+
+// Checkpoints left by a saving prop_forward: valid for the shot and model they were made with.
+bool saved_matches(const prop_s *h, const prop_shot *s, int n_ckpt, int dtype)
+{
+    const auto &sv = h->saved;
+    if (!sv.valid || !s) return false;
+    if (n_ckpt != 0 && (n_ckpt != sv.n_ckpt || dtype != sv.dtype)) return false;
+    int64_t o[3], n[3];
+    if (shot_window(h, s, o, n) != PROP_OK) {
+        g_err.clear();
+        return false;
+    }
+    for (int a = 0; a < 3; ++a)
+        if (o[a] != sv.o[a] || n[a] != sv.n[a]) return false;
+    if (s->nsrc != sv.nsrc || s->src_wavelet != sv.wav) return false;
+    const size_t nv = (size_t)std::max(0, s->nsrc) * h->g.ndim;
+    return nv == sv.src.size() && (nv == 0 || std::memcmp(s->src_xyz, sv.src.data(), nv * sizeof(float)) == 0);
+}
+
+void record_saved(prop_s *h, const prop_shot *s, int n_ckpt, int dtype)
+{
+    auto &sv = h->saved;
+    int64_t o[3], n[3];
+    if (shot_window(h, s, o, n) != PROP_OK) {
+        sv.valid = false;
+        return;
+    }
+    for (int a = 0; a < 3; ++a) sv.o[a] = o[a], sv.n[a] = n[a];
+    sv.nsrc = s->nsrc;
+    sv.wav = s->src_wavelet;
+    const size_t nv = (size_t)std::max(0, s->nsrc) * h->g.ndim;
+    sv.src.assign(s->src_xyz, s->src_xyz + nv);
+    sv.n_ckpt = n_ckpt;
+    sv.dtype = dtype;
+    sv.valid = true;
+}
+
+int tti_forward(prop_s *h, const prop_shot *s, float *rec_out, int save, int dtype)
 {
     Group G;
     float *outs[1] = {rec_out};
+    if (save == 0) {
+        TRY(build_group(h, G, {s}, {&h->slot}, true, true, false, false, nullptr, outs, nullptr));
+        TRY(tti_forward_group(h, G));
+        h->last_state = 1;
+        return PROP_OK;
+    }
+    if (save < 0) return fail(PROP_EINVAL, "save_ckpt must be >= 0");
+    if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
+    h->saved.valid = false;
     TRY(build_group(h, G, {s}, {&h->slot}, true, true, false, false, nullptr, outs, nullptr));
-    TRY(tti_forward_group(h, G));
+    GradPlan P;
+    TRY(tti_grad_setup(h, G, save, dtype, false, false, P));
+    TRY(tti_grad_forward(h, G, P));
+    record_saved(h, s, save, dtype);
     h->last_state = 1;
     return PROP_OK;
 }
@@ -1394,13 +1517,26 @@ int tti_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_o
 int tti_gradient(prop_s *h, const prop_shot *s, const float *residual, float *grad_m, int n_ckpt, int dtype,
                  bool image = false)
 {
-    if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
+    if (n_ckpt < 0) return fail(PROP_EINVAL, "n_ckpt must be >= 0");
     if (dtype < 0 || dtype > 2) return fail(PROP_EINVAL, "unknown checkpoint dtype");
     if (!grad_m) return fail(PROP_EINVAL, image ? "image is NULL" : "grad_m is NULL");
+    const bool reuse = saved_matches(h, s, n_ckpt, dtype);
+    if (n_ckpt == 0 && !reuse)
+        return fail(PROP_ESTATE, "no valid checkpoints of this shot on the handle (none saved by prop_forward, "
+                                 "or invalidated since)");
+    if (reuse) {
+        n_ckpt = h->saved.n_ckpt;
+        dtype = h->saved.dtype;
+    } else {
+        h->saved.valid = false;   // this call stores checkpoints of its own
+    }
     Group G;
     const float *ins[1] = {residual};
     TRY(build_group(h, G, {s}, {&h->slot}, true, false, true, false, ins, nullptr, nullptr));
-    TRY(tti_gradient_group(h, G, n_ckpt, dtype, image));
+    GradPlan P;
+    TRY(tti_grad_setup(h, G, n_ckpt, dtype, image, false, P));
+    if (!reuse) TRY(tti_grad_forward(h, G, P));
+    TRY(tti_grad_reverse(h, G, P));
     aux_copy_out(h->slot.f[10], h->slot.w, grad_m, h->st);
     HIPCHK(hipGetLastError());
     h->last_state = 0;
@@ -1464,6 +1600,7 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
     TRY(plan_groups(h, nshot, shots, grad, n_ckpt, dtype, groups));
     h->last_groups = (int)groups.size();
     if (grad) {   // the planner counted these as reusable: give them back before the groups grow them
+        h->saved.valid = false;
         h->ckpt.release();
         h->ckscale.release();
         h->seg.release();
@@ -1521,27 +1658,42 @@ void el_remix(prop_s *h, Slot &sl)
                  sl.f[5], sl.f[9], sl.f[10], sl.f[11], h->st);
 }
 
-int el_forward(prop_s *h, const prop_shot *s, float *rec_out)
+int el_forward(prop_s *h, const prop_shot *s, float *rec_out, int save, int dtype)
 {
+    if (save < 0) return fail(PROP_EINVAL, "save_ckpt must be >= 0");
+    if (save > 0 && dtype != PROP_CKPT_F32) return fail(PROP_EINVAL, "elastic checkpoints are FP32");
     Slot &sl = h->slot;
     TRY(prepare_shot(h, sl, s, true, true, false, false));
     if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
     if (s->nrec > 0 && !rec_out) return fail(PROP_EINVAL, "rec_out is NULL");
+    // a saving run keeps the state after steps j S (j = 1 .. C-1), the checkpoints of el_gradient
+    const int N = h->g.nt;
+    const int S = save > 0 ? (N + save - 1) / save : N + 1;
+    const int C = save > 0 ? (N + S - 1) / S : 1;
+    const size_t P = sl.plane;
+    if (save > 0) {
+        h->saved.valid = false;
+        TRY(h->ckpt.fit(std::max<size_t>((size_t)(C - 1) * 9 * P * sizeof(float), 16)));
+    }
     aux_fill(sl.f[0], 9 * sl.plane, 0.f, h->st);
     const ElJob *job = sl.job_fwd.as<ElJob>();
     const float dt = (float)h->g.dt;
-    for (int n = 0; n < h->g.nt; ++n) {
+    for (int n = 0; n < N; ++n) {
         el_step_fwd(h, sl, job);
         if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, sl.f[3], tyy_of(h, sl),
                                    sl.f[5], h->st);
         float *row = s->nrec ? rec_out + (size_t)n * s->nrec : nullptr;
         if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], 1.f, row, h->st);
         if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, sl.f[2], nullptr, nullptr, 1.f, row, h->st);
-        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == h->g.nt) {
+        if (save > 0 && (n + 1) % S == 0 && (n + 1) / S < C)
+            HIPCHK(hipMemcpyAsync(h->ckpt.as<float>() + (size_t)((n + 1) / S - 1) * 9 * P, sl.f[0],
+                                  9 * P * sizeof(float), hipMemcpyDeviceToDevice, h->st));
+        if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
             HIPCHK(hipGetLastError());
             TRY(check_finite(h, sl.f[5], sl.w));
         }
     }
+    if (save > 0) record_saved(h, s, save, dtype);
     h->last_state = 1;
     return PROP_OK;
 }
@@ -1585,9 +1737,15 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
 // transposed velocity and stress updates.  out: three dense window fields (vp, vs, rho).
 int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out, int n_ckpt, int dtype)
 {
-    if (n_ckpt < 1) return fail(PROP_EINVAL, "n_ckpt must be >= 1");
-    if (dtype != PROP_CKPT_F32) return fail(PROP_EINVAL, "elastic gradients keep FP32 checkpoints");
+    if (n_ckpt < 0) return fail(PROP_EINVAL, "n_ckpt must be >= 0");
+    if (n_ckpt > 0 && dtype != PROP_CKPT_F32) return fail(PROP_EINVAL, "elastic gradients keep FP32 checkpoints");
     if (!out) return fail(PROP_EINVAL, "grad_m is NULL");
+    const bool reuse = saved_matches(h, s, n_ckpt, dtype);
+    if (n_ckpt == 0 && !reuse)
+        return fail(PROP_ESTATE, "no valid checkpoints of this shot on the handle (none saved by prop_forward, "
+                                 "or invalidated since)");
+    if (reuse) n_ckpt = h->saved.n_ckpt;
+    else h->saved.valid = false;   // this call stores checkpoints of its own
     Slot &sl = h->slot;
     TRY(prepare_shot(h, sl, s, true, false, true, false));
     if (s->nsrc > 0 && !s->src_wavelet) return fail(PROP_EINVAL, "src_wavelet is NULL");
@@ -1639,9 +1797,9 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
         HIPCHK(hipMemcpyAsync(dst, src, nflt * sizeof(float), hipMemcpyDeviceToDevice, h->st));
         return PROP_OK;
     };
-    // 1) forward with checkpoints (state after step jS, j >= 1)
+    // 1) forward with checkpoints (state after step jS, j >= 1), unless a saving forward left them
     aux_fill(fw, 9 * P, 0.f, h->st);
-    for (int n = 0; n < (C > 1 ? N : 0); ++n) {
+    for (int n = 0; n < (C > 1 && !reuse ? N : 0); ++n) {
         fwd_step(n);
         if ((n + 1) % S == 0 && (n + 1) / S < C) TRY(copy(ck + (size_t)((n + 1) / S - 1) * 9 * P, fw, 9 * P));
         if ((n + 1) % WATCH_EVERY == 0) {
@@ -1753,11 +1911,12 @@ int prop_set_model(prop_t h, const prop_model *model)
     return prep_model(h, model);
 }
 
-int prop_forward(prop_t h, const prop_shot *shot, float *rec_out)
+int prop_forward(prop_t h, const prop_shot *shot, float *rec_out, int32_t save_ckpt, prop_ckpt_dtype ckpt_dtype)
 {
     g_err.clear();
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
-    return h->kind == PROP_TTI ? tti_forward(h, shot, rec_out) : el_forward(h, shot, rec_out);
+    return h->kind == PROP_TTI ? tti_forward(h, shot, rec_out, save_ckpt, (int)ckpt_dtype)
+                               : el_forward(h, shot, rec_out, save_ckpt, (int)ckpt_dtype);
 }
 
 int prop_adjoint(prop_t h, const prop_shot *shot, const float *rec_in, float *src_out)
@@ -1875,8 +2034,12 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
         h->opt_batch_mb = value;
         return PROP_OK;
     case PROP_OPT_SCHEME:
-        if (value != TTI_SIX && value != TTI_SCALAR && value != TTI_FUSED && value != TTI_FOUR)
-            return fail(PROP_EINVAL, "scheme must be 0, 1, 2 or 3");
+        if (value != TTI_SIX && value != TTI_SCALAR && value != TTI_FUSED && value != TTI_FOUR && value != TTI_SPLIT)
+            return fail(PROP_EINVAL, "scheme must be 0, 1, 2, 3 or 4");
+        if (value == TTI_SPLIT && h->R > tti_split_max_radius())
+            return fail(PROP_EINVAL, "the split scheme supports space orders up to %d", 2 * tti_split_max_radius());
+        if (value == TTI_SPLIT && !fused_fits(h->g))
+            return fail(PROP_EINVAL, "the split scheme needs x-y planes below 4 GiB");
         if (value == TTI_FUSED && h->R > tti_fused_max_radius())
             return fail(PROP_EINVAL, "the fused scheme supports space orders up to %d", 2 * tti_fused_max_radius());
         if (value == TTI_FUSED && !fused_fits(h->g))
@@ -1921,8 +2084,12 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
     TRY(fold_timing(h));
     if (ms) *ms = h->ms[kclass];
     if (launches) *launches = h->launches[kclass];
-    if (name) *name = (kclass == 1 && h->kind == PROP_TTI && h->opt_scheme == TTI_FUSED) ? "tti_fused (single pass)"
-                                                                                        : names[kclass];
+    if (name) {
+        *name = names[kclass];
+        if (h->kind == PROP_TTI && h->opt_scheme == TTI_FUSED && kclass == 1) *name = "tti_fused (single pass)";
+        if (h->kind == PROP_TTI && h->opt_scheme == TTI_SPLIT)
+            *name = kclass == 0 ? "tti_split A (H0 u)" : kclass == 1 ? "tti_split B (Hz v + update)" : names[kclass];
+    }
     return PROP_OK;
 }
 
@@ -1961,6 +2128,54 @@ int prop_ckpt_decode(const void *codes, const float *scale_dev, int64_t n, prop_
     }
     if (dtype != PROP_CKPT_F16 && dtype != PROP_CKPT_BF16) return fail(PROP_EINVAL, "unknown dtype");
     aux_decode((const uint16_t *)codes, scale_dev, n, (int)dtype, f, st);
+    HIPCHK(hipGetLastError());
+    return PROP_OK;
+}
+
+// A dense (nz, ny, nx) array seen as a window (row pitch nx) for the row-codec kernels.
+static int dense_win(int64_t nx, int64_t ny, int64_t nz, Win &w)
+{
+    if (nx < 1 || nx > 2147483647 || ny < 1 || ny > 65535 || nz < 1 || nz > 65535)
+        return fail(PROP_EINVAL, "row codec needs 1 <= nx < 2^31 and 1 <= ny, nz <= 65535");
+    w = Win{};
+    w.nx = (int)nx;
+    w.ny = (int)ny;
+    w.nz = (int)nz;
+    w.sx = nx;
+    w.sy = nx * ny;
+    w.mx = nx;
+    w.my = nx * ny;
+    w.moff = 0;
+    return PROP_OK;
+}
+
+int prop_ckpt_encode_rows(const float *cur, const float *prev, int64_t nx, int64_t ny, int64_t nz, int32_t pair,
+                          prop_ckpt_dtype dtype, uint16_t *codes_a, uint16_t *codes_b, float *scale_a, float *scale_b,
+                          void *stream)
+{
+    g_err.clear();
+    if (!cur || !prev || !codes_a || !codes_b || !scale_a || !scale_b) return fail(PROP_EINVAL, "NULL row-codec argument");
+    if (dtype != PROP_CKPT_F16 && dtype != PROP_CKPT_BF16) return fail(PROP_EINVAL, "row codecs are FP16 or BF16");
+    if (pair != 0 && pair != 1) return fail(PROP_EINVAL, "pair must be 0 or 1");
+    Win w;
+    TRY(dense_win(nx, ny, nz, w));
+    hipStream_t st = (hipStream_t)stream;
+    if (pair) aux_ckpt_pair_encode(cur, prev, w, (int)dtype, codes_a, codes_b, scale_a, scale_b, st);
+    else aux_encode_rows2(cur, prev, w, (int)dtype, codes_a, codes_b, scale_a, scale_b, st);
+    HIPCHK(hipGetLastError());
+    return PROP_OK;
+}
+
+int prop_ckpt_decode_rows(const uint16_t *codes_a, const uint16_t *codes_b, const float *scale_a, const float *scale_b,
+                          int64_t nx, int64_t ny, int64_t nz, prop_ckpt_dtype dtype, float *cur, float *prev,
+                          void *stream)
+{
+    g_err.clear();
+    if (!cur || !prev || !codes_a || !codes_b || !scale_a || !scale_b) return fail(PROP_EINVAL, "NULL row-codec argument");
+    if (dtype != PROP_CKPT_F16 && dtype != PROP_CKPT_BF16) return fail(PROP_EINVAL, "row codecs are FP16 or BF16");
+    Win w;
+    TRY(dense_win(nx, ny, nz, w));
+    aux_ckpt_pair_decode(codes_a, codes_b, scale_a, scale_b, w, (int)dtype, cur, prev, (hipStream_t)stream);
     HIPCHK(hipGetLastError());
     return PROP_OK;
 }

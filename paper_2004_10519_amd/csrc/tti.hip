@@ -739,7 +739,7 @@ void p2_dispatch(int scheme, int shape, int mode, const TTIJob *jobs, const Tile
 
 int tti_tile_rows(int R, int scheme, int pass, int shape)
 {
-    if (scheme == TTI_FUSED) return 16;
+    if (scheme == TTI_FUSED || scheme == TTI_SPLIT) return 16;
     const int by = shape == 1 ? 16 : 8;
     return pass == 1 ? by * (R <= 6 ? 2 : 1) : by;
 }
@@ -760,6 +760,8 @@ void launch_tti_pass1(int R, int scheme, int shape, bool adj, const TTIJob *jobs
                       int zc, int par, const Weights &W, hipStream_t st)
 {
     if (scheme == TTI_FUSED) return;
+    if (scheme == TTI_SPLIT)
+        return launch_tti_split(R, 0, adj ? K2_ADJ : K2_FWD, jobs, tiles, ntiles, zc, par, W, 0.f, 0, st);
     R_SWITCH(p1_dispatch, scheme, shape, adj, jobs, tiles, ntiles, zc, par, W, st)
 }
 
@@ -767,5 +769,6 @@ void launch_tti_pass2(int R, int scheme, int shape, int mode, const TTIJob *jobs
                       int zc, int par, const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
     if (scheme == TTI_FUSED) return launch_tti_fused(R, shape, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
+    if (scheme == TTI_SPLIT) return launch_tti_split(R, 1, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     R_SWITCH(p2_dispatch, scheme, shape, mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st)
 }

@@ -23,7 +23,7 @@ CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTS = ["prop_create", "prop_cfl_dt", "prop_set_model", "prop_forward", "prop_adjoint", "prop_gradient",
            "prop_image", "prop_forward_batched", "prop_gradient_batched", "prop_image_batched", "prop_read_state", "prop_set_timing",
            "prop_kernel_time", "prop_set_option", "prop_get_option", "prop_ckpt_encode", "prop_ckpt_decode",
-           "prop_dot_f64", "prop_destroy", "prop_last_error"]
+           "prop_ckpt_encode_rows", "prop_ckpt_decode_rows", "prop_dot_f64", "prop_destroy", "prop_last_error"]
 
 # option / info codes of prop_set_option and prop_get_option
 OPTIONS = {"graph": 1, "autotune": 2, "tile1": 3, "tile2": 4, "zc": 5, "xcd": 6, "batch_mb": 7, "scheme": 8, "zc2": 9,
@@ -69,7 +69,7 @@ def lib() -> ctypes.CDLL:
         L.prop_cfl_dt.argtypes = [i32, ctypes.POINTER(CGrid), dbl, dbl]
         L.prop_cfl_dt.restype = dbl
         L.prop_set_model.argtypes = [vp, ctypes.POINTER(CModel)]
-        L.prop_forward.argtypes = [vp, ctypes.POINTER(CShot), vp]
+        L.prop_forward.argtypes = [vp, ctypes.POINTER(CShot), vp, i32, i32]
         L.prop_adjoint.argtypes = [vp, ctypes.POINTER(CShot), vp, vp]
         L.prop_gradient.argtypes = [vp, ctypes.POINTER(CShot), vp, vp, i32, i32]
         L.prop_image.argtypes = [vp, ctypes.POINTER(CShot), vp, vp, i32, i32]
@@ -84,6 +84,8 @@ def lib() -> ctypes.CDLL:
         L.prop_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.prop_ckpt_encode.argtypes = [vp, i64, i32, vp, vp, vp]
         L.prop_ckpt_decode.argtypes = [vp, vp, i64, i32, vp, vp]
+        L.prop_ckpt_encode_rows.argtypes = [vp, vp, i64, i64, i64, i32, i32, vp, vp, vp, vp, vp]
+        L.prop_ckpt_decode_rows.argtypes = [vp, vp, vp, vp, i64, i64, i64, i32, vp, vp, vp]
         L.prop_dot_f64.argtypes = [vp, vp, i64, ctypes.POINTER(dbl), vp]
         L.prop_destroy.argtypes = [vp]
         L.prop_last_error.restype = ctypes.c_char_p
@@ -219,12 +221,17 @@ class Propagator:
             return (nz, ny, nx)
         return self.grid.arr_shape
 
-    def forward(self, shot: Shot, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    def forward(self, shot: Shot, out: Optional[torch.Tensor] = None, save_ckpt: int = 0,
+                ckpt_dtype: str = "f16") -> torch.Tensor:
+        """Traces of one shot.  save_ckpt = n >= 1 also keeps the checkpoints that gradient / image with
+        n_ckpt = n and this ckpt_dtype use, so that they skip their forward sweep (n_ckpt = 0 there
+        asks for that reuse)."""
         nt = self.grid.nt
         if out is None:
             out = torch.empty((nt, shot.nrec), dtype=torch.float32, device="cuda")
         cs = shot.c()
-        _check(lib().prop_forward(self._h, ctypes.byref(cs), _dev(out) if shot.nrec else None))
+        _check(lib().prop_forward(self._h, ctypes.byref(cs), _dev(out) if shot.nrec else None, int(save_ckpt),
+                                  CKPT[ckpt_dtype]))
         return out
 
     def adjoint(self, shot: Shot, rec: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -235,7 +242,7 @@ class Propagator:
                                   _dev(out) if shot.nsrc else None))
         return out
 
-    def gradient(self, shot: Shot, residual: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "bf16",
+    def gradient(self, shot: Shot, residual: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "f16",
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
         if out is None:   # elastic: the gradients with respect to vp, vs and rho, stacked
             shp = self._win_shape(shot)
@@ -245,7 +252,7 @@ class Propagator:
                                    int(n_ckpt), CKPT[ckpt_dtype]))
         return out
 
-    def image(self, shot: Shot, rec_in: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "bf16",
+    def image(self, shot: Shot, rec_in: torch.Tensor, n_ckpt: int = 48, ckpt_dtype: str = "f16",
               out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """Zero-lag cross-correlation image sum_k sum_f f^k y_f^k of one shot (y driven by rec_in)."""
         if out is None:
@@ -337,21 +344,66 @@ def ckpt_decode(codes: torch.Tensor, scale: torch.Tensor, dtype: str, stream=Non
     return f
 
 
+def ckpt_encode_rows(a: torch.Tensor, b: torch.Tensor, pair: bool, dtype: str, stream=None):
+    """Row codec of the gradient's stores on dense (nz, ny, nx) fields: pair = True codes a and a - b
+    (a checkpoint pair), pair = False codes a and b independently.  Returns (codes_a, codes_b, scales_a,
+    scales_b): int16 bit patterns (nz, ny, nx) and FP32 scales (nz, ny), one per x-row."""
+    nz, ny, nx = a.shape
+    ca = torch.empty(a.shape, dtype=torch.int16, device="cuda")
+    cb = torch.empty(a.shape, dtype=torch.int16, device="cuda")
+    sa = torch.empty((nz, ny), dtype=torch.float32, device="cuda")
+    sb = torch.empty((nz, ny), dtype=torch.float32, device="cuda")
+    _check(lib().prop_ckpt_encode_rows(_dev(a), _dev(b), nx, ny, nz, int(bool(pair)), CKPT[dtype], ca.data_ptr(),
+                                       cb.data_ptr(), sa.data_ptr(), sb.data_ptr(), _stream(stream)))
+    return ca, cb, sa, sb
+
+
+def ckpt_decode_rows(ca: torch.Tensor, cb: torch.Tensor, sa: torch.Tensor, sb: torch.Tensor, dtype: str, stream=None):
+    """Inverse of the pair codec: (cur, prev) with cur = s_a a, prev = cur - s_b b."""
+    nz, ny, nx = ca.shape
+    cur = torch.empty(ca.shape, dtype=torch.float32, device="cuda")
+    prev = torch.empty(ca.shape, dtype=torch.float32, device="cuda")
+    _check(lib().prop_ckpt_decode_rows(ca.data_ptr(), cb.data_ptr(), sa.data_ptr(), sb.data_ptr(), nx, ny, nz,
+                                       CKPT[dtype], cur.data_ptr(), prev.data_ptr(), _stream(stream)))
+    return cur, prev
+
+
 class TTIModelling(torch.autograd.Function):
     """d = F(m) for one shot; backward gives grad_m = (dF/dm)^T grad_d through prop_gradient
-    (checkpointed forward recomputation + adjoint + imaging condition)."""
+    (checkpointed forward recomputation + adjoint + imaging condition).
+
+    The forward run keeps its checkpoints (save_ckpt = n_ckpt), so the backward pass reuses them and
+    skips a forward sweep, unless the handle's model or checkpoints changed in between (then it runs
+    the full checkpointed gradient).  m is the whole-grid model; the gradient of a shot on a window is
+    zero outside that window."""
 
     @staticmethod
     def forward(ctx, m, prop: Propagator, aniso: Sequence[torch.Tensor], shot: Shot, n_ckpt: int = 48,
-                ckpt_dtype: str = "bf16"):
-        prop.set_model([m] + list(aniso))
+                ckpt_dtype: str = "f16"):
+        model = [m] + list(aniso)
+        prop.set_model(model)
         ctx.prop, ctx.shot, ctx.n_ckpt, ctx.ckpt_dtype = prop, shot, n_ckpt, ckpt_dtype
-        ctx.model = [m] + list(aniso)
-        return prop.forward(shot)
+        ctx.model = prop._model
+        ctx.m_shape = m.shape
+        return prop.forward(shot, save_ckpt=n_ckpt, ckpt_dtype=ckpt_dtype)
 
     @staticmethod
     def backward(ctx, grad_d):
-        prop = ctx.prop
-        prop.set_model(ctx.model)
-        g = prop.gradient(ctx.shot, grad_d.contiguous(), ctx.n_ckpt, ctx.ckpt_dtype)
+        prop, shot = ctx.prop, ctx.shot
+        res = grad_d.contiguous()
+        g = None
+        if prop._model is ctx.model:
+            try:
+                g = prop.gradient(shot, res, 0)   # the forward run's checkpoints
+            except PropError as e:
+                if e.code != PROP_ESTATE:
+                    raise
+        if g is None:
+            prop.set_model(ctx.model)
+            g = prop.gradient(shot, res, ctx.n_ckpt, ctx.ckpt_dtype)
+        if any(shot.win_shape):
+            (ox, oy, oz), (nx, ny, nz) = shot.win_origin, shot.win_shape
+            full = torch.zeros(ctx.m_shape, dtype=g.dtype, device=g.device)
+            full[oz:oz + nz, oy:oy + ny, ox:ox + nx] = g
+            g = full
         return g, None, None, None, None, None

@@ -1,0 +1,90 @@
+"""Write the full-length parity goldens at 128^3 (the benchmark recipes at a size the checker finishes):
+
+  tti128_so12.npz  3D TTI, 128^3, 12.5 m, space order 12, 40-point absorbing layers, 3000 steps of
+                   1.0 ms, the seed-1 layered TTI model, 15 Hz Ricker 4.5 points below the layer,
+                   16 x 16 receivers 2 points below it (the tti3d_512 recipe on 128^3);
+  el128_so8.npz    3D elastic, 128^3, 10 m, space order 8, 40-point absorbing layers, 2000 steps of
+                   0.76 ms, the seed-2 layered elastic model with its water layer, 12 Hz explosive
+                   source 10 points below the layer, 16 x 16 pressure and 16 x 16 vz receivers
+                   2 points below it (the el3d_400 recipe on 128^3).
+
+Each file keeps every 4th trace sample of every receiver and the final wavefields on the central
+x-z, y-z and x-y planes.  Calls only oracle/ and the seeded input generators.
+Run: python tests/golden/make_parity128.py [tti|elastic]   (minutes per case on 8 cores)
+"""
+import dataclasses
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2004_10519_amd import configs, inputs  # noqa: E402
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TSUB = 4
+
+
+def tti_case():
+    w = configs.tti3d_512(nt=3000, n=128)
+    rec = inputs.surface_receivers(w.shape, w.spacing, (0, 0, 0), w.nbl, w.nbl + 2, 16, 16)
+    return dataclasses.replace(w, rec_xyz=rec)
+
+
+def elastic_case():
+    w = configs.el3d_400(nt=2000, n=128)
+    r = inputs.surface_receivers(w.shape, w.spacing, (0, 0, 0), w.nbl, w.nbl + 2, 16, 16)
+    kind = np.concatenate([np.zeros(len(r), np.int32), np.ones(len(r), np.int32)])
+    return dataclasses.replace(w, rec_xyz=np.concatenate([r, r], axis=0), rec_kind=kind)
+
+
+def planes(f):
+    nz, ny, nx = f.shape
+    return {"xz": f[:, ny // 2, :], "yz": f[:, :, nx // 2], "xy": f[nz // 2, :, :]}
+
+
+def grid(w):
+    return oracle.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, vref=w.v_ref)
+
+
+def make_tti():
+    w = tti_case()
+    g = grid(w)
+    mod = oracle.TTIModel.from_arrays(g, *w.model_list())
+    t0 = time.time()
+    d, (p, q, _, _), _ = oracle.tti_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz,
+                                            callback=lambda n, p, q: (n % 250 == 0) and print(f"tti step {n}", flush=True))
+    out = {"traces": d[::TSUB].astype(np.float32), "tsub": TSUB, "nt": w.nt}
+    for name, f in (("p", p), ("q", q)):
+        for k, v in planes(f).items():
+            out[f"{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
+    np.savez_compressed(os.path.join(HERE, "tti128_so12.npz"), **out)
+    print(f"tti128_so12.npz written ({time.time() - t0:.0f} s), max |d| = {np.abs(d).max():.3e}")
+
+
+def make_elastic():
+    w = elastic_case()
+    g = grid(w)
+    vp, vs, rho = w.model_list()
+    mod = oracle.ElasticModel.from_velocities(g, vp, vs, rho)
+    t0 = time.time()
+    d, fields = oracle.elastic_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz, w.rec_kind,
+                                       callback=lambda n, f: (n % 250 == 0) and print(f"elastic step {n}", flush=True))
+    out = {"traces": d[::TSUB].astype(np.float32), "tsub": TSUB, "nt": w.nt}
+    for i, name in enumerate(("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")):
+        for k, v in planes(fields[i]).items():
+            out[f"{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
+    np.savez_compressed(os.path.join(HERE, "el128_so8.npz"), **out)
+    print(f"el128_so8.npz written ({time.time() - t0:.0f} s), max |d| = {np.abs(d).max():.3e}")
+
+
+if __name__ == "__main__":
+    which = sys.argv[1:] or ["tti", "elastic"]
+    if "tti" in which:
+        make_tti()
+    if "elastic" in which:
+        make_elastic()

@@ -1,5 +1,6 @@
-"""Batched shots (shot groups on uneven windows of one model) against plain per-shot calls, and the
-64^3 gradient against the FP64 checker's stored gradient (full 2000 steps)."""
+"""Batched shots (shot groups on uneven windows of one model) against plain per-shot calls and against
+the FP64 checker's per-window results summed in FP64, and the 64^3 gradient against the FP64
+checker's stored gradient (full 2000 steps)."""
 import os
 
 import numpy as np
@@ -31,6 +32,7 @@ def _setup(prop, nt=120, scheme=None):
     mt = [dev(a) for a in arrs]
     p = prop.Propagator(prop.TTI, g, mt)
     p._keep_model = mt
+    p._host_model = [np.asarray(a, np.float64) for a in arrs]
     if scheme is not None:
         p.set_option("scheme", scheme)
     wins = [((3, 5, 0), (70, 41, 50)), ((20, 0, 4), (80, 77, 56)), ((0, 30, 0), (37, 50, 60))]
@@ -142,7 +144,11 @@ def test_graph_runs_span_watchdog_checks(prop):
         p.set_option("info_groups", 1)
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 1e-2)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3),
+                                       pytest.param("bf16", 1e-3, marks=pytest.mark.xfail(
+                                           strict=True, reason="BF16 keeps 8 mantissa bits (relative rounding "
+                                                               "2^-9 per checkpoint value): measured 2.0e-3")),
+                                       ("bf16", 2.5e-3)], ids=["f32", "f16", "bf16-bar", "bf16-regression"])
 def test_gradient_64cubed_vs_checker(prop, dtype, tol):
     """64^3, so 8, 2000 steps, 48 checkpoints: GPU gradient vs the FP64 checker's stored gradient."""
     import importlib.util
@@ -178,3 +184,51 @@ def test_batched_image_equals_plain_sum(prop):
     p.image_batched(shots, data, gi, n_ckpt=4, ckpt_dtype="f16")
     assert np.array_equal(host(gi), total)
     assert np.abs(total).max() > 0
+
+
+def _oracle_window(orc, p, s, arrs, nbl=6):
+    """The checker's grid and model on a shot's window (absolute coordinates: origin at the window's
+    first node)."""
+    (ox, oy, oz), (nx, ny, nz) = s.win_origin, s.win_shape
+    h = p.grid.spacing
+    g = orc.Grid((nx, ny, nz), h, origin=(ox * h[0], oy * h[1], oz * h[2]), space_order=p.grid.space_order,
+                 nbl=nbl, dt=p.grid.dt, nt=p.grid.nt, vref=p.grid.v_ref)
+    sl = (slice(oz, oz + nz), slice(oy, oy + ny), slice(ox, ox + nx))
+    return g, orc.TTIModel.from_arrays(g, *(a[sl] for a in arrs)), sl
+
+
+@pytest.fixture(scope="module")
+def batched_checker(prop, orc):
+    """The FP64 checker's gradient and image of the three windowed shots (100 steps), each shot on its
+    own window, summed over the shots in FP64; with the residuals that drive them."""
+    p, shots = _setup(prop, nt=100)
+    arrs = p._host_model
+    rng = np.random.default_rng(71)
+    res = [rng.standard_normal((100, s.nrec)).astype(np.float32) for s in shots]
+    go = np.zeros(p.grid.arr_shape)
+    io = np.zeros(p.grid.arr_shape)
+    for s, r in zip(shots, res):
+        g, mod, sl = _oracle_window(orc, p, s, arrs)
+        wav = host(s.wavelet).astype(np.float64)
+        # the checker takes observed data: d_obs = d - r gives the residual d - d_obs = r
+        d, _, _ = orc.tti_forward(g, mod, s.src_xyz, wav, s.rec_xyz)
+        _, gw, _ = orc.tti_gradient(g, mod, s.src_xyz, wav, s.rec_xyz, d - r)
+        go[sl] += gw
+        io[sl] += orc.tti_image(g, mod, s.src_xyz, wav, s.rec_xyz, r)
+    p.close()
+    return res, go, io
+
+
+@pytest.mark.parametrize("dtype,n_ckpt,tol", [("f32", 5, 1e-4), ("f16", 5, 1e-3), ("f16", 1, 1e-3)])
+def test_batched_gradient_and_image_vs_checker(prop, batched_checker, dtype, n_ckpt, tol):
+    """Batched FP64 gradient and image of the three windowed shots against the FP64 checker's per-window
+    gradients and images summed in FP64."""
+    res, go, io = batched_checker
+    p, shots = _setup(prop, nt=100)
+    gg = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.gradient_batched(shots, [dev(r) for r in res], gg, n_ckpt=n_ckpt, ckpt_dtype=dtype)
+    gi = torch.zeros(p.grid.arr_shape, dtype=torch.float64, device="cuda")
+    p.image_batched(shots, [dev(r) for r in res], gi, n_ckpt=n_ckpt, ckpt_dtype=dtype)
+    eg, ei = rel_l2(host(gg), go), rel_l2(host(gi), io)
+    print(f"batched vs FP64 checker ({dtype}, n_ckpt {n_ckpt}): gradient {eg:.2e}, image {ei:.2e}")
+    assert eg <= tol and ei <= tol, (eg, ei)

@@ -9,7 +9,8 @@
   and traces must match the checker there and be exactly zero everywhere else.
 * 512^3 so12 TTI dot test over 20 steps and 65536 receivers.
 * 256^3 so8 gradient (2000 steps; 48 FP16 checkpoints, or the whole run stored in FP16): central
-  finite difference of the FP64 misfit along a smooth model perturbation.
+  finite differences of the FP64 misfit and the Taylor remainder's slope along five seeded smooth
+  model perturbations.
 * 2D marine elastic workload (1701 x 391, free surface over the water layer): the first 800 steps,
   all 3242 traces, against the checker on the whole grid.
 """
@@ -148,10 +149,13 @@ def test_tti512_so12_dot_test(prop, tti512_model):
     assert abs(a - b) / abs(a) < 1e-5, (a, b)
 
 
-@pytest.mark.parametrize("n_ckpt", [48, 1])
-def test_ttigrad256_finite_difference(prop, n_ckpt):
-    """<g, dm> against (J(m + h dm) - J(m - h dm)) / 2h, J = 1/2 ||F(m) s - d_obs||^2 in FP64; FP16
-    storage: 48 checkpoints, or the whole run (n_ckpt = 1, 134 GB)."""
+def test_ttigrad256_finite_differences_five_directions(prop):
+    """The 256^3 gradient workload (so 8, 2000 steps) against finite differences of the FP64 misfit
+    J = 1/2 ||F(m) s - d_obs||^2 along five seeded smooth directions (seeds 100-104: N(0,1) smoothed
+    with sigma 6, zero in the absorbing layers and above the receivers, max |dm| = 1e-2 max |m|), with
+    steps h in {1, 1/2, 1/4}; FP16 storage: 48 checkpoints, and the whole run (n_ckpt = 1, 134 GB).
+    Central differences: (J(m + h dm) - J(m - h dm)) / 2h -> <g, dm> with an O(h^2) error.  Taylor
+    remainder R(h) = |J(m + h dm) - J(m) - h <g, dm>| = O(h^2): slope log2(R(h) / R(h/2)) near 2."""
     from paper_2004_10519_amd import configs, inputs
     w = configs.ttigrad()
     true = w.model_list()
@@ -163,30 +167,49 @@ def test_ttigrad256_finite_difference(prop, n_ckpt):
     shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz)
     dobs = p.forward(shot).clone()
     base = [m0[k] for k in ("m", "eps", "delta", "theta", "phi")]
-    dm = inputs.random_unit_field(w.arr_shape, 100, 6.0).astype(np.float64)
-    dm[: w.nbl + 4] = 0.0                       # zero above the receivers and in the top layer
-    dm[-w.nbl:] = 0.0
-    dm[:, :w.nbl] = 0.0
-    dm[:, -w.nbl:] = 0.0
-    dm[:, :, :w.nbl] = 0.0
-    dm[:, :, -w.nbl:] = 0.0
-    dm *= 1e-2 * np.abs(base[0]).max() / np.abs(dm).max()
+    aniso = [dev(a) for a in base[1:]]
 
     def J(mm):
-        arrs = [dev(mm)] + [dev(a) for a in base[1:]]
+        arrs = [dev(mm)] + aniso
         p.set_model(arrs)
         r = (p.forward(shot) - dobs).contiguous()
         return 0.5 * prop.dot_f64(r, r), r, arrs
 
-    _, res, keep = J(base[0])
-    gr = host(p.gradient(shot, res, n_ckpt=n_ckpt, ckpt_dtype="f16")).astype(np.float64)
-    gd = float(np.vdot(gr, dm))
-    hh = 0.5
-    jp, _, _ = J((base[0] + hh * dm).astype(np.float32))
-    jm, _, _ = J((base[0] - hh * dm).astype(np.float32))
-    fd = (jp - jm) / (2 * hh)
-    print(f"256^3 gradient: <g, dm> = {gd:.6e}, central FD = {fd:.6e}, rel {abs(fd - gd) / abs(gd):.2e}")
-    assert abs(fd - gd) / abs(gd) < 2e-2
+    j0, res, keep = J(base[0])
+    grads = {n: host(p.gradient(shot, res, n_ckpt=n, ckpt_dtype="f16")).astype(np.float64) for n in (48, 1)}
+    rows = []
+    for seed in range(100, 105):
+        dm = inputs.random_unit_field(w.arr_shape, seed, 6.0).astype(np.float64)
+        dm[: w.nbl + 4] = 0.0                   # zero above the receivers and in the top layer
+        dm[-w.nbl:] = 0.0
+        dm[:, :w.nbl] = 0.0
+        dm[:, -w.nbl:] = 0.0
+        dm[:, :, :w.nbl] = 0.0
+        dm[:, :, -w.nbl:] = 0.0
+        dm *= 1e-2 * np.abs(base[0]).max() / np.abs(dm).max()
+        jp, jm = {}, {}
+        for hh in (1.0, 0.5, 0.25):
+            jp[hh] = J((base[0] + hh * dm).astype(np.float32))[0]
+            jm[hh] = J((base[0] - hh * dm).astype(np.float32))[0]
+        for n, gr in grads.items():
+            gd = float(np.vdot(gr, dm))
+            fd = {hh: (jp[hh] - jm[hh]) / (2 * hh) for hh in jp}
+            rem = {hh: abs(jp[hh] - j0 - hh * gd) for hh in jp}
+            slopes = [math.log2(rem[a] / rem[a / 2]) for a in (1.0, 0.5)]
+            rows.append((seed, n, gd, fd, slopes))
+    # a direction nearly orthogonal to the gradient has a directional derivative below the FP32
+    # noise of the misfit differences, so every error is taken against the scale of the directional
+    # derivatives (the largest |<g, dm>| of the five directions)
+    scale = max(abs(r[2]) for r in rows)
+    for seed, n, gd, fd, slopes in rows:
+        err = {hh: abs(v - gd) / scale for hh, v in fd.items()}
+        print(f"256^3 seed {seed} n_ckpt {n}: <g,dm> {gd:.6e}; central FD error / max|<g,dm>| "
+              + ", ".join(f"h={hh}: {e:.2e}" for hh, e in err.items())
+              + f"; Taylor slopes {slopes[0]:.2f}, {slopes[1]:.2f}")
+    for seed, n, gd, fd, slopes in rows:
+        err = {hh: abs(v - gd) / scale for hh, v in fd.items()}
+        assert min(err.values()) < 1e-3, (seed, n, err)
+        assert 1.8 < slopes[0] < 2.2 and 1.8 < slopes[1] < 2.2, (seed, n, slopes)
 
 
 def test_el2d_marine_free_surface_vs_checker(prop, orc):
@@ -217,3 +240,48 @@ def test_el2d_marine_free_surface_vs_checker(prop, orc):
         assert rel_l2(fields[i], fo[i]) <= 1e-4, i
     for c in (3, 5):
         assert not fields[c][:w.nbl].any()
+
+
+def _golden_module():
+    import importlib.util
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("mk128", os.path.join(here, "golden", "make_parity128.py"))
+    mk = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mk)
+    return mk, os.path.join(here, "golden")
+
+
+@pytest.mark.parametrize("kind", ["tti", "elastic"])
+def test_parity128_full_length_vs_checker(prop, kind):
+    """The benchmark recipes at 128^3 over their full lengths (TTI so12, 3000 steps; elastic so8, 2000
+    steps), in the benchmark's launch configuration (library default scheme, autotuned tiles), against
+    the FP64 checker's stored traces (every 4th sample of every receiver) and final wavefields on the
+    three central planes (tests/golden/make_parity128.py)."""
+    import os
+    mk, gdir = _golden_module()
+    w = mk.tti_case() if kind == "tti" else mk.elastic_case()
+    gold = np.load(os.path.join(gdir, "tti128_so12.npz" if kind == "tti" else "el128_so8.npz"))
+    m = w.make_model()
+    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
+    keys = ("m", "eps", "delta", "theta", "phi") if kind == "tti" else ("vp", "vs", "rho")
+    mt = [dev(m[k]) for k in keys]
+    p = prop.Propagator(prop.TTI if kind == "tti" else prop.ELASTIC, g, mt)
+    if kind == "tti":
+        p.set_option("autotune", 1)
+    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz, w.rec_kind)
+    d = host(p.forward(shot))[::int(gold["tsub"])]
+    err = rel_l2(d, gold["traces"])
+    names = ("p", "q") if kind == "tti" else ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
+    nz, ny, nx = g.arr_shape
+    errs = {}
+    for i, name in enumerate(names):
+        f = host(p.read_state(i))
+        for pl, v in (("xz", f[:, ny // 2, :]), ("yz", f[:, :, nx // 2]), ("xy", f[nz // 2, :, :])):
+            ref = gold[f"{name}_{pl}"]
+            if np.abs(ref).max() > 0:
+                errs[f"{name}_{pl}"] = rel_l2(v, ref)
+    print(f"{kind} 128^3 full length: traces rel-L2 {err:.2e}; fields max {max(errs.values()):.2e}")
+    assert err <= 1e-4, err
+    for k, e in errs.items():
+        assert e <= 1e-4, (k, e)

@@ -20,7 +20,12 @@ def prop():
     return P
 
 
-SCHEMES = [0, 1, 2, 3]   # two passes (six-field / scalar / four-field temporaries), one fused pass
+BF16_REASON = ("BF16 keeps 8 mantissa bits: a checkpoint level carries a relative rounding error of up to "
+               "2^-9, above the 1e-3 gradient bar (measured 4.7e-3 here, 2.0e-3 on the 64^3 case); FP16 meets it")
+
+
+# two passes (six-field / scalar / four-field temporaries), one fused pass, two fused single-field passes
+SCHEMES = [0, 1, 2, 3, 4]
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -100,7 +105,10 @@ def _bandlimited_residual(case, seed):
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3), ("bf16", 5e-3)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 1e-3),
+                                       pytest.param("bf16", 1e-3, marks=pytest.mark.xfail(strict=True,
+                                                                                          reason=BF16_REASON)),
+                                       ("bf16", 6e-3)], ids=["f32", "f16", "bf16-bar", "bf16-regression"])
 def test_tti_gradient_parity(prop, orc, dtype, tol, scheme):
     case = tti_case((40, 36, 32), 8, 5, 150, nrec=30)
     p, shot = make_tti(case, prop, scheme)
@@ -115,7 +123,10 @@ def test_tti_gradient_parity(prop, orc, dtype, tol, scheme):
     assert err <= tol, err
 
 
-@pytest.mark.parametrize("dtype,tol", [("f16", 1e-3), ("bf16", 1e-2)])
+@pytest.mark.parametrize("dtype,tol", [("f16", 1e-3),
+                                       pytest.param("bf16", 1e-3, marks=pytest.mark.xfail(strict=True,
+                                                                                          reason=BF16_REASON)),
+                                       ("bf16", 1.5e-3)], ids=["f16", "bf16-bar", "bf16-regression"])
 def test_tti_gradient_whole_run_16bit_storage(prop, orc, dtype, tol):
     """n_ckpt = 1 with a 16-bit type stores every forward level in FP16/BF16 (per-row scales) and
     runs two sweeps."""
@@ -354,3 +365,23 @@ def test_degenerate_shots(prop, orc, scheme):
     gt, mt = oracle_tti(thin, orc)
     dot_, _, _ = orc.tti_forward(gt, mt, thin["src"], thin["wav"], thin["rec"])
     assert np.abs(dot_).max() > 0 and rel_l2(dt_, dot_) <= 1e-4, rel_l2(dt_, dot_)
+
+
+@pytest.mark.parametrize("so,shape", [(8, (70, 37, 29)), (12, (67, 20, 40)), (4, (90, 1, 77))])
+def test_split_scheme_bitwise_equals_fused(prop, so, shape):
+    """The split scheme forms H0 u and Hz v with the fused pass's expressions in the same order (h goes
+    through memory as the same float): forward traces and final state, adjoint and gradient are
+    bitwise those of the fused scheme."""
+    case = tti_case(shape, so, 5, 60, nrec=19)
+    res = dev(np.random.default_rng(3).standard_normal((case["nt"], len(case["rec"]))))
+    out = []
+    for scheme in (2, 4):
+        p, shot = make_tti(case, prop, scheme)
+        d = host(p.forward(shot)).copy()
+        st = [host(p.read_state(i)).copy() for i in range(4)]
+        a = host(p.adjoint(shot, res)).copy()
+        g = host(p.gradient(shot, res, n_ckpt=4, ckpt_dtype="f16")).copy()
+        out.append([d, a, g] + st)
+        p.close()
+    for x, y in zip(*out):
+        assert np.array_equal(x, y)
