@@ -302,6 +302,16 @@ int prop_ckpt_decode_rows(const uint16_t *codes_a, const uint16_t *codes_b, cons
 /* FP64 inner product of two FP32 device vectors (deterministic order); blocks until done. */
 int prop_dot_f64(const float *a, const float *b, int64_t n, double *result, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): prop_dot_f64 without any allocation.  Same arguments, kernels and
+ * result (bitwise) as prop_dot_f64, which allocates its partial sums per call.  The scratch is a
+ * static device array of 1025 doubles per device (the partial sums of the kernels' fixed grid of
+ * 1024 blocks and the result), held until the process ends; its size does not depend on n, and a
+ * build whose kernels would need more fails with PROP_EINVAL.  Every call on a device uses that
+ * device's array: calls that overlap on one device (several threads or streams) race.  stream must
+ * belong to the current device.  Blocks until the result is on the host. */
+int prop_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *result, void *stream);
+
 int prop_destroy(prop_t h);
 
 /* Message of the last error on the calling thread ("" if none). */

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1847,6 +1848,36 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
 
 }  // namespace
 
+// ---------------------------------------------------------------------------------------------
+// Allocation-free FP64 dot product.  Its scratch (the partial sums of the dot kernels' fixed grid
+// and the result) is a file-scope device array; every device holds its own copy, whose device
+// address is looked up once per device, with that device current, and kept.
+// ---------------------------------------------------------------------------------------------
+constexpr int NOALLOC_DOT_SCRATCH = 1024 + 1;    // doubles
+static __device__ __align__(256) double scratch[NOALLOC_DOT_SCRATCH];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (the host-side symbol is only a stand-in).
+int scratch_ptr(double **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(PROP_EINVAL, "device %d beyond the %d supported", dev, MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return PROP_OK;
+}
+}  // namespace
+
 // ============================================================================ C ABI
 extern "C" {
 
@@ -2191,6 +2222,24 @@ int prop_dot_f64(const float *a, const float *b, int64_t n, double *result, void
     aux_dot_f64(a, b, n, part.as<double>(), out.as<double>(), st);
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(result, out.p, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PROP_OK;
+}
+
+int prop_dot_f64_noalloc(const float *a, const float *b, int64_t n, double *result, void *stream)
+{
+    g_err.clear();
+    if (!a || !b || !result || n < 0) return fail(PROP_EINVAL, "bad dot argument");
+    const int parts = aux_dot_blocks();
+    if (parts + 1 > NOALLOC_DOT_SCRATCH)
+        return fail(PROP_EINVAL, "the dot kernels need %d doubles of scratch, the static array holds %d", parts + 1,
+                    NOALLOC_DOT_SCRATCH);
+    double *s = nullptr;
+    TRY(scratch_ptr(&s));
+    hipStream_t st = (hipStream_t)stream;
+    aux_dot_f64(a, b, n, s, s + parts, st);   // every partial sum and the result are written: nothing to clear
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(result, s + parts, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     return PROP_OK;
 }

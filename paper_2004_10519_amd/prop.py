@@ -23,7 +23,8 @@ CKPT = {"f32": 0, "f16": 1, "bf16": 2}
 EXPORTS = ["prop_create", "prop_cfl_dt", "prop_set_model", "prop_forward", "prop_adjoint", "prop_gradient",
            "prop_image", "prop_forward_batched", "prop_gradient_batched", "prop_image_batched", "prop_read_state", "prop_set_timing",
            "prop_kernel_time", "prop_set_option", "prop_get_option", "prop_ckpt_encode", "prop_ckpt_decode",
-           "prop_ckpt_encode_rows", "prop_ckpt_decode_rows", "prop_dot_f64", "prop_destroy", "prop_last_error"]
+           "prop_ckpt_encode_rows", "prop_ckpt_decode_rows", "prop_dot_f64", "prop_dot_f64_noalloc", "prop_destroy",
+           "prop_last_error"]
 
 # option / info codes of prop_set_option and prop_get_option
 OPTIONS = {"graph": 1, "autotune": 2, "tile1": 3, "tile2": 4, "zc": 5, "xcd": 6, "batch_mb": 7, "scheme": 8, "zc2": 9,
@@ -87,6 +88,7 @@ def lib() -> ctypes.CDLL:
         L.prop_ckpt_encode_rows.argtypes = [vp, vp, i64, i64, i64, i32, i32, vp, vp, vp, vp, vp]
         L.prop_ckpt_decode_rows.argtypes = [vp, vp, vp, vp, i64, i64, i64, i32, vp, vp, vp]
         L.prop_dot_f64.argtypes = [vp, vp, i64, ctypes.POINTER(dbl), vp]
+        L.prop_dot_f64_noalloc.argtypes = [vp, vp, i64, ctypes.POINTER(dbl), vp]
         L.prop_destroy.argtypes = [vp]
         L.prop_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -325,6 +327,13 @@ class Propagator:
 def dot_f64(a: torch.Tensor, b: torch.Tensor, stream=None) -> float:
     res = ctypes.c_double()
     _check(lib().prop_dot_f64(_dev(a), _dev(b), a.numel(), ctypes.byref(res), _stream(stream)))
+    return res.value
+
+
+def dot_f64_noalloc(a: torch.Tensor, b: torch.Tensor, stream=None) -> float:
+    """dot_f64 through the allocation-free entry point (static device scratch)."""
+    res = ctypes.c_double()
+    _check(lib().prop_dot_f64_noalloc(_dev(a), _dev(b), a.numel(), ctypes.byref(res), _stream(stream)))
     return res.value
 
 
