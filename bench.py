@@ -77,7 +77,7 @@ def log(*a):
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "tti.hip", "tti_fused.hip"):
+    for f in ("common.h", "jobs.h", "tti.hip", "tti_fused.hip", "tti_split.hip"):
         with open(os.path.join(ROOT, "paper_2004_10519_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -247,8 +247,11 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *                      pass and class 0 is unused); 3 = two passes, pass 1 stores the three
  *                      components of (I - n n^T) grad p and the scalar n . grad q, and pass 2
  *                      re-forms n n^T grad q from it and the axis (bitwise equal to 0, 8 bytes
- *                      a point fewer).  Default: 2 up to space order 8, 3 up to 12, 0 above.
- *                      Same operators; results agree to FP32 rounding.
+ *                      a point fewer); 4 = two fused single-field passes, h = H0 p (or H0 w_p)
+ *                      into a temporary, then Hz q (or Hz w_q) and the update (space order <= 12
+ *                      and x-y planes below 4 GiB; bitwise equal to 2; kernel classes 0 and 1).
+ *                      Default: 2 up to space order 8, 4 up to 12 (3 when the planes are 4 GiB or
+ *                      more), 0 above.
  * Read-only (prop_get_option): PROP_INFO_TILE1/2 and PROP_INFO_ZC1/2, the variant and z-chunk
  * used by the last TTI call; PROP_INFO_GRAPHS, graphs launched since create; PROP_INFO_GROUPS,
  * shot groups of the last batched call.  Unknown options give PROP_EINVAL. */

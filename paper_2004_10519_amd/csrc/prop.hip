@@ -1906,13 +1906,15 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
     h->g = *grid;
     h->st = (hipStream_t)stream;
     h->R = grid->space_order / 2;
-    // default TTI scheme: the fused pass up to space order 8, two passes beyond (measured on the
-    // 512^3 workload: fused 1.62 / 2.10 ms per step at space order 4 / 8 against 2.84 / 2.94 ms;
-    // at space order 12 the fused pass is register-bound and slower, 4.65 against 2.98 ms).  Of the
-    // two-pass schemes the four-field one moves 8 bytes a point less (space order 12: 2.95 against
-    // 3.02 ms per step, bitwise the same results); its pass 2 spills beyond space order 12.
+    // default TTI scheme (512^3 workload, ms per step): space order 8 and below, the fused pass
+    // (so8: 1.70 against 1.50 + 0.80 for the split pair and 2.94 for two passes); space orders 10-12,
+    // the split pair of fused single-field passes (so12: 1.05 + 1.59 = 2.64 against 2.95 for the
+    // four-field two-pass pair; the fused pass is register-bound there, 4.65); above, the six-field
+    // two-pass pair (the others' queues outgrow the registers and LDS of a CU).
     if (kind == PROP_TTI)
-        h->opt_scheme = h->R <= 4 && fused_fits(*grid) ? TTI_FUSED : h->R <= 6 ? TTI_FOUR : TTI_SIX;
+        h->opt_scheme = h->R <= 4 && fused_fits(*grid) ? TTI_FUSED
+                        : h->R <= 6 && fused_fits(*grid) ? TTI_SPLIT
+                        : h->R <= 6 ? TTI_FOUR : TTI_SIX;
     double w[8] = {0};
     if (kind == PROP_TTI) centred_weights(h->R, w);
     else staggered_weights(h->R, w);

@@ -22,7 +22,19 @@
 // then complete.
 #include "jobs.h"
 
+#include <type_traits>
+
 namespace {
+
+// f(integral_constant<int, K>) for K = B .. E-1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 template <int R, int TY>
 struct SplitItems {
@@ -198,132 +210,139 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
     };
     load_upd(zs - R);
     fetch(zs);
-    for (int zf = zs; zf < ze; ++zf) {
-        // 1. advance the queues (plane zf + R enters) and stage plane zf
+    // The march is unrolled by Q planes: in unrolled step K the three queues are rotated by K slots,
+    // so that advancing them costs no register moves.  Logical slot s of the own and halo u queues
+    // (after plane zf + R has entered) is register (s + K + 1) mod Q; accumulator slot s is register
+    // (s + K) mod Q.
+    for (int zb = zs; zb < ze; zb += Q) {
+        static_for<0, Q>([&](auto kc) {
+            constexpr int K = decltype(kc)::value;
+            const int zf = zb + K;
+            if (zf >= ze) return;   // block-uniform
+            auto U_ = [&](int s_) -> float & { return qu[(s_ + K + 1) % Q]; };
+            auto H_ = [&](int s_) -> float & { return hq[(s_ + K + 1) % Q]; };
+            auto A_ = [&](int s_) -> float & { return at[(s_ + K) % Q]; };
+            // 1. plane zf + R enters the queues (into the register of the plane that left); stage plane zf
+            U_(Q - 1) = ok ? nu : 0.f;
+            H_(Q - 1) = hok ? hu : 0.f;
+            Lu[UP::at(ty, tx)] = U_(R);
+            if (hitem) Lu[UP::at(hyy, hxx)] = H_(R);
 #pragma unroll
-        for (int s = 0; s < Q - 1; ++s) {
-            qu[s] = qu[s + 1];
-            hq[s] = hq[s + 1];
-        }
-        qu[Q - 1] = ok ? nu : 0.f;
-        hq[Q - 1] = hok ? hu : 0.f;
-        Lu[UP::at(ty, tx)] = qu[R];
-        if (hitem) Lu[UP::at(hyy, hxx)] = hq[R];
-#pragma unroll
-        for (int k = 0; k < NO; ++k) {
-            const int i = tid + k * NT;
-            if (i < IT::NOI) {
-                int yy, xx;
-                IT::ring(i, yy, xx);
-                Lu[UP::at(yy, xx)] = rok[k] ? ou[k] : 0.f;
+            for (int k = 0; k < NO; ++k) {
+                const int i = tid + k * NT;
+                if (i < IT::NOI) {
+                    int yy, xx;
+                    IT::ring(i, yy, xx);
+                    Lu[UP::at(yy, xx)] = rok[k] ? ou[k] : 0.f;
+                }
             }
-        }
-        const float a0 = on0, a1 = on1, b0 = hn0, b1 = hn1;
-        __syncthreads();
+            const float a0 = on0, a1 = on1, b0 = hn0, b1 = hn1;
+            __syncthreads();
 
-        // plane zo = zf - R is updated in this iteration with the operands loaded one plane earlier
-        const int zo = zf - R;
-        const bool out = zo >= z0;
-        if (PART == 1) {
-            vp0 = nvp0;
-            vq0 = ADJ ? nvq0 : qu[0];
-            vp1 = nvp1;
-            vq1 = nvq1;
-            vm = nvm;
-            vA = nvA;
-            vB = nvB;
-            vh = nvh;
-        }
-        float fpk = 0.f, fqk = 0.f, vg = 0.f;
-        if (PART == 1 && MODE == K2_ADJ_IC && out) {
-            const int y = ok ? gy : 0, x = ok ? gx : 0;
-            seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), fpk, fqk);
-            vg = ldo(sp(Grad, zo), fresh(os));
-        }
-        load_upd(zo + 1);
-        if (zf + 1 < ze) fetch(zf + 1);
-
-        // 2. projected gradient of plane zf: own column (all components), halo column (x or y component)
-        const bool zin = zok(zf);
-        {
-            const int li = UP::at(ty, tx);
-            const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
-            const float duz = dc_q<R>(qu, W.wz);
-            const float n2 = axis_z(a0, a1);
-            const float wu = a0 * dux + a1 * duy + n2 * duz;
-            const bool in = zin && ok;
-            float tz;
-            if (PART == 0) {
-                Lt0[XP::at(ty, tx)] = in ? dux - a0 * wu : 0.f;
-                Lt1[YP::at(ty, tx)] = in ? duy - a1 * wu : 0.f;
-                tz = in ? duz - n2 * wu : 0.f;
-            } else {
-                Lt0[XP::at(ty, tx)] = in ? a0 * wu : 0.f;
-                Lt1[YP::at(ty, tx)] = in ? a1 * wu : 0.f;
-                tz = in ? n2 * wu : 0.f;
+            // plane zo = zf - R is updated in this step with the operands loaded one plane earlier
+            const int zo = zf - R;
+            const bool out = zo >= z0;
+            if (PART == 1) {
+                vp0 = nvp0;
+                vq0 = ADJ ? nvq0 : U_(0);
+                vp1 = nvp1;
+                vq1 = nvq1;
+                vm = nvm;
+                vA = nvA;
+                vB = nvB;
+                vh = nvh;
             }
-#pragma unroll
-            for (int j = 1; j <= R; ++j) {
-                at[R - j] += W.wz[j - 1] * tz;
-                at[R + j] -= W.wz[j - 1] * tz;
+            float fpk = 0.f, fqk = 0.f, vg = 0.f;
+            if (PART == 1 && MODE == K2_ADJ_IC && out) {
+                const int y = ok ? gy : 0, x = ok ? gx : 0;
+                seg_load(J, seg_step, x, y, zo, sidx(w, x, y, zo), fpk, fqk);
+                vg = ldo(sp(Grad, zo), fresh(os));
             }
-        }
-        if (hitem) {
-            const int li = UP::at(hyy, hxx);
-            const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
-            float duz = 0.f;
-#pragma unroll
-            for (int j = 1; j <= R; ++j) duz += W.wz[j - 1] * (hq[R + j] - hq[R - j]);
-            const float n2 = axis_z(b0, b1);
-            const float wu = b0 * dux + b1 * duy + n2 * duz;
-            const bool in = zin && hok;
-            if (hisx) Lt0[XP::at(hyy, hxx)] = in ? (PART == 0 ? dux - b0 * wu : b0 * wu) : 0.f;
-            else      Lt1[YP::at(hyy, hxx)] = in ? (PART == 0 ? duy - b1 * wu : b1 * wu) : 0.f;
-        }
-        __syncthreads();
+            load_upd(zo + 1);
+            if (zf + 1 < ze) fetch(zf + 1);
 
-        // 3. x-y divergence of plane zf; plane zo complete
-        at[R] += dc_lds_x<R>(Lt0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(ty, tx), W.wy);
-        if (out && ok) {
-            const uint32_t uos = fresh(os);
-            if (PART == 0) {
-                sto(spw(Hb, zo), uos, at[0]);
-            } else {
-                const float ezo = gld(Ez, zo);
-                const float h0 = vh, hz = at[0];
-                float Lp, Lq;
-                if (ADJ) {
-                    Lp = h0;
-                    Lq = hz;
+            // 2. projected gradient of plane zf: own column (all components), halo column (x or y component)
+            const bool zin = zok(zf);
+            {
+                const int li = UP::at(ty, tx);
+                const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
+                float duz = 0.f;
+#pragma unroll
+                for (int j = 1; j <= R; ++j) duz += W.wz[j - 1] * (U_(R + j) - U_(R - j));
+                const float n2 = axis_z(a0, a1);
+                const float wu = a0 * dux + a1 * duy + n2 * duz;
+                const bool in = zin && ok;
+                float tz;
+                if (PART == 0) {
+                    Lt0[XP::at(ty, tx)] = in ? dux - a0 * wu : 0.f;
+                    Lt1[YP::at(ty, tx)] = in ? duy - a1 * wu : 0.f;
+                    tz = in ? duz - n2 * wu : 0.f;
                 } else {
-                    Lp = vA * h0 + vB * hz;
-                    Lq = vB * h0 + hz;
+                    Lt0[XP::at(ty, tx)] = in ? a0 * wu : 0.f;
+                    Lt1[YP::at(ty, tx)] = in ? a1 * wu : 0.f;
+                    tz = in ? n2 * wu : 0.f;
                 }
-                const float mm = vm * idt2 + 0.f;
-                const float e = exy + ezo;
-                const float ra = 1.0f / (mm + e);
-                const float cc = mm - e;
-                const float np_ = (2.f * mm * vp0 - cc * vp1 + Lp) * ra;
-                const float nq_ = (2.f * mm * vq0 - cc * vq1 + Lq) * ra;
-                sto(spw(Pn, zo), uos, np_);
-                sto(spw(Qn, zo), uos, nq_);
-                if (ADJ) {
-                    sto(spw(Wn0, zo), uos, vA * np_ + vB * nq_);
-                    sto(spw(Wn1, zo), uos, vB * np_ + nq_);
-                }
-                if (MODE == K2_FWD_STORE && SegP) {
-                    sto(spw(SegP, zo), uos, np_);
-                    sto(spw(SegQ, zo), uos, nq_);
-                }
-                if (MODE == K2_ADJ_IC)
-                    sto(spw(Grad, zo), uos,
-                        image ? vg + (fpk * np_ + fqk * nq_)
-                              : vg - idt2 * (fpk * (np_ - 2.f * vp0 + vp1) + fqk * (nq_ - 2.f * vq0 + vq1)));
-            }
-        }
 #pragma unroll
-        for (int s = 0; s < Q - 1; ++s) at[s] = at[s + 1];
-        at[Q - 1] = 0.f;
+                for (int j = 1; j <= R; ++j) {
+                    A_(R - j) += W.wz[j - 1] * tz;
+                    A_(R + j) -= W.wz[j - 1] * tz;
+                }
+            }
+            if (hitem) {
+                const int li = UP::at(hyy, hxx);
+                const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
+                float duz = 0.f;
+#pragma unroll
+                for (int j = 1; j <= R; ++j) duz += W.wz[j - 1] * (H_(R + j) - H_(R - j));
+                const float n2 = axis_z(b0, b1);
+                const float wu = b0 * dux + b1 * duy + n2 * duz;
+                const bool in = zin && hok;
+                if (hisx) Lt0[XP::at(hyy, hxx)] = in ? (PART == 0 ? dux - b0 * wu : b0 * wu) : 0.f;
+                else      Lt1[YP::at(hyy, hxx)] = in ? (PART == 0 ? duy - b1 * wu : b1 * wu) : 0.f;
+            }
+            __syncthreads();
+
+            // 3. x-y divergence of plane zf; plane zo complete
+            A_(R) += dc_lds_x<R>(Lt0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(ty, tx), W.wy);
+            if (out && ok) {
+                const uint32_t uos = fresh(os);
+                if (PART == 0) {
+                    sto(spw(Hb, zo), uos, A_(0));
+                } else {
+                    const float ezo = gld(Ez, zo);
+                    const float h0 = vh, hz = A_(0);
+                    float Lp, Lq;
+                    if (ADJ) {
+                        Lp = h0;
+                        Lq = hz;
+                    } else {
+                        Lp = vA * h0 + vB * hz;
+                        Lq = vB * h0 + hz;
+                    }
+                    const float mm = vm * idt2 + 0.f;
+                    const float e = exy + ezo;
+                    const float ra = 1.0f / (mm + e);
+                    const float cc = mm - e;
+                    const float np_ = (2.f * mm * vp0 - cc * vp1 + Lp) * ra;
+                    const float nq_ = (2.f * mm * vq0 - cc * vq1 + Lq) * ra;
+                    sto(spw(Pn, zo), uos, np_);
+                    sto(spw(Qn, zo), uos, nq_);
+                    if (ADJ) {
+                        sto(spw(Wn0, zo), uos, vA * np_ + vB * nq_);
+                        sto(spw(Wn1, zo), uos, vB * np_ + nq_);
+                    }
+                    if (MODE == K2_FWD_STORE && SegP) {
+                        sto(spw(SegP, zo), uos, np_);
+                        sto(spw(SegQ, zo), uos, nq_);
+                    }
+                    if (MODE == K2_ADJ_IC)
+                        sto(spw(Grad, zo), uos,
+                            image ? vg + (fpk * np_ + fqk * nq_)
+                                  : vg - idt2 * (fpk * (np_ - 2.f * vp0 + vp1) + fqk * (nq_ - 2.f * vq0 + vq1)));
+                }
+            }
+            A_(0) = 0.f;   // the register of the completed plane becomes the newest accumulator slot
+        });
     }
 }
 
