@@ -86,20 +86,32 @@ __global__ void k_el_remix(Csr c, Win w, const float *__restrict__ gx, const flo
 }
 
 // Multilinear gather: out[pos_o] = scale * sum_c w_oc (f0 + f1 + f2)[idx_oc].  One point per lane.
+// Multilinear gathers run one corner per lane: the nc = 2^d lanes of a point (a power of two that
+// divides the wavefront) each load one corner value times its weight, and a butterfly of lane shuffles
+// within the group sums them in a fixed order (every lane takes part in the shuffles, so lanes past
+// the last point carry zeros instead of returning early); the group's first lane writes the result.
+__device__ __forceinline__ float group_sum(float v, int nc)
+{
+    for (int o = nc >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
 __global__ void k_gather(Gather g, const float *__restrict__ f0, const float *__restrict__ f1,
                          const float *__restrict__ f2, float scale, float *__restrict__ out)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= g.n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = t / g.nc;
+    const bool on = o < g.n;
     float s = 0.f;
-    for (int c = 0; c < g.nc; ++c) {
-        const int64_t i = g.idx[(int64_t)o * g.nc + c];
+    if (on) {
+        const int64_t i = g.idx[t];
         float v = f0[i];
         if (f1) v += f1[i];
         if (f2) v += f2[i];
-        s += g.w[(int64_t)o * g.nc + c] * v;
+        s = g.w[t] * v;
     }
-    out[g.pos[o]] = scale * s;
+    s = group_sum(s, g.nc);
+    if (on && t % g.nc == 0) out[g.pos[o]] = scale * s;
 }
 
 __device__ __forceinline__ float bcsr_row_value(const BCsr &c, int r, const float *data)
@@ -154,19 +166,20 @@ __global__ void k_tti_rec_adj(BCsr c, const TTIJob *__restrict__ jobs, int par, 
 __global__ void k_tti_gather(BGather g, const TTIJob *__restrict__ jobs, int par, int mode, float *const *__restrict__ out,
                              const int *__restrict__ npt, int n)
 {
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= g.n) return;
-    const int sh = g.shot[o];
-    const TTIJob &J = jobs[sh];
-    const float *f0 = J.p[par ^ 1];
-    const float *f1 = J.q[par ^ 1];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t o = t / g.nc;
+    const bool on = o < g.n;
     float s = 0.f;
-    for (int c = 0; c < g.nc; ++c) {
-        const int64_t i = g.idx[(int64_t)o * g.nc + c];
-        const float v = mode == 0 ? f0[i] : f0[i] + f1[i];
-        s += g.w[(int64_t)o * g.nc + c] * v;
+    int sh = 0;
+    if (on) {
+        sh = g.shot[o];
+        const TTIJob &J = jobs[sh];
+        const int64_t i = g.idx[t];
+        const float v = mode == 0 ? J.p[par ^ 1][i] : J.p[par ^ 1][i] + J.q[par ^ 1][i];
+        s = g.w[t] * v;
     }
-    out[sh][(int64_t)n * npt[sh] + g.pos[o]] = s;
+    s = group_sum(s, g.nc);
+    if (on && t % g.nc == 0) out[sh][(int64_t)n * npt[sh] + g.pos[o]] = s;
 }
 
 __global__ void k_fill(float *p, int64_t n, float v)
@@ -545,7 +558,9 @@ void aux_tti_gather(const BGather &g, const TTIJob *jobs, int par, int mode, flo
                     hipStream_t st)
 {
     if (g.n <= 0) return;
-    hipLaunchKernelGGL(k_tti_gather, dim3((g.n + BS - 1) / BS), dim3(BS), 0, st, g, jobs, par, mode, out, npt, n);
+    const int64_t lanes = (int64_t)g.n * g.nc;
+    hipLaunchKernelGGL(k_tti_gather, dim3((unsigned)((lanes + BS - 1) / BS)), dim3(BS), 0, st, g, jobs, par, mode, out,
+                       npt, n);
 }
 
 void aux_tti_inject(const Csr &c, const float *data, float idt2, const float *m, float *d0, float *d1, float *d2,
@@ -582,7 +597,8 @@ void aux_gather(const Gather &g, const float *f0, const float *f1, const float *
                 hipStream_t st)
 {
     if (g.n <= 0) return;
-    hipLaunchKernelGGL(k_gather, dim3((g.n + BS - 1) / BS), dim3(BS), 0, st, g, f0, f1, f2, scale, out);
+    const int64_t lanes = (int64_t)g.n * g.nc;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((lanes + BS - 1) / BS)), dim3(BS), 0, st, g, f0, f1, f2, scale, out);
 }
 
 void aux_fill(float *p, int64_t n, float v, hipStream_t st)

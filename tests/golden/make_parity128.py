@@ -8,8 +8,13 @@
                    source 10 points below the layer, 16 x 16 pressure and 16 x 16 vz receivers
                    2 points below it (the el3d_400 recipe on 128^3).
 
-Each file keeps every 4th trace sample of every receiver and the final wavefields on the central
-x-z, y-z and x-y planes.  Calls only oracle/ and the seeded input generators.
+Each file keeps every 4th trace sample of every receiver and the wavefields on the central x-z, y-z
+and x-y planes twice: after MID steps (the wavefield still in the grid: TTI 400, elastic 300) and at
+the end of the run (most of it absorbed by then).  The TTI file also keeps those planes from a second
+checker run whose stored levels are rounded to FP32 after every step (FP64 arithmetic otherwise): the
+departure that FP32 storage alone causes, which for q (whose equation has near-zero-frequency modes,
+fields nearly constant along the symmetry axis, that integrate the rounding noise) is several times
+larger than for p.  Calls only oracle/ and the seeded input generators.
 Run: python tests/golden/make_parity128.py [tti|elastic]   (minutes per case on 8 cores)
 """
 import dataclasses
@@ -27,6 +32,7 @@ from paper_2004_10519_amd import configs, inputs  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TSUB = 4
+MID = {"tti": 400, "elastic": 300}
 
 
 def tti_case():
@@ -56,14 +62,30 @@ def make_tti():
     g = grid(w)
     mod = oracle.TTIModel.from_arrays(g, *w.model_list())
     t0 = time.time()
-    d, (p, q, _, _), _ = oracle.tti_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz,
-                                            callback=lambda n, p, q: (n % 250 == 0) and print(f"tti step {n}", flush=True))
-    out = {"traces": d[::TSUB].astype(np.float32), "tsub": TSUB, "nt": w.nt}
-    for name, f in (("p", p), ("q", q)):
-        for k, v in planes(f).items():
-            out[f"{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
+    out = {"tsub": TSUB, "nt": w.nt, "mid": MID["tti"]}
+    for tag, fp32 in (("", False), ("fp32store_", True)):
+        def cb(n, p, q, tag=tag, fp32=fp32):
+            if fp32:   # store the new levels in FP32
+                p[...] = p.astype(np.float32)
+                q[...] = q.astype(np.float32)
+            if n % 250 == 0:
+                print(f"tti {tag}step {n}", flush=True)
+            if n + 1 == MID["tti"]:
+                for name, f in (("p", p), ("q", q)):
+                    for k, v in planes(f).items():
+                        out[f"{tag}mid_{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
+
+        d, (p, q, _, _), _ = oracle.tti_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz, callback=cb)
+        if not fp32:
+            out["traces"] = d[::TSUB].astype(np.float32)
+        for name, f in (("p", p), ("q", q)):
+            for k, v in planes(f).items():
+                out[f"{tag}{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
     np.savez_compressed(os.path.join(HERE, "tti128_so12.npz"), **out)
-    print(f"tti128_so12.npz written ({time.time() - t0:.0f} s), max |d| = {np.abs(d).max():.3e}")
+    print(f"tti128_so12.npz written ({time.time() - t0:.0f} s)")
+
+
+EL_FIELDS = ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
 
 
 def make_elastic():
@@ -72,10 +94,19 @@ def make_elastic():
     vp, vs, rho = w.model_list()
     mod = oracle.ElasticModel.from_velocities(g, vp, vs, rho)
     t0 = time.time()
-    d, fields = oracle.elastic_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz, w.rec_kind,
-                                       callback=lambda n, f: (n % 250 == 0) and print(f"elastic step {n}", flush=True))
-    out = {"traces": d[::TSUB].astype(np.float32), "tsub": TSUB, "nt": w.nt}
-    for i, name in enumerate(("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")):
+    out = {"tsub": TSUB, "nt": w.nt, "mid": MID["elastic"]}
+
+    def cb(n, f):
+        if n % 250 == 0:
+            print(f"elastic step {n}", flush=True)
+        if n + 1 == MID["elastic"]:
+            for i, name in enumerate(EL_FIELDS):
+                for k, v in planes(f[i]).items():
+                    out[f"mid_{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
+
+    d, fields = oracle.elastic_forward(g, mod, w.src_xyz, w.wavelet(), w.rec_xyz, w.rec_kind, callback=cb)
+    out["traces"] = d[::TSUB].astype(np.float32)
+    for i, name in enumerate(EL_FIELDS):
         for k, v in planes(fields[i]).items():
             out[f"{name}_{k}"] = np.ascontiguousarray(v, dtype=np.float32)
     np.savez_compressed(os.path.join(HERE, "el128_so8.npz"), **out)

@@ -256,32 +256,58 @@ def _golden_module():
 def test_parity128_full_length_vs_checker(prop, kind):
     """The benchmark recipes at 128^3 over their full lengths (TTI so12, 3000 steps; elastic so8, 2000
     steps), in the benchmark's launch configuration (library default scheme, autotuned tiles), against
-    the FP64 checker's stored traces (every 4th sample of every receiver) and final wavefields on the
-    three central planes (tests/golden/make_parity128.py)."""
+    the FP64 checker's stored results (tests/golden/make_parity128.py): every 4th sample of every
+    trace (rel-L2 1e-4), and the wavefields on the three central planes after MID steps (the wave
+    still in the grid) and at the end (by then the absorbing layers have taken most of the energy, so
+    each plane's error is measured against its norm after MID steps).
+    Bar per plane: 1e-4 of that norm, or, for TTI, 4 times the departure that storing the levels in
+    FP32 alone causes in the checker, if larger: q's equation has near-zero-frequency modes (fields
+    nearly constant along the symmetry axis, where Hz vanishes) that integrate rounding noise instead
+    of propagating it away, so after 400 steps FP32 storage alone moves q by 1.7-3.8e-4 (p by 3e-5)."""
+    import dataclasses
     import os
     mk, gdir = _golden_module()
     w = mk.tti_case() if kind == "tti" else mk.elastic_case()
     gold = np.load(os.path.join(gdir, "tti128_so12.npz" if kind == "tti" else "el128_so8.npz"))
     m = w.make_model()
-    g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=w.nt, v_ref=w.v_ref)
     keys = ("m", "eps", "delta", "theta", "phi") if kind == "tti" else ("vp", "vs", "rho")
     mt = [dev(m[k]) for k in keys]
-    p = prop.Propagator(prop.TTI if kind == "tti" else prop.ELASTIC, g, mt)
-    if kind == "tti":
-        p.set_option("autotune", 1)
-    shot = prop.Shot(w.src_xyz, dev(w.wavelet()), w.rec_xyz, w.rec_kind)
-    d = host(p.forward(shot))[::int(gold["tsub"])]
-    err = rel_l2(d, gold["traces"])
-    names = ("p", "q") if kind == "tti" else ("vx", "vy", "vz", "txx", "tyy", "tzz", "txy", "txz", "tyz")
-    nz, ny, nx = g.arr_shape
-    errs = {}
-    for i, name in enumerate(names):
-        f = host(p.read_state(i))
-        for pl, v in (("xz", f[:, ny // 2, :]), ("yz", f[:, :, nx // 2]), ("xy", f[nz // 2, :, :])):
-            ref = gold[f"{name}_{pl}"]
-            if np.abs(ref).max() > 0:
-                errs[f"{name}_{pl}"] = rel_l2(v, ref)
-    print(f"{kind} 128^3 full length: traces rel-L2 {err:.2e}; fields max {max(errs.values()):.2e}")
+    names = ("p", "q") if kind == "tti" else mk.EL_FIELDS
+
+    def run(nt):
+        g = prop.Grid(w.shape, w.spacing, space_order=w.space_order, nbl=w.nbl, dt=w.dt, nt=nt, v_ref=w.v_ref)
+        p = prop.Propagator(prop.TTI if kind == "tti" else prop.ELASTIC, g, mt)
+        if kind == "tti":
+            p.set_option("autotune", 1)
+        ws = dataclasses.replace(w, nt=nt)
+        shot = prop.Shot(w.src_xyz, dev(ws.wavelet()), w.rec_xyz, w.rec_kind)
+        d = host(p.forward(shot)).copy()
+        nz, ny, nx = g.arr_shape
+        pl = {}
+        for i, name in enumerate(names):
+            f = host(p.read_state(i))
+            pl.update({f"{name}_xz": f[:, ny // 2, :], f"{name}_yz": f[:, :, nx // 2], f"{name}_xy": f[nz // 2, :, :]})
+        p.close()
+        return d, pl
+
+    d, final = run(w.nt)
+    _, mid = run(int(gold["mid"]))
+    err = rel_l2(d[::int(gold["tsub"])], gold["traces"])
+    print(f"{kind} 128^3: traces rel-L2 {err:.2e}")
     assert err <= 1e-4, err
-    for k, e in errs.items():
-        assert e <= 1e-4, (k, e)
+    bad = []
+    for when, got in (("mid_", mid), ("", final)):
+        for k, v in got.items():
+            scale = np.linalg.norm(gold[f"mid_{k}"].astype(np.float64))
+            if scale == 0:
+                continue
+            ref = gold[f"{when}{k}"].astype(np.float64)
+            e = np.linalg.norm(v - ref)
+            bound = 1e-4 * scale
+            fp32 = f"fp32store_{when}{k}"
+            if fp32 in gold.files:
+                bound = max(bound, 4 * np.linalg.norm(gold[fp32].astype(np.float64) - ref))
+            print(f"  {when or 'end_'}{k}: error {e / scale:.2e} of the plane's norm (bound {bound / scale:.2e})")
+            if e > bound:
+                bad.append((when or "end", k, e / scale, bound / scale))
+    assert not bad, bad
