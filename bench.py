@@ -32,15 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes per grid point of one launch of each stencil kernel (FP32).  TTI, per two-pass
-# scheme (0: six-field temporaries, 1: scalar projections) and direction:
+# Algorithmic bytes per grid point of one launch of each stencil kernel (FP32).  TTI, per scheme
+# (0: six-field temporaries, 2: one fused pass, 3: four-field temporaries, 4: split) and direction:
 #   scheme 0 pass 1: read u, v, n_x, n_y; write t (3), s (3)                              -> 10 x 4
 #   scheme 0 pass 2: read t, s (6), f, f- for p and q (4), m, 1+2eps, sqrt(1+2delta) (3);
 #                    write p+, q+ (2); adjoint also writes w = C y+ (2)                  -> 15 / 17 x 4
-#   scheme 1 pass 1: read u, v, n_x, n_y; write n.grad u, n.grad v                       ->  6 x 4
-#   scheme 1 pass 2: read f, f- for p and q (4), the two projections, n_x, n_y, m, 1+2eps,
-#                    sqrt(1+2delta) (7); write p+, q+ (2); adjoint reads u = w_p too and
-#                    writes w = C y+ (2)                                                 -> 13 / 16 x 4
 #   scheme 2 (one fused pass, class 1): read u, v, f- for p and q (4), n_x, n_y, m, 1+2eps,
 #                    sqrt(1+2delta) (5); write p+, q+ (2); adjoint reads y too and writes
 #                    w = C y+ (2)                                                         -> 11 / 15 x 4
@@ -51,7 +47,6 @@ HBM_PEAK_GBS = 8000.0
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
 TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
-                    (1, 0, False): 24, (1, 1, False): 52, (1, 0, True): 24, (1, 1, True): 64,
                     (2, 1, False): 44, (2, 1, True): 60,
                     (3, 0, False): 32, (3, 1, False): 60, (3, 0, True): 32, (3, 1, True): 68,
                     (4, 0, False): 16, (4, 1, False): 48, (4, 0, True): 16, (4, 1, True): 60}
@@ -71,13 +66,22 @@ METHOD_BYTES_PER_PT = {"tti": 44, "elastic": 84}
 TTI_PAPER_FLOPS_PER_PT = {4: 95, 8: 102, 12: 160, 16: 276}
 
 
+_T_START = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    """Progress line on stderr, stamped with the seconds since the benchmark started."""
+    print(f"{time.perf_counter() - _T_START:7.1f}s", *a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+# sources of each TTI scheme's stencil kernels (the counters in profiles/pmc_traffic.json hold only
+# while these are unchanged)
+SCHEME_SOURCES = {0: "tti.hip", 2: "tti_fused.hip", 3: "tti.hip", 4: "tti_split.hip"}
+
+
+def kernel_source_hash(scheme: int) -> str:
     h = hashlib.sha256()
-    for f in ("common.h", "jobs.h", "tti.hip", "tti_fused.hip", "tti_split.hip"):
+    for f in ("common.h", "jobs.h", SCHEME_SOURCES[scheme]):
         with open(os.path.join(ROOT, "paper_2004_10519_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -92,7 +96,7 @@ def traffic_from_profiles(kclass: int, npts: int, scheme: int = 0, tile=None, sp
     with open(path) as fh:
         rec = json.load(fh)
     ent = rec.get(f"{kclass}/{scheme}/so{space_order}")
-    if not ent or ent.get("source_hash") != kernel_source_hash() or ent.get("npts") != npts:
+    if not ent or ent.get("source_hash") != kernel_source_hash(scheme) or ent.get("npts") != npts:
         return None
     if tile is not None and ent.get("tile") != list(tile):
         return None
@@ -118,13 +122,20 @@ def setup_tti(w, torch, prop):
     return p, shot
 
 
-def timed(torch, fn, steps, warmup):
-    for _ in range(warmup):
+def timed(torch, fn, steps, warmup, label=None):
+    """Mean wall time of `steps` calls after `warmup` untimed ones; with a label, one progress line per
+    call on stderr (long legs would otherwise stay silent for minutes)."""
+    for i in range(warmup):
         fn()
+        if label:
+            torch.cuda.synchronize()
+            log(f"[bench] {label}: warm-up {i + 1}/{warmup}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         fn()
+        if label:
+            log(f"[bench] {label}: step {i + 1}/{steps} issued ({time.perf_counter() - t0:.1f} s)")
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps
 
@@ -140,7 +151,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(w, budget_s: float = 12.0, el_budget_s: float = 8.0):
+def cpu_baseline(w, budget_s: float = 8.0, el_budget_s: float = 5.0):
     """The FP64 checker on sub-volumes of the benchmark model (the TTI step of the headline) and of the
     elastic 400^3 model (a bounded sample of each workload)."""
     import oracle
@@ -210,7 +221,6 @@ def kernel_roof(p, classes, npts, scheme=0, adjoint=False):
 
 def measure_tti_adjoint(torch, prop, w, p, shot):
     rec = torch.randn((w.nt, len(w.rec_xyz)), device="cuda")
-    p.adjoint(shot, rec)
     torch.cuda.synchronize()
     p.set_timing(True)
     t = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
@@ -233,7 +243,6 @@ def measure_elastic(torch, prop, nt):
     roof = kernel_roof(p, (2, 3), w.npts)
     p.set_timing(False)
     rec = torch.randn((w.nt, len(w.rec_xyz)), device="cuda")
-    p.adjoint(shot, rec)
     torch.cuda.synchronize()
     ta = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
     g, ga = w.npts * w.nt / t / 1e9, w.npts * w.nt / ta / 1e9
@@ -292,15 +301,15 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
     ds_ = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in start]
     p.set_model(ds_)
     res = (p.forward(shot) - dobs).contiguous()
+    p.adjoint(shot, res)   # the autotuner's choice for the adjoint direction, outside the timed calls
+    torch.cuda.synchronize()
     out = {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
            "checkpoints": 48}
     ref = None
     for dt in ("f32",) + tuple(dtypes):
-        p.gradient(shot, res, 48, dt)
-        torch.cuda.synchronize()
-        t = timed(torch, lambda: p.gradient(shot, res, 48, dt), 1, 0)
-        gr = p.gradient(shot, res, 48, dt)
-        torch.cuda.synchronize()
+        holder = []
+        t = timed(torch, lambda: holder.append(p.gradient(shot, res, 48, dt)), 1, 0)
+        gr = holder[0]
         gp = w.npts * w.nt / t / 1e9
         ent = {"GPts/s": round(gp, 3), "ms": round(t * 1e3, 1),
                "method_hbm_frac_156B": round(gp * 156 / HBM_PEAK_GBS, 4)}
@@ -311,11 +320,9 @@ def measure_gradient(torch, prop, nt, dtypes=("bf16", "f16")):
         out[dt] = ent
     # whole run stored in FP16 (n_ckpt = 1): two sweeps instead of three; method bytes per point and
     # step: forward 44 + store 4 + adjoint 44 + read 4 + gradient read-modify-write 8 = 104
-    p.gradient(shot, res, 1, "f16")
-    torch.cuda.synchronize()
-    t = timed(torch, lambda: p.gradient(shot, res, 1, "f16"), 1, 0)
-    gr = p.gradient(shot, res, 1, "f16")
-    torch.cuda.synchronize()
+    holder = []
+    t = timed(torch, lambda: holder.append(p.gradient(shot, res, 1, "f16")), 1, 0)
+    gr = holder[0]
     gp = w.npts * w.nt / t / 1e9
     out["f16_whole_run"] = {"GPts/s": round(gp, 3), "ms": round(t * 1e3, 1), "checkpoints": 0,
                             "store_GB": round(w.nt * 2 * w.npts * 2 / 1e9, 1),
@@ -451,14 +458,14 @@ def main():
                     help="shots of the batched-vs-plain gradient comparison (default 64, the full workload; "
                          "0 skips it)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--budget", type=float, default=540.0,
+    ap.add_argument("--budget", type=float, default=500.0,
                     help="wall-time budget in seconds: a measured leg that would end past it is skipped")
     ap.add_argument("--tiles", default=None, metavar="T1,Z1,T2,Z2",
                     help="fixed tile variants and z-chunks of the two TTI passes instead of the autotuner "
                          "(counter runs: the profiler serialises launches, which would mislead the autotuner)")
-    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 1, 2, 3, 4),
-                    help="TTI step scheme: 0 two passes with six-field temporaries, 1 two passes with "
-                         "scalar projections, 2 one fused pass, 3 two passes with four-field temporaries, "
+    ap.add_argument("--scheme", type=int, default=TTI_SCHEME, choices=(0, 2, 3, 4),
+                    help="TTI step scheme: 0 two passes with six-field temporaries, "
+                         "2 one fused pass, 3 two passes with four-field temporaries, "
                          "4 two fused single-field passes (default: the library's choice per space "
                          "order, fused up to 8)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -502,11 +509,13 @@ def main():
     def run():
         p.forward(shot)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         run()
+        torch.cuda.synchronize()
+        log(f"[bench] {w.name}: warm-up {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
     p.set_timing(True)
-    t_step = timed(torch, run, args.steps, 0)
+    t_step = timed(torch, run, args.steps, 0, label=w.name)
     kt = {k: p.kernel_time(k) for k in (0, 1)}
     kt = {k: v for k, v in kt.items() if v[1] > 0}   # the fused scheme launches class 1 only
     p.set_timing(False)
@@ -587,7 +596,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline(w)
     if not args.only_main:
         if args.batched:
-            leg("batched_vs_plain", 230, lambda: measure_batched(torch, prop, args.nt or 1500, args.batched), paths)
+            leg("batched_vs_plain", 200, lambda: measure_batched(torch, prop, args.nt or 1500, args.batched), paths)
         log("[bench] 2D marine elastic (free surface) ...")
         leg("elastic_2d_marine", 15, lambda: measure_marine(torch, prop), paths)
     print(json.dumps(out), flush=True)

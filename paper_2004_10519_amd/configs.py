@@ -40,6 +40,7 @@ class Workload:
     rec_kind: np.ndarray = None
     v_ref: float = 1500.0
     free_surface: bool = False
+    model_threads: int = 0        # > 0: the fast FP32 model recipe on that many threads
     model: dict = field(default_factory=dict, repr=False)
 
     @property
@@ -70,9 +71,9 @@ class Workload:
                           "delta": np.full(shp, 0.05, np.float32), "theta": np.full(shp, math.radians(30), np.float32),
                           "phi": np.zeros(shp, np.float32)}
         elif self.kind == "tti":
-            mdl = inputs.tti_model(self.shape, self.nbl, self.seed, progress=progress)
-            self.model = {"m": inputs.slowness_squared(mdl["vp"]), "eps": mdl["eps"], "delta": mdl["delta"],
-                          "theta": mdl["theta"], "phi": mdl["phi"]}
+            mdl = inputs.tti_model(self.shape, self.nbl, self.seed, progress=progress, parallel=self.model_threads)
+            self.model = {"m": inputs.slowness_squared(mdl["vp"], threads=max(1, self.model_threads)),
+                          "eps": mdl["eps"], "delta": mdl["delta"], "theta": mdl["theta"], "phi": mdl["phi"]}
         elif self.name == "el2d_marine":
             self.model = inputs.marine_elastic_model(self.shape, self.nbl, MARINE_WATER_ROWS, self.seed)
         else:
@@ -137,11 +138,12 @@ def batch_64(nshot: int = 64, nt: int = 1500, shape=(1024, 1024, 512), seed_mode
     Windows: edges uniform in [128, 320] per axis (seed 5), x-y origin uniform within the model, z
     origin 0; 32-point absorbing layers inside each window.  Per shot: source at the window centre,
     4 points below the layer; receivers on every 4th node of the window interior, 2 points below
-    the layer.  Returns (model Workload, list of (origin, shape, src_xyz, rec_xyz)).
+    the layer.  The 0.5 G-point model uses the fast FP32 recipe of ``inputs.tti_model`` on 16
+    threads.  Returns (model Workload, list of (origin, shape, src_xyz, rec_xyz)).
     """
     h, nbl = (12.5, 12.5, 12.5), 32
     w = Workload("batch_64", "tti", tuple(shape), h, 8, nt, nbl, 1.116e-3, seed_model, 15.0,
-                 np.zeros((1, 3), np.float32), np.zeros((0, 3), np.float32), v_ref=1500.0)
+                 np.zeros((1, 3), np.float32), np.zeros((0, 3), np.float32), v_ref=1500.0, model_threads=16)
     rng = np.random.Generator(np.random.PCG64(seed_win))
     shots = []
     for _ in range(nshot):
