@@ -240,8 +240,7 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *   PROP_OPT_BATCH_MB  device-memory budget of the batched shot-group planner in MiB,
  *                      0 = 85 % of the free memory (default).
  *   PROP_OPT_SCHEME    TTI step scheme: 0 = two passes, pass 1 stores the six components of
- *                      (I - n n^T) grad p and n n^T grad q; 1 = two passes, pass 1 stores only the
- *                      two scalars n . grad p and n . grad q and pass 2 re-forms the vectors from p;
+ *                      (I - n n^T) grad p and n n^T grad q (value 1 is not used: PROP_EINVAL);
  *                      2 = one fused pass, the projections stay on chip (space order <= 12 and x-y
  *                      planes below 4 GiB, else PROP_EINVAL; kernel class 1 then times the fused
  *                      pass and class 0 is unused); 3 = two passes, pass 1 stores the three

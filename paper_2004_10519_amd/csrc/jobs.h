@@ -11,11 +11,11 @@ struct TTIJob {
     float *p[2], *q[2];           // wavefields (state layout)
     float *wmix[2][2];            // adjoint only: w = C y of the newest level (components p, q), the
                                   // input of pass 1; double-buffered with the step parity (pass 1
-                                  // reads wmix[par], pass 2 writes wmix[par ^ 1]) because the scalar
-                                  // scheme's pass 2 reads w on tile halos while it writes the new w
+                                  // reads wmix[par], pass 2 writes wmix[par ^ 1]) because the fused
+                                  // and split passes read w on tile halos while they write the new w
     float *t[3], *s[3];           // pass-1 outputs (state layout): six-field scheme: the vectors
-                                  // (I - n n^T) grad u and n n^T grad v; scalar scheme: t[0] = n . grad u,
-                                  // t[1] = n . grad v; four-field scheme: t as six-field, s[0] = n . grad v
+                                  // (I - n n^T) grad u and n n^T grad v; four-field scheme: t as
+                                  // six-field, s[0] = n . grad v; split scheme: t[0] = h = H0 u
     const float *m, *A, *B;       // m, 1 + 2 eps, sqrt(1 + 2 delta) (model layout)
     const float *nx, *ny;         // symmetry axis (model layout); n_z = sqrt(1 - n_x^2 - n_y^2) >= 0
     const float *ex, *ey, *ez;    // absorbing layer: eta/(2 dt) per window axis
@@ -76,11 +76,11 @@ struct ElGradJob {
 };
 
 enum { K2_FWD = 0, K2_FWD_STORE = 1, K2_ADJ = 2, K2_ADJ_IC = 3 };
-// Schemes of the TTI step: two passes with six-field temporaries, two passes with the two scalar
-// projections n . grad, one fused pass (projections kept on chip), two passes with four
-// temporaries: t and the scalar n . grad v, from which pass 2 re-forms s = n (n . grad v), or two
-// fused single-field passes (h = H0 u, then Hz v and the update; one temporary, h).
-enum { TTI_SIX = 0, TTI_SCALAR = 1, TTI_FUSED = 2, TTI_FOUR = 3, TTI_SPLIT = 4 };
+// Schemes of the TTI step: two passes with six-field temporaries, one fused pass (projections
+// kept on chip), two passes with four temporaries: t and the scalar n . grad v, from which pass 2
+// re-forms s = n (n . grad v), or two fused single-field passes (h = H0 u, then Hz v and the
+// update; one temporary, h).  (Value 1 is not used.)
+enum { TTI_SIX = 0, TTI_FUSED = 2, TTI_FOUR = 3, TTI_SPLIT = 4 };
 
 // shape: tile-shape variant of the pass; tti_tile_rows gives its tile height.
 void launch_tti_pass1(int R, int scheme, int shape, bool adjoint, const TTIJob *jobs, const Tile *tiles, int ntiles,

@@ -249,7 +249,7 @@ struct prop_s {
     int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
     int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1)
-    int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_SCALAR, TTI_FUSED or TTI_FOUR); set at create
+    int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_FUSED, TTI_FOUR or TTI_SPLIT); set at create
     int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
     // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
     struct Tune {
@@ -2067,8 +2067,8 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
         h->opt_batch_mb = value;
         return PROP_OK;
     case PROP_OPT_SCHEME:
-        if (value != TTI_SIX && value != TTI_SCALAR && value != TTI_FUSED && value != TTI_FOUR && value != TTI_SPLIT)
-            return fail(PROP_EINVAL, "scheme must be 0, 1, 2, 3 or 4");
+        if (value != TTI_SIX && value != TTI_FUSED && value != TTI_FOUR && value != TTI_SPLIT)
+            return fail(PROP_EINVAL, "scheme must be 0, 2, 3 or 4");
         if (value == TTI_SPLIT && h->R > tti_split_max_radius())
             return fail(PROP_EINVAL, "the split scheme supports space orders up to %d", 2 * tti_split_max_radius());
         if (value == TTI_SPLIT && !fused_fits(h->g))

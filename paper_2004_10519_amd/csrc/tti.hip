@@ -27,7 +27,7 @@ namespace {
 // Rows per thread drop to 1 for the widest stencils to keep the register queues in budget.
 template <int R> constexpr int ny1_of() { return R <= 6 ? 2 : 1; }
 
-// SCH: TTI_SIX (t and s), TTI_SCALAR (n . grad u and n . grad v), TTI_FOUR (t and n . grad v)
+// SCH: TTI_SIX (t and s), TTI_FOUR (t and n . grad v)
 template <int R, int NY, int BY, bool ADJ, int SCH>
 __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W)
@@ -143,20 +143,15 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass1(const TTIJob *__restri
                 const float wp = n0[r] * dpx + n1[r] * dpy + n2[r] * dpz;
                 const float wq = n0[r] * dqx + n1[r] * dqy + n2[r] * dqz;
                 const int64_t si = sidx(w, gx, y, z);
-                if (SCH == TTI_SCALAR) {
-                    gst(J.t[0], si, wp);
-                    gst(J.t[1], si, wq);
+                gst(J.t[0], si, dpx - n0[r] * wp);
+                gst(J.t[1], si, dpy - n1[r] * wp);
+                gst(J.t[2], si, dpz - n2[r] * wp);
+                if (SCH == TTI_FOUR) {
+                    gst(J.s[0], si, wq);
                 } else {
-                    gst(J.t[0], si, dpx - n0[r] * wp);
-                    gst(J.t[1], si, dpy - n1[r] * wp);
-                    gst(J.t[2], si, dpz - n2[r] * wp);
-                    if (SCH == TTI_FOUR) {
-                        gst(J.s[0], si, wq);
-                    } else {
-                        gst(J.s[0], si, n0[r] * wq);
-                        gst(J.s[1], si, n1[r] * wq);
-                        gst(J.s[2], si, n2[r] * wq);
-                    }
+                    gst(J.s[0], si, n0[r] * wq);
+                    gst(J.s[1], si, n1[r] * wq);
+                    gst(J.s[2], si, n2[r] * wq);
                 }
             }
         }
@@ -400,251 +395,6 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_pass2(const TTIJob *__restri
     }
 }
 
-// Scalar scheme, pass 2.  Pass 1 stored only wp = n . grad u and wq = n . grad v; here
-//     H0 u = div t,  t = grad u - n wp,        Hz v = div s,  s = n wq,
-// with every intermediate zero outside the window (the same operators as the six-field scheme).
-// Per plane z: u with 2R-wide halos is staged in LDS; t0, s0 (tile and x-halo) and t1, s1 (tile
-// and y-halo) are formed in LDS from it and from wp, wq and the axis at those points; t2 and s2
-// sit in register queues over planes z-R .. z+R whose leading plane z+R is formed from a register
-// queue of u over planes z .. z+2R.  A chunk starts 2R planes early to fill the queues.  Two
-// barriers per plane; the next plane's loads are in flight during the compute.
-template <int R, int BY, int MODE>
-__global__ __launch_bounds__(PROP_TX * BY) void tti_pass2s(const TTIJob *__restrict__ jobs,
-                                                        const Tile *__restrict__ tiles, int zc, int par, Weights W,
-                                                        float idt2, int seg_step)
-{
-    constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
-    constexpr bool ADJ = (MODE == K2_ADJ || MODE == K2_ADJ_IC);
-    using UP = Plane<2 * R, TY>;
-    using UH = Halo<2 * R, TY, NT>;
-    using WH = Halo<R, TY, NT>;
-    using XP = XPlane<R, TY>;
-    using YP = YPlane<R, TY>;
-    __shared__ float Lu[UP::SIZE], Lt0[XP::SIZE], Ls0[XP::SIZE], Lt1[YP::SIZE], Ls1[YP::SIZE];
-
-    const Tile tl = tiles[blockIdx.x];
-    const TTIJob &J = jobs[tl.job];
-    const Win w = J.w;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * PROP_TX + tx;
-    const int x0 = tl.x0, y0 = tl.y0, z0 = tl.z0, z1 = min(z0 + zc, w.nz);
-    const int gx = x0 + tx, gy = y0 + ty;
-    const bool own_in = gx < w.nx && gy < w.ny;
-    const float *__restrict__ U = ADJ ? J.wmix[par][0] : J.p[par];
-    const float *__restrict__ WP = J.t[0];
-    const float *__restrict__ WQ = J.t[1];
-    const float *__restrict__ pc = J.p[par];
-    const float *__restrict__ qc = J.q[par];
-    float *__restrict__ pn = J.p[par ^ 1];   // holds the previous level, receives the new one
-    float *__restrict__ qn = J.q[par ^ 1];
-    auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
-    };
-    auto ldm = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? gld(f, midx(w, x, y, z)) : 0.f;
-    };
-
-    const int zs = z0 - 2 * R;
-    float uq[Q], t2q[Q], s2q[Q];
-    // before the first shift, uq slot s holds plane zs + s - 1 (s = 1 .. 2R)
-#pragma unroll
-    for (int s = 0; s < Q; ++s) {
-        uq[s] = s >= 1 ? ld(U, gx, gy, zs + s - 1) : 0.f;
-        t2q[s] = 0.f;
-        s2q[s] = 0.f;
-    }
-    float nu, lwp, lwq, ln0, ln1;                       // u at z+2R; wp, wq, axis at z+R
-    float cwp = 0.f, cwq = 0.f, cn0 = 0.f, cn1 = 0.f;   // own wp, wq, axis at z
-    float hux[UH::NXH], huy[UH::NYH];                   // u halo items of plane z
-    float hxw[WH::NXH], hxq[WH::NXH], hxn[WH::NXH];     // x-halo wp, wq, n0 of plane z
-    float hyw[WH::NYH], hyq[WH::NYH], hyn[WH::NYH];     // y-halo wp, wq, n1 of plane z
-    auto fetch_lead = [&](int z) {
-        nu = ld(U, gx, gy, z + 2 * R);
-        lwp = ld(WP, gx, gy, z + R);
-        lwq = ld(WQ, gx, gy, z + R);
-        ln0 = ldm(J.nx, gx, gy, z + R);
-        ln1 = ldm(J.ny, gx, gy, z + R);
-    };
-    auto fetch_plane = [&](int z) {
-        cwp = ld(WP, gx, gy, z);
-        cwq = ld(WQ, gx, gy, z);
-        cn0 = ldm(J.nx, gx, gy, z);
-        cn1 = ldm(J.ny, gx, gy, z);
-#pragma unroll
-        for (int k = 0; k < UH::NXH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < UH::NXI) UH::xitem(i, yy, xx);
-            hux[k] = i < UH::NXI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < UH::NYH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < UH::NYI) UH::yitem(i, yy, xx);
-            huy[k] = i < UH::NYI ? ld(U, x0 + xx, y0 + yy, z) : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < WH::NXH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < WH::NXI) WH::xitem(i, yy, xx);
-            const bool v = i < WH::NXI;
-            hxw[k] = v ? ld(WP, x0 + xx, y0 + yy, z) : 0.f;
-            hxq[k] = v ? ld(WQ, x0 + xx, y0 + yy, z) : 0.f;
-            hxn[k] = v ? ldm(J.nx, x0 + xx, y0 + yy, z) : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < WH::NYH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < WH::NYI) WH::yitem(i, yy, xx);
-            const bool v = i < WH::NYI;
-            hyw[k] = v ? ld(WP, x0 + xx, y0 + yy, z) : 0.f;
-            hyq[k] = v ? ld(WQ, x0 + xx, y0 + yy, z) : 0.f;
-            hyn[k] = v ? ldm(J.ny, x0 + xx, y0 + yy, z) : 0.f;
-        }
-    };
-    fetch_lead(zs);
-    for (int z = zs; z < z1; ++z) {
-        // shift the u queue (now planes z .. z+2R) and form t2, s2 of plane z+R
-#pragma unroll
-        for (int s = 0; s < Q - 1; ++s) {
-            uq[s] = uq[s + 1];
-            t2q[s] = t2q[s + 1];
-            s2q[s] = s2q[s + 1];
-        }
-        uq[Q - 1] = nu;
-        {
-            const bool lin = own_in && (unsigned)(z + R) < (unsigned)w.nz;
-            const float duz = dc_q<R>(uq, W.wz);
-            const float n2 = axis_z(ln0, ln1);
-            t2q[Q - 1] = lin ? duz - n2 * lwp : 0.f;
-            s2q[Q - 1] = lin ? n2 * lwq : 0.f;
-        }
-        if (z < z0) {   // filling the queues (block-uniform)
-            fetch_lead(z + 1);
-            if (z + 1 == z0) fetch_plane(z0);
-            continue;
-        }
-        // stage u of plane z; keep plane z's own and halo values for the t, s formation
-        Lu[UP::at(ty, tx)] = uq[0];
-#pragma unroll
-        for (int k = 0; k < UH::NXH; ++k) {
-            const int i = tid + k * NT;
-            if (i < UH::NXI) {
-                int yy, xx;
-                UH::xitem(i, yy, xx);
-                Lu[UP::at(yy, xx)] = hux[k];
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < UH::NYH; ++k) {
-            const int i = tid + k * NT;
-            if (i < UH::NYI) {
-                int yy, xx;
-                UH::yitem(i, yy, xx);
-                Lu[UP::at(yy, xx)] = huy[k];
-            }
-        }
-        const float pwp = cwp, pwq = cwq, pn0 = cn0, pn1 = cn1;
-        float xw[WH::NXH], xq[WH::NXH], xn[WH::NXH], yw[WH::NYH], yq[WH::NYH], yn[WH::NYH];
-#pragma unroll
-        for (int k = 0; k < WH::NXH; ++k) xw[k] = hxw[k], xq[k] = hxq[k], xn[k] = hxn[k];
-#pragma unroll
-        for (int k = 0; k < WH::NYH; ++k) yw[k] = hyw[k], yq[k] = hyq[k], yn[k] = hyn[k];
-        __syncthreads();
-        // per-point values of plane z for the update, then the prefetch of plane z+1
-        float vp0, vq0, vp1, vq1, vm, vA, vB, fpk = 0.f, fqk = 0.f, vg = 0.f;
-        {
-            const int64_t si = sidx(w, own_in ? gx : 0, own_in ? gy : 0, z);
-            const int64_t mi = midx(w, own_in ? gx : 0, own_in ? gy : 0, z);
-            vp0 = gld(pc, si);
-            vq0 = gld(qc, si);
-            vp1 = gld(pn, si);
-            vq1 = gld(qn, si);
-            vm = gld(J.m, mi) * idt2 + 0.f;
-            vA = gld(J.A, mi);
-            vB = gld(J.B, mi);
-            if (MODE == K2_ADJ_IC) {
-                seg_load(J, seg_step, own_in ? gx : 0, own_in ? gy : 0, z, si, fpk, fqk);
-                vg = gld(J.grad, si);
-            }
-        }
-        if (z + 1 < z1) {
-            fetch_lead(z + 1);
-            fetch_plane(z + 1);
-        }
-        // t0, t1, s0, s1 of plane z: own points, x-halo (t0, s0) and y-halo (t1, s1)
-        {
-            const int li = UP::at(ty, tx);
-            const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
-            Lt0[XP::at(ty, tx)] = own_in ? dux - pn0 * pwp : 0.f;
-            Ls0[XP::at(ty, tx)] = own_in ? pn0 * pwq : 0.f;
-            Lt1[YP::at(ty, tx)] = own_in ? duy - pn1 * pwp : 0.f;
-            Ls1[YP::at(ty, tx)] = own_in ? pn1 * pwq : 0.f;
-        }
-#pragma unroll
-        for (int k = 0; k < WH::NXH; ++k) {
-            const int i = tid + k * NT;
-            if (i < WH::NXI) {
-                int yy, xx;
-                WH::xitem(i, yy, xx);
-                const bool in = in_win(w, x0 + xx, y0 + yy, z);
-                const float d = dc_lds_x<R>(Lu, UP::at(yy, xx), W.wx);
-                Lt0[XP::at(yy, xx)] = in ? d - xn[k] * xw[k] : 0.f;
-                Ls0[XP::at(yy, xx)] = in ? xn[k] * xq[k] : 0.f;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < WH::NYH; ++k) {
-            const int i = tid + k * NT;
-            if (i < WH::NYI) {
-                int yy, xx;
-                WH::yitem(i, yy, xx);
-                const bool in = in_win(w, x0 + xx, y0 + yy, z);
-                const float d = dc_lds_y<R, UP::LX>(Lu, UP::at(yy, xx), W.wy);
-                Lt1[YP::at(yy, xx)] = in ? d - yn[k] * yw[k] : 0.f;
-                Ls1[YP::at(yy, xx)] = in ? yn[k] * yq[k] : 0.f;
-            }
-        }
-        __syncthreads();
-        const float h0 = dc_lds_x<R>(Lt0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(ty, tx), W.wy) +
-                         dc_q<R>(t2q, W.wz);
-        const float hz = dc_lds_x<R>(Ls0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Ls1, YP::at(ty, tx), W.wy) +
-                         dc_q<R>(s2q, W.wz);
-        if (own_in) {
-            const int64_t si = sidx(w, gx, gy, z);
-            float Lp, Lq;
-            if (ADJ) {
-                Lp = h0;
-                Lq = hz;
-            } else {
-                Lp = vA * h0 + vB * hz;
-                Lq = vB * h0 + hz;
-            }
-            const float e = gld(J.ex, gx) + gld(J.ey, gy) + gld(J.ez, z);
-            const float ra = 1.0f / (vm + e);
-            const float cc = vm - e;
-            const float np_ = (2.f * vm * vp0 - cc * vp1 + Lp) * ra;
-            const float nq_ = (2.f * vm * vq0 - cc * vq1 + Lq) * ra;
-            gst(pn, si, np_);
-            gst(qn, si, nq_);
-            if (ADJ) {
-                gst(J.wmix[par ^ 1][0], si, vA * np_ + vB * nq_);
-                gst(J.wmix[par ^ 1][1], si, vB * np_ + nq_);
-            }
-            if (MODE == K2_FWD_STORE && J.seg_dtype == 0) {
-                float *sp = J.seg + (int64_t)seg_step * 2 * J.seg_field;
-                gst(sp, si, np_);
-                gst(sp, J.seg_field + si, nq_);
-            }
-            if (MODE == K2_ADJ_IC)
-                gst(J.grad, si, J.image ? vg + (fpk * np_ + fqk * nq_)
-                                        : vg - idt2 * (fpk * (np_ - 2.f * vp0 + vp1) + fqk * (nq_ - 2.f * vq0 + vq1)));
-        }
-    }
-}
-
 template <int R, int BY, int SCH>
 void p1_launch(bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
                hipStream_t st)
@@ -667,9 +417,8 @@ template <int R>
 void p1_dispatch(int scheme, int shape, bool adj, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, hipStream_t st)
 {
-    if (scheme == TTI_SCALAR)    p1_shape<R, TTI_SCALAR>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
-    else if (scheme == TTI_FOUR) p1_shape<R, TTI_FOUR>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
-    else                         p1_shape<R, TTI_SIX>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
+    if (scheme == TTI_FOUR) p1_shape<R, TTI_FOUR>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
+    else                    p1_shape<R, TTI_SIX>(shape, adj, jobs, tiles, ntiles, zc, par, W, st);
 }
 
 template <int R, int BY, bool FOUR>
@@ -697,36 +446,11 @@ void p2_launch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int 
     }
 }
 
-template <int R, int BY>
-void p2s_launch(int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par, const Weights &W,
-                float idt2, int seg_step, hipStream_t st)
-{
-    dim3 blk(PROP_TX, BY), grd(ntiles);
-    switch (mode) {
-    case K2_FWD:
-        hipLaunchKernelGGL((tti_pass2s<R, BY, K2_FWD>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
-        break;
-    case K2_FWD_STORE:
-        hipLaunchKernelGGL((tti_pass2s<R, BY, K2_FWD_STORE>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2,
-                           seg_step);
-        break;
-    case K2_ADJ:
-        hipLaunchKernelGGL((tti_pass2s<R, BY, K2_ADJ>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
-        break;
-    default:
-        hipLaunchKernelGGL((tti_pass2s<R, BY, K2_ADJ_IC>), grd, blk, 0, st, jobs, tiles, zc, par, W, idt2, seg_step);
-        break;
-    }
-}
-
 template <int R>
 void p2_dispatch(int scheme, int shape, int mode, const TTIJob *jobs, const Tile *tiles, int ntiles, int zc, int par,
                  const Weights &W, float idt2, int seg_step, hipStream_t st)
 {
-    if (scheme == TTI_SCALAR) {
-        if (shape == 1) p2s_launch<R, 16>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
-        else            p2s_launch<R, 8>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
-    } else if (scheme == TTI_FOUR) {
+    if (scheme == TTI_FOUR) {
         if (shape == 1) p2_launch<R, 16, true>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
         else            p2_launch<R, 8, true>(mode, jobs, tiles, ntiles, zc, par, W, idt2, seg_step, st);
     } else {

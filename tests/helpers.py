@@ -65,9 +65,9 @@ def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20, free_surfac
 
 
 def make_tti(case, prop, scheme=0, **options):
-    """TTI propagator for a test case; scheme 0 = six-field pass-1 temporaries, 1 = scalar projections,
-    2 = one fused pass, 3 = four-field temporaries (t and n . grad q), 4 = two fused single-field
-    passes (schemes 2 and 4 support space orders up to 12: the test is skipped beyond)."""
+    """TTI propagator for a test case; scheme 0 = six-field pass-1 temporaries, 2 = one fused pass,
+    3 = four-field temporaries (t and n . grad q), 4 = two fused single-field passes (schemes 2 and 4
+    support space orders up to 12: the test is skipped beyond)."""
     if scheme in (2, 4) and case["so"] > 12:
         import pytest
         pytest.skip("the fused and split schemes support space orders up to 12")

@@ -24,8 +24,8 @@ BF16_REASON = ("BF16 keeps 8 mantissa bits: a checkpoint level carries a relativ
                "2^-9, above the 1e-3 gradient bar (measured 4.7e-3 here, 2.0e-3 on the 64^3 case); FP16 meets it")
 
 
-# two passes (six-field / scalar / four-field temporaries), one fused pass, two fused single-field passes
-SCHEMES = [0, 1, 2, 3, 4]
+# two passes (six-field / four-field temporaries), one fused pass, two fused single-field passes
+SCHEMES = [0, 2, 3, 4]
 
 
 @pytest.mark.parametrize("scheme", SCHEMES)
@@ -178,24 +178,24 @@ def test_four_field_scheme_bitwise_equals_six(prop, so, shape):
 
 
 @pytest.mark.parametrize("so", [4, 8, 12, 16])
-def test_scalar_scheme_tiles_and_chunks(prop, so):
-    """Scalar scheme: both tile variants of each pass and short z-chunks (more chunk seams and queue
-    refills) give the traces of its default launch to 1e-6, and the six-field scheme's to 1e-5 (the
-    two schemes round differently: the axis component n_z is re-formed from n_x, n_y, and the
-    vectors are formed in the other pass)."""
+def test_six_field_scheme_tiles_and_chunks(prop, so):
+    """Six-field scheme: both tile variants of each pass and short z-chunks (more chunk seams and
+    queue refills) give the traces of its default launch bit for bit (every point is computed by the
+    same expressions); pass 2 takes pass 1's z-chunk unless its own is set."""
     case = tti_case((83, 29, 41), so, 5, 60)
     p0, shot = make_tti(case, prop, 0)
-    six = host(p0.forward(shot)).copy()
-    p1, shot = make_tti(case, prop, 1)
-    ref = host(p1.forward(shot)).copy()
-    assert rel_l2(ref, six) <= 1e-5, rel_l2(ref, six)
+    ref = host(p0.forward(shot)).copy()
     for t1 in (0, 1):
         for t2 in (0, 1):
             for zc in (0, 5):
-                p, shot = make_tti(case, prop, 1, tile1=t1, tile2=t2, zc=zc)
-                d = host(p.forward(shot))
-                assert rel_l2(d, ref) <= 1e-6, (t1, t2, zc, rel_l2(d, ref))
-                assert p.get_option("info_zc2") == (zc if zc else p.get_option("info_zc1"))
+                p, shot = make_tti(case, prop, 0, tile1=t1, tile2=t2, zc=zc)
+                assert np.array_equal(host(p.forward(shot)), ref), (t1, t2, zc)
+                assert p.get_option("info_zc2") == p.get_option("info_zc1")
+                if zc:
+                    assert p.get_option("info_zc1") == zc
+    p, shot = make_tti(case, prop, 0, zc=7, zc2=4)
+    assert np.array_equal(host(p.forward(shot)), ref)
+    assert (p.get_option("info_zc1"), p.get_option("info_zc2")) == (7, 4)
 
 
 @pytest.mark.parametrize("so", [2, 4, 8, 12])
@@ -221,6 +221,11 @@ def test_fused_scheme_rejects_wide_stencils(prop):
     p, _ = make_tti(case, prop, 0)
     with pytest.raises(prop.PropError, match="space orders up to 12"):
         p.set_option("scheme", 2)
+    with pytest.raises(prop.PropError, match="space orders up to 12"):
+        p.set_option("scheme", 4)
+    for bad in (1, 5, -1):
+        with pytest.raises(prop.PropError, match="scheme must be"):
+            p.set_option("scheme", bad)
 
 
 def test_codec_bit_exact(prop, orc):
