@@ -46,11 +46,12 @@ HBM_PEAK_GBS = 8000.0
 # Elastic:
 #   el_vel:    read 9 fields + buoyancy; write 3                                  -> 13 x 4
 #   el_stress: read 9 fields + lambda, mu; write 6                                -> 17 x 4
+#   el_fused:  read 9 fields + lambda, mu, buoyancy; write 9 (one step)           -> 21 x 4
 TTI_KERNEL_BYTES = {(0, 0, False): 40, (0, 1, False): 60, (0, 0, True): 40, (0, 1, True): 68,
                     (2, 1, False): 44, (2, 1, True): 60,
                     (3, 0, False): 32, (3, 1, False): 60, (3, 0, True): 32, (3, 1, True): 68,
                     (4, 0, False): 16, (4, 1, False): 48, (4, 0, True): 16, (4, 1, True): 60}
-KERNEL_BYTES_PER_PT = {2: 52, 3: 68}
+KERNEL_BYTES_PER_PT = {2: 52, 3: 68, 4: 84}
 TTI_SCHEME = None   # step scheme of every TTI handle (--scheme); None = the library default
 FIXED_TILES = None  # (tile1, zc1, tile2, zc2) of the main run instead of the autotuner (--tiles)
 
@@ -240,12 +241,19 @@ def measure_elastic(torch, prop, nt):
     torch.cuda.synchronize()
     p.set_timing(True)
     t = timed(torch, lambda: p.forward(shot), 1, 0)
-    roof = kernel_roof(p, (2, 3), w.npts)
+    roof = kernel_roof(p, (2, 3, 4), w.npts)
     p.set_timing(False)
     rec = torch.randn((w.nt, len(w.rec_xyz)), device="cuda")
     torch.cuda.synchronize()
     ta = timed(torch, lambda: p.adjoint(shot, rec), 1, 0)
     g, ga = w.npts * w.nt / t / 1e9, w.npts * w.nt / ta / 1e9
+    # the fused velocity-stress step (opt-in; bitwise the same traces)
+    p.set_option("el_fused", 1)
+    p.set_timing(True)
+    tf = timed(torch, lambda: p.forward(shot), 1, 0)
+    roof_f = kernel_roof(p, (4,), w.npts)
+    p.set_timing(False)
+    p.set_option("el_fused", 0)
     # gradient with respect to (vp, vs, rho), 48 FP32 checkpoints (a residual-shaped random input:
     # the cost does not depend on the values)
     log("[bench] elastic gradient ...")
@@ -256,7 +264,8 @@ def measure_elastic(torch, prop, nt):
             "forward_GPts/s": round(g, 3), "adjoint_GPts/s": round(ga, 3),
             "gradient_vp_vs_rho_GPts/s": round(gg, 3), "gradient_checkpoints": 48,
             "forward_method_hbm_frac": round(g * METHOD_BYTES_PER_PT["elastic"] / HBM_PEAK_GBS, 4),
-            "forward_kernels": roof}
+            "forward_kernels": roof,
+            "forward_fused_step_GPts/s": round(w.npts * w.nt / tf / 1e9, 3), "forward_fused_kernel": roof_f}
 
 
 def measure_marine(torch, prop):

@@ -214,8 +214,9 @@ int prop_read_state(prop_t h, int32_t field, float *out);
 
 /* Kernel timing: when enabled, every stencil launch is bracketed by HIP events on the handle's
  * stream.  prop_kernel_time returns, for kernel class k (0 = the TTI gradient/mix pass, 1 = the
- * TTI divergence/update pass, 2 = elastic velocity pass, 3 = elastic stress pass), the summed
- * milliseconds and the number of launches since the last reset, and names the class. */
+ * TTI divergence/update pass, 2 = elastic velocity pass, 3 = elastic stress pass, 4 = the fused
+ * elastic step), the summed milliseconds and the number of launches since the last reset, and
+ * names the class. */
 int prop_set_timing(prop_t h, int32_t enable);
 int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name);
 
@@ -237,6 +238,12 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
  *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default).
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
+ *   PROP_OPT_EL_FUSED  0/1 (default 0): elastic prop_forward on 3D grids up to space order 8 runs
+ *                      one fused velocity-stress launch a step (kernel class 4) instead of the
+ *                      velocity and stress passes (classes 2 and 3): the same expressions, so the
+ *                      same bits, and fewer HBM bytes, but slower on this chip (its register and
+ *                      LDS budget allows only 32 x 16 tiles and half the waves per CU).  The
+ *                      adjoint and the gradient always run the two passes.
  *   PROP_OPT_BATCH_MB  device-memory budget of the batched shot-group planner in MiB,
  *                      0 = 85 % of the free memory (default).
  *   PROP_OPT_SCHEME    TTI step scheme: 0 = two passes, pass 1 stores the six components of
@@ -264,6 +271,7 @@ enum {
     PROP_OPT_BATCH_MB = 7,
     PROP_OPT_SCHEME = 8,
     PROP_OPT_ZC2 = 9,
+    PROP_OPT_EL_FUSED = 10,
     PROP_INFO_TILE1 = 101,
     PROP_INFO_TILE2 = 102,
     PROP_INFO_ZC1 = 103,

@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INC = os.path.join(os.path.dirname(HERE), "include")
 OUT = os.path.join(HERE, "libprop.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["prop.hip", "tti.hip", "tti_fused.hip", "tti_split.hip", "elastic.hip", "aux.hip"]
+SOURCES = ["prop.hip", "tti.hip", "tti_fused.hip", "tti_split.hip", "elastic.hip", "el_fused.hip", "aux.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-I", INC, "-I", CSRC]
 

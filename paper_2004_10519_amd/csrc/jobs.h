@@ -62,6 +62,16 @@ struct ElJob {
     const float *gx, *gy, *gz;    // absorbing layer: exp(-kappa_a dt) per window axis
 };
 
+// The fused elastic step (3D): reads the state (vi, ti) and writes the next state (vo, to); the two
+// sets must not overlap.
+struct ElFusedJob {
+    Win w;
+    const float *vi[3], *ti[6];   // v and tau of the step's start (state layout)
+    float *vo[3], *to[6];         // v+ and tau+ (state layout)
+    const float *lam, *mu, *b;    // lambda, mu, buoyancy (model layout)
+    const float *gx, *gy, *gz;    // absorbing layer: exp(-kappa_a dt) per window axis
+};
+
 // Elastic gradient: the imaging condition of one adjoint step, and the final spread to the nodes.
 struct ElGradJob {
     Win w;
@@ -98,6 +108,13 @@ void launch_tti_fused(int R, int shape, int mode, const TTIJob *jobs, const Tile
                       const Weights &W, float idt2, int seg_step, hipStream_t st);
 
 enum { EL_FWD = 0, EL_ADJ = 1 };
+// The fused elastic step supports space orders up to 2 * el_fused_max_radius() on 3D windows; its
+// tiles are EF_TX x EF_TY (one block of EF_TX * EF_TY threads per CU: 256 registers a lane).
+#define EF_TX 32
+#define EF_TY 16
+int el_fused_max_radius();
+void launch_el_fused(int R, const ElFusedJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W, float dt,
+                     hipStream_t st);
 // by: tile rows of the launch (el_tile_rows); the tiles must have been made with that height.
 void launch_el_vel(int R, int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc,
                    const Weights &W, float dt, hipStream_t st);

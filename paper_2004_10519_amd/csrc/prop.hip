@@ -212,6 +212,8 @@ struct Slot {
     DevBuf job_fwd, job_adj;    // TTIJob / ElJob on the device
     DevBuf tiles, tiles2;        // tile lists (TTI: pass 1 and pass 2 use different tile heights)
     int ntiles = 0, ntiles2 = 0, zc = 0;
+    DevBuf tiles_ef, job_ef;     // elastic fused step: its tiles and its two jobs (one per buffer set)
+    int ntiles_ef = 0, zc_ef = 0;
     int nsrc = 0, nrec = 0;
 };
 
@@ -238,14 +240,15 @@ struct prop_s {
     // timing
     bool timing = false;
     std::vector<hipEvent_t> evpool;
-    std::vector<std::pair<int, int>> pending[4];
+    std::vector<std::pair<int, int>> pending[5];
     int evnext = 0;
-    double ms[4] = {0, 0, 0, 0};
-    int64_t launches[4] = {0, 0, 0, 0};
+    double ms[5] = {0, 0, 0, 0, 0};
+    int64_t launches[5] = {0, 0, 0, 0, 0};
     int last_state = 0;         // 0 none, 1 forward, 2 adjoint
     int last_groups = 0;        // shot groups used by the last batched call
     // options (prop_set_option)
     int opt_graph = 0, opt_autotune = 0, opt_xcd = 0;
+    int opt_el_fused = 0;       // elastic forward: the fused velocity-stress step where it applies
     int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
     int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1)
@@ -304,14 +307,14 @@ int tile_rows(const prop_s *h, int pass, int shape)
 // Tiles of a set of windows in spatial order (x fastest, then y, then z chunk of zc planes).  With
 // the XCD option the order is dealt round-robin over the 8 XCDs so that each XCD gets a contiguous
 // range of neighbouring tiles (measured on the 512^3 workload: plain order is ~3% faster).
-void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std::vector<Tile> &out)
+void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std::vector<Tile> &out, int TX = PROP_TX)
 {
     std::vector<Tile> sp;
     for (size_t j = 0; j < slots.size(); ++j) {
         const Win &w = slots[j]->w;
         for (int z0 = 0; z0 < w.nz; z0 += zc)
             for (int y0 = 0; y0 < w.ny; y0 += TY)
-                for (int x0 = 0; x0 < w.nx; x0 += PROP_TX) sp.push_back(Tile{(int)j, x0, y0, z0});
+                for (int x0 = 0; x0 < w.nx; x0 += TX) sp.push_back(Tile{(int)j, x0, y0, z0});
     }
     const size_t T = sp.size(), X = xcd ? 8 : 1;
     out.assign(T, Tile{});
@@ -600,10 +603,10 @@ hipEvent_t next_event(prop_s *h)
 int fold_timing(prop_s *h)
 {
     bool any = false;
-    for (int k = 0; k < 4; ++k) any |= !h->pending[k].empty();
+    for (int k = 0; k < 5; ++k) any |= !h->pending[k].empty();
     if (!any) return PROP_OK;
     HIPCHK(hipStreamSynchronize(h->st));
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < 5; ++k) {
         for (auto &pr : h->pending[k]) {
             float ms = 0;
             HIPCHK(hipEventElapsedTime(&ms, h->evpool[pr.first], h->evpool[pr.second]));
@@ -1636,6 +1639,74 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
 // 3D; txx, tzz in 2D, where the stress tensor is 2 x 2 (tyy is then not part of it).
 float *tyy_of(const prop_s *h, const Slot &sl) { return h->g.ndim == 3 ? sl.f[4] : nullptr; }
 
+// The fused velocity-stress step (one launch a step, double-buffered state) applies to 3D windows
+// up to space order 2 * el_fused_max_radius(); the two-pass step serves the rest.
+bool el_fused_on(const prop_s *h)
+{
+    return h->kind == PROP_ELASTIC && h->g.ndim == 3 && h->R <= el_fused_max_radius() && h->opt_el_fused;
+}
+
+// z-chunks of the fused step: it recomputes v+ on 2R planes beyond each chunk and holds one block
+// per CU, so the chunk count trades that recomputation against whole waves of blocks.
+int choose_zc_ef(const prop_s *h, int nz, int64_t txy)
+{
+    if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        ncu = 256;
+    const int maxch = std::max(1, nz / (4 * h->R));
+    double best = -1.0;
+    int bz = nz;
+    for (int nch = 1; nch <= maxch; ++nch) {
+        const int zc = (nz + nch - 1) / nch;
+        const int64_t nb = txy * ((nz + zc - 1) / zc);
+        const double fill = (double)nb / (double)(((nb + ncu - 1) / ncu) * ncu);
+        const double len = (double)nz / (double)((nz + zc - 1) / zc);
+        const double eff = fill * len / (len + 2.0 * h->R);
+        if (eff > best + 1e-9) {
+            best = eff;
+            bz = zc;
+        }
+    }
+    return bz;
+}
+
+// Tiles and the two jobs of the fused step: job k reads buffer set k (fields 9k .. 9k+8 of the
+// slot: v, then tau) and writes set k ^ 1.
+int el_fused_setup(prop_s *h, Slot &sl)
+{
+    const Win &w = sl.w;
+    const int64_t txy = (int64_t)((w.nx + EF_TX - 1) / EF_TX) * ((w.ny + EF_TY - 1) / EF_TY);
+    sl.zc_ef = choose_zc_ef(h, w.nz, txy);
+    std::vector<Slot *> one{&sl};
+    std::vector<Tile> tiles;
+    make_tiles(one, EF_TY, sl.zc_ef, h->opt_xcd, tiles, EF_TX);
+    sl.ntiles_ef = (int)tiles.size();
+    TRY(upload(sl.tiles_ef, tiles, h->st));
+    std::vector<ElFusedJob> jobs(2);
+    const float *tab = sl.tabs.as<float>();
+    for (int k = 0; k < 2; ++k) {
+        ElFusedJob &J = jobs[k];
+        J.w = w;
+        for (int i = 0; i < 3; ++i) {
+            J.vi[i] = sl.f[9 * k + i];
+            J.vo[i] = sl.f[9 * (k ^ 1) + i];
+        }
+        for (int i = 0; i < 6; ++i) {
+            J.ti[i] = sl.f[9 * k + 3 + i];
+            J.to[i] = sl.f[9 * (k ^ 1) + 3 + i];
+        }
+        J.lam = h->c[0];
+        J.mu = h->c[1];
+        J.b = h->c[2];
+        J.gx = tab;
+        J.gy = tab + w.nx;
+        J.gz = tab + w.nx + w.ny;
+    }
+    return upload(sl.job_ef, jobs, h->st);
+}
+
 void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
 {
     const float dt = (float)h->g.dt;
@@ -1678,22 +1749,36 @@ int el_forward(prop_s *h, const prop_shot *s, float *rec_out, int save, int dtyp
     }
     aux_fill(sl.f[0], 9 * sl.plane, 0.f, h->st);
     const ElJob *job = sl.job_fwd.as<ElJob>();
+    const bool fused = el_fused_on(h);
+    if (fused) TRY(el_fused_setup(h, sl));
     const float dt = (float)h->g.dt;
     for (int n = 0; n < N; ++n) {
-        el_step_fwd(h, sl, job);
-        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, sl.f[3], tyy_of(h, sl),
-                                   sl.f[5], h->st);
+        // the state after the step: buffer set 0 (fields 0-8), or with the fused step set (n + 1) & 1
+        const int cur = fused ? (n + 1) & 1 : 0;
+        float *const *F = sl.f + 9 * cur;
+        if (fused) {
+            Timed t(h, 4);
+            launch_el_fused(h->R, sl.job_ef.as<ElFusedJob>() + (n & 1), sl.tiles_ef.as<Tile>(), sl.ntiles_ef,
+                            sl.zc_ef, h->W, dt, h->st);
+        } else {
+            el_step_fwd(h, sl, job);
+        }
+        float *tyy = h->g.ndim == 3 ? F[4] : nullptr;
+        if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, F[3], tyy, F[5], h->st);
         float *row = s->nrec ? rec_out + (size_t)n * s->nrec : nullptr;
-        if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], 1.f, row, h->st);
-        if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, sl.f[2], nullptr, nullptr, 1.f, row, h->st);
+        if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, F[3], tyy, F[5], 1.f, row, h->st);
+        if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, F[2], nullptr, nullptr, 1.f, row, h->st);
         if (save > 0 && (n + 1) % S == 0 && (n + 1) / S < C)
-            HIPCHK(hipMemcpyAsync(h->ckpt.as<float>() + (size_t)((n + 1) / S - 1) * 9 * P, sl.f[0],
+            HIPCHK(hipMemcpyAsync(h->ckpt.as<float>() + (size_t)((n + 1) / S - 1) * 9 * P, F[0],
                                   9 * P * sizeof(float), hipMemcpyDeviceToDevice, h->st));
         if ((n + 1) % WATCH_EVERY == 0 || n + 1 == N) {
             HIPCHK(hipGetLastError());
-            TRY(check_finite(h, sl.f[5], sl.w));
+            TRY(check_finite(h, F[5], sl.w));
         }
     }
+    // the final state where every later call looks for it: buffer set 0
+    if (fused && (N & 1))
+        HIPCHK(hipMemcpyAsync(sl.f[0], sl.f[9], 9 * P * sizeof(float), hipMemcpyDeviceToDevice, h->st));
     if (save > 0) record_saved(h, s, save, dtype);
     h->last_state = 1;
     return PROP_OK;
@@ -2037,7 +2122,7 @@ int prop_set_timing(prop_t h, int32_t enable)
     if (!h) return fail(PROP_EINVAL, "handle is NULL");
     TRY(fold_timing(h));
     h->timing = enable != 0;
-    for (int k = 0; k < 4; ++k) h->ms[k] = 0, h->launches[k] = 0;
+    for (int k = 0; k < 5; ++k) h->ms[k] = 0, h->launches[k] = 0;
     return PROP_OK;
 }
 
@@ -2062,6 +2147,7 @@ int prop_set_option(prop_t h, int32_t option, int64_t value)
         h->opt_zc2 = (int)value;
         return PROP_OK;
     case PROP_OPT_XCD: h->opt_xcd = value != 0; return PROP_OK;
+    case PROP_OPT_EL_FUSED: h->opt_el_fused = value != 0; return PROP_OK;
     case PROP_OPT_BATCH_MB:
         if (value < 0) return fail(PROP_EINVAL, "batch budget must be >= 0");
         h->opt_batch_mb = value;
@@ -2096,6 +2182,7 @@ int prop_get_option(prop_t h, int32_t option, int64_t *value)
     case PROP_OPT_ZC2: *value = h->opt_zc2; break;
     case PROP_OPT_XCD: *value = h->opt_xcd; break;
     case PROP_OPT_BATCH_MB: *value = h->opt_batch_mb; break;
+    case PROP_OPT_EL_FUSED: *value = h->opt_el_fused; break;
     case PROP_OPT_SCHEME: *value = h->opt_scheme; break;
     case PROP_INFO_TILE1: *value = h->last_tune.shape[0]; break;
     case PROP_INFO_TILE2: *value = h->last_tune.shape[1]; break;
@@ -2111,9 +2198,10 @@ int prop_get_option(prop_t h, int32_t option, int64_t *value)
 int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, const char **name)
 {
     g_err.clear();
-    static const char *names[4] = {"tti_pass1 (gradient + axis projection)", "tti_pass2 (divergence + update)",
-                                   "el_vel (velocity pass)", "el_stress (stress pass)"};
-    if (!h || kclass < 0 || kclass > 3) return fail(PROP_EINVAL, "bad handle or kernel class");
+    static const char *names[5] = {"tti_pass1 (gradient + axis projection)", "tti_pass2 (divergence + update)",
+                                   "el_vel (velocity pass)", "el_stress (stress pass)",
+                                   "el_fused (velocity + stress)"};
+    if (!h || kclass < 0 || kclass > 4) return fail(PROP_EINVAL, "bad handle or kernel class");
     TRY(fold_timing(h));
     if (ms) *ms = h->ms[kclass];
     if (launches) *launches = h->launches[kclass];

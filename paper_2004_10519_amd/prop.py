@@ -28,6 +28,7 @@ EXPORTS = ["prop_create", "prop_cfl_dt", "prop_set_model", "prop_forward", "prop
 
 # option / info codes of prop_set_option and prop_get_option
 OPTIONS = {"graph": 1, "autotune": 2, "tile1": 3, "tile2": 4, "zc": 5, "xcd": 6, "batch_mb": 7, "scheme": 8, "zc2": 9,
+           "el_fused": 10,
            "info_tile1": 101, "info_tile2": 102, "info_zc1": 103, "info_zc2": 104, "info_graphs": 105,
            "info_groups": 106}
 
@@ -298,7 +299,7 @@ class Propagator:
         _check(lib().prop_set_timing(self._h, int(bool(enable))))
 
     def set_option(self, name: str, value: int):
-        """Set a run-time option: graph, autotune, tile1, tile2, zc, zc2, xcd, batch_mb, scheme."""
+        """Set a run-time option: graph, autotune, tile1, tile2, zc, zc2, xcd, batch_mb, scheme, el_fused."""
         _check(lib().prop_set_option(self._h, OPTIONS[name], int(value)))
 
     def get_option(self, name: str) -> int:

@@ -57,7 +57,7 @@ def el_case(shape, so, nbl, nt, seed=6, h=(10.0, 9.0, 8.0), nrec=20, free_surfac
     rec = np.stack([rng.uniform(0, 1, nrec) * ext[0], rng.uniform(0, 1, nrec) * ext[1],
                     rng.uniform(0.05, 0.95, nrec) * ext[2]], axis=1)
     kind = (np.arange(nrec) % 2).astype(np.int32)
-    dt = 0.8 * min(h) / (4725.0 * np.sqrt(3) * {4: 1.16667, 8: 1.28631, 12: 1.33906}[so])
+    dt = 0.8 * min(h) / (4725.0 * np.sqrt(3) * {2: 1.0, 4: 1.16667, 6: 1.24167, 8: 1.28631, 12: 1.33906}[so])
     wav = inputs.ricker(30.0, dt, nt)[:, None]
     return dict(shape=shape, h=h, so=so, nbl=nbl, nt=nt, dt=float(dt), model=model, src=src.astype(np.float32),
                 rec=rec.astype(np.float32), kind=kind, wav=np.ascontiguousarray(wav, dtype=np.float32),

@@ -32,6 +32,7 @@ def test_kernel_bytes(bench):
     assert bench.kernel_bytes(1, 3) == bench.kernel_bytes(1, 0)
     assert bench.kernel_bytes(1, 3, adjoint=True) == bench.kernel_bytes(1, 0, adjoint=True)
     assert bench.kernel_bytes(2) == 13 * 4 and bench.kernel_bytes(3) == 17 * 4
+    assert bench.kernel_bytes(4) == 21 * 4 == bench.METHOD_BYTES_PER_PT["elastic"]
 
 
 def test_traffic_lookup_follows_the_committed_counters(bench):

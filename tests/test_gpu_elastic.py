@@ -220,3 +220,49 @@ def test_free_surface_rejections(prop):
                     win_shape=(40, 20, 29))
     with pytest.raises(prop.PropError, match="starts at z index 0"):
         p.forward(off)
+
+
+# ---- the fused velocity-stress step (3D forward up to space order 8) against the two passes
+@pytest.mark.parametrize("so,shape,nt,zc,fs", [(8, (70, 37, 29), 61, 0, False), (8, (70, 37, 29), 60, 5, False),
+                                              (6, (45, 19, 33), 41, 7, False), (4, (66, 20, 40), 50, 0, False),
+                                              (2, (33, 17, 24), 37, 3, False), (8, (70, 37, 29), 47, 9, True),
+                                              (4, (66, 20, 40), 40, 0, True)])
+def test_fused_elastic_step_bitwise_equals_two_passes(prop, so, shape, nt, zc, fs):
+    """The fused step forms v+ and tau+ with the two passes' expressions, term for term, so traces
+    and every final field are equal bit for bit: ragged tiles in x and y, one and several z chunks
+    (short ones: many chunk seams, each recomputing v+ on 2R planes beyond it), an odd step count
+    (the final state is copied back to the first buffer set), the free surface."""
+    case = el_case(shape, so, 5, nt, free_surface=fs)
+    if fs:
+        case["src"][0, -1] = case["h"][2] * (case["nbl"] + 3.4)
+    out = []
+    for fused in (0, 1):
+        p, shot = make_el(case, prop)
+        p.set_option("el_fused", fused)
+        if zc:
+            p.set_option("zc", zc)
+        p.set_timing(True)
+        d = host(p.forward(shot)).copy()
+        f = [host(p.read_state(i)).copy() for i in range(9)]
+        launches = {k: p.kernel_time(k)[1] for k in (2, 3, 4)}
+        out.append((d, f, launches))
+        p.close()
+    (d0, f0, l0), (d1, f1, l1) = out
+    assert l0 == {2: nt, 3: nt, 4: 0} and l1 == {2: 0, 3: 0, 4: nt}, (l0, l1)
+    assert np.abs(d0).max() > 0
+    assert np.array_equal(d0, d1), rel_l2(d1, d0)
+    for i in range(9):
+        assert np.array_equal(f0[i], f1[i]), (i, rel_l2(f1[i], f0[i]))
+
+
+def test_fused_elastic_checkpoints_feed_the_gradient(prop):
+    """A saving forward on the fused step keeps the checkpoints of the buffer set that holds each
+    state; the gradient that reuses them equals the one that runs its own (two-pass) forward sweep."""
+    case = el_case((70, 37, 29), 8, 5, 61)
+    p, shot = make_el(case, prop)
+    p.set_option("el_fused", 1)
+    rec = dev(np.random.default_rng(4).standard_normal((case["nt"], len(case["rec"]))))
+    g_fresh = host(p.gradient(shot, rec, n_ckpt=6, ckpt_dtype="f32")).copy()
+    p.forward(shot, save_ckpt=6, ckpt_dtype="f32")
+    g_reuse = host(p.gradient(shot, rec, n_ckpt=0, ckpt_dtype="f32"))
+    assert np.array_equal(g_reuse, g_fresh), rel_l2(g_reuse, g_fresh)
