@@ -330,16 +330,18 @@ void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std:
 
 // z-chunk length: enough chunks for ~2048 blocks (elastic: ~4096; its two passes have no
 // autotuner, and 17-plane chunks measured 4 % faster than 34-plane ones at 400^3 so8), but chunks
-// of at least 4R planes (the z halo of a chunk is re-read by its neighbour).  The fused TTI pass
-// holds one block per CU (its LDS), so it aims at ~512 blocks: longer chunks re-read less of the
-// z halo (at 256^3 so8, 512 blocks ran 272 us a step against 343 us for 1024 and 442 us for 2048).
+// of at least 4R planes (the z halo of a chunk is re-read by its neighbour).  The fused and split
+// TTI passes hold one block per CU (LDS, registers), so they aim at ~256 blocks, one wave: longer
+// chunks re-read less of the z halo (at 256^3 so8, 512 blocks ran 272 us a step against 343 us for
+// 1024 and 442 us for 2048; at 512^3 so12 split pass B ran 1.507 ms with 256 blocks against 1.529
+// with 512 and 1.579 with 1024).
 // 2D elastic grids run one-row tiles with few of them per plane and fit in cache: chunks down to
 // R planes (5-plane chunks measured 1.4x faster than 17-plane ones on the 1701 x 391 marine grid).
 int choose_zc(const prop_s *h, int nz, int64_t tiles_xy)
 {
     if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
     const bool one_block_per_cu = h->opt_scheme == TTI_FUSED || h->opt_scheme == TTI_SPLIT;
-    const int64_t target = h->kind == PROP_TTI ? (one_block_per_cu ? 512 : 2048) : 4096;
+    const int64_t target = h->kind == PROP_TTI ? (one_block_per_cu ? 256 : 2048) : 4096;
     const int minlen = h->kind == PROP_ELASTIC && h->g.ndim == 2 ? h->R : 4 * h->R;
     int64_t nch = (target + tiles_xy - 1) / tiles_xy;
     nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / minlen)));
@@ -904,7 +906,7 @@ struct EventPair {
 
 // Autotuner: on the first call for a window set and direction, time every tile variant of each
 // pass at three z-chunk lengths (half, one and two times the automatic one).  The untuned choice
-// is timed first and a candidate replaces the current pick only when it is at least 3 % faster, so
+// comes first and a candidate replaces the current pick only when it is at least 3 % faster, so
 // that near-ties (within run-to-run noise) resolve the same way every time.  The trial launches
 // run on the group's zero state, which they leave zero (no sources yet), so they change no result;
 // the choice is cached on the handle.
@@ -935,33 +937,42 @@ int tune_group(prop_s *h, Group &G, bool adj)
                 if (std::find(cand.begin(), cand.end(), c) == cand.end()) cand.push_back(c);
             }
         }
-        double best_ms = 1e300;
-        for (const auto &c : cand) {
-            const int shape = c.first, zc = c.second;
-            make_tiles(G.slots, tile_rows(h, pass, shape), zc, h->opt_xcd, tl);
-            TRY(upload(tb, tl, h->st));
-            const int nt = (int)tl.size();
-            auto run = [&]() {
-                if (pass == 1)
-                    launch_tti_pass1(h->R, h->opt_scheme, shape, adj, job, tb.as<Tile>(), nt, zc, 0, h->W, h->st);
-                else
-                    launch_tti_pass2(h->R, h->opt_scheme, shape, adj ? K2_ADJ : K2_FWD, job, tb.as<Tile>(), nt, zc, 0,
-                                     h->W, idt2, 0, h->st);
-            };
-            run();
-            HIPCHK(hipEventRecord(ev.a, h->st));
-            for (int r = 0; r < 4; ++r) run();
-            HIPCHK(hipEventRecord(ev.b, h->st));
-            HIPCHK(hipEventSynchronize(ev.b));
-            HIPCHK(hipGetLastError());
-            float ms = 0;
-            HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
-            if (ms < 0.97 * best_ms) {
-                best_ms = ms;
-                best.shape[pass - 1] = shape;
-                best.zc[pass - 1] = zc;
+        // each candidate is timed in three rounds (after one warm-up launch each) and keeps its
+        // fastest round, so that clock ramps and one-off stalls do not decide
+        std::vector<double> cms(cand.size(), 1e300);
+        for (int round = 0; round < 4; ++round)
+            for (size_t ci = 0; ci < cand.size(); ++ci) {
+                const int shape = cand[ci].first, zc = cand[ci].second;
+                make_tiles(G.slots, tile_rows(h, pass, shape), zc, h->opt_xcd, tl);
+                TRY(upload(tb, tl, h->st));
+                const int nt = (int)tl.size();
+                auto run = [&]() {
+                    if (pass == 1)
+                        launch_tti_pass1(h->R, h->opt_scheme, shape, adj, job, tb.as<Tile>(), nt, zc, 0, h->W, h->st);
+                    else
+                        launch_tti_pass2(h->R, h->opt_scheme, shape, adj ? K2_ADJ : K2_FWD, job, tb.as<Tile>(), nt,
+                                         zc, 0, h->W, idt2, 0, h->st);
+                };
+                if (round == 0) {
+                    run();
+                    continue;
+                }
+                HIPCHK(hipEventRecord(ev.a, h->st));
+                for (int r = 0; r < 3; ++r) run();
+                HIPCHK(hipEventRecord(ev.b, h->st));
+                HIPCHK(hipEventSynchronize(ev.b));
+                HIPCHK(hipGetLastError());
+                float ms = 0;
+                HIPCHK(hipEventElapsedTime(&ms, ev.a, ev.b));
+                cms[ci] = std::min(cms[ci], (double)ms);
             }
-        }
+        double best_ms = 1e300;
+        for (size_t ci = 0; ci < cand.size(); ++ci)
+            if (cms[ci] < 0.97 * best_ms) {
+                best_ms = cms[ci];
+                best.shape[pass - 1] = cand[ci].first;
+                best.zc[pass - 1] = cand[ci].second;
+            }
     }
     h->tuned[key] = best;
     return apply_tune(h, G, dir, best);
