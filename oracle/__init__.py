@@ -97,6 +97,14 @@ class Grid:
     (reading: the paper only names a free surface as an equation on a sub-domain; the vacuum
     formulation keeps the propagator a plain velocity-stress step in a heterogeneous medium, so its
     transpose, dot test and gradients are those of that step).
+    free_surface = "image": the same vacuum rows, plus the method of images for the tractions:
+    after every step the rows above the surface row ks = nbl receive odd copies of tau_zz (about
+    node row ks, which is set to zero) and of tau_xz, tau_yz (about the same plane, half a cell
+    off their storage rows), and the density of those rows mirrors the rows below (so that the
+    velocities above the surface are the mirror images a pressure-release plane needs).  The
+    surface row and the R rows below it must be fluid (vs = 0): then no shear stress that the image
+    rows feed is read back by them (with a solid at the surface this variant is unstable), and in a
+    fluid it is exactly the method of images (needs nbl >= 2R - 2).
     """
     shape: tuple
     spacing: tuple
@@ -106,7 +114,12 @@ class Grid:
     dt: float = 1e-3
     nt: int = 1
     vref: float = 1500.0
-    free_surface: bool = False
+    free_surface: object = False
+
+    @property
+    def image_surface(self) -> bool:
+        """The free surface uses the method of images for the tractions (free_surface = "image")."""
+        return self.free_surface == "image"
 
     @property
     def ndim(self) -> int:
@@ -508,10 +521,17 @@ class ElasticModel:
         c = lambda a: np.asarray(a, dtype=np.float64).reshape(g.arr_shape)
         vp, vs, rho = c(vp), c(vs), c(rho)
         lam, mu = rho * (vp * vp - 2 * vs * vs), rho * vs * vs
+        b = 1.0 / rho
         if g.free_surface:
             lam[:g.nbl] = 0.0
             mu[:g.nbl] = 0.0
-        return ElasticModel(np.ascontiguousarray(lam), np.ascontiguousarray(mu), np.ascontiguousarray(1.0 / rho))
+        if g.image_surface:   # density of the rows above the surface row nbl: mirror of the rows below
+            ks = g.nbl
+            if np.any(vs[ks:ks + g.r + 1] != 0.0):
+                raise ValueError("an image free surface needs a fluid (vs = 0) on rows nbl .. nbl + space_order/2")
+            for k in range(1, ks + 1):
+                b[ks - k] = b[ks + k]
+        return ElasticModel(np.ascontiguousarray(lam), np.ascontiguousarray(mu), np.ascontiguousarray(b))
 
 
 VZ_STAGGER = (0.0, 0.0, 0.5)
@@ -522,6 +542,36 @@ def _normal(g: Grid):
     the tensor is 2 x 2 (reading: the explosive source enters them and the pressure is their sum,
     the trace of the tensor, as in the paper's 2D example)."""
     return (0, 2) if g.ndim == 2 else (0, 1, 2)
+
+
+def image_fill(g: Grid, t) -> None:
+    """Method-of-images step of the free surface (free_surface = "image"), in place on the
+    stresses [txx, tyy, tzz, txy, txz, tyz]: with ks = nbl the surface node row,
+        tzz[ks] = 0,  tzz[ks - k] = -tzz[ks + k]                 (k = 1 .. ks; node rows)
+        tc[ks - k] = -tc[ks + k - 1] for tc = txz, tyz          (k = 1 .. ks; storage row i holds
+                                                                   the half row i + 1/2)."""
+    ks = g.nbl
+    tzz, txz, tyz = t[2], t[4], t[5]
+    tzz[ks] = 0.0
+    for k in range(1, ks + 1):
+        tzz[ks - k] = -tzz[ks + k]
+        txz[ks - k] = -txz[ks + k - 1]
+        tyz[ks - k] = -tyz[ks + k - 1]
+
+
+def image_fill_T(g: Grid, t) -> None:
+    """Transpose of ``image_fill`` on adjoint stresses: every overwritten row hands its value,
+    negated, to the row it was copied from, and is cleared; tzz[ks] is cleared."""
+    ks = g.nbl
+    tzz, txz, tyz = t[2], t[4], t[5]
+    for k in range(1, ks + 1):
+        tzz[ks + k] -= tzz[ks - k]
+        tzz[ks - k] = 0.0
+        txz[ks + k - 1] -= txz[ks - k]
+        txz[ks - k] = 0.0
+        tyz[ks + k - 1] -= tyz[ks - k]
+        tyz[ks - k] = 0.0
+    tzz[ks] = 0.0
 
 
 def _el_call(fn, g, mod, damp, v, t):
@@ -565,6 +615,8 @@ def elastic_forward(g: Grid, mod: ElasticModel, src_xyz, wavelet, rec_xyz, rec_k
         if src is not None:
             for c in _normal(g):
                 inject(src, t[c], g.dt * wav[n])
+        if g.image_surface:
+            image_fill(g, t)
         if force is not None:
             fr = force(n)
             if fr is not None:
@@ -608,6 +660,8 @@ def elastic_adjoint(g: Grid, mod: ElasticModel, src_xyz, rec_xyz, rec_data, rec_
                     arr += add
         if callback is not None:
             callback(n, v + t)
+        if g.image_surface:
+            image_fill_T(g, t)
         if src is not None:
             out[n] = g.dt * interp(src, sum(t[c] for c in _normal(g)))
         _el_call(lib().orc_el_step_T, g, mod, damp, v, t)
@@ -692,6 +746,8 @@ def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec
                 inject(spP, t[k], res[n, iP])
         if spV is not None:
             inject(spV, v[2], res[n, iV])
+        if g.image_surface:
+            image_fill_T(g, t)
         e = elastic_strain(g, states[n + 1][:3])
         gdt = g.dt * damp
         g_lam += gdt * (t[0] + t[1] + t[2]) * (e[0] + e[1] + e[2])
@@ -714,6 +770,11 @@ def elastic_gradient(g: Grid, vp, vs, rho, src_xyz, wavelet, rec_xyz, d_obs, rec
     if g.free_surface:   # the vacuum rows' lambda and mu do not depend on (vp, vs, rho)
         g_lam[:g.nbl] = 0.0
         g_mu[:g.nbl] = 0.0
+    if g.image_surface:  # the mirrored buoyancy above the surface belongs to the rows it copies
+        ks = g.nbl
+        for k in range(1, ks + 1):
+            g_b[ks + k] += g_b[ks - k]
+            g_b[ks - k] = 0.0
     g_vp = 2.0 * rho * vp * g_lam
     g_vs = 2.0 * rho * vs * (g_mu - 2.0 * g_lam)
     g_rho = (vp * vp - 2.0 * vs * vs) * g_lam + vs * vs * g_mu - g_b / (rho * rho)

@@ -64,6 +64,17 @@ void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, floa
 void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, const float *gz, const float *lam,
                   const float *mu, const float *t0, const float *t1, const float *t2, float *a0, float *a1, float *a2,
                   hipStream_t st);
+// Free surface by the method of images: the forward fill of the rows above the surface row ks
+// (tyz NULL in 2D), and its transpose on the adjoint stresses followed by sigma = C (g tau~) on
+// rows 0 .. 2 ks.
+struct ElImage {
+    float *t[6];                  // adjoint stresses tau~ (state layout)
+    float *s[6];                  // sigma = C (g tau~) (state layout)
+    const float *lam, *mu;        // model layout
+    const float *gx, *gy, *gz;    // absorbing factors per window axis
+};
+void aux_el_image_fill(const Win &w, int ks, float *tzz, float *txz, float *tyz, hipStream_t st);
+void aux_el_image_fold(const Win &w, int ks, int ndim, const ElImage &J, hipStream_t st);
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
                 hipStream_t st);
 void aux_fill(float *p, int64_t n, float v, hipStream_t st);
@@ -90,8 +101,10 @@ void aux_dot_f64(const float *a, const float *b, int64_t n, double *part, double
 int aux_dot_blocks();
 void aux_tti_prep(const float *m, const float *eps, const float *dl, const float *th, const float *ph, int64_t n,
                   int ndim, float *A, float *B, float *nx, float *ny, unsigned *stats, hipStream_t st);
+// Elastic parameters (lambda, mu, b) from (vp, vs, rho); stats[2] gets flag 4 when vs > 0 on a plane
+// row in [fluid_lo, fluid_hi) (rows of `plane` points).
 void aux_el_prep(const float *vp, const float *vs, const float *rho, int64_t n, float *lam, float *mu, float *b,
-                 unsigned *stats, hipStream_t st);
+                 unsigned *stats, int64_t plane, int fluid_lo, int fluid_hi, hipStream_t st);
 void aux_nonfinite_win(const float *f, const Win &w, unsigned *flag, hipStream_t st);
 void aux_copy_out(const float *src, const Win &w, float *dst, hipStream_t st);
 void aux_accum_f64(const float *src, const Win &w, double *dst, hipStream_t st);

@@ -85,6 +85,70 @@ __global__ void k_el_remix(Csr c, Win w, const float *__restrict__ gx, const flo
     a2[si] = lt + m2 * s2;
 }
 
+// Free surface by the method of images (surface node row ks): after a forward step the rows above
+// the surface take odd copies of the tractions, tzz[ks] = 0, tzz[ks - k] = -tzz[ks + k], and for
+// txz, tyz, whose storage row i holds the half row i + 1/2, tc[ks - k] = -tc[ks + k - 1]
+// (k = 1 .. ks).  One thread per (x, y, k); k = 0 clears the surface row.  Rows read (>= ks) and
+// rows written (< ks, and tzz at ks by k = 0 only) are disjoint.
+__global__ void k_el_image_fill(Win w, int ks, float *tzz, float *txz, float *tyz)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
+    if (x >= w.nx) return;
+    if (k == 0) {
+        tzz[sidx(w, x, y, ks)] = 0.f;
+        return;
+    }
+    const int64_t lo = sidx(w, x, y, ks - k);
+    tzz[lo] = -tzz[sidx(w, x, y, ks + k)];
+    txz[lo] = -txz[sidx(w, x, y, ks + k - 1)];
+    if (tyz) tyz[lo] = -tyz[sidx(w, x, y, ks + k - 1)];
+}
+
+// Transpose of k_el_image_fill on the adjoint stresses tau~ (one thread per (x, y) column): each
+// image row hands its value, negated, to the row it copies and is cleared, and tau~_zz[ks] is
+// cleared; then sigma = C (g tau~) is formed again on the rows the fold touched (0 .. 2 ks), with
+// the expressions of the transposed stress pass's epilogue, for the transposed velocity pass.
+__global__ void k_el_image_fold(Win w, int ks, int ndim, ElImage J)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    if (x >= w.nx) return;
+    float *const tzz = J.t[2], *const txz = J.t[4], *const tyz = J.t[5];
+    for (int k = 1; k <= ks; ++k) {
+        const int64_t lo = sidx(w, x, y, ks - k), hz = sidx(w, x, y, ks + k), hs = sidx(w, x, y, ks + k - 1);
+        tzz[hz] -= tzz[lo];
+        tzz[lo] = 0.f;
+        txz[hs] -= txz[lo];
+        txz[lo] = 0.f;
+        if (ndim == 3) {
+            tyz[hs] -= tyz[lo];
+            tyz[lo] = 0.f;
+        }
+    }
+    tzz[sidx(w, x, y, ks)] = 0.f;
+    const int zmax = min(2 * ks, w.nz - 1);
+    const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0;
+    const float gxy = J.gx[x] * J.gy[y];
+    for (int z = 0; z <= zmax; ++z) {
+        const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
+        const int64_t oz = z + 1 < w.nz ? w.my : 0;
+        const float g = gxy * J.gz[z];
+        const float s0 = g * J.t[0][si], s1 = g * J.t[1][si], s2 = g * tzz[si];
+        const float lam = J.lam[mi], mu0 = J.mu[mi];
+        const float lt = lam * (s0 + s1 + s2), m2 = 2.f * mu0;
+        J.s[0][si] = lt + m2 * s0;
+        J.s[1][si] = lt + m2 * s1;
+        J.s[2][si] = lt + m2 * s2;
+        const float mx_ = J.mu[mi + ox], mz_ = J.mu[mi + oz];
+        const float mxz = 0.25f * (mu0 + mx_ + mz_ + J.mu[mi + ox + oz]);
+        J.s[4][si] = mxz * (g * txz[si]);
+        if (ndim == 3) {
+            const float my_ = J.mu[mi + oy];
+            const float myz = 0.25f * (mu0 + my_ + mz_ + J.mu[mi + oy + oz]);
+            J.s[5][si] = myz * (g * tyz[si]);
+        }
+    }
+}
+
 // Multilinear gather: out[pos_o] = scale * sum_c w_oc (f0 + f1 + f2)[idx_oc].  One point per lane.
 // Multilinear gathers run one corner per lane: the nc = 2^d lanes of a point (a power of two that
 // divides the wavefront) each load one corner value times its weight, and a butterfly of lane shuffles
@@ -492,8 +556,11 @@ __global__ void k_tti_prep(const float *__restrict__ m, const float *__restrict_
 
 // Elastic coefficients: lambda = rho (vp^2 - 2 vs^2), mu = rho vs^2, b = 1/rho; stats: max vp (bits),
 // flags (bit 0: rho <= 0, vp <= 0, vs < 0 or non-finite; bit 1: lambda < 0).
+// flags: 1 invalid value, 2 negative lambda, 4 vs > 0 on the plane rows [fluid_lo, fluid_hi) that
+// must be fluid (the image free surface)
 __global__ void k_el_prep(const float *__restrict__ vp, const float *__restrict__ vs, const float *__restrict__ rho,
-                          int64_t n, float *lam, float *mu, float *b, unsigned *stats)
+                          int64_t n, float *lam, float *mu, float *b, unsigned *stats, int64_t plane, int fluid_lo,
+                          int fluid_hi)
 {
     unsigned vmax = 0, flags = 0;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -504,6 +571,8 @@ __global__ void k_el_prep(const float *__restrict__ vp, const float *__restrict_
         if (!(r > 0.f) || !(p > 0.f) || !(s >= 0.f) || !isfinite(p) || !isfinite(s) || !isfinite(r)) flags |= 1u;
         else vmax = max(vmax, __float_as_uint(p));
         if (p * p < 2.f * s * s) flags |= 2u;
+        const int64_t z = i / plane;
+        if (z >= fluid_lo && z < fluid_hi && s != 0.f) flags |= 4u;
     }
     atomicMax(&stats[0], vmax);
     atomicOr(&stats[2], flags);
@@ -591,6 +660,19 @@ void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, 
     if (c.nrows <= 0) return;
     hipLaunchKernelGGL(k_el_remix, dim3((c.nrows + BS - 1) / BS), dim3(BS), 0, st, c, w, gx, gy, gz, lam, mu, t0, t1,
                        t2, a0, a1, a2);
+}
+
+void aux_el_image_fill(const Win &w, int ks, float *tzz, float *txz, float *tyz, hipStream_t st)
+{
+    if (ks <= 0) return;
+    hipLaunchKernelGGL(k_el_image_fill, dim3((w.nx + BS - 1) / BS, w.ny, ks + 1), dim3(BS), 0, st, w, ks, tzz, txz,
+                       tyz);
+}
+
+void aux_el_image_fold(const Win &w, int ks, int ndim, const ElImage &J, hipStream_t st)
+{
+    if (ks <= 0) return;
+    hipLaunchKernelGGL(k_el_image_fold, dim3((w.nx + BS - 1) / BS, w.ny), dim3(BS), 0, st, w, ks, ndim, J);
 }
 
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
@@ -681,9 +763,10 @@ void aux_tti_prep(const float *m, const float *eps, const float *dl, const float
 }
 
 void aux_el_prep(const float *vp, const float *vs, const float *rho, int64_t n, float *lam, float *mu, float *b,
-                 unsigned *stats, hipStream_t st)
+                 unsigned *stats, int64_t plane, int fluid_lo, int fluid_hi, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_el_prep, dim3(nblocks(n)), dim3(BS), 0, st, vp, vs, rho, n, lam, mu, b, stats);
+    hipLaunchKernelGGL(k_el_prep, dim3(nblocks(n)), dim3(BS), 0, st, vp, vs, rho, n, lam, mu, b, stats, plane,
+                       fluid_lo, fluid_hi);
 }
 
 void aux_nonfinite_win(const float *f, const Win &w, unsigned *flag, hipStream_t st)

@@ -508,8 +508,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
 // node i collects from p = i - 1 (weight 1) and p = i (weight 1 + [i = n - 1]), times 1/2 per axis.
 __device__ __forceinline__ float spread_w(int p, int i, int n) { return (p == i ? 1.f : 0.f) + (min(p + 1, n - 1) == i ? 1.f : 0.f); }
 
-__global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, int nvac, const float *__restrict__ vp,
-                               const float *__restrict__ vs, const float *__restrict__ rho, float *__restrict__ out)
+__global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, int nvac, int nimg,
+                               const float *__restrict__ vp, const float *__restrict__ vs,
+                               const float *__restrict__ rho, float *__restrict__ out)
 {
     const ElGradJob &J = jobs[0];
     const Win w = J.w;
@@ -540,20 +541,30 @@ __global__ void el_grad_finish(const ElGradJob *__restrict__ jobs, int ndim, int
             }
         }
     }
-    float gb = 0.f;
-    for (int a = 0; a < 3; ++a) {
-        if (ndim == 2 && a == 1) continue;
-        for (int d = -1; d <= 0; ++d) {
-            const int pa = c3[a] + d;
-            if (pa < 0) continue;
-            int p[3] = {x, y, z};
-            p[a] = pa;
-            gb += 0.5f * spread_w(pa, c3[a], n[a]) * at(J.acc[5 + a], p[0], p[1], p[2]);
+    // buoyancy sensitivity of node (x, y, zz): the shares of the two-node means it enters
+    auto gb_at = [&](int zz) {
+        const int cz[3] = {x, y, zz};
+        float acc = 0.f;
+        for (int a = 0; a < 3; ++a) {
+            if (ndim == 2 && a == 1) continue;
+            for (int d = -1; d <= 0; ++d) {
+                const int pa = cz[a] + d;
+                if (pa < 0) continue;
+                int p[3] = {x, y, zz};
+                p[a] = pa;
+                acc += 0.5f * spread_w(pa, cz[a], n[a]) * at(J.acc[5 + a], p[0], p[1], p[2]);
+            }
         }
-    }
+        return acc;
+    };
+    float gb = gb_at(z);
     if (z < nvac) {   // vacuum: lambda and mu are fixed at zero; only the buoyancy depends on rho
         gl = 0.f;
         gm = 0.f;
+    }
+    if (nimg > 0) {   // image rows above the surface row nimg copy the buoyancy of the rows below
+        if (z < nimg) gb = 0.f;
+        else if (z > nimg && z <= 2 * nimg) gb += gb_at(2 * nimg - z);
     }
     const int64_t mi = midx(w, x, y, z);
     const float a = gld(vp, mi), s = gld(vs, mi), r = gld(rho, mi);
@@ -644,9 +655,9 @@ void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, i
     EL_SWITCH(gic_dispatch, by, job, tiles, ntiles, zc, W, dt, st)
 }
 
-void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,
-                           const float *rho, float *out, hipStream_t st)
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, int nimg, const float *vp,
+                           const float *vs, const float *rho, float *out, hipStream_t st)
 {
     dim3 blk(256), grd((w.nx + 255) / 256, w.ny, w.nz);
-    hipLaunchKernelGGL(el_grad_finish, grd, blk, 0, st, job, ndim, nvac, vp, vs, rho, out);
+    hipLaunchKernelGGL(el_grad_finish, grd, blk, 0, st, job, ndim, nvac, nimg, vp, vs, rho, out);
 }

@@ -125,6 +125,9 @@ void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, i
 // Spread the accumulators to the nodes (transpose of the half-node averages) and convert to
 // (vp, vs, rho): out = three dense window fields.  Rows z < nvac are vacuum (lambda = mu = 0 there,
 // independent of vp, vs and rho).
-void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, const float *vp, const float *vs,
+// nvac: vacuum rows above a free surface (their lambda, mu are fixed); nimg: the surface row of an
+// image free surface (0: none), whose image rows copy the buoyancy of the rows below.
+void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, int nimg, const float *vp,
+                           const float *vs,
                            const float *rho, float *out, hipStream_t st);
 int el_tile_rows(int R, int ndim);

@@ -159,10 +159,12 @@ int check_grid(prop_kind kind, const prop_grid *g)
     if (g->nbl < 0) return fail(PROP_EINVAL, "nbl must be >= 0");
     if (!(g->dt > 0) || g->nt < 1) return fail(PROP_EINVAL, "dt must be > 0 and nt >= 1");
     if (g->nbl > 0 && !(g->v_ref > 0)) return fail(PROP_EINVAL, "v_ref must be > 0 with an absorbing layer");
-    if (g->free_surface != 0 && g->free_surface != 1) return fail(PROP_EINVAL, "free_surface must be 0 or 1");
+    if (g->free_surface < 0 || g->free_surface > 2) return fail(PROP_EINVAL, "free_surface must be 0, 1 or 2");
     if (g->free_surface && kind != PROP_ELASTIC) return fail(PROP_EINVAL, "a free surface is elastic only");
     if (g->free_surface && g->nbl < g->space_order / 2)
         return fail(PROP_EINVAL, "a free surface needs nbl >= space_order / 2 vacuum rows");
+    if (g->free_surface == 2 && g->nbl < g->space_order - 2)
+        return fail(PROP_EINVAL, "an image free surface needs nbl >= space_order - 2 image rows");
     for (int a = 0; a < 3; ++a) {
         if (g->ndim == 2 && a == 1) continue;
         if (!(g->spacing[a] > 0)) return fail(PROP_EINVAL, "spacing must be > 0");
@@ -682,11 +684,18 @@ int prep_model(prop_s *h, const prop_model *m)
         aux_tti_prep(m->p[0], m->p[1], m->p[2], m->p[3], h->g.ndim == 3 ? m->p[4] : m->p[3], n, h->g.ndim, cc,
                      cc + n, cc + 2 * n, cc + 3 * n, h->stats.as<unsigned>(), h->st);
     else
-        aux_el_prep(m->p[0], m->p[1], m->p[2], n, cc, cc + n, cc + 2 * n, h->stats.as<unsigned>(), h->st);
+        aux_el_prep(m->p[0], m->p[1], m->p[2], n, cc, cc + n, cc + 2 * n, h->stats.as<unsigned>(),
+                    (int64_t)h->g.shape[0] * h->g.shape[1], h->g.nbl, h->g.free_surface == 2 ? h->g.nbl + h->R + 1 : 0,
+                    h->st);
     if (h->kind == PROP_ELASTIC && h->g.free_surface) {   // vacuum rows above the free surface
-        const int64_t nv = (int64_t)h->g.nbl * h->g.shape[1] * h->g.shape[0];
+        const int64_t plane = (int64_t)h->g.shape[1] * h->g.shape[0], nv = (int64_t)h->g.nbl * plane;
         aux_fill(cc, nv, 0.f, h->st);
         aux_fill(cc + n, nv, 0.f, h->st);
+        if (h->g.free_surface == 2)   // image rows: the buoyancy of the rows below, mirrored
+            for (int k = 1; k <= h->g.nbl; ++k)
+                HIPCHK(hipMemcpyAsync(cc + 2 * n + (int64_t)(h->g.nbl - k) * plane,
+                                      cc + 2 * n + (int64_t)(h->g.nbl + k) * plane, plane * sizeof(float),
+                                      hipMemcpyDeviceToDevice, h->st));
     }
     HIPCHK(hipGetLastError());
     unsigned s[4];
@@ -695,6 +704,8 @@ int prep_model(prop_s *h, const prop_model *m)
     if (s[2] & 1u) return fail(PROP_EINVAL, "model has non-positive or non-finite values");
     if (h->kind == PROP_TTI && (s[2] & 2u)) return fail(PROP_EUNSTABLE, "epsilon < delta somewhere (unstable)");
     if (h->kind == PROP_ELASTIC && (s[2] & 2u)) return fail(PROP_EINVAL, "vp^2 < 2 vs^2 somewhere (negative lambda)");
+    if (h->kind == PROP_ELASTIC && (s[2] & 4u))
+        return fail(PROP_EINVAL, "an image free surface needs a fluid (vs = 0) on rows nbl .. nbl + space_order / 2");
     float vmax, emax;
     std::memcpy(&vmax, &s[0], 4);
     std::memcpy(&emax, &s[1], 4);
@@ -1650,6 +1661,34 @@ int tti_batched(prop_s *h, int nshot, const prop_shot *shots, float *const *rec_
 // 3D; txx, tzz in 2D, where the stress tensor is 2 x 2 (tyy is then not part of it).
 float *tyy_of(const prop_s *h, const Slot &sl) { return h->g.ndim == 3 ? sl.f[4] : nullptr; }
 
+// Free surface by the method of images: the surface node row (0: none).
+int image_row(const prop_s *h) { return h->kind == PROP_ELASTIC && h->g.free_surface == 2 ? h->g.nbl : 0; }
+
+// The forward fill of the image rows on a set of nine fields (v, then tau).
+void image_fill(prop_s *h, const Slot &sl, float *const *F)
+{
+    if (const int ks = image_row(h)) aux_el_image_fill(sl.w, ks, F[5], F[7], h->g.ndim == 3 ? F[8] : nullptr, h->st);
+}
+
+// Its transpose on the slot's adjoint stresses, then sigma = C (g tau~) of the rows it touched.
+void image_fold(prop_s *h, const Slot &sl)
+{
+    const int ks = image_row(h);
+    if (!ks) return;
+    ElImage J{};
+    for (int i = 0; i < 6; ++i) {
+        J.t[i] = sl.f[3 + i];
+        J.s[i] = sl.f[9 + i];
+    }
+    J.lam = h->c[0];
+    J.mu = h->c[1];
+    const float *tab = sl.tabs.as<float>();
+    J.gx = tab;
+    J.gy = tab + sl.w.nx;
+    J.gz = tab + sl.w.nx + sl.w.ny;
+    aux_el_image_fold(sl.w, ks, h->g.ndim, J, h->st);
+}
+
 // The fused velocity-stress step (one launch a step, double-buffered state) applies to 3D windows
 // up to space order 2 * el_fused_max_radius(); the two-pass step serves the rest.
 bool el_fused_on(const prop_s *h)
@@ -1776,6 +1815,7 @@ int el_forward(prop_s *h, const prop_shot *s, float *rec_out, int save, int dtyp
         }
         float *tyy = h->g.ndim == 3 ? F[4] : nullptr;
         if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, F[3], tyy, F[5], h->st);
+        image_fill(h, sl, F);
         float *row = s->nrec ? rec_out + (size_t)n * s->nrec : nullptr;
         if (sl.rec_gat.gat.n) aux_gather(sl.rec_gat.gat, F[3], tyy, F[5], 1.f, row, h->st);
         if (sl.rec_gat_vz.gat.n) aux_gather(sl.rec_gat_vz.gat, F[2], nullptr, nullptr, 1.f, row, h->st);
@@ -1809,6 +1849,7 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
         if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
         if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
         el_remix(h, sl);
+        image_fold(h, sl);
         if (s->nsrc) aux_gather(sl.src_gat.gat, sl.f[3], tyy_of(h, sl), sl.f[5], dt, src_out + (size_t)n * s->nsrc,
                                 h->st);
         {
@@ -1885,10 +1926,12 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
     TRY(upload(h->eljob_g, gjs, h->st));
     const ElGradJob *dgj = h->eljob_g.as<ElGradJob>();
     const float dt = (float)h->g.dt;
+    float *const fwf[9] = {jf.v[0], jf.v[1], jf.v[2], jf.t[0], jf.t[1], jf.t[2], jf.t[3], jf.t[4], jf.t[5]};
     auto fwd_step = [&](int n) {
         el_step_fwd(h, sl, djf);
         if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, jf.t[0],
                                    h->g.ndim == 3 ? jf.t[1] : nullptr, jf.t[2], h->st);
+        image_fill(h, sl, fwf);
     };
     auto copy = [&](float *dst, const float *src, size_t nflt) -> int {
         HIPCHK(hipMemcpyAsync(dst, src, nflt * sizeof(float), hipMemcpyDeviceToDevice, h->st));
@@ -1921,6 +1964,7 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
             if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
             if (sl.rec_inj_vz.csr.nrows) aux_el_inject(sl.rec_inj_vz.csr, row, 1.f, sl.f[2], nullptr, nullptr, h->st);
             el_remix(h, sl);
+            image_fold(h, sl);
             {
                 Timed t(h, 2);
                 launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
@@ -1934,8 +1978,8 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
         HIPCHK(hipGetLastError());
         TRY(check_finite(h, sl.f[5], sl.w, "adjoint tau_zz (gradient)", start));
     }
-    launch_el_grad_finish(dgj, sl.w, h->g.ndim, h->g.free_surface ? h->g.nbl : 0, h->model.p[0], h->model.p[1],
-                          h->model.p[2], out, h->st);
+    launch_el_grad_finish(dgj, sl.w, h->g.ndim, h->g.free_surface ? h->g.nbl : 0, image_row(h), h->model.p[0],
+                          h->model.p[1], h->model.p[2], out, h->st);
     HIPCHK(hipGetLastError());
     TRY(check_finite(h, acc, sl.w, "gradient accumulator", 0));
     h->last_state = 0;

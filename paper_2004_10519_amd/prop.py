@@ -128,7 +128,8 @@ class Grid:
     dt: float = 1e-3
     nt: int = 1
     v_ref: float = 1500.0
-    free_surface: bool = False   # elastic: free surface on the top face (vacuum rows above row nbl)
+    free_surface: object = False   # elastic: free surface on the top face (vacuum rows above row nbl);
+                                   # "image": the same with the method of images for the tractions
 
     @property
     def ndim(self) -> int:
@@ -151,7 +152,7 @@ class Grid:
         g.dt = float(self.dt)
         g.nt = int(self.nt)
         g.v_ref = float(self.v_ref)
-        g.free_surface = int(bool(self.free_surface))
+        g.free_surface = 2 if self.free_surface == "image" else int(bool(self.free_surface))
         return g
 
 

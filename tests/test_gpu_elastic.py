@@ -133,8 +133,16 @@ def test_elastic_gradient_parity(prop, orc, so, shape):
 FS_CASES = [((70, 37, 29), 8), ((90, 1, 61), 8), ((66, 20, 40), 4)]
 
 
-def _fs_case(shape, so, nt):
-    case = el_case(shape, so, 5, nt, free_surface=True)
+def _fluid_top(case):
+    """A fluid on the surface row and the R rows below it, which an image free surface needs."""
+    case["model"]["vs"][:case["nbl"] + case["so"] // 2 + 1] = 0.0
+    return case
+
+
+def _fs_case(shape, so, nt, mode=True):
+    case = el_case(shape, so, 5 if mode is True else max(5, so - 2), nt, free_surface=mode)
+    if mode == "image":
+        case = _fluid_top(case)
     if shape[1] == 1:
         case = _to_2d(case)
     # source below the surface, near it (the ghost and the surface waves matter)
@@ -142,9 +150,10 @@ def _fs_case(shape, so, nt):
     return case
 
 
+@pytest.mark.parametrize("mode", [True, "image"])
 @pytest.mark.parametrize("shape,so", FS_CASES)
-def test_free_surface_forward_parity(prop, orc, shape, so):
-    case = _fs_case(shape, so, 80)
+def test_free_surface_forward_parity(prop, orc, shape, so, mode):
+    case = _fs_case(shape, so, 80, mode)
     p, shot = make_el(case, prop)
     d = host(p.forward(shot))
     fields = [host(p.read_state(i)) for i in range(9)]
@@ -157,13 +166,21 @@ def test_free_surface_forward_parity(prop, orc, shape, so):
         else:
             assert not a.any(), i
     nb = case["nbl"]
-    for c in (3, 4, 5):   # normal stresses vanish in the vacuum rows
-        assert not fields[c][:nb].any()
+    if mode is True:
+        for c in (3, 4, 5):   # normal stresses vanish in the vacuum rows
+            assert not fields[c][:nb].any()
+    else:                     # odd images of the tractions above the surface row, tau_zz = 0 on it
+        assert not fields[3][:nb].any() and not fields[4][:nb].any() and not fields[5][nb].any()
+        for k in range(1, nb + 1):
+            assert np.array_equal(fields[5][nb - k], -fields[5][nb + k])
+            assert np.array_equal(fields[7][nb - k], -fields[7][nb + k - 1])
+            assert np.array_equal(fields[8][nb - k], -fields[8][nb + k - 1])
 
 
+@pytest.mark.parametrize("mode", [True, "image"])
 @pytest.mark.parametrize("shape,so", FS_CASES[:2])
-def test_free_surface_adjoint_parity_and_dot(prop, orc, shape, so):
-    case = _fs_case(shape, so, 60)
+def test_free_surface_adjoint_parity_and_dot(prop, orc, shape, so, mode):
+    case = _fs_case(shape, so, 60, mode)
     p, shot = make_el(case, prop)
     rng = np.random.default_rng(3)
     rec = rng.standard_normal((case["nt"], len(case["rec"]))).astype(np.float32)
@@ -181,10 +198,11 @@ def test_free_surface_adjoint_parity_and_dot(prop, orc, shape, so):
     assert abs(a - b) / abs(a) < 1e-5, (a, b)
 
 
+@pytest.mark.parametrize("mode", [True, "image"])
 @pytest.mark.parametrize("shape,so", FS_CASES[:2])
-def test_free_surface_gradient_parity(prop, orc, shape, so):
+def test_free_surface_gradient_parity(prop, orc, shape, so, mode):
     from paper_2004_10519_amd import inputs
-    case = _fs_case(shape, so, 60)
+    case = _fs_case(shape, so, 60, mode)
     p, shot = make_el(case, prop)
     g, mod = oracle_el(case, orc)
     m = case["model"]
@@ -202,12 +220,21 @@ def test_free_surface_gradient_parity(prop, orc, shape, so):
         assert err <= 1e-3, (name, err)
     nb = case["nbl"]
     assert not gg[0][:nb].any() and not gg[1][:nb].any()
+    if mode == "image":
+        assert not gg[2][:nb].any()
 
 
 def test_free_surface_rejections(prop):
     from helpers import tti_case
     case = el_case((40, 20, 30), 8, 3, 10, free_surface=True)
     with pytest.raises(prop.PropError, match="nbl >= space_order"):
+        make_el(case, prop)
+    case = el_case((40, 20, 30), 8, 5, 10, free_surface="image")
+    with pytest.raises(prop.PropError, match="nbl >= space_order - 2"):
+        make_el(case, prop)
+    case = el_case((40, 20, 30), 8, 6, 10, free_surface="image")
+    case["model"]["vs"][:] = 1000.0
+    with pytest.raises(prop.PropError, match="fluid"):
         make_el(case, prop)
     tcase = tti_case((40, 20, 30), 8, 5, 10)
     g = prop.Grid(tcase["shape"], tcase["h"], space_order=8, nbl=5, dt=tcase["dt"], nt=10, free_surface=True)
@@ -226,7 +253,7 @@ def test_free_surface_rejections(prop):
 @pytest.mark.parametrize("so,shape,nt,zc,fs", [(8, (70, 37, 29), 61, 0, False), (8, (70, 37, 29), 60, 5, False),
                                               (6, (45, 19, 33), 41, 7, False), (4, (66, 20, 40), 50, 0, False),
                                               (2, (33, 17, 24), 37, 3, False), (8, (70, 37, 29), 47, 9, True),
-                                              (4, (66, 20, 40), 40, 0, True)])
+                                              (4, (66, 20, 40), 40, 0, True), (4, (66, 20, 40), 41, 7, "image")])
 def test_fused_elastic_step_bitwise_equals_two_passes(prop, so, shape, nt, zc, fs):
     """The fused step forms v+ and tau+ with the two passes' expressions, term for term, so traces
     and every final field are equal bit for bit: ragged tiles in x and y, one and several z chunks
@@ -235,6 +262,8 @@ def test_fused_elastic_step_bitwise_equals_two_passes(prop, so, shape, nt, zc, f
     case = el_case(shape, so, 5, nt, free_surface=fs)
     if fs:
         case["src"][0, -1] = case["h"][2] * (case["nbl"] + 3.4)
+    if fs == "image":
+        case = _fluid_top(case)
     out = []
     for fused in (0, 1):
         p, shot = make_el(case, prop)

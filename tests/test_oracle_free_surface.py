@@ -8,7 +8,10 @@
   vacuum formulations have with long stencils;
 * normal stresses stay exactly zero in the vacuum rows, shear stresses one half-row above the
   surface and higher;
-* dot test of the exact transpose and the gradient's finite differences with a free surface.
+* dot test of the exact transpose and the gradient's finite differences with a free surface;
+* the image variant (free_surface = "image": odd copies of the tractions above the surface row and
+  mirrored density there) equals the method of images in the acoustic limit at every space order,
+  to rounding, and has the same dot test and gradient checks.
 """
 import numpy as np
 import pytest
@@ -16,12 +19,13 @@ import pytest
 from paper_2004_10519_amd import inputs
 
 
-def _image_case(orc, so, nt=160):
-    nx, nz, nbl, h = 60, 50, 8, 10.0
+def _image_case(orc, so, nt=160, mode=True, rec_top=0.5, nz=50):
+    nx, nbl, h = 60, max(8, so - 2), 10.0
     vp, rho = 2000.0, 1000.0
     dt = 0.3 * h / vp
-    gf = orc.Grid((nx, 1, nz), (h, h, h), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=vp, free_surface=True)
-    km = nbl - 1                      # last vacuum node row: the mirror plane
+    gf = orc.Grid((nx, 1, nz), (h, h, h), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=vp, free_surface=mode)
+    # mirror plane: the last vacuum node row (vacuum rows), or the surface row nbl (images)
+    km = nbl if mode == "image" else nbl - 1
     H = nz - km
     ne, shift = 2 * H - 1, H - 1 - km   # extended grid rows; extended row = row + shift
     ge = orc.Grid((nx, 1, ne), (h, h, h), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=vp)
@@ -30,7 +34,7 @@ def _image_case(orc, so, nt=160):
     xs, zs = 30.3 * h, (nbl + 6.4) * h
     wav = inputs.ricker(25.0, dt, nt).astype(np.float64)[:, None]
     rng = np.random.default_rng(21)
-    rec = np.stack([rng.uniform(10, 50, 10) * h, rng.uniform(nbl + 0.5, nbl + 20, 10) * h], axis=1)
+    rec = np.stack([rng.uniform(10, 50, 10) * h, rng.uniform(nbl + rec_top, nbl + 20, 10) * h], axis=1)
     kind = (np.arange(10) % 2).astype(np.int32)
     df, ff = orc.elastic_forward(gf, mods[0], np.array([[xs, zs]]), wav, rec, kind)
     src_e = np.array([[xs, zs + shift * h], [xs, 2 * km * h - zs + shift * h]])
@@ -57,6 +61,97 @@ def test_free_surface_close_to_image_method_at_space_order_8(orc):
     assert 1e-6 < err < 0.15
 
 
+@pytest.mark.parametrize("so", [2, 4, 8, 12])
+def test_image_surface_equals_method_of_images(orc, so):
+    """The image free surface in the acoustic limit (mu = 0) at every space order: below the surface
+    row the solution is the free-space solution of the source plus its sign-flipped mirror image
+    about that row, to rounding (receivers and fields from the row below the surface down; on the
+    surface row itself tau_zz is held at zero while tau_xx keeps its own update, which reaches only
+    that row).  Exact when the image rows are at least 2R - 2 deep: the velocities up to R - 1 rows
+    above the surface, which the stress update below it reads, take z derivatives of tau_zz that
+    reach 2R - 2 rows up.  (The grid is tall enough that no wave reaches the bottom absorbing layer
+    and its mirror in the free-space run, which do not mirror each other exactly: the staggered
+    fields take the layer's damping at their storage node, not at their half-node position.)"""
+    gf, df, de, ff, fe, shift = _image_case(orc, so, mode="image", rec_top=1.0, nz=70)
+    assert np.abs(df).max() > 0
+    err = np.linalg.norm(df - de) / np.linalg.norm(de)
+    print(f"so{so} image free surface vs method of images: rel-L2 {err:.3e}")
+    assert err <= 1e-12
+    ks = gf.nbl
+    for c in (3, 5, 2, 0):   # txx, tzz, vz, vx below the surface row (rounding of 160 FP64 steps)
+        a, b = ff[c][ks + 1:], fe[c][ks + 1 + shift:]
+        assert np.abs(a - b).max() <= 1e-10 * np.abs(b).max(), (c, np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_image_surface_shallow_image_rows_are_inexact(orc):
+    """Control of the depth condition: at space order 12 with 8 image rows (2R - 2 = 10 needed) the
+    agreement drops from rounding to ~1e-8."""
+    nx, nz, nbl, h, so, nt = 60, 70, 8, 10.0, 12, 160
+    vp, rho = 2000.0, 1000.0
+    dt = 0.3 * h / vp
+    gf = orc.Grid((nx, 1, nz), (h, h, h), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=vp, free_surface="image")
+    km, H = nbl, nz - nbl
+    ne, shift = 2 * H - 1, H - 1 - km
+    ge = orc.Grid((nx, 1, ne), (h, h, h), space_order=so, nbl=nbl, dt=dt, nt=nt, vref=vp)
+    mods = [orc.ElasticModel.from_velocities(g, np.full(g.arr_shape, vp), np.zeros(g.arr_shape),
+                                             np.full(g.arr_shape, rho)) for g in (gf, ge)]
+    xs, zs = 30.3 * h, (nbl + 6.4) * h
+    wav = inputs.ricker(25.0, dt, nt).astype(np.float64)[:, None]
+    rec = np.stack([np.linspace(10, 50, 8) * h, np.linspace(nbl + 1, nbl + 20, 8) * h], axis=1)
+    df, _ = orc.elastic_forward(gf, mods[0], np.array([[xs, zs]]), wav, rec)
+    de, _ = orc.elastic_forward(ge, mods[1], np.array([[xs, zs + shift * h], [xs, 2 * km * h - zs + shift * h]]),
+                                np.concatenate([wav, -wav], axis=1), rec + np.array([0.0, shift * h]))
+    err = np.linalg.norm(df - de) / np.linalg.norm(de)
+    assert 1e-11 < err < 1e-5, err
+
+
+def test_image_surface_needs_a_fluid_at_the_surface(orc):
+    """With a solid within R rows of the surface the variant is rejected: there a shear stress fed
+    by the image rows is read back by them, and the run grows without bound (measured: 1e-10 ->
+    5.8 in 300 steps at space order 8 with vs = 1100 m/s up to the surface; stable with two fluid
+    rows or more, required here are R + 1 for a loop-free coupling)."""
+    g = orc.Grid((20, 1, 30), (10.0, 10.0, 10.0), space_order=8, nbl=6, dt=1e-3, nt=2, vref=2000.0,
+                 free_surface="image")
+    vp, rho = np.full(g.arr_shape, 2000.0), np.full(g.arr_shape, 1000.0)
+    vs = np.zeros(g.arr_shape)
+    vs[g.nbl + g.r + 1:] = 1000.0
+    orc.ElasticModel.from_velocities(g, vp, vs, rho)
+    vs[g.nbl + g.r] = 1000.0
+    with pytest.raises(ValueError, match="fluid"):
+        orc.ElasticModel.from_velocities(g, vp, vs, rho)
+
+
+def test_image_surface_control_mirror_plane_off_by_one(orc):
+    """Control: the same comparison with the vacuum surface (mirror plane one row higher) is far
+    from rounding at space order 8, so the pin above does not pass by construction."""
+    _, df, de, _, _, _ = _image_case(orc, 8, mode=True, rec_top=1.0)
+    assert np.linalg.norm(df - de) / np.linalg.norm(de) > 1e-3
+
+
+def test_image_surface_ghost_rows(orc):
+    """After a step the rows above the surface hold odd copies of the tractions and the surface
+    row's tau_zz is zero; the other stresses stay zero there (vacuum parameters), the velocities
+    do not."""
+    shape, nbl = (26, 20, 26), 6
+    g = orc.Grid(shape, (10.0, 9.0, 8.0), space_order=8, nbl=nbl, dt=4e-4, nt=40, vref=2000.0,
+                 free_surface="image")
+    mdl = inputs.elastic_model(shape, nbl, 14)
+    mdl["vs"][:nbl + g.r + 1] = 0.0
+    mod = orc.ElasticModel.from_velocities(g, mdl["vp"], mdl["vs"], mdl["rho"])
+    assert np.array_equal(mod.b[nbl - 3], mod.b[nbl + 3])
+    src = np.array([[10.0 * 13.2, 9.0 * 10.1, 8.0 * (nbl + 3.3)]])
+    wav = inputs.ricker(40.0, g.dt, g.nt).astype(np.float64)[:, None]
+    _, f = orc.elastic_forward(g, mod, src, wav, None)
+    ks = nbl
+    assert np.abs(f[5][ks]).max() == 0.0 and np.abs(f[5][ks + 1]).max() > 0
+    for k in range(1, ks + 1):
+        assert np.array_equal(f[5][ks - k], -f[5][ks + k])
+        assert np.array_equal(f[7][ks - k], -f[7][ks + k - 1]) and np.array_equal(f[8][ks - k], -f[8][ks + k - 1])
+    for c in (3, 4, 6):
+        assert np.abs(f[c][:ks]).max() == 0.0
+    assert np.abs(f[2][:ks]).max() > 0
+
+
 def test_free_surface_vacuum_rows_hold_no_stress(orc):
     shape, nbl = (26, 20, 24), 5
     g = orc.Grid(shape, (10.0, 9.0, 8.0), space_order=8, nbl=nbl, dt=4e-4, nt=60, vref=2000.0, free_surface=True)
@@ -73,10 +168,12 @@ def test_free_surface_vacuum_rows_hold_no_stress(orc):
     assert np.abs(f[5][nbl]).max() > 0
 
 
-def _fs_case(orc, shape, nt, seed):
-    nbl = 4
-    g = orc.Grid(shape, (10.0, 9.0, 8.0), space_order=8, nbl=nbl, dt=5e-4, nt=nt, vref=2000.0, free_surface=True)
+def _fs_case(orc, shape, nt, seed, mode=True):
+    nbl = 6 if mode == "image" else 4
+    g = orc.Grid(shape, (10.0, 9.0, 8.0), space_order=8, nbl=nbl, dt=5e-4, nt=nt, vref=2000.0, free_surface=mode)
     mdl = inputs.elastic_model(shape, nbl, seed)
+    if mode == "image":   # a fluid on the surface row and the R rows below it
+        mdl["vs"][:nbl + g.r + 1] = 0.0
     nx, ny, nz = shape
     h = g.spacing
     rng = np.random.default_rng(seed)
@@ -91,9 +188,10 @@ def _fs_case(orc, shape, nt, seed):
     return g, mdl, src, rec, kind
 
 
+@pytest.mark.parametrize("mode", [True, "image"])
 @pytest.mark.parametrize("shape", [(11, 10, 14), (20, 1, 18)])
-def test_free_surface_dot_test(orc, shape):
-    g, mdl, src, rec, kind = _fs_case(orc, shape, 30, 5)
+def test_free_surface_dot_test(orc, shape, mode):
+    g, mdl, src, rec, kind = _fs_case(orc, shape, 30, 5, mode)
     mod = orc.ElasticModel.from_velocities(g, mdl["vp"], mdl["vs"], mdl["rho"])
     rng = np.random.default_rng(4)
     x = rng.standard_normal((g.nt, len(src)))
@@ -104,11 +202,13 @@ def test_free_surface_dot_test(orc, shape):
     assert abs(lhs - rhs) / abs(lhs) < 1e-12
 
 
+@pytest.mark.parametrize("mode", [True, "image"])
 @pytest.mark.parametrize("shape", [(12, 11, 14), (22, 1, 20)])
-def test_free_surface_gradient_fd(orc, shape):
+def test_free_surface_gradient_fd(orc, shape, mode):
     """Gradient with respect to vp, vs and rho with a free surface: zero for vp and vs in the vacuum
-    rows, and central finite differences along smooth directions that also cover those rows."""
-    g, mdl, src, rec, kind = _fs_case(orc, shape, 50, 8)
+    rows (and for rho there too with images: those rows copy the density below), and central finite
+    differences along smooth directions that also cover those rows."""
+    g, mdl, src, rec, kind = _fs_case(orc, shape, 50, 8, mode)
     vp, vs, rho = (mdl[k].astype(np.float64) for k in ("vp", "vs", "rho"))
     wav = inputs.ricker(45.0, g.dt, g.nt).astype(np.float64)[:, None]
     pert = 1 + 0.04 * inputs.random_unit_field(g.arr_shape, 2, 1.5)
@@ -116,7 +216,10 @@ def test_free_surface_gradient_fd(orc, shape):
     dobs, _ = orc.elastic_forward(g, tmod, src, wav, rec, kind)
     J0, (gvp, gvs, grho), _ = orc.elastic_gradient(g, vp, vs, rho, src, wav, rec, dobs, kind)
     assert np.abs(gvp[:g.nbl]).max() == 0 and np.abs(gvs[:g.nbl]).max() == 0
-    assert np.abs(grho[:g.nbl]).max() > 0
+    if mode == "image":
+        assert np.abs(grho[:g.nbl]).max() == 0
+    else:
+        assert np.abs(grho[:g.nbl]).max() > 0
 
     def J(m):
         mod = orc.ElasticModel.from_velocities(g, m["vp"], m["vs"], m["rho"])
