@@ -286,7 +286,7 @@ def measure_marine(torch, prop):
     tg = timed(torch, lambda: p.gradient(shot, res, n_ckpt=48, ckpt_dtype="f32"), 1, 0)
     p.close()
     return {"workload": w.name, "grid": list(w.shape), "space_order": w.space_order, "time_steps": w.nt,
-            "free_surface": True, "s": round(t, 4), "GPts/s": round(w.npts * w.nt / t / 1e9, 3),
+            "free_surface": w.free_surface, "s": round(t, 4), "GPts/s": round(w.npts * w.nt / t / 1e9, 3),
             "gradient_vp_vs_rho_s": round(tg, 4), "gradient_checkpoints": 48,
             "receivers": {"pressure_5m": npr, "vz_seabed": len(w.rec_xyz) - npr},
             "peak_pressure": peak[0], "peak_vz": peak[1]}

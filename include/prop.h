@@ -84,12 +84,14 @@ typedef struct {
                              equation on a sub-domain, the elastic section; the vacuum form keeps
                              the step, its transpose and its gradient unchanged in form.)
                              2 = free surface by the method of images (PROP_ELASTIC only, nbl >=
-                             space_order - 2): as 1, and after every step the nbl rows above the
-                             surface row nbl take odd copies of tau_zz (about node row nbl, where
-                             tau_zz is set to zero) and of tau_xz, tau_yz (about the same plane), and
-                             their density mirrors the rows below (the input density of those rows
-                             is not used; the gradient there is zero and flows to the mirrored
-                             rows).  In the acoustic limit this is the method of images exactly. */
+                             space_order - 2, a fluid (vs = 0) on rows nbl .. nbl + space_order / 2,
+                             else PROP_EINVAL from prop_create / prop_set_model): as 1, and after
+                             every step the normal stresses of the surface row nbl are set to zero
+                             and the nbl rows above it take odd copies of tau_zz (about that row) and
+                             of tau_xz, tau_yz (about the same plane); their density mirrors the
+                             rows below (the input density of those rows is not used; the gradient
+                             there is zero and flows to the mirrored rows).  In a fluid this is the
+                             method of images exactly. */
 } prop_grid;
 
 /* Model parameters, DEVICE, dense (nz, ny, nx) over the whole grid.

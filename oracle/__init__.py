@@ -99,8 +99,8 @@ class Grid:
     transpose, dot test and gradients are those of that step).
     free_surface = "image": the same vacuum rows, plus the method of images for the tractions:
     after every step the rows above the surface row ks = nbl receive odd copies of tau_zz (about
-    node row ks, which is set to zero) and of tau_xz, tau_yz (about the same plane, half a cell
-    off their storage rows), and the density of those rows mirrors the rows below (so that the
+    node row ks, whose normal stresses are set to zero) and of tau_xz, tau_yz (about the same
+    plane, half a cell off their storage rows), and the density of those rows mirrors the rows below (so that the
     velocities above the surface are the mirror images a pressure-release plane needs).  The
     surface row and the R rows below it must be fluid (vs = 0): then no shear stress that the image
     rows feed is read back by them (with a solid at the surface this variant is unstable), and in a
@@ -546,12 +546,15 @@ def _normal(g: Grid):
 
 def image_fill(g: Grid, t) -> None:
     """Method-of-images step of the free surface (free_surface = "image"), in place on the
-    stresses [txx, tyy, tzz, txy, txz, tyz]: with ks = nbl the surface node row,
-        tzz[ks] = 0,  tzz[ks - k] = -tzz[ks + k]                 (k = 1 .. ks; node rows)
+    stresses [txx, tyy, tzz, txy, txz, tyz]: with ks = nbl the surface node row (a fluid, so its
+    pressure vanishes: all normal stresses are zero there),
+        txx[ks] = tyy[ks] = tzz[ks] = 0,  tzz[ks - k] = -tzz[ks + k]   (k = 1 .. ks; node rows)
         tc[ks - k] = -tc[ks + k - 1] for tc = txz, tyz          (k = 1 .. ks; storage row i holds
                                                                    the half row i + 1/2)."""
     ks = g.nbl
     tzz, txz, tyz = t[2], t[4], t[5]
+    t[0][ks] = 0.0
+    t[1][ks] = 0.0
     tzz[ks] = 0.0
     for k in range(1, ks + 1):
         tzz[ks - k] = -tzz[ks + k]
@@ -561,7 +564,8 @@ def image_fill(g: Grid, t) -> None:
 
 def image_fill_T(g: Grid, t) -> None:
     """Transpose of ``image_fill`` on adjoint stresses: every overwritten row hands its value,
-    negated, to the row it was copied from, and is cleared; tzz[ks] is cleared."""
+    negated, to the row it was copied from, and is cleared; the normal stresses of row ks are
+    cleared."""
     ks = g.nbl
     tzz, txz, tyz = t[2], t[4], t[5]
     for k in range(1, ks + 1):
@@ -571,6 +575,8 @@ def image_fill_T(g: Grid, t) -> None:
         txz[ks - k] = 0.0
         tyz[ks + k - 1] -= tyz[ks - k]
         tyz[ks - k] = 0.0
+    t[0][ks] = 0.0
+    t[1][ks] = 0.0
     tzz[ks] = 0.0
 
 

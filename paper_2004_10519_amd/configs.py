@@ -9,9 +9,9 @@ has to supply them to the other.
   el3d_400     3D elastic, 400^3, h 10 m, space order 8, 2000 steps, 40-point layers
   ttigrad_256  3D TTI gradient, 256^3, h 12.5 m, space order 8, 2000 steps (and a 64^3 check)
   batch_64     64 TTI shots on windows of a 1024 x 1024 x 512 model, space order 8, 1500 steps
-  el2d_marine  2D elastic, 1701 x 391, h 10 m, space order 8, 5 s, free surface over a 450 m water
-               layer; pressure 5 m below the surface and vz on the sea bed (the paper's 2D example's
-               geometry on a seeded layered model)
+  el2d_marine  2D elastic, 1701 x 391, h 10 m, space order 8, 5 s, free surface (method of images)
+               over a 450 m water layer; pressure 5 m below the surface and vz on the sea bed (the
+               paper's 2D example's geometry on a seeded layered model)
 """
 from __future__ import annotations
 
@@ -39,7 +39,7 @@ class Workload:
     rec_xyz: np.ndarray
     rec_kind: np.ndarray = None
     v_ref: float = 1500.0
-    free_surface: bool = False
+    free_surface: object = False  # True: vacuum rows above the surface; "image": method of images
     model_threads: int = 0        # > 0: the fast FP32 model recipe on that many threads
     model: dict = field(default_factory=dict, repr=False)
 
@@ -176,4 +176,4 @@ def el2d_marine(nt: int = 5556) -> Workload:
     rec = np.concatenate([rp, rv], axis=0).astype(np.float32)
     kind = np.concatenate([np.zeros(xs.size, np.int32), np.ones(xs.size, np.int32)])
     return Workload("el2d_marine", "elastic", shape, h, 8, nt, nbl, 0.9e-3, 9, 12.0, src, rec, kind,
-                    v_ref=1500.0, free_surface=True)
+                    v_ref=1500.0, free_surface="image")

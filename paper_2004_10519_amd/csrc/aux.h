@@ -64,16 +64,17 @@ void aux_el_inject(const Csr &c, const float *data, float scale, float *d0, floa
 void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, const float *gz, const float *lam,
                   const float *mu, const float *t0, const float *t1, const float *t2, float *a0, float *a1, float *a2,
                   hipStream_t st);
-// Free surface by the method of images: the forward fill of the rows above the surface row ks
-// (tyz NULL in 2D), and its transpose on the adjoint stresses followed by sigma = C (g tau~) on
-// rows 0 .. 2 ks.
+// Free surface by the method of images: the forward fill of the surface row ks and the rows above
+// it (tyz NULL in 2D; tyy is formed in 2D too), and its transpose on the adjoint stresses followed by sigma = C (g tau~)
+// on rows 0 .. 2 ks.
 struct ElImage {
     float *t[6];                  // adjoint stresses tau~ (state layout)
     float *s[6];                  // sigma = C (g tau~) (state layout)
     const float *lam, *mu;        // model layout
     const float *gx, *gy, *gz;    // absorbing factors per window axis
 };
-void aux_el_image_fill(const Win &w, int ks, float *tzz, float *txz, float *tyz, hipStream_t st);
+void aux_el_image_fill(const Win &w, int ks, float *txx, float *tyy, float *tzz, float *txz, float *tyz,
+                       hipStream_t st);
 void aux_el_image_fold(const Win &w, int ks, int ndim, const ElImage &J, hipStream_t st);
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
                 hipStream_t st);

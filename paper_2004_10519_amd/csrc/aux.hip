@@ -85,17 +85,21 @@ __global__ void k_el_remix(Csr c, Win w, const float *__restrict__ gx, const flo
     a2[si] = lt + m2 * s2;
 }
 
-// Free surface by the method of images (surface node row ks): after a forward step the rows above
-// the surface take odd copies of the tractions, tzz[ks] = 0, tzz[ks - k] = -tzz[ks + k], and for
-// txz, tyz, whose storage row i holds the half row i + 1/2, tc[ks - k] = -tc[ks + k - 1]
-// (k = 1 .. ks).  One thread per (x, y, k); k = 0 clears the surface row.  Rows read (>= ks) and
-// rows written (< ks, and tzz at ks by k = 0 only) are disjoint.
-__global__ void k_el_image_fill(Win w, int ks, float *tzz, float *txz, float *tyz)
+// Free surface by the method of images (surface node row ks, a fluid): after a forward step the
+// surface row's normal stresses are zero (txx, tyy, tzz) and the rows above take odd copies of the
+// tractions, tzz[ks - k] = -tzz[ks + k], and for txz, tyz, whose storage row i holds the half row
+// i + 1/2, tc[ks - k] = -tc[ks + k - 1] (k = 1 .. ks).  One thread per (x, y, k); k = 0 clears the
+// surface row.  Rows read (> ks for tzz, >= ks for txz, tyz) and rows written (< ks, and row ks by
+// k = 0 only) are disjoint.
+__global__ void k_el_image_fill(Win w, int ks, float *txx, float *tyy, float *tzz, float *txz, float *tyz)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
     if (x >= w.nx) return;
     if (k == 0) {
-        tzz[sidx(w, x, y, ks)] = 0.f;
+        const int64_t s0 = sidx(w, x, y, ks);
+        txx[s0] = 0.f;
+        if (tyy) tyy[s0] = 0.f;
+        tzz[s0] = 0.f;
         return;
     }
     const int64_t lo = sidx(w, x, y, ks - k);
@@ -105,9 +109,10 @@ __global__ void k_el_image_fill(Win w, int ks, float *tzz, float *txz, float *ty
 }
 
 // Transpose of k_el_image_fill on the adjoint stresses tau~ (one thread per (x, y) column): each
-// image row hands its value, negated, to the row it copies and is cleared, and tau~_zz[ks] is
-// cleared; then sigma = C (g tau~) is formed again on the rows the fold touched (0 .. 2 ks), with
-// the expressions of the transposed stress pass's epilogue, for the transposed velocity pass.
+// image row hands its value, negated, to the row it copies and is cleared, and the normal stresses
+// of row ks are cleared; then sigma = C (g tau~) is formed again on the rows the fold touched
+// (0 .. 2 ks), with the expressions of the transposed stress pass's epilogue, for the transposed
+// velocity pass.
 __global__ void k_el_image_fold(Win w, int ks, int ndim, ElImage J)
 {
     const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
@@ -124,7 +129,12 @@ __global__ void k_el_image_fold(Win w, int ks, int ndim, ElImage J)
             tyz[lo] = 0.f;
         }
     }
-    tzz[sidx(w, x, y, ks)] = 0.f;
+    {
+        const int64_t s0 = sidx(w, x, y, ks);
+        J.t[0][s0] = 0.f;
+        J.t[1][s0] = 0.f;
+        tzz[s0] = 0.f;
+    }
     const int zmax = min(2 * ks, w.nz - 1);
     const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0;
     const float gxy = J.gx[x] * J.gy[y];
@@ -662,11 +672,12 @@ void aux_el_remix(const Csr &c, const Win &w, const float *gx, const float *gy, 
                        t2, a0, a1, a2);
 }
 
-void aux_el_image_fill(const Win &w, int ks, float *tzz, float *txz, float *tyz, hipStream_t st)
+void aux_el_image_fill(const Win &w, int ks, float *txx, float *tyy, float *tzz, float *txz, float *tyz,
+                       hipStream_t st)
 {
     if (ks <= 0) return;
-    hipLaunchKernelGGL(k_el_image_fill, dim3((w.nx + BS - 1) / BS, w.ny, ks + 1), dim3(BS), 0, st, w, ks, tzz, txz,
-                       tyz);
+    hipLaunchKernelGGL(k_el_image_fill, dim3((w.nx + BS - 1) / BS, w.ny, ks + 1), dim3(BS), 0, st, w, ks, txx, tyy,
+                       tzz, txz, tyz);
 }
 
 void aux_el_image_fold(const Win &w, int ks, int ndim, const ElImage &J, hipStream_t st)

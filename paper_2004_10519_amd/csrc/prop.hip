@@ -1667,7 +1667,8 @@ int image_row(const prop_s *h) { return h->kind == PROP_ELASTIC && h->g.free_sur
 // The forward fill of the image rows on a set of nine fields (v, then tau).
 void image_fill(prop_s *h, const Slot &sl, float *const *F)
 {
-    if (const int ks = image_row(h)) aux_el_image_fill(sl.w, ks, F[5], F[7], h->g.ndim == 3 ? F[8] : nullptr, h->st);
+    if (const int ks = image_row(h))
+        aux_el_image_fill(sl.w, ks, F[3], F[4], F[5], F[7], h->g.ndim == 3 ? F[8] : nullptr, h->st);
 }
 
 // Its transpose on the slot's adjoint stresses, then sigma = C (g tau~) of the rows it touched.
