@@ -108,54 +108,54 @@ __global__ void k_el_image_fill(Win w, int ks, float *txx, float *tyy, float *tz
     if (tyz) tyz[lo] = -tyz[sidx(w, x, y, ks + k - 1)];
 }
 
-// Transpose of k_el_image_fill on the adjoint stresses tau~ (one thread per (x, y) column): each
-// image row hands its value, negated, to the row it copies and is cleared, and the normal stresses
-// of row ks are cleared; then sigma = C (g tau~) is formed again on the rows the fold touched
-// (0 .. 2 ks), with the expressions of the transposed stress pass's epilogue, for the transposed
-// velocity pass.
+// Transpose of k_el_image_fill on the adjoint stresses tau~ (one thread per (x, y, k), like the
+// fill): each image row hands its value, negated, to the row it copies and is cleared (k >= 1);
+// k = 0 clears the normal stresses of row ks.  Every thread touches its own rows.
 __global__ void k_el_image_fold(Win w, int ks, int ndim, ElImage J)
 {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, k = blockIdx.z;
     if (x >= w.nx) return;
     float *const tzz = J.t[2], *const txz = J.t[4], *const tyz = J.t[5];
-    for (int k = 1; k <= ks; ++k) {
-        const int64_t lo = sidx(w, x, y, ks - k), hz = sidx(w, x, y, ks + k), hs = sidx(w, x, y, ks + k - 1);
-        tzz[hz] -= tzz[lo];
-        tzz[lo] = 0.f;
-        txz[hs] -= txz[lo];
-        txz[lo] = 0.f;
-        if (ndim == 3) {
-            tyz[hs] -= tyz[lo];
-            tyz[lo] = 0.f;
-        }
-    }
-    {
+    if (k == 0) {
         const int64_t s0 = sidx(w, x, y, ks);
         J.t[0][s0] = 0.f;
         J.t[1][s0] = 0.f;
         tzz[s0] = 0.f;
+        return;
     }
-    const int zmax = min(2 * ks, w.nz - 1);
-    const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0;
-    const float gxy = J.gx[x] * J.gy[y];
-    for (int z = 0; z <= zmax; ++z) {
-        const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
-        const int64_t oz = z + 1 < w.nz ? w.my : 0;
-        const float g = gxy * J.gz[z];
-        const float s0 = g * J.t[0][si], s1 = g * J.t[1][si], s2 = g * tzz[si];
-        const float lam = J.lam[mi], mu0 = J.mu[mi];
-        const float lt = lam * (s0 + s1 + s2), m2 = 2.f * mu0;
-        J.s[0][si] = lt + m2 * s0;
-        J.s[1][si] = lt + m2 * s1;
-        J.s[2][si] = lt + m2 * s2;
-        const float mx_ = J.mu[mi + ox], mz_ = J.mu[mi + oz];
-        const float mxz = 0.25f * (mu0 + mx_ + mz_ + J.mu[mi + ox + oz]);
-        J.s[4][si] = mxz * (g * txz[si]);
-        if (ndim == 3) {
-            const float my_ = J.mu[mi + oy];
-            const float myz = 0.25f * (mu0 + my_ + mz_ + J.mu[mi + oy + oz]);
-            J.s[5][si] = myz * (g * tyz[si]);
-        }
+    const int64_t lo = sidx(w, x, y, ks - k), hz = sidx(w, x, y, ks + k), hs = sidx(w, x, y, ks + k - 1);
+    tzz[hz] -= tzz[lo];
+    tzz[lo] = 0.f;
+    txz[hs] -= txz[lo];
+    txz[lo] = 0.f;
+    if (ndim == 3) {
+        tyz[hs] -= tyz[lo];
+        tyz[lo] = 0.f;
+    }
+}
+
+// sigma = C (g tau~) of the rows the fold touched (z = 0 .. 2 ks; one thread per point), with the
+// expressions of the transposed stress pass's epilogue, for the transposed velocity pass.
+__global__ void k_el_image_sigma(Win w, int ndim, ElImage J)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y, z = blockIdx.z;
+    if (x >= w.nx || z >= w.nz) return;
+    const int64_t si = sidx(w, x, y, z), mi = midx(w, x, y, z);
+    const int64_t ox = x + 1 < w.nx ? 1 : 0, oy = y + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
+    const float g = J.gx[x] * J.gy[y] * J.gz[z];
+    const float s0 = g * J.t[0][si], s1 = g * J.t[1][si], s2 = g * J.t[2][si];
+    const float lam = J.lam[mi], mu0 = J.mu[mi];
+    const float lt = lam * (s0 + s1 + s2), m2 = 2.f * mu0;
+    J.s[0][si] = lt + m2 * s0;
+    J.s[1][si] = lt + m2 * s1;
+    J.s[2][si] = lt + m2 * s2;
+    const float mx_ = J.mu[mi + ox], mz_ = J.mu[mi + oz];
+    const float mxz = 0.25f * (mu0 + mx_ + mz_ + J.mu[mi + ox + oz]);
+    J.s[4][si] = mxz * (g * J.t[4][si]);
+    if (ndim == 3) {
+        const float my_ = J.mu[mi + oy];
+        const float myz = 0.25f * (mu0 + my_ + mz_ + J.mu[mi + oy + oz]);
+        J.s[5][si] = myz * (g * J.t[5][si]);
     }
 }
 
@@ -683,7 +683,9 @@ void aux_el_image_fill(const Win &w, int ks, float *txx, float *tyy, float *tzz,
 void aux_el_image_fold(const Win &w, int ks, int ndim, const ElImage &J, hipStream_t st)
 {
     if (ks <= 0) return;
-    hipLaunchKernelGGL(k_el_image_fold, dim3((w.nx + BS - 1) / BS, w.ny), dim3(BS), 0, st, w, ks, ndim, J);
+    hipLaunchKernelGGL(k_el_image_fold, dim3((w.nx + BS - 1) / BS, w.ny, ks + 1), dim3(BS), 0, st, w, ks, ndim, J);
+    hipLaunchKernelGGL(k_el_image_sigma, dim3((w.nx + BS - 1) / BS, w.ny, std::min(2 * ks + 1, w.nz)), dim3(BS), 0,
+                       st, w, ndim, J);
 }
 
 void aux_gather(const Gather &g, const float *f0, const float *f1, const float *f2, float scale, float *out,
