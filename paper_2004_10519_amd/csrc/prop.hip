@@ -333,17 +333,19 @@ void make_tiles(const std::vector<Slot *> &slots, int TY, int zc, bool xcd, std:
 // z-chunk length: enough chunks for ~2048 blocks (elastic: ~4096; its two passes have no
 // autotuner, and 17-plane chunks measured 4 % faster than 34-plane ones at 400^3 so8), but chunks
 // of at least 4R planes (the z halo of a chunk is re-read by its neighbour).  The fused and split
-// TTI passes hold one block per CU (LDS, registers), so they aim at ~256 blocks, one wave: longer
-// chunks re-read less of the z halo (at 256^3 so8, 512 blocks ran 272 us a step against 343 us for
-// 1024 and 442 us for 2048; at 512^3 so12 split pass B ran 1.507 ms with 256 blocks against 1.529
-// with 512 and 1.579 with 1024).
+// TTI passes hold one block per CU (LDS, registers), so they aim at fewer blocks: longer chunks
+// re-read less of the z halo.  The fused pass aims at ~512 (at 256^3 so8, 512 blocks ran 272 us a
+// step against 343 us for 1024 and 442 us for 2048; 256 made the 64 plain shots of the batched
+// workload 10 % slower), the split pair at ~256, one wave (at 512^3 so12 pass B ran 1.507 ms with
+// 256 blocks against 1.529 with 512 and 1.579 with 1024).
 // 2D elastic grids run one-row tiles with few of them per plane and fit in cache: chunks down to
 // R planes (5-plane chunks measured 1.4x faster than 17-plane ones on the 1701 x 391 marine grid).
 int choose_zc(const prop_s *h, int nz, int64_t tiles_xy)
 {
     if (h->opt_zc > 0) return std::min(h->opt_zc, nz);
     const bool one_block_per_cu = h->opt_scheme == TTI_FUSED || h->opt_scheme == TTI_SPLIT;
-    const int64_t target = h->kind == PROP_TTI ? (one_block_per_cu ? 256 : 2048) : 4096;
+    const int64_t target =
+        h->kind == PROP_TTI ? (h->opt_scheme == TTI_SPLIT ? 256 : one_block_per_cu ? 512 : 2048) : 4096;
     const int minlen = h->kind == PROP_ELASTIC && h->g.ndim == 2 ? h->R : 4 * h->R;
     int64_t nch = (target + tiles_xy - 1) / tiles_xy;
     nch = std::max<int64_t>(1, std::min<int64_t>(nch, std::max(1, nz / minlen)));
