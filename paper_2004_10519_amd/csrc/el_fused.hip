@@ -9,8 +9,8 @@
 // other, because a block recomputes v+ on an R-wide ring around its tile from the old stresses of
 // its neighbours' tiles, which must not change under it.
 //
-// A block owns a 64 x 16 tile and the output planes [z0, z1) and marches a front plane zf from
-// z0 - R to z1 + R - 1.  Per front plane:
+// A block owns an EF_TX x EF_TY (32 x 16) tile and the output planes [z0, z1) and marches a front
+// plane zf from z0 - R to z1 + R - 1.  Per front plane:
 //   1. the old stresses of plane zf are staged in LDS over the tile and a 2R ring (x and y
 //      derivatives of the velocity update); tau_zz, tau_xz, tau_yz also enter z queues (registers
 //      for the tile's own columns, LDS for the ring's columns);
