@@ -165,9 +165,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
                          ds_q<R, true>(qzz, W.wz);
         if (own) {
             if (MODE == EL_FWD) {
-                gst(J.v[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
-                if (!SKIPY) gst(J.v[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
-                gst(J.v[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
+                gst(J.vo[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
+                if (!SKIPY) gst(J.vo[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                gst(J.vo[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
             } else {
                 const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
                 const float c0 = g * a0, c1 = g * a1, c2 = g * a2;

@@ -55,6 +55,7 @@ __device__ __forceinline__ void seg_load(const TTIJob &J, int s, int x, int y, i
 struct ElJob {
     Win w;
     float *v[3];                  // vx, vy, vz
+    float *vo[3];                 // forward velocity pass: where v+ goes (v itself for a step in place)
     float *t[6];                  // txx, tyy, tzz, txy, txz, tyz
     float *aux[6];                // adjoint: stiffness-weighted stresses sigma = C (g tau~)
     float *u[3];                  // adjoint: buoyancy-weighted velocities u = bbar (g v~)

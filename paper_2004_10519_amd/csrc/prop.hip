@@ -562,7 +562,7 @@ ElJob el_job(const prop_s *h, const Slot &sl)
 {
     ElJob J{};
     J.w = sl.w;
-    for (int i = 0; i < 3; ++i) J.v[i] = sl.f[i];
+    for (int i = 0; i < 3; ++i) J.v[i] = J.vo[i] = sl.f[i];
     for (int i = 0; i < 6; ++i) J.t[i] = sl.f[3 + i];
     for (int i = 0; i < 6; ++i) J.aux[i] = sl.f[9 + i];
     for (int i = 0; i < 3; ++i) J.u[i] = sl.f[15 + i];
@@ -1760,7 +1760,9 @@ int el_fused_setup(prop_s *h, Slot &sl)
     return upload(sl.job_ef, jobs, h->st);
 }
 
-void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
+// One forward step: the velocity pass with `job`, the stress pass with `job_stress` (the same job
+// for a step in place; another where the velocity pass writes v+ elsewhere).
+void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job, const ElJob *job_stress = nullptr)
 {
     const float dt = (float)h->g.dt;
     {
@@ -1769,7 +1771,8 @@ void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job)
     }
     {
         Timed t(h, 3);
-        launch_el_stress(h->R, el_tile_rows(h->R, h->g.ndim), EL_FWD, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+        launch_el_stress(h->R, el_tile_rows(h->R, h->g.ndim), EL_FWD, job_stress ? job_stress : job, sl.tiles.as<Tile>(),
+                         sl.ntiles, sl.zc, h->W, dt, h->st);
     }
 }
 
@@ -1902,10 +1905,23 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
     TRY(h->seg.fit((size_t)(S + 1) * 3 * P * sizeof(float)));
     float *fw = h->elfwd.as<float>(), *acc = h->elacc.as<float>(), *ck = h->ckpt.as<float>();
     float *vs_ = h->seg.as<float>();
+    // 2D velocity passes never store v_y (it stays zero), so the store's v_y planes are cleared here
+    if (h->g.ndim == 2) aux_fill(vs_, (size_t)(S + 1) * 3 * P, 0.f, h->st);
     ElJob jf = el_job(h, sl);
-    for (int i = 0; i < 3; ++i) jf.v[i] = fw + (size_t)i * P;
+    for (int i = 0; i < 3; ++i) jf.v[i] = jf.vo[i] = fw + (size_t)i * P;
     for (int i = 0; i < 6; ++i) jf.t[i] = fw + (size_t)(3 + i) * P;
-    TRY(upload_one(h->eljob_f, jf, h->st));
+    // job 0: a step in place (checkpoint sweep); jobs 1 + 2k, 2 + 2k: step k of a segment's recompute,
+    // whose velocity pass reads v from store slot k and writes v+ into slot k + 1, where the stress
+    // pass reads it (the stresses stay in place)
+    std::vector<ElJob> jfs(1 + 2 * (size_t)S, jf);
+    for (int k = 0; k < S; ++k)
+        for (int i = 0; i < 3; ++i) {
+            float *const a = vs_ + ((size_t)k * 3 + i) * P, *const b = vs_ + ((size_t)(k + 1) * 3 + i) * P;
+            jfs[1 + 2 * k].v[i] = a;
+            jfs[1 + 2 * k].vo[i] = b;
+            jfs[2 + 2 * k].v[i] = jfs[2 + 2 * k].vo[i] = b;
+        }
+    TRY(upload(h->eljob_f, jfs, h->st));
     const ElJob *djf = h->eljob_f.as<ElJob>();
     const ElJob *dja = sl.job_fwd.as<ElJob>();   // adjoint fields: the slot's own
     ElGradJob gj{};
@@ -1930,8 +1946,10 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
     const ElGradJob *dgj = h->eljob_g.as<ElGradJob>();
     const float dt = (float)h->g.dt;
     float *const fwf[9] = {jf.v[0], jf.v[1], jf.v[2], jf.t[0], jf.t[1], jf.t[2], jf.t[3], jf.t[4], jf.t[5]};
-    auto fwd_step = [&](int n) {
-        el_step_fwd(h, sl, djf);
+    // forward step n; k >= 0: step k of a segment's recompute, v+ into store slot k + 1
+    auto fwd_step = [&](int n, int k) {
+        if (k < 0) el_step_fwd(h, sl, djf);
+        else el_step_fwd(h, sl, djf + 1 + 2 * k, djf + 2 + 2 * k);
         if (s->nsrc) aux_el_inject(sl.src_inj.csr, s->src_wavelet + (size_t)n * s->nsrc, dt, jf.t[0],
                                    h->g.ndim == 3 ? jf.t[1] : nullptr, jf.t[2], h->st);
         image_fill(h, sl, fwf);
@@ -1943,7 +1961,7 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
     // 1) forward with checkpoints (state after step jS, j >= 1), unless a saving forward left them
     aux_fill(fw, 9 * P, 0.f, h->st);
     for (int n = 0; n < (C > 1 && !reuse ? N : 0); ++n) {
-        fwd_step(n);
+        fwd_step(n, -1);
         if ((n + 1) % S == 0 && (n + 1) / S < C) TRY(copy(ck + (size_t)((n + 1) / S - 1) * 9 * P, fw, 9 * P));
         if ((n + 1) % WATCH_EVERY == 0) {
             HIPCHK(hipGetLastError());
@@ -1958,10 +1976,7 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
         if (j == 0) aux_fill(fw, 9 * P, 0.f, h->st);
         else TRY(copy(fw, ck + (size_t)(j - 1) * 9 * P, 9 * P));
         TRY(copy(vs_, fw, 3 * P));
-        for (int n = start; n < end; ++n) {
-            fwd_step(n);
-            TRY(copy(vs_ + (size_t)(n + 1 - start) * 3 * P, fw, 3 * P));
-        }
+        for (int n = start; n < end; ++n) fwd_step(n, n - start);
         for (int n = end - 1; n >= start; --n) {
             const float *row = s->nrec ? residual + (size_t)n * s->nrec : nullptr;
             if (sl.rec_inj.csr.nrows) aux_el_inject(sl.rec_inj.csr, row, 1.f, sl.f[3], tyy_of(h, sl), sl.f[5], h->st);
