@@ -38,8 +38,13 @@ __device__ __forceinline__ float gld(const float *p, int64_t i) { return ((const
 __device__ __forceinline__ void gst(float *p, int64_t i, float v) { ((gfloat *)p)[i] = v; }
 
 // Third component of the unit symmetry axis from the other two (the axis is stored with nz >= 0;
-// n and -n give the same operators).
-__device__ __forceinline__ float axis_z(float n0, float n1) { return sqrtf(fmaxf(0.f, 1.f - n0 * n0 - n1 * n1)); }
+// n and -n give the same operators).  The hardware square root (within 1 ulp) rather than the
+// correctly rounded sqrtf, whose fix-up costs about a dozen more VALU instructions: the stencil
+// passes form n_z at every point of every plane, twice where halo columns are recomputed.
+__device__ __forceinline__ float axis_z(float n0, float n1)
+{
+    return __builtin_amdgcn_sqrtf(fmaxf(0.f, 1.f - n0 * n0 - n1 * n1));
+}
 
 __device__ __forceinline__ bool in_win(const Win &w, int x, int y, int z)
 {
@@ -52,6 +57,22 @@ __device__ __forceinline__ int64_t sidx(const Win &w, int x, int y, int z)
 __device__ __forceinline__ int64_t midx(const Win &w, int x, int y, int z)
 {
     return w.moff + (int64_t)z * w.my + (int64_t)y * w.mx + x;
+}
+
+// Plane addressing of the z-marching kernels: a load or store names a uniform plane base (64-bit,
+// scalar registers) and a per-lane 32-bit byte offset within the plane that stays fixed through the
+// march.
+typedef __attribute__((address_space(1))) const char gcchar;
+typedef __attribute__((address_space(1))) char gchar;
+__device__ __forceinline__ float ldo(gcchar *plane, uint32_t off) { return *(const gfloat *)(plane + off); }
+__device__ __forceinline__ void sto(gchar *plane, uint32_t off, float v) { *(gfloat *)(plane + off) = v; }
+// Re-define an offset inside the loop body (no instruction of its own): keeps it a 32-bit register
+// that the loads add to their scalar base, instead of a widened 64-bit copy per field hoisted out of
+// the loop.
+__device__ __forceinline__ uint32_t fresh(uint32_t o)
+{
+    asm volatile("" : "+v"(o));
+    return o;
 }
 
 // LDS plane of a tile with an R-wide halo on every side (corners unused).

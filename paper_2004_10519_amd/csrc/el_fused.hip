@@ -92,17 +92,6 @@ struct EFGeom {
     }
 };
 
-typedef __attribute__((address_space(1))) const char gcchar;
-typedef __attribute__((address_space(1))) char gchar;
-__device__ __forceinline__ float eld(gcchar *plane, uint32_t off) { return *(const gfloat *)(plane + off); }
-__device__ __forceinline__ void est(gchar *plane, uint32_t off, float v) { *(gfloat *)(plane + off) = v; }
-// Re-define an offset inside the loop body (no instruction), so that it stays a 32-bit register added
-// to a scalar plane base.
-__device__ __forceinline__ uint32_t efresh(uint32_t o)
-{
-    asm volatile("" : "+v"(o));
-    return o;
-}
 
 template <int R>
 __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__restrict__ jobs,
@@ -186,13 +175,13 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
 #pragma unroll
     for (int s = 0; s < U - 1; ++s) {
         const int za = zs0 - R + 1 + s, zb = zs0 - R + s;
-        qzz[s] = ok && zok(za) ? eld(sp(Tzz, za), os) : 0.f;
-        qxz[s] = ok && zok(zb) ? eld(sp(Txz, zb), os) : 0.f;
-        qyz[s] = ok && zok(zb) ? eld(sp(Tyz, zb), os) : 0.f;
+        qzz[s] = ok && zok(za) ? ldo(sp(Tzz, za), os) : 0.f;
+        qxz[s] = ok && zok(zb) ? ldo(sp(Txz, zb), os) : 0.f;
+        qyz[s] = ok && zok(zb) ? ldo(sp(Tyz, zb), os) : 0.f;
         if (hitem) {
-            Hq[0][s][tid] = hok && zok(za) ? eld(sp(Tzz, za), hs) : 0.f;
-            Hq[1][s][tid] = hok && zok(zb) ? eld(sp(Txz, zb), hs) : 0.f;
-            Hq[2][s][tid] = hok && zok(zb) ? eld(sp(Tyz, zb), hs) : 0.f;
+            Hq[0][s][tid] = hok && zok(za) ? ldo(sp(Tzz, za), hs) : 0.f;
+            Hq[1][s][tid] = hok && zok(zb) ? ldo(sp(Txz, zb), hs) : 0.f;
+            Hq[2][s][tid] = hok && zok(zb) ? ldo(sp(Tyz, zb), hs) : 0.f;
         }
     }
 
@@ -204,35 +193,35 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
     auto fetch = [&](int zf) {
         const bool za = zok(zf + R), zb = zok(zf + R - 1), zc0 = zok(zf);
         const int zbn = min(zf + 1, w.nz - 1);
-        const uint32_t fos = efresh(os), fhs = efresh(hs);
-        nzz = ok && za ? eld(sp(Tzz, zf + R), fos) : 0.f;
-        nxz = ok && zb ? eld(sp(Txz, zf + R - 1), fos) : 0.f;
-        nyz = ok && zb ? eld(sp(Tyz, zf + R - 1), fos) : 0.f;
-        nxx = ok && zc0 ? eld(sp(Txx, zf), fos) : 0.f;
-        nyy = ok && zc0 ? eld(sp(Tyy, zf), fos) : 0.f;
-        nxy = ok && zc0 ? eld(sp(Txy, zf), fos) : 0.f;
-        nb = zf + 1 >= 0 ? eld(mp(Bm, zbn), efresh(obm)) : 0.f;
-        hzz = hok && za ? eld(sp(Tzz, zf + R), fhs) : 0.f;
-        hxz = hok && zb ? eld(sp(Txz, zf + R - 1), fhs) : 0.f;
-        hyz = hok && zb ? eld(sp(Tyz, zf + R - 1), fhs) : 0.f;
-        hxx_ = hok && zc0 ? eld(sp(Txx, zf), fhs) : 0.f;
-        hyy_ = hok && zc0 ? eld(sp(Tyy, zf), fhs) : 0.f;
-        hxy = hok && zc0 ? eld(sp(Txy, zf), fhs) : 0.f;
-        hb = hbin && zf + 1 >= 0 ? eld(mp(Bm, zbn), efresh(hbm)) : 0.f;
+        const uint32_t fos = fresh(os), fhs = fresh(hs);
+        nzz = ok && za ? ldo(sp(Tzz, zf + R), fos) : 0.f;
+        nxz = ok && zb ? ldo(sp(Txz, zf + R - 1), fos) : 0.f;
+        nyz = ok && zb ? ldo(sp(Tyz, zf + R - 1), fos) : 0.f;
+        nxx = ok && zc0 ? ldo(sp(Txx, zf), fos) : 0.f;
+        nyy = ok && zc0 ? ldo(sp(Tyy, zf), fos) : 0.f;
+        nxy = ok && zc0 ? ldo(sp(Txy, zf), fos) : 0.f;
+        nb = zf + 1 >= 0 ? ldo(mp(Bm, zbn), fresh(obm)) : 0.f;
+        hzz = hok && za ? ldo(sp(Tzz, zf + R), fhs) : 0.f;
+        hxz = hok && zb ? ldo(sp(Txz, zf + R - 1), fhs) : 0.f;
+        hyz = hok && zb ? ldo(sp(Tyz, zf + R - 1), fhs) : 0.f;
+        hxx_ = hok && zc0 ? ldo(sp(Txx, zf), fhs) : 0.f;
+        hyy_ = hok && zc0 ? ldo(sp(Tyy, zf), fhs) : 0.f;
+        hxy = hok && zc0 ? ldo(sp(Txy, zf), fhs) : 0.f;
+        hb = hbin && zf + 1 >= 0 ? ldo(mp(Bm, zbn), fresh(hbm)) : 0.f;
 #pragma unroll
         for (int k = 0; k < NO; ++k) {
-            const uint32_t frs = efresh(rs[k]);
-            rxx_[k] = rok[k] && zc0 ? eld(sp(Txx, zf), frs) : 0.f;
-            ryy_[k] = rok[k] && zc0 ? eld(sp(Tyy, zf), frs) : 0.f;
-            rxy[k] = rok[k] && zc0 ? eld(sp(Txy, zf), frs) : 0.f;
-            rxz[k] = rok[k] && zc0 ? eld(sp(Txz, zf), frs) : 0.f;
-            ryz[k] = rok[k] && zc0 ? eld(sp(Tyz, zf), frs) : 0.f;
-            rb[k] = rbin[k] && zc0 ? eld(mp(Bm, zf), efresh(rbm[k])) : 0.f;
+            const uint32_t frs = fresh(rs[k]);
+            rxx_[k] = rok[k] && zc0 ? ldo(sp(Txx, zf), frs) : 0.f;
+            ryy_[k] = rok[k] && zc0 ? ldo(sp(Tyy, zf), frs) : 0.f;
+            rxy[k] = rok[k] && zc0 ? ldo(sp(Txy, zf), frs) : 0.f;
+            rxz[k] = rok[k] && zc0 ? ldo(sp(Txz, zf), frs) : 0.f;
+            ryz[k] = rok[k] && zc0 ? ldo(sp(Tyz, zf), frs) : 0.f;
+            rb[k] = rbin[k] && zc0 ? ldo(mp(Bm, zf), fresh(rbm[k])) : 0.f;
         }
     };
     // buoyancy of plane zf at the own and ring columns (the first front's is loaded here)
-    float ob = zok(zs0) && obin ? eld(mp(Bm, zs0), obm) : 0.f;
-    float hb0 = hbin && zok(zs0) ? eld(mp(Bm, zs0), hbm) : 0.f;
+    float ob = zok(zs0) && obin ? ldo(mp(Bm, zs0), obm) : 0.f;
+    float hb0 = hbin && zok(zs0) ? ldo(mp(Bm, zs0), hbm) : 0.f;
     fetch(zs0);
 
     for (int zb = zs0; zb < ze; zb += U) {
@@ -297,13 +286,13 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
             __syncthreads();
 
             // 2. operands of this plane's velocity update, then the next front's prefetch
-            const uint32_t vos = efresh(os), vhs = efresh(hs);
-            const float v0 = ok && zin ? eld(sp(J.vi[0], zf), vos) : 0.f;
-            const float v1 = ok && zin ? eld(sp(J.vi[1], zf), vos) : 0.f;
-            const float v2 = ok && zin ? eld(sp(J.vi[2], zf), vos) : 0.f;
-            const float hv0 = hok && zin ? eld(sp(J.vi[0], zf), vhs) : 0.f;
-            const float hv1 = hok && zin ? eld(sp(J.vi[1], zf), vhs) : 0.f;
-            const float hv2 = hok && zin ? eld(sp(J.vi[2], zf), vhs) : 0.f;
+            const uint32_t vos = fresh(os), vhs = fresh(hs);
+            const float v0 = ok && zin ? ldo(sp(J.vi[0], zf), vos) : 0.f;
+            const float v1 = ok && zin ? ldo(sp(J.vi[1], zf), vos) : 0.f;
+            const float v2 = ok && zin ? ldo(sp(J.vi[2], zf), vos) : 0.f;
+            const float hv0 = hok && zin ? ldo(sp(J.vi[0], zf), vhs) : 0.f;
+            const float hv1 = hok && zin ? ldo(sp(J.vi[1], zf), vhs) : 0.f;
+            const float hv2 = hok && zin ? ldo(sp(J.vi[2], zf), vhs) : 0.f;
             const float gz = zin ? gld(J.gz, zf) : 0.f;
             if (zf + 1 < ze) fetch(zf + 1);
 
@@ -329,10 +318,10 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
                     vn1 = g * (v1 + dt * (0.5f * (b0 + byn)) * fy);
                     vn2 = g * (v2 + dt * (0.5f * (b0 + obz)) * fz);
                     if (zf >= z0 && zf < z1) {
-                        const uint32_t uos = efresh(os);
-                        est(spw(J.vo[0], zf), uos, vn0);
-                        est(spw(J.vo[1], zf), uos, vn1);
-                        est(spw(J.vo[2], zf), uos, vn2);
+                        const uint32_t uos = fresh(os);
+                        sto(spw(J.vo[0], zf), uos, vn0);
+                        sto(spw(J.vo[1], zf), uos, vn1);
+                        sto(spw(J.vo[2], zf), uos, vn2);
                     }
                 }
                 const int lv = G::at_v(ty, tx);
@@ -375,19 +364,19 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
             //    delay line), with the stress pass's expressions
             const int zs = zf - R;
             if (zs >= z0 && ok) {
-                const uint32_t tos = efresh(os), tom = efresh(om);
+                const uint32_t tos = fresh(os), tom = fresh(om);
                 const uint32_t tomx = tom + dmx, tomy = tom + dmy, tomxy = tomx + dmy;
                 const int64_t oz = zs + 1 < w.nz ? w.my : 0;
                 float t[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) t[c] = eld(sp(J.ti[c], zs), tos);
+                for (int c = 0; c < 6; ++c) t[c] = ldo(sp(J.ti[c], zs), tos);
                 gcchar *ml = mp(Lm, zs), *mu_ = mp(Mm, zs), *muz = mp(Mm, zs) + 4 * oz;
-                const float lam = eld(ml, tom);
-                const float mu0 = eld(mu_, tom);
-                const float mx_ = eld(mu_, tomx), mz_ = eld(muz, tom), my_ = eld(mu_, tomy);
-                const float mxz = 0.25f * (mu0 + mx_ + mz_ + eld(muz, tomx));
-                const float mxy = 0.25f * (mu0 + mx_ + my_ + eld(mu_, tomxy));
-                const float myz = 0.25f * (mu0 + my_ + mz_ + eld(muz, tomy));
+                const float lam = ldo(ml, tom);
+                const float mu0 = ldo(mu_, tom);
+                const float mx_ = ldo(mu_, tomx), mz_ = ldo(muz, tom), my_ = ldo(mu_, tomy);
+                const float mxz = 0.25f * (mu0 + mx_ + mz_ + ldo(muz, tomx));
+                const float mxy = 0.25f * (mu0 + mx_ + my_ + ldo(mu_, tomxy));
+                const float myz = 0.25f * (mu0 + my_ + mz_ + ldo(muz, tomy));
                 const float g = gxy * gld(J.gz, zs);
                 float ezz = 0.f, gxz_z = 0.f, gyz_z = 0.f;
 #pragma unroll
@@ -399,13 +388,13 @@ __global__ __launch_bounds__(EF_TX * EF_TY) void el_fused(const ElFusedJob *__re
                 const float exx = DXX(0), eyy = DYY(0), gxy_ = DXY(0);
                 const float gxz = gxz_z + DXZ(0), gyz = gyz_z + DYZ(0);
                 const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
-                const uint32_t uos = efresh(os);
-                est(spw(J.to[0], zs), uos, g * (t[0] + dt * (lt + m2 * exx)));
-                est(spw(J.to[1], zs), uos, g * (t[1] + dt * (lt + m2 * eyy)));
-                est(spw(J.to[2], zs), uos, g * (t[2] + dt * (lt + m2 * ezz)));
-                est(spw(J.to[3], zs), uos, g * (t[3] + dt * mxy * gxy_));
-                est(spw(J.to[4], zs), uos, g * (t[4] + dt * mxz * gxz));
-                est(spw(J.to[5], zs), uos, g * (t[5] + dt * myz * gyz));
+                const uint32_t uos = fresh(os);
+                sto(spw(J.to[0], zs), uos, g * (t[0] + dt * (lt + m2 * exx)));
+                sto(spw(J.to[1], zs), uos, g * (t[1] + dt * (lt + m2 * eyy)));
+                sto(spw(J.to[2], zs), uos, g * (t[2] + dt * (lt + m2 * ezz)));
+                sto(spw(J.to[3], zs), uos, g * (t[3] + dt * mxy * gxy_));
+                sto(spw(J.to[4], zs), uos, g * (t[4] + dt * mxz * gxz));
+                sto(spw(J.to[5], zs), uos, g * (t[5] + dt * myz * gyz));
             }
             VZ(0) = vn2;   // the register of plane zf - 2R now holds v+_z of zf
             // 5. x-y terms of the stress update of plane zf from the LDS plane of v+

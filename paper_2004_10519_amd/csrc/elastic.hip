@@ -385,9 +385,35 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
     const float *__restrict__ Vx = J.vn1[0];
     const float *__restrict__ Vy = J.vn1[1];
     const float *__restrict__ Vz = J.vn1[2];
-    auto ld = [&](const float *f, int x, int y, int z) -> float {
-        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
-    };
+    // addressing: uniform plane bases and per-lane byte offsets within a plane (own column, halo items)
+    auto sp = [&](const float *f, int zz) { return (gcchar *)(f + (int64_t)zz * w.sy); };
+    auto spw = [&](float *f, int zz) { return (gchar *)(f + (int64_t)zz * w.sy); };
+    auto mp = [&](const float *f, int zz) { return (gcchar *)(f + w.moff + (int64_t)zz * w.my); };
+    auto zok = [&](int zz) { return (unsigned)zz < (unsigned)w.nz; };
+    const int cx = own ? gx : 0, cy = own ? gy : 0;
+    const uint32_t os = 4u * (uint32_t)(cy * w.sx + cx), om = 4u * (uint32_t)(cy * w.mx + cx);
+    const uint32_t omx = om + (gx + 1 < w.nx ? 4u : 0u), omy = om + (gy + 1 < w.ny ? 4u * (uint32_t)w.mx : 0u);
+    const float gab_xy = gld(J.gx, cx) * gld(J.gy, cy);   // absorbing factors of the column
+    bool hxok[H::NXH], hyok[H::NYH];
+    uint32_t hxo[H::NXH], hyo[H::NYH];
+#pragma unroll
+    for (int k = 0; k < H::NXH; ++k) {
+        const int i = tid + k * NT;
+        int yy = 0, xx = 0;
+        if (i < H::NXI) H::xitem(i, yy, xx);
+        const int x = x0 + xx, y = y0 + yy;
+        hxok[k] = i < H::NXI && (unsigned)x < (unsigned)w.nx && (unsigned)y < (unsigned)w.ny;
+        hxo[k] = hxok[k] ? 4u * (uint32_t)(y * w.sx + x) : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < H::NYH; ++k) {
+        const int i = tid + k * NT;
+        int yy = 0, xx = 0;
+        if (i < H::NYI) H::yitem(i, yy, xx);
+        const int x = x0 + xx, y = y0 + yy;
+        hyok[k] = !TWO_D && i < H::NYI && (unsigned)x < (unsigned)w.nx && (unsigned)y < (unsigned)w.ny;
+        hyo[k] = hyok[k] ? 4u * (uint32_t)(y * w.sx + x) : 0u;
+    }
 
     float qx[Q], qy[Q], qz[Q];
     float nx_, ny_, nz_;
@@ -395,36 +421,54 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
 #pragma unroll
     for (int s = 1; s < Q; ++s) {
         const int z = z0 - R + s - 1;
-        qx[s] = ld(Vx, gx, gy, z);
-        qy[s] = ld(Vy, gx, gy, z);
-        qz[s] = ld(Vz, gx, gy, z);
+        const bool v = own && zok(z);
+        qx[s] = v ? ldo(sp(Vx, z), os) : 0.f;
+        qy[s] = v ? ldo(sp(Vy, z), os) : 0.f;
+        qz[s] = v ? ldo(sp(Vz, z), os) : 0.f;
     }
     auto fetch = [&](int z) {
-        nx_ = ld(Vx, gx, gy, z + R);
-        ny_ = ld(Vy, gx, gy, z + R);
-        nz_ = ld(Vz, gx, gy, z + R);
+        const bool va = own && zok(z + R), vz = zok(z);
+        const uint32_t fos = fresh(os);
+        nx_ = va ? ldo(sp(Vx, z + R), fos) : 0.f;
+        ny_ = va ? ldo(sp(Vy, z + R), fos) : 0.f;
+        nz_ = va ? ldo(sp(Vz, z + R), fos) : 0.f;
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NXI) H::xitem(i, yy, xx);
-            const bool v = i < H::NXI;
-            hx[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
-            hx[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
-            hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+            const bool v = vz && hxok[k];
+            const uint32_t o = fresh(hxo[k]);
+            hx[0][k] = v ? ldo(sp(Vx, z), o) : 0.f;
+            hx[1][k] = v ? ldo(sp(Vy, z), o) : 0.f;
+            hx[2][k] = v ? ldo(sp(Vz, z), o) : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NYI) H::yitem(i, yy, xx);
-            const bool v = i < H::NYI;
-            hy[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
-            hy[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
-            hy[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+            const bool v = vz && hyok[k];
+            const uint32_t o = fresh(hyo[k]);
+            hy[0][k] = v ? ldo(sp(Vx, z), o) : 0.f;
+            hy[1][k] = v ? ldo(sp(Vy, z), o) : 0.f;
+            hy[2][k] = v ? ldo(sp(Vz, z), o) : 0.f;
         }
     };
     fetch(z0);
+    // per-point operands, loaded a plane ahead: tau~, v~, v^n, buoyancy at the node and its +x, +y, +z
+    // neighbours (clamped at the window's far faces)
+    float pt_t[6], pt_vt[3], pt_v0[3], pt_b[4];
+    auto load_pt = [&](int z) {
+        const uint32_t fos = fresh(os), fom = fresh(om);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) pt_t[c] = ldo(sp(J.tt[c], z), fos);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pt_vt[c] = ldo(sp(J.vt[c], z), fos);
+            pt_v0[c] = ldo(sp(J.vn0[c], z), fos);
+        }
+        gcchar *const bz = mp(J.b, z);
+        pt_b[0] = ldo(bz, fom);
+        pt_b[1] = ldo(bz, fresh(omx));
+        pt_b[2] = ldo(bz, fresh(omy));
+        pt_b[3] = ldo(mp(J.b, z + 1 < w.nz ? z + 1 : z), fom);
+    };
+    load_pt(z0);
     int b = 0;
     for (int z = z0; z < z1; ++z) {
         float *lx = Lx[b], *ly = Ly[b], *lz = Lz[b];
@@ -464,23 +508,18 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
             }
         }
         __syncthreads();
-        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
-        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
         float t[6], vt[3], v0[3];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = gld(J.tt[c], si);
+        for (int c = 0; c < 6; ++c) t[c] = pt_t[c];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            vt[c] = gld(J.vt[c], si);
-            v0[c] = gld(J.vn0[c], si);
-        }
-        const float b0 = gld(J.b, mi);
-        const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
-        const float byn = gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
-        const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
-        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
+        for (int c = 0; c < 3; ++c) vt[c] = pt_vt[c], v0[c] = pt_v0[c];
+        const float b0 = pt_b[0], bxn = pt_b[1], byn = pt_b[2], bzn = pt_b[3];
+        const float g = gab_xy * gld(J.gz, z);
         const float v1[3] = {qx[R], qy[R], qz[R]};
-        if (z + 1 < z1) fetch(z + 1);
+        if (z + 1 < z1) {
+            load_pt(z + 1);
+            fetch(z + 1);
+        }
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
         const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
         const float ezz = ds_q<R, false>(qz, W.wz);
@@ -490,14 +529,15 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
         if (own) {
             const float gdt = g * dt;
             const float bb[3] = {0.5f * (b0 + bxn), 0.5f * (b0 + byn), 0.5f * (b0 + bzn)};
-            gst(J.acc[0], si, gld(J.acc[0], si) + gdt * (t[0] + t[1] + t[2]) * (exx + eyy + ezz));
-            gst(J.acc[1], si, gld(J.acc[1], si) + 2.f * gdt * (t[0] * exx + t[1] * eyy + t[2] * ezz));
-            gst(J.acc[2], si, gld(J.acc[2], si) + gdt * t[3] * gxy);
-            gst(J.acc[3], si, gld(J.acc[3], si) + gdt * t[4] * gxz);
-            gst(J.acc[4], si, gld(J.acc[4], si) + gdt * t[5] * gyz);
+            const uint32_t aos = fresh(os);
+            auto acc_add = [&](int c, float d) { sto(spw(J.acc[c], z), aos, ldo(sp(J.acc[c], z), aos) + d); };
+            acc_add(0, gdt * (t[0] + t[1] + t[2]) * (exx + eyy + ezz));
+            acc_add(1, 2.f * gdt * (t[0] * exx + t[1] * eyy + t[2] * ezz));
+            acc_add(2, gdt * t[3] * gxy);
+            acc_add(3, gdt * t[4] * gxz);
+            acc_add(4, gdt * t[5] * gyz);
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
-                gst(J.acc[5 + c], si, gld(J.acc[5 + c], si) + vt[c] * (v1[c] - g * v0[c]) / (g * bb[c]));
+            for (int c = 0; c < 3; ++c) acc_add(5 + c, vt[c] * (v1[c] - g * v0[c]) / (g * bb[c]));
         }
         b ^= 1;
     }

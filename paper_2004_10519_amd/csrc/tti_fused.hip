@@ -73,19 +73,6 @@ struct FusedItems {
     }
 };
 
-// Addressing: a load or store names a uniform plane base (64-bit, scalar registers) and a per-lane
-// 32-bit byte offset within the plane that stays fixed through the z-march.
-typedef __attribute__((address_space(1))) const char gcchar;
-typedef __attribute__((address_space(1))) char gchar;
-__device__ __forceinline__ float ldo(gcchar *plane, uint32_t off) { return *(const gfloat *)(plane + off); }
-__device__ __forceinline__ void sto(gchar *plane, uint32_t off, float v) { *(gfloat *)(plane + off) = v; }
-// Re-define an offset inside the loop body (no instruction): keeps it a 32-bit register that the
-// loads add to their scalar base, instead of a widened 64-bit copy hoisted out of the loop.
-__device__ __forceinline__ uint32_t fresh(uint32_t o)
-{
-    asm volatile("" : "+v"(o));
-    return o;
-}
 
 template <int R, int BY, int NY, int MODE>
 __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restrict__ jobs,

@@ -76,17 +76,6 @@ struct SplitItems {
     }
 };
 
-typedef __attribute__((address_space(1))) const char gcchar;
-typedef __attribute__((address_space(1))) char gchar;
-__device__ __forceinline__ float ldo(gcchar *plane, uint32_t off) { return *(const gfloat *)(plane + off); }
-__device__ __forceinline__ void sto(gchar *plane, uint32_t off, float v) { *(gfloat *)(plane + off) = v; }
-// Re-define an offset inside the loop body (no instruction), so that it stays a 32-bit register added
-// to a scalar plane base rather than a widened 64-bit address hoisted out of the loop.
-__device__ __forceinline__ uint32_t fresh(uint32_t o)
-{
-    asm volatile("" : "+v"(o));
-    return o;
-}
 
 // PART 0: pass A (h = H0 u into J.t[0]).  PART 1: pass B (Hz v and the update), MODE as K2_*.
 template <int R, int PART, int MODE>
