@@ -36,7 +36,7 @@ constexpr int EBY = 16;
 // load nor store them, and the fields keep the zeros they were filled with.  tau_yy is still
 // formed (it is part of the final state), but in 2D nothing reads it back: its y derivative is
 // zero.
-// Per-lane byte offsets of a z-marching elastic kernel within a plane: the own column (state and
+// Per-lane byte offsets within a plane for the imaging-condition kernel: the own column (state and
 // model layouts, with the +x and +y neighbours of the buoyancy average, clamped at the far faces)
 // and the x- and y-halo items, with whether each lies in the window; and the column's absorbing
 // factor g_x g_y.
@@ -104,18 +104,8 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
     const float *__restrict__ Fxy = F[3];
     const float *__restrict__ Fxz = F[4];
     const float *__restrict__ Fyz = F[5];
-    const ElCols<R, TY, NT> cols(w, x0, y0, gx, gy, own, tid, TWO_D, J);
-    auto sp = [&](const float *f, int zz) { return (gcchar *)(f + (int64_t)zz * w.sy); };
-    auto spw = [&](float *f, int zz) { return (gchar *)(f + (int64_t)zz * w.sy); };
-    auto mp = [&](const float *f, int zz) { return (gcchar *)(f + w.moff + (int64_t)zz * w.my); };
-    auto zok = [&](int zz) { return (unsigned)zz < (unsigned)w.nz; };
-    // own column / halo item k of plane z, zero outside the window
-    auto ldo_own = [&](const float *f, int zz) { return own && zok(zz) ? ldo(sp(f, zz), fresh(cols.os)) : 0.f; };
-    auto ldo_hx = [&](const float *f, int k, int zz) {
-        return cols.hxok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hxo[k])) : 0.f;
-    };
-    auto ldo_hy = [&](const float *f, int k, int zz) {
-        return cols.hyok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hyo[k])) : 0.f;
+    auto ld = [&](const float *f, int x, int y, int z) -> float {
+        return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
     };
 
     float qzz[Q], qxz[Q], qyz[Q];
@@ -124,28 +114,36 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
 #pragma unroll
     for (int s = 1; s < Q; ++s) {
         const int z = z0 - R + s - 1;
-        qzz[s] = ldo_own(Fzz, z);
-        qxz[s] = ldo_own(Fxz, z);
-        qyz[s] = SKIPY ? 0.f : ldo_own(Fyz, z);
+        qzz[s] = ld(Fzz, gx, gy, z);
+        qxz[s] = ld(Fxz, gx, gy, z);
+        qyz[s] = SKIPY ? 0.f : ld(Fyz, gx, gy, z);
     }
     auto fetch = [&](int z) {
-        nzz = ldo_own(Fzz, z + R);
-        nxz = ldo_own(Fxz, z + R);
-        nyz = SKIPY ? 0.f : ldo_own(Fyz, z + R);
-        ixx = ldo_own(Fxx, z);
-        iyy = TWO_D ? 0.f : ldo_own(Fyy, z);   // read only by the y derivative
-        ixy = SKIPY ? 0.f : ldo_own(Fxy, z);
+        nzz = ld(Fzz, gx, gy, z + R);
+        nxz = ld(Fxz, gx, gy, z + R);
+        nyz = SKIPY ? 0.f : ld(Fyz, gx, gy, z + R);
+        ixx = ld(Fxx, gx, gy, z);
+        iyy = TWO_D ? 0.f : ld(Fyy, gx, gy, z);   // read only by the y derivative
+        ixy = SKIPY ? 0.f : ld(Fxy, gx, gy, z);
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            hxx[k] = ldo_hx(Fxx, k, z);
-            hxy_x[k] = SKIPY ? 0.f : ldo_hx(Fxy, k, z);
-            hxz[k] = ldo_hx(Fxz, k, z);
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            const bool v = i < H::NXI;
+            hxx[k] = v ? ld(Fxx, x0 + xx, y0 + yy, z) : 0.f;
+            hxy_x[k] = v && !SKIPY ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
+            hxz[k] = v ? ld(Fxz, x0 + xx, y0 + yy, z) : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
-            hyy[k] = ldo_hy(Fyy, k, z);
-            hxy_y[k] = ldo_hy(Fxy, k, z);
-            hyz[k] = ldo_hy(Fyz, k, z);
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NYI) H::yitem(i, yy, xx);
+            const bool v = i < H::NYI;
+            hyy[k] = v ? ld(Fyy, x0 + xx, y0 + yy, z) : 0.f;
+            hxy_y[k] = v ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
+            hyz[k] = v ? ld(Fyz, x0 + xx, y0 + yy, z) : 0.f;
         }
     };
     fetch(z0);
@@ -191,15 +189,14 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         }
         __syncthreads();
         // per-point values of plane z, then the prefetch of plane z+1
-        const uint32_t fos = fresh(cols.os), fom = fresh(cols.om);
-        const float v0 = ldo(sp(J.v[0], z), fos), v1 = SKIPY ? 0.f : ldo(sp(J.v[1], z), fos);
-        const float v2 = ldo(sp(J.v[2], z), fos);
-        gcchar *const bz = mp(J.b, z);
-        const float b0 = ldo(bz, fom);
-        const float bxn = ldo(bz, fresh(cols.omx));
-        const float byn = SKIPY ? 0.f : ldo(bz, fresh(cols.omy));
-        const float bzn = ldo(mp(J.b, z + 1 < w.nz ? z + 1 : z), fom);
-        const float g = cols.gxy * gld(J.gz, z);
+        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+        const float v0 = gld(J.v[0], si), v1 = SKIPY ? 0.f : gld(J.v[1], si), v2 = gld(J.v[2], si);
+        const float b0 = gld(J.b, mi);
+        const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
+        const float byn = SKIPY ? 0.f : gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+        const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
+        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
         if (z + 1 < z1) fetch(z + 1);
         const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lxy, li, LX, W.wy)) +
                          ds_q<R, false>(qxz, W.wz);
@@ -209,20 +206,19 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lyz, li, LX, W.wy)) +
                          ds_q<R, true>(qzz, W.wz);
         if (own) {
-            const uint32_t sos = fresh(cols.os);
             if (MODE == EL_FWD) {
-                sto(spw(J.vo[0], z), sos, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
-                if (!SKIPY) sto(spw(J.vo[1], z), sos, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
-                sto(spw(J.vo[2], z), sos, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
+                gst(J.vo[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
+                if (!SKIPY) gst(J.vo[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                gst(J.vo[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
             } else {
                 const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
                 const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
-                sto(spw(J.v[0], z), sos, c0);
-                if (!SKIPY) sto(spw(J.v[1], z), sos, c1);
-                sto(spw(J.v[2], z), sos, c2);
-                sto(spw(J.u[0], z), sos, (0.5f * (b0 + bxn)) * c0);
-                if (!SKIPY) sto(spw(J.u[1], z), sos, (0.5f * (b0 + byn)) * c1);
-                sto(spw(J.u[2], z), sos, (0.5f * (b0 + bzn)) * c2);
+                gst(J.v[0], si, c0);
+                if (!SKIPY) gst(J.v[1], si, c1);
+                gst(J.v[2], si, c2);
+                gst(J.u[0], si, (0.5f * (b0 + bxn)) * c0);
+                if (!SKIPY) gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
+                gst(J.u[2], si, (0.5f * (b0 + bzn)) * c2);
             }
         }
         b ^= 1;
