@@ -349,10 +349,10 @@ __global__ __launch_bounds__(PROP_TX * BY) void tti_fused(const TTIJob *__restri
             const float tz = in ? duz - n2 * wu : 0.f, sz = in ? n2 * wv : 0.f;
 #pragma unroll
             for (int j = 1; j <= R; ++j) {
-                at[r][R - j] += W.wz[j - 1] * tz;
-                at[r][R + j] -= W.wz[j - 1] * tz;
-                as[r][R - j] += W.wz[j - 1] * sz;
-                as[r][R + j] -= W.wz[j - 1] * sz;
+                at[r][R - j] = __builtin_fmaf(W.wz[j - 1], tz, at[r][R - j]);
+                at[r][R + j] = __builtin_fmaf(-W.wz[j - 1], tz, at[r][R + j]);
+                as[r][R - j] = __builtin_fmaf(W.wz[j - 1], sz, as[r][R - j]);
+                as[r][R + j] = __builtin_fmaf(-W.wz[j - 1], sz, as[r][R + j]);
             }
         }
 #pragma unroll

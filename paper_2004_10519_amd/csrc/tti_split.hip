@@ -18,8 +18,11 @@
 // registers), plane zf is staged in LDS over the tile, the halo, a second R-wide ring and the
 // corners; the projected gradient of plane zf is formed on the tile (all components) and on the
 // halo (its x or y component); the z components are scattered into per-column accumulators of
-// planes zf - R .. zf + R; the x-y divergence of plane zf joins its accumulator; plane zf - R is
-// then complete.
+// planes zf - R .. zf + R; plane zf - R is then complete.  The LDS planes are double-buffered, so a
+// plane needs one barrier (pass A; pass B keeps a second one): the x-y divergence of plane zf - 1
+// (read from the other buffer) joins its accumulator right after the barrier of plane zf, before
+// plane zf's z components are scattered, which keeps every accumulator's order of additions that of
+// the two-field pass.
 #include "jobs.h"
 
 #include <type_traits>
@@ -91,7 +94,11 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
     using IT = SplitItems<R, TY>;
     static_assert(IT::NHI <= NT, "one halo column per thread");
     constexpr int NO = (IT::NOI + NT - 1) / NT;
-    __shared__ float Lu[UP::SIZE], Lt0[XP::SIZE], Lt1[YP::SIZE];
+    // Double-buffered LDS (one barrier a plane) in pass A; pass B keeps single buffers and a second
+    // barrier, since the deferred divergence adds registers that its update operands need.
+    constexpr bool DB = PART == 0;
+    constexpr int NB = DB ? 2 : 1;
+    __shared__ float Lu[NB * UP::SIZE], Lt0[NB * XP::SIZE], Lt1[NB * YP::SIZE];
 
     const Tile tl = tiles[blockIdx.x];
     const TTIJob &J = jobs[tl.job];
@@ -154,9 +161,10 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
         at[s] = 0.f;
     }
 
-    float nu, on0, on1, hu, hn0, hn1;   // next front zf: own u of plane zf + R, own axis of plane zf; halo
-    float ou[NO];                        // ring u of plane zf
-    auto fetch = [&](int zf) {
+    // next front zf: own u of plane zf + R, own axis of plane zf; halo; ring u of plane zf.  Pass A keeps
+    // two sets, alternating with the plane, so a prefetch never overwrites operands still in use.
+    float nu[NB], on0[NB], on1[NB], hu[NB], hn0[NB], hn1[NB], ou[NB][NO];
+    auto fetch = [&](int zf, int f) {
         const bool za = zok(zf + R), zb = zok(zf);
         const uint32_t fos = fresh(os), fom = fresh(om), fhs = fresh(hs), fhm = fresh(hm);
         uint32_t frs[NO];
@@ -164,19 +172,19 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
         for (int k = 0; k < NO; ++k) frs[k] = fresh(rs[k]);
         gcchar *bu = sp(U, zf + R), *cu = sp(U, zf);
         gcchar *bn0 = mp(Nx, zf), *bn1 = mp(Ny, zf);
-        nu = on0 = on1 = hu = hn0 = hn1 = 0.f;
+        nu[f] = on0[f] = on1[f] = hu[f] = hn0[f] = hn1[f] = 0.f;
         if (za) {
-            nu = ldo(bu, fos);
-            hu = ldo(bu, fhs);
+            nu[f] = ldo(bu, fos);
+            hu[f] = ldo(bu, fhs);
         }
         if (zb) {
-            on0 = ldo(bn0, fom);
-            on1 = ldo(bn1, fom);
-            hn0 = ldo(bn0, fhm);
-            hn1 = ldo(bn1, fhm);
+            on0[f] = ldo(bn0, fom);
+            on1[f] = ldo(bn1, fom);
+            hn0[f] = ldo(bn0, fhm);
+            hn1[f] = ldo(bn1, fhm);
         }
 #pragma unroll
-        for (int k = 0; k < NO; ++k) ou[k] = zb ? ldo(cu, frs[k]) : 0.f;
+        for (int k = 0; k < NO; ++k) ou[f][k] = zb ? ldo(cu, frs[k]) : 0.f;
     };
     // update operands (pass B): current plane (v*) and next plane (nv*)
     float vp0 = 0.f, vq0 = 0.f, vp1 = 0.f, vq1 = 0.f, vm = 0.f, vA = 0.f, vB = 0.f, vh = 0.f;
@@ -198,35 +206,45 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
         }
     };
     load_upd(zs - R);
-    fetch(zs);
-    // The march is unrolled by Q planes: in unrolled step K the three queues are rotated by K slots,
-    // so that advancing them costs no register moves.  Logical slot s of the own and halo u queues
-    // (after plane zf + R has entered) is register (s + K + 1) mod Q; accumulator slot s is register
-    // (s + K) mod Q.
-    for (int zb = zs; zb < ze; zb += Q) {
-        static_for<0, Q>([&](auto kc) {
+    fetch(zs, 0);
+    // The march is unrolled by Q planes (2Q in pass A, so that its LDS buffer and prefetch set follow the
+    // parity of K): in unrolled step K the three queues are rotated by K slots, so that advancing them
+    // costs no register moves.  Logical slot s of the own and halo u queues (after plane zf + R has
+    // entered) is register (s + K + 1) mod Q; accumulator slot s is register (s + K) mod Q.
+    constexpr int UNR = NB * Q;
+    for (int zb = zs; zb < ze; zb += UNR) {
+        static_for<0, UNR>([&](auto kc) {
             constexpr int K = decltype(kc)::value;
             const int zf = zb + K;
             if (zf >= ze) return;   // block-uniform
             auto U_ = [&](int s_) -> float & { return qu[(s_ + K + 1) % Q]; };
             auto H_ = [&](int s_) -> float & { return hq[(s_ + K + 1) % Q]; };
             auto A_ = [&](int s_) -> float & { return at[(s_ + K) % Q]; };
+            // LDS buffers of plane zf (b) and of plane zf - 1 (b ^ 1)
+            constexpr int b = DB ? K & 1 : 0, F = b;
+            float *const Lub = Lu + b * UP::SIZE;
+            float *const Lt0b = Lt0 + b * XP::SIZE, *const Lt1b = Lt1 + b * YP::SIZE;
+            const float *const Lt0o = Lt0 + (b ^ 1) * XP::SIZE, *const Lt1o = Lt1 + (b ^ 1) * YP::SIZE;
             // 1. plane zf + R enters the queues (into the register of the plane that left); stage plane zf
-            U_(Q - 1) = ok ? nu : 0.f;
-            H_(Q - 1) = hok ? hu : 0.f;
-            Lu[UP::at(ty, tx)] = U_(R);
-            if (hitem) Lu[UP::at(hyy, hxx)] = H_(R);
+            U_(Q - 1) = ok ? nu[F] : 0.f;
+            H_(Q - 1) = hok ? hu[F] : 0.f;
+            Lub[UP::at(ty, tx)] = U_(R);
+            if (hitem) Lub[UP::at(hyy, hxx)] = H_(R);
 #pragma unroll
             for (int k = 0; k < NO; ++k) {
                 const int i = tid + k * NT;
                 if (i < IT::NOI) {
                     int yy, xx;
                     IT::ring(i, yy, xx);
-                    Lu[UP::at(yy, xx)] = rok[k] ? ou[k] : 0.f;
+                    Lub[UP::at(yy, xx)] = rok[k] ? ou[F][k] : 0.f;
                 }
             }
-            const float a0 = on0, a1 = on1, b0 = hn0, b1 = hn1;
+            const float a0 = on0[F], a1 = on1[F], b0 = hn0[F], b1 = hn1[F];
             __syncthreads();
+
+            // x-y divergence of plane zf - 1 (its x and y components were written before this barrier)
+            if (DB && zf > zs)
+                A_(R - 1) += dc_lds_x<R>(Lt0o, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1o, YP::at(ty, tx), W.wy);
 
             // plane zo = zf - R is updated in this step with the operands loaded one plane earlier
             const int zo = zf - R;
@@ -248,13 +266,13 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
                 vg = ldo(sp(Grad, zo), fresh(os));
             }
             load_upd(zo + 1);
-            if (zf + 1 < ze) fetch(zf + 1);
+            if (zf + 1 < ze) fetch(zf + 1, F ^ (NB - 1));
 
             // 2. projected gradient of plane zf: own column (all components), halo column (x or y component)
             const bool zin = zok(zf);
             {
                 const int li = UP::at(ty, tx);
-                const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
+                const float dux = dc_lds_x<R>(Lub, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lub, li, W.wy);
                 float duz = 0.f;
 #pragma unroll
                 for (int j = 1; j <= R; ++j) duz += W.wz[j - 1] * (U_(R + j) - U_(R - j));
@@ -263,36 +281,40 @@ __global__ __launch_bounds__(PROP_TX * 16) void tti_split(const TTIJob *__restri
                 const bool in = zin && ok;
                 float tz;
                 if (PART == 0) {
-                    Lt0[XP::at(ty, tx)] = in ? dux - a0 * wu : 0.f;
-                    Lt1[YP::at(ty, tx)] = in ? duy - a1 * wu : 0.f;
+                    Lt0b[XP::at(ty, tx)] = in ? dux - a0 * wu : 0.f;
+                    Lt1b[YP::at(ty, tx)] = in ? duy - a1 * wu : 0.f;
                     tz = in ? duz - n2 * wu : 0.f;
                 } else {
-                    Lt0[XP::at(ty, tx)] = in ? a0 * wu : 0.f;
-                    Lt1[YP::at(ty, tx)] = in ? a1 * wu : 0.f;
+                    Lt0b[XP::at(ty, tx)] = in ? a0 * wu : 0.f;
+                    Lt1b[YP::at(ty, tx)] = in ? a1 * wu : 0.f;
                     tz = in ? n2 * wu : 0.f;
                 }
 #pragma unroll
                 for (int j = 1; j <= R; ++j) {
-                    A_(R - j) += W.wz[j - 1] * tz;
-                    A_(R + j) -= W.wz[j - 1] * tz;
+                    A_(R - j) = __builtin_fmaf(W.wz[j - 1], tz, A_(R - j));
+                    A_(R + j) = __builtin_fmaf(-W.wz[j - 1], tz, A_(R + j));
                 }
             }
             if (hitem) {
                 const int li = UP::at(hyy, hxx);
-                const float dux = dc_lds_x<R>(Lu, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lu, li, W.wy);
+                const float dux = dc_lds_x<R>(Lub, li, W.wx), duy = dc_lds_y<R, UP::LX>(Lub, li, W.wy);
                 float duz = 0.f;
 #pragma unroll
                 for (int j = 1; j <= R; ++j) duz += W.wz[j - 1] * (H_(R + j) - H_(R - j));
                 const float n2 = axis_z(b0, b1);
                 const float wu = b0 * dux + b1 * duy + n2 * duz;
                 const bool in = zin && hok;
-                if (hisx) Lt0[XP::at(hyy, hxx)] = in ? (PART == 0 ? dux - b0 * wu : b0 * wu) : 0.f;
-                else      Lt1[YP::at(hyy, hxx)] = in ? (PART == 0 ? duy - b1 * wu : b1 * wu) : 0.f;
+                if (hisx) Lt0b[XP::at(hyy, hxx)] = in ? (PART == 0 ? dux - b0 * wu : b0 * wu) : 0.f;
+                else      Lt1b[YP::at(hyy, hxx)] = in ? (PART == 0 ? duy - b1 * wu : b1 * wu) : 0.f;
             }
-            __syncthreads();
 
-            // 3. x-y divergence of plane zf; plane zo complete
-            A_(R) += dc_lds_x<R>(Lt0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(ty, tx), W.wy);
+            if (!DB) {
+                // x-y divergence of plane zf
+                __syncthreads();
+                A_(R) += dc_lds_x<R>(Lt0, XP::at(ty, tx), W.wx) + dc_lds_y<R, PROP_TX>(Lt1, YP::at(ty, tx), W.wy);
+            }
+
+            // 3. plane zo complete (its x-y divergence has joined its accumulator)
             if (out && ok) {
                 const uint32_t uos = fresh(os);
                 if (PART == 0) {
