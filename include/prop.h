@@ -243,9 +243,14 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *   PROP_OPT_TILE1/2   0 or 1 (default 1): tile variant of TTI pass 1 / pass 2 when not
  *                      autotuning (0: 64 x 8 threads, 1: 64 x 16 threads; the fused pass uses
  *                      TILE2 and a 64 x 16 tile either way, 0: 512 threads of two rows,
- *                      1: 1024 threads of one row).
+ *                      1: 1024 threads of one row).  Elastic handles on 3D grids read TILE1 for
+ *                      the velocity pass (default 0) and TILE2 for the stress pass and the
+ *                      gradient's imaging condition (default 1), 0: 64 x 8 tiles, 1: 64 x 16.
+ *                      Traces, states and adjoint traces are bitwise the same either way; the
+ *                      elastic gradient may differ at rounding level (1e-7) with TILE2.
  *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
- *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default).
+ *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default);
+ *                      elastic: z-chunk of the stress pass, 0 = automatic for its tiles.
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
  *   PROP_OPT_EL_FUSED  0/1 (default 0): elastic prop_forward on 3D grids up to space order 8 runs
  *                      one fused velocity-stress launch a step (kernel class 4) instead of the

@@ -22,9 +22,13 @@
 
 namespace {
 
-// Tile rows (= threads in y, one row each): 16 on 3D grids; 2D grids (ny = 1) use one row, so a
-// block is a single wavefront and no y-halo work is done (its y derivatives are zero).
+// Tile rows (= threads in y, one row each): 16 (or 8, the tile option's variant 0) on 3D grids; 2D
+// grids (ny = 1) use one row, so a block is a single wavefront and no y-halo work is done (its y
+// derivatives are zero).
 constexpr int EBY = 16;
+#ifndef EL8_WAVES
+#define EL8_WAVES 6
+#endif
 
 // Velocity pass.  Fields read: F[0..5] = (xx, yy, zz, xy, xz, yz) stresses (forward: tau;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
@@ -79,7 +83,7 @@ struct ElCols {
 };
 
 template <int R, int MODE, int BY>
-__global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__ jobs,
+__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL8_WAVES : 1))) void el_vel(const ElJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
@@ -104,8 +108,31 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
     const float *__restrict__ Fxy = F[3];
     const float *__restrict__ Fxz = F[4];
     const float *__restrict__ Fyz = F[5];
+    // 2D one-row tiles address every load by a 64-bit index; 3D tiles by a uniform plane base plus
+    // a fixed 32-bit lane offset (fewer registers: 3D measured faster, 2D slower that way).
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
+    };
+    const ElCols<R, TY, NT> cols(w, x0, y0, gx, gy, own, tid, TWO_D, J);
+    auto sp = [&](const float *f, int zz) { return (gcchar *)(f + (int64_t)zz * w.sy); };
+    auto zok = [&](int zz) { return (unsigned)zz < (unsigned)w.nz; };
+    // own column / halo item k of plane z, zero outside the window
+    auto ld_own = [&](const float *f, int zz) -> float {
+        if constexpr (TWO_D) return ld(f, gx, gy, zz);
+        else return own && zok(zz) ? ldo(sp(f, zz), fresh(cols.os)) : 0.f;
+    };
+    auto ld_hx = [&](const float *f, int k, int zz) -> float {
+        if constexpr (TWO_D) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            return i < H::NXI ? ld(f, x0 + xx, y0 + yy, zz) : 0.f;
+        } else {
+            return cols.hxok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hxo[k])) : 0.f;
+        }
+    };
+    auto ld_hy = [&](const float *f, int k, int zz) -> float {
+        return cols.hyok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hyo[k])) : 0.f;
     };
 
     float qzz[Q], qxz[Q], qyz[Q];
@@ -114,36 +141,28 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
 #pragma unroll
     for (int s = 1; s < Q; ++s) {
         const int z = z0 - R + s - 1;
-        qzz[s] = ld(Fzz, gx, gy, z);
-        qxz[s] = ld(Fxz, gx, gy, z);
-        qyz[s] = SKIPY ? 0.f : ld(Fyz, gx, gy, z);
+        qzz[s] = ld_own(Fzz, z);
+        qxz[s] = ld_own(Fxz, z);
+        qyz[s] = SKIPY ? 0.f : ld_own(Fyz, z);
     }
     auto fetch = [&](int z) {
-        nzz = ld(Fzz, gx, gy, z + R);
-        nxz = ld(Fxz, gx, gy, z + R);
-        nyz = SKIPY ? 0.f : ld(Fyz, gx, gy, z + R);
-        ixx = ld(Fxx, gx, gy, z);
-        iyy = TWO_D ? 0.f : ld(Fyy, gx, gy, z);   // read only by the y derivative
-        ixy = SKIPY ? 0.f : ld(Fxy, gx, gy, z);
+        nzz = ld_own(Fzz, z + R);
+        nxz = ld_own(Fxz, z + R);
+        nyz = SKIPY ? 0.f : ld_own(Fyz, z + R);
+        ixx = ld_own(Fxx, z);
+        iyy = TWO_D ? 0.f : ld_own(Fyy, z);   // read only by the y derivative
+        ixy = SKIPY ? 0.f : ld_own(Fxy, z);
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NXI) H::xitem(i, yy, xx);
-            const bool v = i < H::NXI;
-            hxx[k] = v ? ld(Fxx, x0 + xx, y0 + yy, z) : 0.f;
-            hxy_x[k] = v && !SKIPY ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
-            hxz[k] = v ? ld(Fxz, x0 + xx, y0 + yy, z) : 0.f;
+            hxx[k] = ld_hx(Fxx, k, z);
+            hxy_x[k] = SKIPY ? 0.f : ld_hx(Fxy, k, z);
+            hxz[k] = ld_hx(Fxz, k, z);
         }
 #pragma unroll
         for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NYI) H::yitem(i, yy, xx);
-            const bool v = i < H::NYI;
-            hyy[k] = v ? ld(Fyy, x0 + xx, y0 + yy, z) : 0.f;
-            hxy_y[k] = v ? ld(Fxy, x0 + xx, y0 + yy, z) : 0.f;
-            hyz[k] = v ? ld(Fyz, x0 + xx, y0 + yy, z) : 0.f;
+            hyy[k] = ld_hy(Fyy, k, z);
+            hxy_y[k] = ld_hy(Fxy, k, z);
+            hyz[k] = ld_hy(Fyz, k, z);
         }
     };
     fetch(z0);
@@ -189,36 +208,74 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
         }
         __syncthreads();
         // per-point values of plane z, then the prefetch of plane z+1
-        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
-        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
-        const float v0 = gld(J.v[0], si), v1 = SKIPY ? 0.f : gld(J.v[1], si), v2 = gld(J.v[2], si);
-        const float b0 = gld(J.b, mi);
-        const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
-        const float byn = SKIPY ? 0.f : gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
-        const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
-        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
-        if (z + 1 < z1) fetch(z + 1);
-        const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lxy, li, LX, W.wy)) +
-                         ds_q<R, false>(qxz, W.wz);
-        const float fy = SKIPY ? 0.f
-                               : ds_lds<R, false>(lxy, li, 1, W.wx) +
-                                     (TWO_D ? 0.f : ds_lds<R, true>(lyy, li, LX, W.wy)) + ds_q<R, false>(qyz, W.wz);
-        const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lyz, li, LX, W.wy)) +
-                         ds_q<R, true>(qzz, W.wz);
-        if (own) {
-            if (MODE == EL_FWD) {
-                gst(J.vo[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
-                if (!SKIPY) gst(J.vo[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
-                gst(J.vo[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
-            } else {
-                const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
-                const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
-                gst(J.v[0], si, c0);
-                if (!SKIPY) gst(J.v[1], si, c1);
-                gst(J.v[2], si, c2);
-                gst(J.u[0], si, (0.5f * (b0 + bxn)) * c0);
-                if (!SKIPY) gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
-                gst(J.u[2], si, (0.5f * (b0 + bzn)) * c2);
+        if constexpr (TWO_D) {
+            const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+            const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+            const float v0 = gld(J.v[0], si), v1 = SKIPY ? 0.f : gld(J.v[1], si), v2 = gld(J.v[2], si);
+            const float b0 = gld(J.b, mi);
+            const float bxn = gld(J.b, mi + (gx + 1 < w.nx ? 1 : 0));
+            const float byn = SKIPY ? 0.f : gld(J.b, mi + (gy + 1 < w.ny ? w.mx : 0));
+            const float bzn = gld(J.b, mi + (z + 1 < w.nz ? w.my : 0));
+            const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
+            if (z + 1 < z1) fetch(z + 1);
+            const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lxy, li, LX, W.wy)) +
+                             ds_q<R, false>(qxz, W.wz);
+            const float fy = SKIPY ? 0.f
+                                   : ds_lds<R, false>(lxy, li, 1, W.wx) +
+                                         (TWO_D ? 0.f : ds_lds<R, true>(lyy, li, LX, W.wy)) + ds_q<R, false>(qyz, W.wz);
+            const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + (TWO_D ? 0.f : ds_lds<R, false>(lyz, li, LX, W.wy)) +
+                             ds_q<R, true>(qzz, W.wz);
+            if (own) {
+                if (MODE == EL_FWD) {
+                    gst(J.vo[0], si, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
+                    if (!SKIPY) gst(J.vo[1], si, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                    gst(J.vo[2], si, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
+                } else {
+                    const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
+                    const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
+                    gst(J.v[0], si, c0);
+                    if (!SKIPY) gst(J.v[1], si, c1);
+                    gst(J.v[2], si, c2);
+                    gst(J.u[0], si, (0.5f * (b0 + bxn)) * c0);
+                    if (!SKIPY) gst(J.u[1], si, (0.5f * (b0 + byn)) * c1);
+                    gst(J.u[2], si, (0.5f * (b0 + bzn)) * c2);
+                }
+            }
+        } else {
+            auto spw = [&](float *f, int zz) { return (gchar *)(f + (int64_t)zz * w.sy); };
+            auto mp = [&](const float *f, int zz) { return (gcchar *)(f + w.moff + (int64_t)zz * w.my); };
+            const uint32_t fos = fresh(cols.os), fom = fresh(cols.om);
+            const float v0 = ldo(sp(J.v[0], z), fos), v1 = ldo(sp(J.v[1], z), fos);
+            const float v2 = ldo(sp(J.v[2], z), fos);
+            gcchar *const bz = mp(J.b, z);
+            const float b0 = ldo(bz, fom);
+            const float bxn = ldo(bz, fresh(cols.omx));
+            const float byn = ldo(bz, fresh(cols.omy));
+            const float bzn = ldo(mp(J.b, z + 1 < w.nz ? z + 1 : z), fom);
+            const float g = cols.gxy * gld(J.gz, z);
+            if (z + 1 < z1) fetch(z + 1);
+            const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
+                             ds_q<R, false>(qxz, W.wz);
+            const float fy = ds_lds<R, false>(lxy, li, 1, W.wx) + ds_lds<R, true>(lyy, li, LX, W.wy) +
+                             ds_q<R, false>(qyz, W.wz);
+            const float fz = ds_lds<R, false>(lxz, li, 1, W.wx) + ds_lds<R, false>(lyz, li, LX, W.wy) +
+                             ds_q<R, true>(qzz, W.wz);
+            if (own) {
+                const uint32_t sos = fresh(cols.os);
+                if (MODE == EL_FWD) {
+                    sto(spw(J.vo[0], z), sos, g * (v0 + dt * (0.5f * (b0 + bxn)) * fx));
+                    sto(spw(J.vo[1], z), sos, g * (v1 + dt * (0.5f * (b0 + byn)) * fy));
+                    sto(spw(J.vo[2], z), sos, g * (v2 + dt * (0.5f * (b0 + bzn)) * fz));
+                } else {
+                    const float a0 = v0 - dt * fx, a1 = v1 - dt * fy, a2 = v2 - dt * fz;
+                    const float c0 = g * a0, c1 = g * a1, c2 = g * a2;
+                    sto(spw(J.v[0], z), sos, c0);
+                    sto(spw(J.v[1], z), sos, c1);
+                    sto(spw(J.v[2], z), sos, c2);
+                    sto(spw(J.u[0], z), sos, (0.5f * (b0 + bxn)) * c0);
+                    sto(spw(J.u[1], z), sos, (0.5f * (b0 + byn)) * c1);
+                    sto(spw(J.u[2], z), sos, (0.5f * (b0 + bzn)) * c2);
+                }
             }
         }
         b ^= 1;
@@ -228,7 +285,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_vel(const ElJob *__restrict__
 // Stress pass.  Fields read: V[0..2] (forward: v; adjoint: u = bbar g v~), each staged in LDS
 // with x and y halos and queued in z.
 template <int R, int MODE, int BY>
-__global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restrict__ jobs,
+__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL8_WAVES : 1))) void el_stress(const ElJob *__restrict__ jobs,
                                                           const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
@@ -250,8 +307,29 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
     const float *__restrict__ Vx = V[0];
     const float *__restrict__ Vy = V[1];
     const float *__restrict__ Vz = V[2];
+    // addressing as in the velocity pass: 64-bit indices in 2D, plane base + lane offset in 3D
     auto ld = [&](const float *f, int x, int y, int z) -> float {
         return in_win(w, x, y, z) ? gld(f, sidx(w, x, y, z)) : 0.f;
+    };
+    const ElCols<R, TY, NT> cols(w, x0, y0, gx, gy, own, tid, TWO_D, J);
+    auto sp = [&](const float *f, int zz) { return (gcchar *)(f + (int64_t)zz * w.sy); };
+    auto zok = [&](int zz) { return (unsigned)zz < (unsigned)w.nz; };
+    auto ld_own = [&](const float *f, int zz) -> float {
+        if constexpr (TWO_D) return ld(f, gx, gy, zz);
+        else return own && zok(zz) ? ldo(sp(f, zz), fresh(cols.os)) : 0.f;
+    };
+    auto ld_hx = [&](const float *f, int k, int zz) -> float {
+        if constexpr (TWO_D) {
+            const int i = tid + k * NT;
+            int yy = 0, xx = 0;
+            if (i < H::NXI) H::xitem(i, yy, xx);
+            return i < H::NXI ? ld(f, x0 + xx, y0 + yy, zz) : 0.f;
+        } else {
+            return cols.hxok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hxo[k])) : 0.f;
+        }
+    };
+    auto ld_hy = [&](const float *f, int k, int zz) -> float {
+        return cols.hyok[k] && zok(zz) ? ldo(sp(f, zz), fresh(cols.hyo[k])) : 0.f;
     };
 
     float qx[Q], qy[Q], qz[Q];
@@ -260,33 +338,25 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
 #pragma unroll
     for (int s = 1; s < Q; ++s) {
         const int z = z0 - R + s - 1;
-        qx[s] = ld(Vx, gx, gy, z);
-        qy[s] = SKIPY ? 0.f : ld(Vy, gx, gy, z);
-        qz[s] = ld(Vz, gx, gy, z);
+        qx[s] = ld_own(Vx, z);
+        qy[s] = SKIPY ? 0.f : ld_own(Vy, z);
+        qz[s] = ld_own(Vz, z);
     }
     auto fetch = [&](int z) {
-        nx_ = ld(Vx, gx, gy, z + R);
-        ny_ = SKIPY ? 0.f : ld(Vy, gx, gy, z + R);
-        nz_ = ld(Vz, gx, gy, z + R);
+        nx_ = ld_own(Vx, z + R);
+        ny_ = SKIPY ? 0.f : ld_own(Vy, z + R);
+        nz_ = ld_own(Vz, z + R);
 #pragma unroll
         for (int k = 0; k < H::NXH; ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NXI) H::xitem(i, yy, xx);
-            const bool v = i < H::NXI;
-            hx[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
-            hx[1][k] = v && !SKIPY ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
-            hx[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+            hx[0][k] = ld_hx(Vx, k, z);
+            hx[1][k] = SKIPY ? 0.f : ld_hx(Vy, k, z);
+            hx[2][k] = ld_hx(Vz, k, z);
         }
 #pragma unroll
         for (int k = 0; k < (TWO_D ? 0 : H::NYH); ++k) {
-            const int i = tid + k * NT;
-            int yy = 0, xx = 0;
-            if (i < H::NYI) H::yitem(i, yy, xx);
-            const bool v = i < H::NYI;
-            hy[0][k] = v ? ld(Vx, x0 + xx, y0 + yy, z) : 0.f;
-            hy[1][k] = v ? ld(Vy, x0 + xx, y0 + yy, z) : 0.f;
-            hy[2][k] = v ? ld(Vz, x0 + xx, y0 + yy, z) : 0.f;
+            hy[0][k] = ld_hy(Vx, k, z);
+            hy[1][k] = ld_hy(Vy, k, z);
+            hy[2][k] = ld_hy(Vz, k, z);
         }
     };
     fetch(z0);
@@ -329,68 +399,127 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_stress(const ElJob *__restric
             }
         }
         __syncthreads();
-        const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
-        const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
-        float t[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) t[c] = SKIPY && (c == 3 || c == 5) ? 0.f : gld(J.t[c], si);
-        float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
-        const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
-        {   // (the adjoint needs them for sigma of the new tau~)
-            const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
-            lam = gld(J.lam, mi);
-            mu0 = gld(J.mu, mi);
-            const float mx_ = gld(J.mu, mi + ox), mz_ = gld(J.mu, mi + oz);
-            mxz = 0.25f * (mu0 + mx_ + mz_ + gld(J.mu, mi + ox + oz));
-            if (!SKIPY) {
-                const float my_ = gld(J.mu, mi + oy);
-                mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
-                myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
+        if constexpr (TWO_D) {
+            const int64_t si = sidx(w, own ? gx : 0, own ? gy : 0, z);
+            const int64_t mi = midx(w, own ? gx : 0, own ? gy : 0, z);
+            float t[6];
+    #pragma unroll
+            for (int c = 0; c < 6; ++c) t[c] = SKIPY && (c == 3 || c == 5) ? 0.f : gld(J.t[c], si);
+            float lam = 0.f, mu0 = 0.f, mxy = 0.f, mxz = 0.f, myz = 0.f;
+            const float g = gld(J.gx, own ? gx : 0) * gld(J.gy, own ? gy : 0) * gld(J.gz, z);
+            {   // (the adjoint needs them for sigma of the new tau~)
+                const int64_t ox = gx + 1 < w.nx ? 1 : 0, oy = gy + 1 < w.ny ? w.mx : 0, oz = z + 1 < w.nz ? w.my : 0;
+                lam = gld(J.lam, mi);
+                mu0 = gld(J.mu, mi);
+                const float mx_ = gld(J.mu, mi + ox), mz_ = gld(J.mu, mi + oz);
+                mxz = 0.25f * (mu0 + mx_ + mz_ + gld(J.mu, mi + ox + oz));
+                if (!SKIPY) {
+                    const float my_ = gld(J.mu, mi + oy);
+                    mxy = 0.25f * (mu0 + mx_ + my_ + gld(J.mu, mi + ox + oy));
+                    myz = 0.25f * (mu0 + my_ + mz_ + gld(J.mu, mi + oy + oz));
+                }
             }
-        }
-        if (z + 1 < z1) fetch(z + 1);
-        const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
-        const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
-        const float ezz = ds_q<R, false>(qz, W.wz);
-        const float gxy =
-            SKIPY ? 0.f : (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
-        const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
-        const float gyz = SKIPY ? 0.f : ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
-        if (own) {
-            if (MODE == EL_FWD) {
-                const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
-                gst(J.t[0], si, g * (t[0] + dt * (lt + m2 * exx)));
-                gst(J.t[1], si, g * (t[1] + dt * (lt + m2 * eyy)));
-                gst(J.t[2], si, g * (t[2] + dt * (lt + m2 * ezz)));
-                if (!SKIPY) gst(J.t[3], si, g * (t[3] + dt * mxy * gxy));
-                gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
-                if (!SKIPY) gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
-            } else {
-                float tg[6], tn[6];
+            if (z + 1 < z1) fetch(z + 1);
+            const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
+            const float eyy = (TWO_D ? 0.f : ds_lds<R, false>(ly, li, LX, W.wy));
+            const float ezz = ds_q<R, false>(qz, W.wz);
+            const float gxy =
+                SKIPY ? 0.f : (TWO_D ? 0.f : ds_lds<R, true>(lx, li, LX, W.wy)) + ds_lds<R, true>(ly, li, 1, W.wx);
+            const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
+            const float gyz = SKIPY ? 0.f : ds_q<R, true>(qy, W.wz) + (TWO_D ? 0.f : ds_lds<R, true>(lz, li, LX, W.wy));
+            if (own) {
+                if (MODE == EL_FWD) {
+                    const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
+                    gst(J.t[0], si, g * (t[0] + dt * (lt + m2 * exx)));
+                    gst(J.t[1], si, g * (t[1] + dt * (lt + m2 * eyy)));
+                    gst(J.t[2], si, g * (t[2] + dt * (lt + m2 * ezz)));
+                    if (!SKIPY) gst(J.t[3], si, g * (t[3] + dt * mxy * gxy));
+                    gst(J.t[4], si, g * (t[4] + dt * mxz * gxz));
+                    if (!SKIPY) gst(J.t[5], si, g * (t[5] + dt * myz * gyz));
+                } else {
+                    float tg[6], tn[6];
+    #pragma unroll
+                    for (int c = 0; c < 6; ++c) tg[c] = g * t[c];
+                    tn[0] = tg[0] - dt * exx;
+                    tn[1] = tg[1] - dt * eyy;
+                    tn[2] = tg[2] - dt * ezz;
+                    tn[3] = tg[3] - dt * gxy;
+                    tn[4] = tg[4] - dt * gxz;
+                    tn[5] = tg[5] - dt * gyz;
+    #pragma unroll
+                    for (int c = 0; c < 6; ++c)
+                        if (!(SKIPY && (c == 3 || c == 5))) gst(J.t[c], si, tn[c]);
+                    // sigma = C (g tau~) of the new tau~, which the velocity pass of the next (earlier)
+                    // step reads; where that step injects receiver residuals into tau~, el_remix
+                    // recomputes the diagonal components after the injection
+                    float sg[6];
+    #pragma unroll
+                    for (int c = 0; c < 6; ++c) sg[c] = g * tn[c];
+                    const float lt = lam * (sg[0] + sg[1] + sg[2]), m2 = 2.f * mu0;
+                    gst(J.aux[0], si, lt + m2 * sg[0]);
+                    gst(J.aux[1], si, lt + m2 * sg[1]);
+                    gst(J.aux[2], si, lt + m2 * sg[2]);
+                    if (!SKIPY) gst(J.aux[3], si, mxy * sg[3]);
+                    gst(J.aux[4], si, mxz * sg[4]);
+                    if (!SKIPY) gst(J.aux[5], si, myz * sg[5]);
+                }
+            }
+        } else {
+            auto spw = [&](float *f, int zz) { return (gchar *)(f + (int64_t)zz * w.sy); };
+            auto mp = [&](const float *f, int zz) { return (gcchar *)(f + w.moff + (int64_t)zz * w.my); };
+            const uint32_t fos = fresh(cols.os), fom = fresh(cols.om);
+            float t[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c) tg[c] = g * t[c];
-                tn[0] = tg[0] - dt * exx;
-                tn[1] = tg[1] - dt * eyy;
-                tn[2] = tg[2] - dt * ezz;
-                tn[3] = tg[3] - dt * gxy;
-                tn[4] = tg[4] - dt * gxz;
-                tn[5] = tg[5] - dt * gyz;
+            for (int c = 0; c < 6; ++c) t[c] = ldo(sp(J.t[c], z), fos);
+            const float g = cols.gxy * gld(J.gz, z);
+            gcchar *const m0 = mp(J.mu, z), *const m1 = mp(J.mu, z + 1 < w.nz ? z + 1 : z);
+            const uint32_t omx = fresh(cols.omx), omy = fresh(cols.omy), omxy = omx + omy - fom;
+            const float lam = ldo(mp(J.lam, z), fom);
+            const float mu0 = ldo(m0, fom);
+            const float mx_ = ldo(m0, omx), mz_ = ldo(m1, fom), my_ = ldo(m0, omy);
+            const float mxz = 0.25f * (mu0 + mx_ + mz_ + ldo(m1, omx));
+            const float mxy = 0.25f * (mu0 + mx_ + my_ + ldo(m0, omxy));
+            const float myz = 0.25f * (mu0 + my_ + mz_ + ldo(m1, omy));
+            if (z + 1 < z1) fetch(z + 1);
+            const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
+            const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
+            const float ezz = ds_q<R, false>(qz, W.wz);
+            const float gxy = ds_lds<R, true>(lx, li, LX, W.wy) + ds_lds<R, true>(ly, li, 1, W.wx);
+            const float gxz = ds_q<R, true>(qx, W.wz) + ds_lds<R, true>(lz, li, 1, W.wx);
+            const float gyz = ds_q<R, true>(qy, W.wz) + ds_lds<R, true>(lz, li, LX, W.wy);
+            if (own) {
+                const uint32_t sos = fresh(cols.os);
+                if (MODE == EL_FWD) {
+                    const float lt = lam * (exx + eyy + ezz), m2 = 2.f * mu0;
+                    sto(spw(J.t[0], z), sos, g * (t[0] + dt * (lt + m2 * exx)));
+                    sto(spw(J.t[1], z), sos, g * (t[1] + dt * (lt + m2 * eyy)));
+                    sto(spw(J.t[2], z), sos, g * (t[2] + dt * (lt + m2 * ezz)));
+                    sto(spw(J.t[3], z), sos, g * (t[3] + dt * mxy * gxy));
+                    sto(spw(J.t[4], z), sos, g * (t[4] + dt * mxz * gxz));
+                    sto(spw(J.t[5], z), sos, g * (t[5] + dt * myz * gyz));
+                } else {
+                    float tg[6], tn[6];
 #pragma unroll
-                for (int c = 0; c < 6; ++c)
-                    if (!(SKIPY && (c == 3 || c == 5))) gst(J.t[c], si, tn[c]);
-                // sigma = C (g tau~) of the new tau~, which the velocity pass of the next (earlier)
-                // step reads; where that step injects receiver residuals into tau~, el_remix
-                // recomputes the diagonal components after the injection
-                float sg[6];
+                    for (int c = 0; c < 6; ++c) tg[c] = g * t[c];
+                    tn[0] = tg[0] - dt * exx;
+                    tn[1] = tg[1] - dt * eyy;
+                    tn[2] = tg[2] - dt * ezz;
+                    tn[3] = tg[3] - dt * gxy;
+                    tn[4] = tg[4] - dt * gxz;
+                    tn[5] = tg[5] - dt * gyz;
 #pragma unroll
-                for (int c = 0; c < 6; ++c) sg[c] = g * tn[c];
-                const float lt = lam * (sg[0] + sg[1] + sg[2]), m2 = 2.f * mu0;
-                gst(J.aux[0], si, lt + m2 * sg[0]);
-                gst(J.aux[1], si, lt + m2 * sg[1]);
-                gst(J.aux[2], si, lt + m2 * sg[2]);
-                if (!SKIPY) gst(J.aux[3], si, mxy * sg[3]);
-                gst(J.aux[4], si, mxz * sg[4]);
-                if (!SKIPY) gst(J.aux[5], si, myz * sg[5]);
+                    for (int c = 0; c < 6; ++c) sto(spw(J.t[c], z), sos, tn[c]);
+                    float sg[6];
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) sg[c] = g * tn[c];
+                    const float lt = lam * (sg[0] + sg[1] + sg[2]), m2 = 2.f * mu0;
+                    sto(spw(J.aux[0], z), sos, lt + m2 * sg[0]);
+                    sto(spw(J.aux[1], z), sos, lt + m2 * sg[1]);
+                    sto(spw(J.aux[2], z), sos, lt + m2 * sg[2]);
+                    sto(spw(J.aux[3], z), sos, mxy * sg[3]);
+                    sto(spw(J.aux[4], z), sos, mxz * sg[4]);
+                    sto(spw(J.aux[5], z), sos, myz * sg[5]);
+                }
             }
         }
         b ^= 1;
@@ -647,8 +776,9 @@ template <int R>
 void vel_dispatch(int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                   float dt, hipStream_t st)
 {
-    if (by == 1) vel_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
-    else         vel_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    if (by == 1)      vel_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else if (by == 8) vel_launch<R, 8>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else              vel_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
 }
 
 template <int R, int BY>
@@ -664,16 +794,17 @@ template <int R>
 void stress_dispatch(int by, int mode, const ElJob *jobs, const Tile *tiles, int ntiles, int zc, const Weights &W,
                      float dt, hipStream_t st)
 {
-    if (by == 1) stress_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
-    else         stress_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    if (by == 1)      stress_launch<R, 1>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else if (by == 8) stress_launch<R, 8>(mode, jobs, tiles, ntiles, zc, W, dt, st);
+    else              stress_launch<R, EBY>(mode, jobs, tiles, ntiles, zc, W, dt, st);
 }
 
 }  // namespace
 
-int el_tile_rows(int R, int ndim)
+int el_tile_rows(int R, int ndim, int variant)
 {
     (void)R;
-    return ndim == 2 ? 1 : EBY;
+    return ndim == 2 ? 1 : variant == 0 ? 8 : EBY;
 }
 
 #define EL_SWITCH(FN, ...)                                  \
@@ -706,6 +837,8 @@ void gic_dispatch(int by, const ElGradJob *job, const Tile *tiles, int ntiles, i
                   hipStream_t st)
 {
     if (by == 1) hipLaunchKernelGGL((el_grad_ic<R, 1>), dim3(ntiles), dim3(PROP_TX, 1), 0, st, job, tiles, zc, W, dt);
+    else if (by == 8)
+        hipLaunchKernelGGL((el_grad_ic<R, 8>), dim3(ntiles), dim3(PROP_TX, 8), 0, st, job, tiles, zc, W, dt);
     else hipLaunchKernelGGL((el_grad_ic<R, EBY>), dim3(ntiles), dim3(PROP_TX, EBY), 0, st, job, tiles, zc, W, dt);
 }
 

@@ -213,7 +213,7 @@ struct Slot {
     Plans src_inj, rec_inj, rec_inj_vz, rec_gat, rec_gat_vz, src_gat;
     DevBuf job_fwd, job_adj;    // TTIJob / ElJob on the device
     DevBuf tiles, tiles2;        // tile lists (TTI: pass 1 and pass 2 use different tile heights)
-    int ntiles = 0, ntiles2 = 0, zc = 0;
+    int ntiles = 0, ntiles2 = 0, zc = 0, zc2 = 0;   // zc2: z-chunk of tiles2 (elastic stress pass)
     DevBuf tiles_ef, job_ef;     // elastic fused step: its tiles and its two jobs (one per buffer set)
     int ntiles_ef = 0, zc_ef = 0;
     int nsrc = 0, nrec = 0;
@@ -251,9 +251,11 @@ struct prop_s {
     // options (prop_set_option)
     int opt_graph = 0, opt_autotune = 0, opt_xcd = 0;
     int opt_el_fused = 0;       // elastic forward: the fused velocity-stress step where it applies
-    int opt_shape[2] = {1, 1};  // fixed TTI tile variants of pass 1 / pass 2 when not autotuning
+    int opt_shape[2] = {1, 1};  // tile variants: TTI pass 1 / pass 2 when not autotuning; elastic
+                                // velocity / stress pass (and imaging condition)
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
-    int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1)
+    int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1) or of the elastic
+                                // stress pass (0: automatic)
     int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_FUSED, TTI_FOUR or TTI_SPLIT); set at create
     int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
     // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
@@ -303,7 +305,7 @@ bool fused_fits(const prop_grid &g)
 int tile_rows(const prop_s *h, int pass, int shape)
 {
     if (h->kind == PROP_TTI) return tti_tile_rows(h->R, h->opt_scheme, pass, shape);
-    return el_tile_rows(h->R, h->g.ndim);
+    return el_tile_rows(h->R, h->g.ndim, shape);
 }
 
 // Tiles of a set of windows in spatial order (x fastest, then y, then z chunk of zc planes).  With
@@ -525,6 +527,12 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
     const int TY = tile_rows(h, 1, h->opt_shape[0]);
     const int64_t txy = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY - 1) / TY);
     sl.zc = choose_zc(h, w.nz, txy);
+    sl.zc2 = sl.zc;
+    if (h->kind == PROP_ELASTIC) {   // the stress pass runs its own tiles (TILE2) and z-chunk
+        const int TY2 = tile_rows(h, 2, h->opt_shape[1]);
+        const int64_t txy2 = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY2 - 1) / TY2);
+        sl.zc2 = h->opt_zc2 > 0 ? std::min(h->opt_zc2, (int)w.nz) : choose_zc(h, w.nz, txy2);
+    }
     return PROP_OK;
 }
 
@@ -590,7 +598,7 @@ int set_tiles(prop_s *h, Slot &sl)
     make_tiles(one, tile_rows(h, 1, h->opt_shape[0]), sl.zc, h->opt_xcd, tiles);
     sl.ntiles = (int)tiles.size();
     TRY(upload(sl.tiles, tiles, h->st));
-    make_tiles(one, tile_rows(h, 2, h->opt_shape[1]), sl.zc, h->opt_xcd, tiles);
+    make_tiles(one, tile_rows(h, 2, h->opt_shape[1]), sl.zc2, h->opt_xcd, tiles);
     sl.ntiles2 = (int)tiles.size();
     return upload(sl.tiles2, tiles, h->st);
 }
@@ -1767,12 +1775,12 @@ void el_step_fwd(prop_s *h, Slot &sl, const ElJob *job, const ElJob *job_stress 
     const float dt = (float)h->g.dt;
     {
         Timed t(h, 2);
-        launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_FWD, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+        launch_el_vel(h->R, tile_rows(h, 1, h->opt_shape[0]), EL_FWD, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
     }
     {
         Timed t(h, 3);
-        launch_el_stress(h->R, el_tile_rows(h->R, h->g.ndim), EL_FWD, job_stress ? job_stress : job, sl.tiles.as<Tile>(),
-                         sl.ntiles, sl.zc, h->W, dt, h->st);
+        launch_el_stress(h->R, tile_rows(h, 2, h->opt_shape[1]), EL_FWD, job_stress ? job_stress : job,
+                         sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc2, h->W, dt, h->st);
     }
 }
 
@@ -1860,11 +1868,11 @@ int el_adjoint(prop_s *h, const prop_shot *s, const float *rec_in, float *src_ou
                                 h->st);
         {
             Timed t(h, 2);
-            launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            launch_el_vel(h->R, tile_rows(h, 1, h->opt_shape[0]), EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
         }
         {
             Timed t(h, 3);
-            launch_el_stress(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, job, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            launch_el_stress(h->R, tile_rows(h, 2, h->opt_shape[1]), EL_ADJ, job, sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc2, h->W, dt, h->st);
         }
         if ((h->g.nt - n) % WATCH_EVERY == 0 || n == 0) {
             HIPCHK(hipGetLastError());
@@ -1985,12 +1993,14 @@ int el_gradient(prop_s *h, const prop_shot *s, const float *residual, float *out
             image_fold(h, sl);
             {
                 Timed t(h, 2);
-                launch_el_vel(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+                launch_el_vel(h->R, tile_rows(h, 1, h->opt_shape[0]), EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
             }
-            launch_el_grad_ic(h->R, el_tile_rows(h->R, h->g.ndim), dgj + (n - start), sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+            launch_el_grad_ic(h->R, tile_rows(h, 2, h->opt_shape[1]), dgj + (n - start), sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc2, h->W,
+                              dt, h->st);
             {
                 Timed t(h, 3);
-                launch_el_stress(h->R, el_tile_rows(h->R, h->g.ndim), EL_ADJ, dja, sl.tiles.as<Tile>(), sl.ntiles, sl.zc, h->W, dt, h->st);
+                launch_el_stress(h->R, tile_rows(h, 2, h->opt_shape[1]), EL_ADJ, dja, sl.tiles2.as<Tile>(), sl.ntiles2, sl.zc2, h->W, dt,
+                                 h->st);
             }
         }
         HIPCHK(hipGetLastError());
@@ -2064,6 +2074,9 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
     h->g = *grid;
     h->st = (hipStream_t)stream;
     h->R = grid->space_order / 2;
+    // elastic 3D grids: 64 x 8 tiles for the velocity pass (three blocks of 512 threads a CU; 400^3
+    // so8: 0.78-0.79 against 0.87 ms), 64 x 16 for the stress pass (1.00 against 1.02-1.04 ms)
+    if (kind == PROP_ELASTIC) h->opt_shape[0] = 0;
     // default TTI scheme (512^3 workload, ms per step): space order 8 and below, the fused pass
     // (so8: 1.70 against 1.50 + 0.80 for the split pair and 2.94 for two passes); space orders 10-12,
     // the split pair of fused single-field passes (so12: 1.05 + 1.59 = 2.64 against 2.95 for the

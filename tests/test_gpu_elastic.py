@@ -295,3 +295,45 @@ def test_fused_elastic_checkpoints_feed_the_gradient(prop):
     p.forward(shot, save_ckpt=6, ckpt_dtype="f32")
     g_reuse = host(p.gradient(shot, rec, n_ckpt=0, ckpt_dtype="f32"))
     assert np.array_equal(g_reuse, g_fresh), rel_l2(g_reuse, g_fresh)
+
+
+# ---- tile heights of the elastic passes (TILE1: velocity pass, TILE2: stress pass and imaging
+# condition; 0: 64 x 8, 1: 64 x 16; default 0 and 1)
+@pytest.mark.parametrize("so,shape,zc", [(8, (70, 37, 29), 0), (4, (66, 20, 40), 7), (12, (40, 22, 30), 0),
+                                         (8, (130, 45, 33), 5)])
+def test_elastic_tile_rows_change_no_bit(prop, so, shape, zc):
+    """Forward traces and final fields and adjoint source traces are equal bit for bit with 64 x 8
+    and 64 x 16 tiles in either pass: each point is formed by the same expressions, whichever tile
+    computes it (ragged tiles in x and y, one and several z chunks).  So is the (vp, vs, rho)
+    gradient while the imaging condition keeps its tile height; with the other height it runs
+    another instantiation of that kernel, whose products and sums the compiler may contract into
+    fused multiply-adds differently: rounding level."""
+    case = el_case(shape, so, 5, 41)
+    rec = dev(np.random.default_rng(6).standard_normal((case["nt"], len(case["rec"]))))
+    out = []
+    for t1, t2 in ((None, None), (1, 1), (0, 0)):
+        p, shot = make_el(case, prop)
+        if t1 is None:
+            assert (p.get_option("tile1"), p.get_option("tile2")) == (0, 1)
+        else:
+            p.set_option("tile1", t1)
+            p.set_option("tile2", t2)
+        if zc:
+            p.set_option("zc", zc)
+        d = host(p.forward(shot)).copy()
+        f = [host(p.read_state(i)).copy() for i in range(9)]
+        a = host(p.adjoint(shot, rec)).copy()
+        g = host(p.gradient(shot, rec, n_ckpt=4, ckpt_dtype="f32")).copy()
+        out.append((d, f, a, g))
+        p.close()
+    d0, f0, a0, g0 = out[0]
+    assert np.abs(d0).max() > 0 and np.abs(g0).max() > 0
+    for k, (d1, f1, a1, g1) in enumerate(out[1:]):
+        assert np.array_equal(d0, d1), (k, rel_l2(d1, d0))
+        for i in range(9):
+            assert np.array_equal(f0[i], f1[i]), (k, i, rel_l2(f1[i], f0[i]))
+        assert np.array_equal(a0, a1), (k, rel_l2(a1, a0))
+        if k == 0:
+            assert np.array_equal(g0, g1), rel_l2(g1, g0)
+        else:
+            assert rel_l2(g1, g0) <= 1e-6, rel_l2(g1, g0)
