@@ -22,8 +22,8 @@
 
 namespace {
 
-// Tile rows (= threads in y, one row each): 16 (or 8, the tile option's variant 0) on 3D grids; 2D
-// grids (ny = 1) use one row, so a block is a single wavefront and no y-halo work is done (its y
+// Tile rows (= threads in y, one row each): 16 on 3D grids (the launchers also take 8); 2D grids
+// (ny = 1) use one row, so a block is a single wavefront and no y-halo work is done (its y
 // derivatives are zero).
 constexpr int EBY = 16;
 #ifndef EL8_WAVES
@@ -801,10 +801,10 @@ void stress_dispatch(int by, int mode, const ElJob *jobs, const Tile *tiles, int
 
 }  // namespace
 
-int el_tile_rows(int R, int ndim, int variant)
+int el_tile_rows(int R, int ndim)
 {
     (void)R;
-    return ndim == 2 ? 1 : variant == 0 ? 8 : EBY;
+    return ndim == 2 ? 1 : EBY;
 }
 
 #define EL_SWITCH(FN, ...)                                  \

@@ -131,5 +131,4 @@ void launch_el_grad_ic(int R, int by, const ElGradJob *job, const Tile *tiles, i
 void launch_el_grad_finish(const ElGradJob *job, const Win &w, int ndim, int nvac, int nimg, const float *vp,
                            const float *vs,
                            const float *rho, float *out, hipStream_t st);
-// Tile rows of the elastic stencil passes: 1 on 2D grids; in 3D 8 (variant 0) or 16 (variant 1).
-int el_tile_rows(int R, int ndim, int variant);
+int el_tile_rows(int R, int ndim);

@@ -305,7 +305,8 @@ bool fused_fits(const prop_grid &g)
 int tile_rows(const prop_s *h, int pass, int shape)
 {
     if (h->kind == PROP_TTI) return tti_tile_rows(h->R, h->opt_scheme, pass, shape);
-    return el_tile_rows(h->R, h->g.ndim, shape);
+    // elastic: the launchers take el_tile_rows' height or, on 3D grids, 8 rows (tile variant 0)
+    return h->g.ndim == 3 && shape == 0 ? 8 : el_tile_rows(h->R, h->g.ndim);
 }
 
 // Tiles of a set of windows in spatial order (x fastest, then y, then z chunk of zc planes).  With
