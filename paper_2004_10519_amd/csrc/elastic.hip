@@ -166,6 +166,9 @@ __global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY
         }
     };
     fetch(z0);
+    // 3D: b of plane z, carried from the previous plane's plane-z+1 load (the same address)
+    float c_b0 = 0.f;
+    if constexpr (!TWO_D) c_b0 = ldo((gcchar *)(J.b + w.moff + (int64_t)z0 * w.my), cols.om);
     int b = 0;
     for (int z = z0; z < z1; ++z) {
         float *lxx = Lxx[b], *lyy = Lyy[b], *lxy = Lxy[b], *lxz = Lxz[b], *lyz = Lyz[b];
@@ -248,10 +251,11 @@ __global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY
             const float v0 = ldo(sp(J.v[0], z), fos), v1 = ldo(sp(J.v[1], z), fos);
             const float v2 = ldo(sp(J.v[2], z), fos);
             gcchar *const bz = mp(J.b, z);
-            const float b0 = ldo(bz, fom);
+            const float b0 = c_b0;
             const float bxn = ldo(bz, fresh(cols.omx));
             const float byn = ldo(bz, fresh(cols.omy));
             const float bzn = ldo(mp(J.b, z + 1 < w.nz ? z + 1 : z), fom);
+            c_b0 = bzn;
             const float g = cols.gxy * gld(J.gz, z);
             if (z + 1 < z1) fetch(z + 1);
             const float fx = ds_lds<R, true>(lxx, li, 1, W.wx) + ds_lds<R, false>(lxy, li, LX, W.wy) +
@@ -360,6 +364,15 @@ __global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY
         }
     };
     fetch(z0);
+    // 3D: mu at the own column, its +x and +y neighbours of plane z, carried from the previous plane's
+    // plane-z+1 loads (the same addresses, so the same values)
+    float c_mu0 = 0.f, c_mx = 0.f, c_my = 0.f;
+    if constexpr (!TWO_D) {
+        gcchar *const mz0 = (gcchar *)(J.mu + w.moff + (int64_t)z0 * w.my);
+        c_mu0 = ldo(mz0, cols.om);
+        c_mx = ldo(mz0, cols.omx);
+        c_my = ldo(mz0, cols.omy);
+    }
     int b = 0;
     for (int z = z0; z < z1; ++z) {
         float *lx = Lx[b], *ly = Ly[b], *lz = Lz[b];
@@ -475,11 +488,14 @@ __global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY
             gcchar *const m0 = mp(J.mu, z), *const m1 = mp(J.mu, z + 1 < w.nz ? z + 1 : z);
             const uint32_t omx = fresh(cols.omx), omy = fresh(cols.omy), omxy = omx + omy - fom;
             const float lam = ldo(mp(J.lam, z), fom);
-            const float mu0 = ldo(m0, fom);
-            const float mx_ = ldo(m0, omx), mz_ = ldo(m1, fom), my_ = ldo(m0, omy);
-            const float mxz = 0.25f * (mu0 + mx_ + mz_ + ldo(m1, omx));
+            const float mu0 = c_mu0, mx_ = c_mx, my_ = c_my;
+            const float mz_ = ldo(m1, fom), mxz1 = ldo(m1, omx), myz1 = ldo(m1, omy);
+            c_mu0 = mz_;
+            c_mx = mxz1;
+            c_my = myz1;
+            const float mxz = 0.25f * (mu0 + mx_ + mz_ + mxz1);
             const float mxy = 0.25f * (mu0 + mx_ + my_ + ldo(m0, omxy));
-            const float myz = 0.25f * (mu0 + my_ + mz_ + ldo(m1, omy));
+            const float myz = 0.25f * (mu0 + my_ + mz_ + myz1);
             if (z + 1 < z1) fetch(z + 1);
             const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
             const float eyy = ds_lds<R, false>(ly, li, LX, W.wy);
