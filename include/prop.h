@@ -250,7 +250,7 @@ int prop_kernel_time(prop_t h, int32_t kclass, double *ms, int64_t *launches, co
  *                      elastic gradient may differ at rounding level (1e-7) with TILE2.
  *   PROP_OPT_ZC        z-chunk length in planes when not autotuning, 0 = automatic (default).
  *   PROP_OPT_ZC2       z-chunk of TTI pass 2 when not autotuning, 0 = that of pass 1 (default);
- *                      elastic: z-chunk of the stress pass, 0 = automatic for its tiles.
+ *                      elastic: z-chunk of the stress pass, 0 = that of the velocity pass.
  *   PROP_OPT_XCD       0/1 (default 0): deal the tiles over the 8 XCDs in contiguous ranges.
  *   PROP_OPT_EL_FUSED  0/1 (default 0): elastic prop_forward on 3D grids up to space order 8 runs
  *                      one fused velocity-stress launch a step (kernel class 4) instead of the

@@ -525,15 +525,15 @@ int setup_slot(prop_s *h, Slot &sl, const int64_t o[3], const int64_t n[3])
                                              : (float)std::exp(-k * h->g.dt);
         }
     TRY(upload(sl.tabs, tab, h->st));
-    const int TY = tile_rows(h, 1, h->opt_shape[0]);
+    // 3D elastic z-chunks are sized on 64 x 16 tile columns whatever the tile heights of the two passes
+    // (400^3 so8: the 64 x 8 velocity pass ran 0.743 ms with the 17-plane chunks this gives, 0.775 ms
+    // with the 34 that its own tile count would give; the 64 x 16 stress pass 0.990 ms with 17
+    // planes, 0.999 with 16 or 13)
+    const int TY = h->kind == PROP_ELASTIC && h->g.ndim == 3 ? 16 : tile_rows(h, 1, h->opt_shape[0]);
     const int64_t txy = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY - 1) / TY);
     sl.zc = choose_zc(h, w.nz, txy);
-    sl.zc2 = sl.zc;
-    if (h->kind == PROP_ELASTIC) {   // the stress pass runs its own tiles (TILE2) and z-chunk
-        const int TY2 = tile_rows(h, 2, h->opt_shape[1]);
-        const int64_t txy2 = (int64_t)((w.nx + PROP_TX - 1) / PROP_TX) * ((w.ny + TY2 - 1) / TY2);
-        sl.zc2 = h->opt_zc2 > 0 ? std::min(h->opt_zc2, (int)w.nz) : choose_zc(h, w.nz, txy2);
-    }
+    sl.zc2 = sl.zc;   // the elastic stress pass runs its own tiles (TILE2) and may take its own z-chunk
+    if (h->kind == PROP_ELASTIC && h->opt_zc2 > 0) sl.zc2 = std::min(h->opt_zc2, (int)w.nz);
     return PROP_OK;
 }
 
