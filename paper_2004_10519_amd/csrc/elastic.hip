@@ -618,7 +618,9 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
     // per-point operands, loaded a plane ahead: tau~, v~, v^n, buoyancy at the node and its +x, +y, +z
     // neighbours (clamped at the window's far faces)
     float pt_t[6], pt_vt[3], pt_v0[3], pt_b[4];
-    auto load_pt = [&](int z) {
+    // (after the first plane, b at the node is the previous plane's +z neighbour, already loaded: the
+    // same address, so the same value)
+    auto load_pt = [&](int z, bool carry) {
         const uint32_t fos = fresh(os), fom = fresh(om);
 #pragma unroll
         for (int c = 0; c < 6; ++c) pt_t[c] = ldo(sp(J.tt[c], z), fos);
@@ -628,12 +630,12 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
             pt_v0[c] = ldo(sp(J.vn0[c], z), fos);
         }
         gcchar *const bz = mp(J.b, z);
-        pt_b[0] = ldo(bz, fom);
+        pt_b[0] = carry ? pt_b[3] : ldo(bz, fom);
         pt_b[1] = ldo(bz, fresh(omx));
         pt_b[2] = ldo(bz, fresh(omy));
         pt_b[3] = ldo(mp(J.b, z + 1 < w.nz ? z + 1 : z), fom);
     };
-    load_pt(z0);
+    load_pt(z0, false);
     int b = 0;
     for (int z = z0; z < z1; ++z) {
         float *lx = Lx[b], *ly = Ly[b], *lz = Lz[b];
@@ -682,7 +684,7 @@ __global__ __launch_bounds__(PROP_TX * BY) void el_grad_ic(const ElGradJob *__re
         const float g = cols.gxy * gld(J.gz, z);
         const float v1[3] = {qx[R], qy[R], qz[R]};
         if (z + 1 < z1) {
-            load_pt(z + 1);
+            load_pt(z + 1, true);
             fetch(z + 1);
         }
         const float exx = ds_lds<R, false>(lx, li, 1, W.wx);
