@@ -26,9 +26,9 @@ namespace {
 // (ny = 1) use one row, so a block is a single wavefront and no y-halo work is done (its y
 // derivatives are zero).
 constexpr int EBY = 16;
-#ifndef EL8_WAVES
-#define EL8_WAVES 6
-#endif
+// 64 x 8 tiles (512 threads) are built for three blocks a CU, 6 waves a SIMD (at most 80 VGPRs) up
+// to space order 8; beyond it their registers would spill, and they take what they need.
+constexpr int EL_NARROW_WAVES = 6;
 
 // Velocity pass.  Fields read: F[0..5] = (xx, yy, zz, xy, xz, yz) stresses (forward: tau;
 // adjoint: sigma).  LDS: xx (x-halo), yy (y-halo), xy (x and y), xz (x), yz (y);
@@ -83,7 +83,7 @@ struct ElCols {
 };
 
 template <int R, int MODE, int BY>
-__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL8_WAVES : 1))) void el_vel(const ElJob *__restrict__ jobs,
+__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL_NARROW_WAVES : 1))) void el_vel(const ElJob *__restrict__ jobs,
                                                        const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY
 // Stress pass.  Fields read: V[0..2] (forward: v; adjoint: u = bbar g v~), each staged in LDS
 // with x and y halos and queued in z.
 template <int R, int MODE, int BY>
-__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL8_WAVES : 1))) void el_stress(const ElJob *__restrict__ jobs,
+__global__ __launch_bounds__(PROP_TX * BY) __attribute__((amdgpu_waves_per_eu(BY == 8 && R <= 4 ? EL_NARROW_WAVES : 1))) void el_stress(const ElJob *__restrict__ jobs,
                                                           const Tile *__restrict__ tiles, int zc, Weights W, float dt)
 {
     constexpr int TY = BY, Q = 2 * R + 1, NT = PROP_TX * BY;
