@@ -254,8 +254,8 @@ struct prop_s {
     int opt_shape[2] = {1, 1};  // tile variants: TTI pass 1 / pass 2 when not autotuning; elastic
                                 // velocity / stress pass (and imaging condition)
     int opt_zc = 0;             // fixed z-chunk length (0: automatic)
-    int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 (0: that of pass 1) or of the elastic
-                                // stress pass (0: automatic)
+    int opt_zc2 = 0;            // fixed z-chunk of TTI pass 2 or of the elastic stress pass (0: that
+                                // of pass 1 / the velocity pass)
     int opt_scheme = TTI_SIX;   // TTI step scheme (TTI_SIX, TTI_FUSED, TTI_FOUR or TTI_SPLIT); set at create
     int64_t opt_batch_mb = 0;   // memory budget of the batched planner (0: 85 % of free memory)
     // autotuner: best tile variant and z-chunk per pass, per (direction, window set)
@@ -2076,7 +2076,8 @@ int prop_create(prop_t *out, prop_kind kind, const prop_grid *grid, const prop_m
     h->st = (hipStream_t)stream;
     h->R = grid->space_order / 2;
     // elastic 3D grids: 64 x 8 tiles for the velocity pass (three blocks of 512 threads a CU; 400^3
-    // so8: 0.78-0.79 against 0.87 ms), 64 x 16 for the stress pass (1.00 against 1.02-1.04 ms)
+    // so8: 0.74 against 0.87 ms), 64 x 16 for the stress pass and the imaging condition (stress:
+    // 0.99 against 0.98-1.04 ms, and the velocity pass after a 64 x 8 stress pass ran slower)
     if (kind == PROP_ELASTIC) h->opt_shape[0] = 0;
     // default TTI scheme (512^3 workload, ms per step): space order 8 and below, the fused pass
     // (so8: 1.70 against 1.50 + 0.80 for the split pair and 2.94 for two passes); space orders 10-12,
